@@ -1,0 +1,192 @@
+/*
+ * hodlr.h - C ABI of the MI355X (gfx950) HODLR QR library.
+ *
+ * The library computes the QR decomposition A ~= Q R of a square HODLR matrix
+ * A with Q = I - Y T Y^T (compact WY representation, Schreiber & Van Loan),
+ * following Algorithm hQR of Kressner & Susnjara, "Fast QR decomposition of
+ * HODLR matrices" (Sec. 4).  Y (unit lower triangular), T and R (upper
+ * triangular) are HODLR matrices of the same level and partition as A.
+ *
+ * Conventions shared by every entry point
+ *  - All arithmetic is IEEE binary64.
+ *  - Matrices are column-major.  A HODLR matrix of level l on the partition
+ *    n = n_1 + ... + n_{2^l} (Sec. 2.1, eq. integerpart) has 2^l dense leaves
+ *    and, for every internal node v of its binary tree (heap numbering: root 1,
+ *    children 2v and 2v+1), an upper block A(I_left, I_right) = U V^T and a
+ *    lower block A(I_right, I_left) = U V^T (eq. factoroffdiagonal with
+ *    V = A_R^T).  Blocks are listed in level order (depth 0 .. l-1, nodes left
+ *    to right), the upper block of a node before its lower block.
+ *  - "device" pointers are HIP device memory on the current device, "host"
+ *    pointers are ordinary host memory.  The caller owns every array it passes;
+ *    the library owns the handles and all device memory behind them.
+ *  - Every call returns a hodlr_status.  Argument errors are detected on the
+ *    host before any work is queued; hodlr_last_error() then describes the
+ *    failure (thread-local string).  No call aborts or throws.
+ *  - Work is queued on the given stream (0 = the null stream).  hodlr_build
+ *    and hodlr_qr synchronise that stream before returning (they read back a
+ *    few scalars); hodlr_apply_q, hodlr_solve and hodlr_matmul are
+ *    asynchronous.
+ *  - A handle may be used from one thread at a time.
+ */
+#ifndef HODLR_H
+#define HODLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hodlr_s hodlr_t;       /* device-resident HODLR matrix            */
+typedef struct hodlr_qr_s hodlr_qr_t; /* device-resident factors {Y, T, R}       */
+typedef void *hodlr_stream_t;         /* a hipStream_t                           */
+
+typedef enum {
+  HODLR_OK = 0,
+  HODLR_EINVAL = -1,     /* invalid argument (sizes, partition, ranks, NULL)      */
+  HODLR_ENOMEM = -2,     /* device allocation failed                              */
+  HODLR_ENONFINITE = -3, /* NaN or Inf in the input                               */
+  HODLR_ECAPACITY = -4,  /* an off-diagonal rank outgrew the capacity; retry with
+                            a larger rank_cap or a looser eps                      */
+  HODLR_EDEVICE = -5,    /* a HIP call failed; hodlr_last_error() has its text     */
+  HODLR_ENOTBUILT = -6   /* the library was loaded without device code            */
+} hodlr_status;
+
+/* hodlr_qr flags */
+#define HODLR_QR_NO_GRAPH 1u  /* launch the schedule directly instead of replaying
+                                 a captured HIP graph                              */
+
+/*
+ * hodlr_build - copy a HODLR matrix to the device.
+ *
+ *  n, levels      order and level l >= 0 of the matrix.
+ *  leaf_off       host, 2^l + 1 prefix offsets of the partition (leaf_off[0] = 0,
+ *                 leaf_off[2^l] = n, strictly increasing).
+ *  leaves         host, the dense leaves one after another, leaf j column-major
+ *                 n_j x n_j starting at leaves + leaf_data_off[j].
+ *  leaf_data_off  host, 2^l offsets (in doubles) into `leaves`.
+ *  U, u_off       host, block b's left factor (rows_b x rank_b, column-major) at
+ *                 U + u_off[b]; blocks in the order stated above (2^(l+1) - 2 of
+ *                 them).
+ *  V, v_off       host, block b's right factor (cols_b x rank_b) at V + v_off[b].
+ *  ranks          host, rank_b of every block, 0 <= rank_b <= min(rows_b, cols_b,
+ *                 rank_cap).
+ *  rank_cap       capacity (columns) reserved for every off-diagonal factor of A
+ *                 and of the factors Y, T, R computed from it; 1..64.
+ *  out            receives the new handle (release with hodlr_free).
+ * Returns HODLR_EINVAL for an inconsistent partition or rank, HODLR_ENONFINITE
+ * if any input entry is NaN/Inf, HODLR_ENOMEM if the device is full.
+ */
+hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t *leaf_off,
+                         const double *leaves, const int64_t *leaf_data_off,
+                         const double *U, const int64_t *u_off,
+                         const double *V, const int64_t *v_off,
+                         const int32_t *ranks, int32_t rank_cap,
+                         hodlr_stream_t stream, hodlr_t **out);
+
+/*
+ * hodlr_qr - hQR factorisation A ~= (I - Y T Y^T) R  (Algorithm hQR, Sec. 4).
+ *
+ *  eps    truncation tolerance >= 0.  Recompressions of A-valued blocks (the
+ *         sum S~, the new upper block of R, the low-rank update of the trailing
+ *         HODLR part) keep singular values > eps*anorm; the off-diagonal blocks
+ *         of T keep singular values > eps (as written in the algorithm).
+ *  anorm  |A|_2 used for the threshold; if anorm <= 0 it is estimated on the
+ *         device by 50 steps of power iteration on A^T A (see hodlr_norm2_est).
+ *  flags  0 or HODLR_QR_NO_GRAPH.
+ *  out    receives the factors (release with hodlr_qr_free).  A is not modified.
+ * Returns HODLR_ECAPACITY if a rank outgrew rank_cap (or a recompression width
+ * exceeded 128); the partial factors are then released.
+ */
+hodlr_status hodlr_qr(const hodlr_t *A, double eps, double anorm, uint32_t flags,
+                      hodlr_stream_t stream, hodlr_qr_t **out);
+
+/*
+ * hodlr_apply_q - X <- Q X (trans = 0) or X <- Q^T X (trans = 1), with
+ * Q = I - Y T Y^T (eq. compactwy).  X: device, n x nrhs, leading dimension
+ * ldx >= n.  Asynchronous.
+ */
+hodlr_status hodlr_apply_q(const hodlr_qr_t *F, int32_t trans, int64_t nrhs, double *X,
+                           int64_t ldx, hodlr_stream_t stream);
+
+/*
+ * hodlr_solve - B <- R^{-1} Q^T B, i.e. the solution of A x = b for every
+ * column of B (device, n x nrhs, ldb >= n).  Back substitution with the upper
+ * triangular HODLR R runs leaf by leaf from the last one.  Asynchronous.
+ */
+hodlr_status hodlr_solve(const hodlr_qr_t *F, int64_t nrhs, double *B, int64_t ldb,
+                         hodlr_stream_t stream);
+
+/*
+ * hodlr_matmul - Z <- op(A) X for the HODLR matrix A (HODLR matrix times a
+ * dense block, Table 1's matrix-vector product applied to nrhs columns).
+ * trans = 0: op(A) = A, 1: A^T.  X, Z: device, n x nrhs, distinct.  Asynchronous.
+ */
+hodlr_status hodlr_matmul(const hodlr_t *A, int32_t trans, int64_t nrhs, const double *X,
+                          int64_t ldx, double *Z, int64_t ldz, hodlr_stream_t stream);
+
+/*
+ * hodlr_qr_matmul - Z <- op(M) X for one factor M of F: which = 'Y' (unit lower),
+ * 'T' (upper) or 'R' (upper).  Same operand rules as hodlr_matmul.
+ */
+hodlr_status hodlr_qr_matmul(const hodlr_qr_t *F, char which, int32_t trans, int64_t nrhs,
+                             const double *X, int64_t ldx, double *Z, int64_t ldz,
+                             hodlr_stream_t stream);
+
+/*
+ * hodlr_norm2_est - |A|_2 estimate: x0 = (1,...,1)/sqrt(n), 'iters' steps of
+ * x <- A^T A x / |A^T A x|, result |A x|.  Synchronises the stream; *out host.
+ */
+hodlr_status hodlr_norm2_est(const hodlr_t *A, int32_t iters, hodlr_stream_t stream,
+                             double *out);
+
+/* Factor summary (host struct filled by hodlr_qr_info). */
+typedef struct {
+  int64_t n;
+  int32_t levels;
+  int32_t rank_cap;
+  int32_t max_rank_y, max_rank_t, max_rank_r; /* largest off-diagonal ranks          */
+  double anorm, tau_a, tau_t;                 /* thresholds actually used             */
+  double flops;        /* algorithmic FP64 flops of the factorisation (counted on the
+                          device from the realised sizes and ranks)                  */
+  int64_t n_truncations; /* recompressions performed                                 */
+  int64_t n_launches;    /* kernel launches in one factorisation                     */
+  int64_t device_bytes;  /* device memory held by the factors                        */
+} hodlr_qr_info_t;
+
+hodlr_status hodlr_qr_info(const hodlr_qr_t *F, hodlr_qr_info_t *info);
+
+/*
+ * hodlr_export / hodlr_qr_export - copy a matrix (or one factor of F:
+ * which = 'Y', 'T', 'R') back to host memory in the hodlr_build layout.
+ * leaves: sum n_j^2 doubles.  U, V: room for (2^(l+1) - 2) blocks of
+ * rank_cap columns each, packed as rows_b*rank_b (U) and cols_b*rank_b (V)
+ * at the offsets written to u_off / v_off; ranks: 2^(l+1) - 2 ints.
+ * For Y the stored leaf is the unit lower triangle (ones on the diagonal), for
+ * T and R the upper triangle; blocks that are zero by structure get rank 0.
+ * Synchronous.
+ */
+hodlr_status hodlr_export(const hodlr_t *A, double *leaves, double *U, int64_t *u_off,
+                          double *V, int64_t *v_off, int32_t *ranks);
+hodlr_status hodlr_qr_export(const hodlr_qr_t *F, char which, double *leaves, double *U,
+                             int64_t *u_off, double *V, int64_t *v_off, int32_t *ranks);
+
+/*
+ * hodlr_qr_time - run the factorisation of A `reps` times on `stream` after
+ * `warmup` untimed runs, bracketing each run with HIP events on that stream,
+ * and return the per-run durations in ms (host array of reps doubles).  The
+ * factors of the last run are discarded.
+ */
+hodlr_status hodlr_qr_time(const hodlr_t *A, double eps, double anorm, uint32_t flags,
+                           int32_t warmup, int32_t reps, hodlr_stream_t stream, double *ms);
+
+void hodlr_free(hodlr_t *A);        /* NULL-safe */
+void hodlr_qr_free(hodlr_qr_t *F);  /* NULL-safe */
+const char *hodlr_last_error(void); /* thread-local; empty string if none */
+const char *hodlr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HODLR_H */

@@ -1,0 +1,191 @@
+"""MI355X (gfx950) HODLR QR decomposition: Python binding of libhodlr.so.
+
+The functions carry the names of the C ABI (include/hodlr.h) and only marshal
+arguments: the factorisation, the products, apply-Q and solve all run in the
+library's HIP kernels.  Dense operands are torch float64 tensors on the GPU,
+laid out column-major: an n x nrhs operand is a tensor of shape (n, nrhs) with
+strides (1, ld) -- use `colmajor` to make one.  Nothing here falls back to the
+CPU; a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import HODLR_QR_NO_GRAPH, HodlrError, QRInfo
+
+__all__ = [
+    "hodlr_build", "hodlr_qr", "hodlr_apply_q", "hodlr_solve", "hodlr_matmul", "hodlr_qr_matmul",
+    "hodlr_norm2_est", "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time",
+    "HodlrMatrix", "QRFactors", "HodlrError", "colmajor", "HODLR_QR_NO_GRAPH", "load",
+]
+
+load = _lib.load
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+def colmajor(a, device="cuda"):
+    """torch float64 tensor (n, k) with column-major strides (1, n) from an array."""
+    import torch
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a[:, None]
+    t = torch.from_numpy(np.ascontiguousarray(a.T)).to(device)
+    return t.t()
+
+
+def _operand(X, n):
+    import torch
+    if not isinstance(X, torch.Tensor) or X.dtype != torch.float64 or not X.is_cuda:
+        raise HodlrError(-1, "operand must be a float64 CUDA (HIP) tensor")
+    if X.dim() == 1:
+        X = X[:, None]
+    if X.shape[0] != n:
+        raise HodlrError(-1, f"operand has {X.shape[0]} rows, expected {n}")
+    if X.shape[1] > 1 and X.stride(0) != 1:
+        raise HodlrError(-1, "operand must be column-major (strides (1, ld)); see colmajor()")
+    ld = X.stride(1) if X.shape[1] > 1 else n
+    return X, max(ld, n)
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class HodlrMatrix:
+    """Owning wrapper of a hodlr_t handle."""
+
+    def __init__(self, handle, n, levels, rank_cap):
+        self.handle, self.n, self.levels, self.rank_cap = handle, n, levels, rank_cap
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        lib = getattr(_lib, "_lib", None) if _lib is not None else None
+        if h and lib is not None:
+            lib.hodlr_free(h)
+            self.handle = None
+
+
+class QRFactors:
+    """Owning wrapper of a hodlr_qr_t handle (factors Y, T, R)."""
+
+    def __init__(self, handle, A):
+        self.handle, self.n, self.levels, self.rank_cap = handle, A.n, A.levels, A.rank_cap
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        lib = getattr(_lib, "_lib", None) if _lib is not None else None
+        if h and lib is not None:
+            lib.hodlr_qr_free(h)
+            self.handle = None
+
+
+def hodlr_build(H, rank_cap: int = 64, stream=None) -> HodlrMatrix:
+    """Copy a HODLR matrix (hodlr_gen.HodlrInput or its .pack() dict) to the GPU."""
+    lib = load()
+    p = H.pack() if hasattr(H, "pack") else H
+    h = C.c_void_p()
+    _lib.check(lib.hodlr_build(
+        int(p["n"]), int(p["levels"]), _ptr(p["leaf_off"], C.c_int64), _ptr(p["leaves"], C.c_double),
+        _ptr(p["leaf_data_off"], C.c_int64), _ptr(p["U"], C.c_double), _ptr(p["u_off"], C.c_int64),
+        _ptr(p["V"], C.c_double), _ptr(p["v_off"], C.c_int64), _ptr(p["ranks"], C.c_int32),
+        int(rank_cap), _stream(stream), C.byref(h)))
+    return HodlrMatrix(h, int(p["n"]), int(p["levels"]), int(rank_cap))
+
+
+def hodlr_qr(A: HodlrMatrix, eps: float, anorm: float = 0.0, flags: int = 0, stream=None) -> QRFactors:
+    lib = load()
+    h = C.c_void_p()
+    _lib.check(lib.hodlr_qr(A.handle, float(eps), float(anorm), int(flags), _stream(stream), C.byref(h)))
+    return QRFactors(h, A)
+
+
+def hodlr_apply_q(F: QRFactors, X, trans: bool = False, stream=None):
+    """X <- Q X (or Q^T X) in place."""
+    X, ld = _operand(X, F.n)
+    _lib.check(load().hodlr_apply_q(F.handle, 1 if trans else 0, X.shape[1], C.c_void_p(X.data_ptr()), ld,
+                                    _stream(stream)))
+    return X
+
+
+def hodlr_solve(F: QRFactors, B, stream=None):
+    """B <- R^{-1} Q^T B in place (solution of A x = b per column)."""
+    B, ld = _operand(B, F.n)
+    _lib.check(load().hodlr_solve(F.handle, B.shape[1], C.c_void_p(B.data_ptr()), ld, _stream(stream)))
+    return B
+
+
+def _new_like(X):
+    import torch
+    return torch.empty((X.shape[1], X.shape[0]), dtype=torch.float64, device=X.device).t()
+
+
+def hodlr_matmul(A: HodlrMatrix, X, trans: bool = False, stream=None):
+    X, ldx = _operand(X, A.n)
+    Z = _new_like(X)
+    _lib.check(load().hodlr_matmul(A.handle, 1 if trans else 0, X.shape[1], C.c_void_p(X.data_ptr()), ldx,
+                                   C.c_void_p(Z.data_ptr()), A.n, _stream(stream)))
+    return Z
+
+
+def hodlr_qr_matmul(F: QRFactors, which: str, X, trans: bool = False, stream=None):
+    X, ldx = _operand(X, F.n)
+    Z = _new_like(X)
+    _lib.check(load().hodlr_qr_matmul(F.handle, which.encode()[:1], 1 if trans else 0, X.shape[1],
+                                      C.c_void_p(X.data_ptr()), ldx, C.c_void_p(Z.data_ptr()), F.n,
+                                      _stream(stream)))
+    return Z
+
+
+def hodlr_norm2_est(A: HodlrMatrix, iters: int = 50, stream=None) -> float:
+    out = C.c_double()
+    _lib.check(load().hodlr_norm2_est(A.handle, int(iters), _stream(stream), C.byref(out)))
+    return out.value
+
+
+def hodlr_qr_info(F: QRFactors) -> dict:
+    info = QRInfo()
+    _lib.check(load().hodlr_qr_info(F.handle, C.byref(info)))
+    return info.as_dict()
+
+
+def _export(call, n, levels, rank_cap, leaf_sizes):
+    nb = 2 * ((1 << levels) - 1)
+    leaves = np.zeros(int(sum(m * m for m in leaf_sizes)))
+    cap_u = n * levels * rank_cap + 1
+    U = np.zeros(cap_u)
+    V = np.zeros(cap_u)
+    u_off = np.zeros(max(nb, 1), dtype=np.int64)
+    v_off = np.zeros(max(nb, 1), dtype=np.int64)
+    ranks = np.zeros(max(nb, 1), dtype=np.int32)
+    _lib.check(call(_ptr(leaves, C.c_double), _ptr(U, C.c_double), _ptr(u_off, C.c_int64),
+                    _ptr(V, C.c_double), _ptr(v_off, C.c_int64), _ptr(ranks, C.c_int32)))
+    return dict(leaves=leaves, U=U, V=V, u_off=u_off[:nb], v_off=v_off[:nb], ranks=ranks[:nb])
+
+
+def hodlr_export(A: HodlrMatrix, leaf_sizes) -> dict:
+    """Host copy of A in the hodlr_build layout (leaf_sizes: the partition)."""
+    return _export(lambda *a: load().hodlr_export(A.handle, *a), A.n, A.levels, A.rank_cap, leaf_sizes)
+
+
+def hodlr_qr_export(F: QRFactors, which: str, leaf_sizes) -> dict:
+    """Host copy of the factor 'Y', 'T' or 'R' in the hodlr_build layout."""
+    return _export(lambda *a: load().hodlr_qr_export(F.handle, which.encode()[:1], *a), F.n, F.levels,
+                   F.rank_cap, leaf_sizes)
+
+
+def hodlr_qr_time(A: HodlrMatrix, eps: float, anorm: float = 0.0, flags: int = 0, warmup: int = 1,
+                  reps: int = 3, stream=None):
+    """Per-run wall times (ms, HIP events on the stream) of `reps` factorisations."""
+    ms = np.zeros(reps)
+    _lib.check(load().hodlr_qr_time(A.handle, float(eps), float(anorm), int(flags), int(warmup), int(reps),
+                                    _stream(stream), _ptr(ms, C.c_double)))
+    return ms

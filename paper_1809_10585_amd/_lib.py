@@ -1,0 +1,92 @@
+"""ctypes binding of libhodlr.so (include/hodlr.h).  Argument marshalling only:
+every step of the factorisation runs in the library's HIP kernels.  PyTorch
+supplies device memory and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhodlr.so")
+
+HODLR_OK = 0
+STATUS = {0: "HODLR_OK", -1: "HODLR_EINVAL", -2: "HODLR_ENOMEM", -3: "HODLR_ENONFINITE",
+          -4: "HODLR_ECAPACITY", -5: "HODLR_EDEVICE", -6: "HODLR_ENOTBUILT"}
+HODLR_QR_NO_GRAPH = 1
+
+# every symbol include/hodlr.h declares
+EXPORTS = [
+    "hodlr_build", "hodlr_qr", "hodlr_apply_q", "hodlr_solve", "hodlr_matmul", "hodlr_qr_matmul",
+    "hodlr_norm2_est", "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time",
+    "hodlr_free", "hodlr_qr_free", "hodlr_last_error", "hodlr_version",
+]
+
+
+class HodlrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class QRInfo(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("levels", C.c_int32), ("rank_cap", C.c_int32),
+        ("max_rank_y", C.c_int32), ("max_rank_t", C.c_int32), ("max_rank_r", C.c_int32),
+        ("anorm", C.c_double), ("tau_a", C.c_double), ("tau_t", C.c_double),
+        ("flops", C.c_double), ("n_truncations", C.c_int64), ("n_launches", C.c_int64),
+        ("device_bytes", C.c_int64),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+P = C.c_void_p
+PP = C.POINTER(C.c_void_p)
+I64 = C.c_int64
+I32 = C.c_int32
+D = C.c_double
+PD = C.POINTER(C.c_double)
+PI64 = C.POINTER(C.c_int64)
+PI32 = C.POINTER(C.c_int32)
+
+
+def load(path: str = LIB_PATH):
+    """Load libhodlr.so; raises if it has not been built (no CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise HodlrError(-6, f"{path} is missing; run paper_1809_10585_amd/build.py first")
+    lib = C.CDLL(path)
+    sig = {
+        "hodlr_build": (I32, [I64, I32, PI64, PD, PI64, PD, PI64, PD, PI64, PI32, I32, P, PP]),
+        "hodlr_qr": (I32, [P, D, D, C.c_uint32, P, PP]),
+        "hodlr_apply_q": (I32, [P, I32, I64, P, I64, P]),
+        "hodlr_solve": (I32, [P, I64, P, I64, P]),
+        "hodlr_matmul": (I32, [P, I32, I64, P, I64, P, I64, P]),
+        "hodlr_qr_matmul": (I32, [P, C.c_char, I32, I64, P, I64, P, I64, P]),
+        "hodlr_norm2_est": (I32, [P, I32, P, PD]),
+        "hodlr_qr_info": (I32, [P, C.POINTER(QRInfo)]),
+        "hodlr_export": (I32, [P, PD, PD, PI64, PD, PI64, PI32]),
+        "hodlr_qr_export": (I32, [P, C.c_char, PD, PD, PI64, PD, PI64, PI32]),
+        "hodlr_qr_time": (I32, [P, D, D, C.c_uint32, I32, I32, P, PD]),
+        "hodlr_free": (None, [P]),
+        "hodlr_qr_free": (None, [P]),
+        "hodlr_last_error": (C.c_char_p, []),
+        "hodlr_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status):
+    if status != HODLR_OK:
+        raise HodlrError(status, load().hodlr_last_error().decode())

@@ -1,0 +1,1347 @@
+// Host side of the HODLR QR library: device-resident HODLR storage, the
+// depth-first schedule of Algorithm hQR (Kressner & Susnjara, Sec. 4)
+// compiled into a flat list of batched kernel launches, its execution
+// (directly or as a captured HIP graph), and the C ABI of include/hodlr.h.
+//
+// Storage of the factors (all on A's partition):
+//  * leaf j        : R (upper triangle) and Y (strictly lower, unit diagonal
+//                    implied) share the leaf array; T has its own leaf array.
+//  * upper block v : A12 on input; the recompressed block of R afterwards.
+//  * lower block v : A21 = U V^T on input.  U is made orthonormal up front and
+//                    stays the left factor of Y's lower block; V is
+//                    overwritten by Y~_B^T slice by slice as the leaves below
+//                    node v's left child are factorised (Y_B = B_L Y~_B).
+//  * T block v     : T12 = -T1 T~12 T2 in factored form.
+#include "kernels.hip"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hodlr.h"
+
+using namespace hq;
+
+namespace {
+
+thread_local std::string g_err;
+
+hodlr_status fail(hodlr_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+#define HIPCHK(x)                                                                       \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess) {                                                             \
+      g_err = std::string(#x) + ": " + hipGetErrorString(e_);                           \
+      return e_ == hipErrorOutOfMemory ? HODLR_ENOMEM : HODLR_EDEVICE;                  \
+    }                                                                                   \
+  } while (0)
+
+// ------------------------------------------------------------------ device memory
+struct DMem {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  ~DMem() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <class T>
+  hodlr_status alloc(T** out, size_t count) {
+    *out = nullptr;
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(HODLR_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    ptrs.push_back(p);
+    bytes += count * sizeof(T);
+    *out = static_cast<T*>(p);
+    return HODLR_OK;
+  }
+};
+
+#define TRY(x)                       \
+  do {                               \
+    hodlr_status s_ = (x);           \
+    if (s_ != HODLR_OK) return s_;   \
+  } while (0)
+
+template <class T>
+hodlr_status upload(DMem& mem, T** d, const std::vector<T>& h, hipStream_t st) {
+  TRY(mem.alloc(d, h.size()));
+  if (!h.empty()) HIPCHK(hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return HODLR_OK;
+}
+
+// ------------------------------------------------------------------ tree
+struct Tree {
+  int L = 0;
+  int64_t n = 0;
+  std::vector<int64_t> lo, hi;  // heap numbering 1 .. 2^(L+1)-1
+  int nleaf() const { return 1 << L; }
+  bool is_leaf(int v) const { return v >= (1 << L); }
+  int64_t m(int v) const { return hi[v] - lo[v]; }
+  void init(int levels, const int64_t* off) {
+    L = levels;
+    n = off[1 << L];
+    lo.assign(2 << L, 0);
+    hi.assign(2 << L, 0);
+    for (int j = 0; j < (1 << L); ++j) {
+      lo[(1 << L) + j] = off[j];
+      hi[(1 << L) + j] = off[j + 1];
+    }
+    for (int v = (1 << L) - 1; v >= 1; --v) {
+      lo[v] = lo[2 * v];
+      hi[v] = hi[2 * v + 1];
+    }
+  }
+  void subtree_internal(int v, std::vector<int>& out) const {
+    if (is_leaf(v)) return;
+    out.push_back(v);
+    subtree_internal(2 * v, out);
+    subtree_internal(2 * v + 1, out);
+  }
+  void subtree_leaves(int v, std::vector<int>& out) const {
+    if (is_leaf(v)) {
+      out.push_back(v - (1 << L));
+      return;
+    }
+    subtree_leaves(2 * v, out);
+    subtree_leaves(2 * v + 1, out);
+  }
+  int subtree_size(int v) const {  // nodes in the subtree (heap-relative numbering bound)
+    int d = 31 - __builtin_clz(v);
+    return (2 << (L - d)) - 1;
+  }
+};
+
+// One family of off-diagonal blocks (upper, lower or T's upper) with rank
+// capacity `cap` per block.
+struct BlockSet {
+  double* U = nullptr;
+  double* V = nullptr;
+  std::vector<int64_t> uoff, voff;
+  int64_t usz = 0, vsz = 0;
+  int* rank = nullptr;  // device, indexed by node
+  HBlk* dview = nullptr;
+  std::vector<HBlk> hview;
+};
+
+enum BKind { BK_UP = 0, BK_LO = 1 };
+
+hodlr_status make_blocks(DMem& mem, const Tree& t, int cap, BKind kind, int* rank, BlockSet& B) {
+  const int nn = 1 << t.L;
+  B.uoff.assign(nn, 0);
+  B.voff.assign(nn, 0);
+  B.usz = B.vsz = 0;
+  for (int v = 1; v < nn; ++v) {
+    const int64_t rows = kind == BK_UP ? t.m(2 * v) : t.m(2 * v + 1);
+    const int64_t cols = kind == BK_UP ? t.m(2 * v + 1) : t.m(2 * v);
+    B.uoff[v] = B.usz;
+    B.voff[v] = B.vsz;
+    B.usz += rows * cap;
+    B.vsz += cols * cap;
+  }
+  TRY(mem.alloc(&B.U, (size_t)B.usz));
+  TRY(mem.alloc(&B.V, (size_t)B.vsz));
+  B.rank = rank;
+  B.hview.assign(nn, HBlk{});
+  for (int v = 1; v < nn; ++v) {
+    HBlk& b = B.hview[v];
+    const bool up = kind == BK_UP;
+    b.rows = (int)(up ? t.m(2 * v) : t.m(2 * v + 1));
+    b.cols = (int)(up ? t.m(2 * v + 1) : t.m(2 * v));
+    b.r0 = up ? t.lo[2 * v] : t.lo[2 * v + 1];
+    b.c0 = up ? t.lo[2 * v + 1] : t.lo[2 * v];
+    b.U = B.U + B.uoff[v];
+    b.V = B.V + B.voff[v];
+    b.ldU = b.rows;
+    b.ldV = b.cols;
+    b.rank = rank + v;
+  }
+  return HODLR_OK;
+}
+
+struct LeafSet {
+  double* D = nullptr;
+  std::vector<int64_t> off;
+  int64_t size = 0;
+  HLeaf* dview = nullptr;
+  std::vector<HLeaf> hview;
+};
+
+hodlr_status make_leaves(DMem& mem, const Tree& t, LeafSet& S) {
+  const int nl = t.nleaf();
+  S.off.assign(nl, 0);
+  S.size = 0;
+  for (int j = 0; j < nl; ++j) {
+    S.off[j] = S.size;
+    const int64_t m = t.m(nl + j);
+    S.size += m * m;
+  }
+  TRY(mem.alloc(&S.D, (size_t)S.size));
+  S.hview.assign(nl, HLeaf{});
+  for (int j = 0; j < nl; ++j) {
+    const int64_t m = t.m(nl + j);
+    S.hview[j] = HLeaf{S.D + S.off[j], (int)m, t.lo[nl + j], (int)m};
+  }
+  return HODLR_OK;
+}
+
+// ------------------------------------------------------------------ schedule
+enum OpType {
+  OP_TRQR, OP_TRFORM, OP_MMPROJ, OP_MMAPPLY, OP_GTALL, OP_GRED, OP_LGATHER, OP_LPANEL,
+  OP_LUPDATE, OP_LSCATTER, OP_FILL, OP_NORMALIZE, OP_TRSM
+};
+
+struct Op {
+  int type;
+  int first, count;  // item range (grid = count blocks)
+  int a0;            // leaf job / panel / misc
+  int a1;
+  const double* p0;
+  double* p1;
+  double d0;
+  int64_t n;
+};
+
+struct TrSpec {
+  Seg seg[2][2];
+  int m[2];
+  double tau;
+  int flags;
+  double* out[2];
+  int ldout[2];
+  int cap;
+  int* out_rank;
+  int fc;
+};
+
+struct MmSpec {
+  HView M;
+  bool has_up, has_lo;
+  int v, trans;
+  const double* X;
+  int ldX;
+  int s;
+  const int* s_dev;
+  double* Z;
+  int ldZ;
+  double alpha, beta;
+  int tri;
+};
+
+struct GSpec {  // gemm job with host-side capacities for tiling
+  GemmJob J;
+  int Mcap, Ncap, Kstat;
+};
+
+Seg mkseg(const double* p, int ld, const int* ncols_dev, double scale = 1.0, int ncols = 0) {
+  Seg s;
+  s.p = p;
+  s.ld = ld;
+  s.ncols = ncols;
+  s.ncols_dev = ncols_dev;
+  s.scale = scale;
+  return s;
+}
+
+Seg noseg() { return mkseg(nullptr, 1, nullptr); }
+
+struct Plan {
+  std::vector<TrJob> trj;
+  std::vector<TrChunk> trc;
+  std::vector<TrForm> trf;
+  std::vector<MmJob> mmj;
+  std::vector<MmProj> mmp;
+  std::vector<MmApply> mma;
+  std::vector<GemmJob> gj;
+  std::vector<GemmTile> gt;
+  std::vector<GemmRed> gr;
+  std::vector<LeafJob> lj;
+  std::vector<Op> ops;
+  int64_t ws_need = 0;
+  int cnt_need = 1;
+  int64_t n_trunc = 0;
+  // device copies
+  TrJob* d_trj = nullptr;
+  TrChunk* d_trc = nullptr;
+  TrForm* d_trf = nullptr;
+  MmJob* d_mmj = nullptr;
+  MmProj* d_mmp = nullptr;
+  MmApply* d_mma = nullptr;
+  GemmJob* d_gj = nullptr;
+  GemmTile* d_gt = nullptr;
+  GemmRed* d_gr = nullptr;
+  LeafJob* d_lj = nullptr;
+
+  void trunc(const std::vector<TrSpec>& specs) {
+    if (specs.empty()) return;
+    int64_t off = 0;
+    int cnt = 0;
+    const int c_first = (int)trc.size(), f_first = (int)trf.size();
+    for (const TrSpec& sp : specs) {
+      TrJob J{};
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) J.seg[a][b] = sp.seg[a][b];
+      J.tau = sp.tau;
+      J.flags = sp.flags;
+      J.out[0] = sp.out[0];
+      J.out[1] = sp.out[1];
+      J.ldout[0] = sp.ldout[0];
+      J.ldout[1] = sp.ldout[1];
+      J.cap = sp.cap;
+      J.out_rank = sp.out_rank;
+      J.fc = sp.fc;
+      J.hdr = off;
+      off += TR_HDR;
+      for (int side = 0; side < 2; ++side) {
+        TrSide& S = J.side[side];
+        S.m = sp.m[side];
+        if (side == 1 && (sp.flags & TR_ORTH)) {
+          S.p0 = 0;
+          S.node0 = 0;
+          S.cnt0 = 0;
+          continue;
+        }
+        S.p0 = std::max(1, (S.m + CH - 1) / CH);
+        S.node0 = off;
+        off += 2 * (int64_t)S.p0 * TR_NODE;
+        S.cnt0 = cnt;
+        cnt += S.p0;
+      }
+      J.jcounter = cnt++;
+      const int jid = (int)trj.size();
+      trj.push_back(J);
+      for (int side = 0; side < 2; ++side)
+        for (int c = 0; c < J.side[side].p0; ++c) trc.push_back(TrChunk{jid, side, c});
+      bool leader = true;
+      for (int c = 0; c < J.side[0].p0; ++c) {
+        trf.push_back(TrForm{jid, 0, c, 0, 0, leader ? 1 : 0});
+        leader = false;
+      }
+      for (int r0 = 0; r0 < J.side[1].m; r0 += 64)
+        trf.push_back(TrForm{jid, 1, 0, r0, std::min(64, J.side[1].m - r0), 0});
+      ++n_trunc;
+    }
+    ops.push_back(Op{OP_TRQR, c_first, (int)trc.size() - c_first});
+    ops.push_back(Op{OP_TRFORM, f_first, (int)trf.size() - f_first});
+    ws_need = std::max(ws_need, off);
+    cnt_need = std::max(cnt_need, cnt);
+  }
+
+  void mm(const Tree& t, const std::vector<MmSpec>& specs) {
+    int64_t off = 0;
+    int cnt = 0;
+    const int p_first = (int)mmp.size(), a_first = (int)mma.size();
+    for (const MmSpec& sp : specs) {
+      MmJob J{};
+      J.M = sp.M;
+      J.v = sp.v;
+      J.trans = sp.trans;
+      J.X = sp.X;
+      J.ldX = sp.ldX;
+      J.s = sp.s;
+      J.s_dev = sp.s_dev;
+      J.Z = sp.Z;
+      J.ldZ = sp.ldZ;
+      J.alpha = sp.alpha;
+      J.beta = sp.beta;
+      J.row0 = t.lo[sp.v];
+      J.tri = sp.tri;
+      const int jid = (int)mmj.size();
+      std::vector<int> nodes;
+      t.subtree_internal(sp.v, nodes);
+      for (int u : nodes) {
+        for (int kind = 0; kind < 2; ++kind) {
+          if ((kind == 0 && !sp.has_up) || (kind == 1 && !sp.has_lo)) continue;
+          const int64_t rows = kind == 0 ? t.m(2 * u) : t.m(2 * u + 1);
+          const int64_t cols = kind == 0 ? t.m(2 * u + 1) : t.m(2 * u);
+          const int64_t len = sp.trans ? rows : cols;
+          const int nch = (int)((len + CH - 1) / CH);
+          const int counter = cnt++;
+          for (int c = 0; c < nch; ++c) {
+            mmp.push_back(MmProj{jid, u, kind, c, nch, off + (int64_t)c * KCAP * SMAX, counter});
+          }
+          if (nch > 1) off += (int64_t)nch * KCAP * SMAX;
+        }
+      }
+      J.red0 = off;
+      off += 2 * (int64_t)t.subtree_size(sp.v) * KCAP * SMAX;
+      mmj.push_back(J);
+      std::vector<int> leaves;
+      t.subtree_leaves(sp.v, leaves);
+      for (int j : leaves) {
+        const int m = (int)t.m(t.nleaf() + j);
+        for (int r0 = 0; r0 < m; r0 += 64) mma.push_back(MmApply{jid, j, r0, std::min(64, m - r0)});
+      }
+    }
+    if ((int)mmp.size() > p_first) ops.push_back(Op{OP_MMPROJ, p_first, (int)mmp.size() - p_first});
+    ops.push_back(Op{OP_MMAPPLY, a_first, (int)mma.size() - a_first});
+    ws_need = std::max(ws_need, off);
+    cnt_need = std::max(cnt_need, cnt);
+  }
+
+  void gemm_tall(const std::vector<GSpec>& specs) {
+    if (specs.empty()) return;
+    const int t_first = (int)gt.size();
+    for (const GSpec& g : specs) {
+      const int jid = (int)gj.size();
+      gj.push_back(g.J);
+      for (int r0 = 0; r0 < g.Mcap; r0 += 64)
+        for (int c0 = 0; c0 < g.Ncap; c0 += 64) gt.push_back(GemmTile{jid, r0, c0});
+    }
+    if ((int)gt.size() > t_first) ops.push_back(Op{OP_GTALL, t_first, (int)gt.size() - t_first});
+  }
+
+  void gemm_red(const std::vector<GSpec>& specs) {
+    if (specs.empty()) return;
+    int64_t off = 0;
+    int cnt = 0;
+    const int r_first = (int)gr.size();
+    for (const GSpec& g : specs) {
+      const int jid = (int)gj.size();
+      gj.push_back(g.J);
+      const int K = g.Kstat;
+      const int nch = std::max(1, (K + CH - 1) / CH);
+      const int counter = cnt++;
+      for (int c = 0; c < nch; ++c)
+        gr.push_back(GemmRed{jid, c * CH, std::min(CH, K - c * CH), nch, c, off + (int64_t)c * KCAP * KCAP,
+                             counter});
+      if (nch > 1) off += (int64_t)nch * KCAP * KCAP;
+    }
+    ops.push_back(Op{OP_GRED, r_first, (int)gr.size() - r_first});
+    ws_need = std::max(ws_need, off);
+    cnt_need = std::max(cnt_need, cnt);
+  }
+
+  hodlr_status upload_all(DMem& mem, hipStream_t st) {
+    TRY(upload(mem, &d_trj, trj, st));
+    TRY(upload(mem, &d_trc, trc, st));
+    TRY(upload(mem, &d_trf, trf, st));
+    TRY(upload(mem, &d_mmj, mmj, st));
+    TRY(upload(mem, &d_mmp, mmp, st));
+    TRY(upload(mem, &d_mma, mma, st));
+    TRY(upload(mem, &d_gj, gj, st));
+    TRY(upload(mem, &d_gt, gt, st));
+    TRY(upload(mem, &d_gr, gr, st));
+    TRY(upload(mem, &d_lj, lj, st));
+    return HODLR_OK;
+  }
+};
+
+// Workspace + counters + error word + flop counters shared by a handle's plans.
+struct Work {
+  double* ws = nullptr;
+  int64_t ws_size = 0;
+  int* counters = nullptr;
+  int cnt_size = 0;
+  int* err = nullptr;
+  double* fc = nullptr;
+  LeafWs leaf{};
+};
+
+hodlr_status ensure_work(DMem& mem, Work& W, int64_t ws_need, int cnt_need, bool leafws,
+                         hipStream_t st) {
+  if (W.err == nullptr) {
+    TRY(mem.alloc(&W.err, 4));
+    TRY(mem.alloc(&W.fc, 8));
+    HIPCHK(hipMemsetAsync(W.err, 0, 4 * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(W.fc, 0, 8 * sizeof(double), st));
+  }
+  if (ws_need > W.ws_size) {
+    TRY(mem.alloc(&W.ws, (size_t)ws_need));
+    W.ws_size = ws_need;
+  }
+  if (cnt_need > W.cnt_size) {
+    TRY(mem.alloc(&W.counters, (size_t)cnt_need));
+    HIPCHK(hipMemsetAsync(W.counters, 0, (size_t)cnt_need * sizeof(int), st));
+    W.cnt_size = cnt_need;
+  }
+  if (leafws && W.leaf.H == nullptr) {
+    TRY(mem.alloc(&W.leaf.H, (size_t)MAXSTACK * MAXLEAF));
+    TRY(mem.alloc(&W.leaf.T, (size_t)MAXLEAF * MAXLEAF));
+    TRY(mem.alloc(&W.leaf.G, (size_t)MAXLEAF * MAXLEAF));
+  }
+  return HODLR_OK;
+}
+
+bool g_attr_done = false;
+
+hodlr_status run_ops(const Plan& P, const Work& W, hipStream_t st) {
+  if (!g_attr_done) {
+    HIPCHK(hipFuncSetAttribute((const void*)k_tr_qr, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)TR_QR_LDS));
+    HIPCHK(hipFuncSetAttribute((const void*)k_tr_form, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)TR_FORM_LDS));
+    HIPCHK(hipFuncSetAttribute((const void*)k_leaf_panel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)LEAF_PANEL_LDS));
+    g_attr_done = true;
+  }
+  for (const Op& o : P.ops) {
+    if (o.count <= 0 && o.type != OP_FILL && o.type != OP_NORMALIZE && o.type != OP_LPANEL) continue;
+    switch (o.type) {
+      case OP_TRQR:
+        k_tr_qr<<<o.count, NT_TR, TR_QR_LDS, st>>>(P.d_trj, P.d_trc, o.first, W.ws, W.counters, W.err,
+                                                    W.fc);
+        break;
+      case OP_TRFORM:
+        k_tr_form<<<o.count, NT_MM, TR_FORM_LDS, st>>>(P.d_trj, P.d_trf, o.first, W.ws);
+        break;
+      case OP_MMPROJ:
+        k_mm_proj<<<o.count, NT_MM, 0, st>>>(P.d_mmj, P.d_mmp, o.first, W.ws, W.counters, W.fc);
+        break;
+      case OP_MMAPPLY:
+        k_mm_apply<<<o.count, NT_MM, 0, st>>>(P.d_mmj, P.d_mma, o.first, W.ws, W.fc);
+        break;
+      case OP_GTALL:
+        k_gemm_tall<<<o.count, NT_MM, 0, st>>>(P.d_gj, P.d_gt, o.first, W.fc);
+        break;
+      case OP_GRED:
+        k_gemm_red<<<o.count, NT_MM, 0, st>>>(P.d_gj, P.d_gr, o.first, W.ws, W.counters, W.fc);
+        break;
+      case OP_LGATHER:
+        k_leaf_gather<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, W.err);
+        break;
+      case OP_LPANEL:
+        k_leaf_panel<<<1, NT_TR, LEAF_PANEL_LDS, st>>>(P.d_lj, o.a0, W.leaf, o.a1, W.err);
+        break;
+      case OP_LUPDATE:
+        k_leaf_update<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, o.a1, W.err);
+        break;
+      case OP_LSCATTER:
+        k_leaf_scatter<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, W.err, W.fc);
+        break;
+      case OP_FILL:
+        k_fill<<<(unsigned)((o.n + 255) / 256), 256, 0, st>>>(o.p1, o.n, o.d0);
+        break;
+      case OP_NORMALIZE:
+        k_normalize<<<1, 1024, 0, st>>>(o.p0, o.p1, o.n, o.a0 ? W.fc + 7 : nullptr);
+        break;
+      case OP_TRSM:
+        k_leaf_trsm<<<o.count, NT_MM, 0, st>>>(o.p0, o.a0, o.a0, o.p1, (int)o.n, o.count);
+        break;
+    }
+  }
+  HIPCHK(hipGetLastError());
+  return HODLR_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handles
+struct hodlr_s {
+  Tree t;
+  int cap = 0;
+  DMem mem;
+  LeafSet leaves;
+  BlockSet up, lo;
+  int* ranks = nullptr;  // [0,2^L) up, [2^L, 2^(L+1)) lo
+  std::vector<int32_t> h_ranks_in;
+  Work work;  // for products / norm estimates
+};
+
+struct hodlr_qr_s {
+  Tree t;
+  int cap = 0;
+  DMem mem;
+  LeafSet leaves, tleaves;
+  BlockSet up, lo, tup;
+  int* ranks = nullptr;  // up | lo | t | scalars
+  double anorm = 0, eps = 0, tauA = 0, tauT = 0;
+  Work work;
+  // temporaries of the node steps (n x cap each)
+  double *SL = nullptr, *SR = nullptr, *SLt = nullptr, *Z1 = nullptr, *Z2 = nullptr, *Z4 = nullptr,
+         *SRW = nullptr, *TL = nullptr, *TR = nullptr, *Z5 = nullptr, *Wm = nullptr, *Mg = nullptr;
+  double *X1 = nullptr, *X2 = nullptr;  // n x SMAX scratch of apply_q / solve
+  Plan plan;
+  hipGraphExec_t graph = nullptr;
+  int64_t n_launch = 0;
+  ~hodlr_qr_s() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+  }
+  HView view_gen() const { return HView{t.L, up.dview, lo.dview, leaves.dview, LEAF_FULL}; }
+  HView view_y() const { return HView{t.L, nullptr, lo.dview, leaves.dview, LEAF_UNIT_LOWER}; }
+  HView view_t() const { return HView{t.L, tup.dview, nullptr, tleaves.dview, LEAF_UPPER}; }
+  HView view_r() const { return HView{t.L, up.dview, nullptr, leaves.dview, LEAF_UPPER}; }
+  int* rank_up(int v) { return ranks + v; }
+  int* rank_lo(int v) { return ranks + (1 << t.L) + v; }
+  int* rank_t(int v) { return ranks + 2 * (1 << t.L) + v; }
+  int* rank_s() { return ranks + 3 * (1 << t.L); }
+};
+
+namespace {
+
+MmSpec mmspec(HView M, bool up, bool lo, int v, int trans, const double* X, int ldX, const int* s_dev,
+              double* Z, int ldZ, double alpha, double beta, int tri, int s = 0) {
+  MmSpec m;
+  m.M = M;
+  m.has_up = up;
+  m.has_lo = lo;
+  m.v = v;
+  m.trans = trans;
+  m.X = X;
+  m.ldX = ldX;
+  m.s = s;
+  m.s_dev = s_dev;
+  m.Z = Z;
+  m.ldZ = ldZ;
+  m.alpha = alpha;
+  m.beta = beta;
+  m.tri = tri;
+  return m;
+}
+
+GemmJob gjob(int ta, int tb, int M, const int* Md, int N, const int* Nd, int K, const int* Kd,
+             const double* A, int lda, const double* B, int ldb, double* C, int ldc, double alpha,
+             double beta, int fc) {
+  GemmJob J;
+  J.ta = ta;
+  J.tb = tb;
+  J.M = M;
+  J.N = N;
+  J.K = K;
+  J.Md = Md;
+  J.Nd = Nd;
+  J.Kd = Kd;
+  J.A = A;
+  J.lda = lda;
+  J.B = B;
+  J.ldb = ldb;
+  J.C = C;
+  J.ldc = ldc;
+  J.alpha = alpha;
+  J.beta = beta;
+  J.fc = fc;
+  return J;
+}
+
+// Builds the launch list of one factorisation (Algorithm hQR, depth first).
+struct QRBuilder {
+  hodlr_qr_s& F;
+  Plan& P;
+  const Tree& t;
+  int cap;
+  QRBuilder(hodlr_qr_s& f) : F(f), P(f.plan), t(f.t), cap(f.cap) {}
+
+  // right factor slice of ancestor g's lower block over node x's columns
+  double* gslice(int g, int x) { return F.lo.hview[g].V + (t.lo[x] - t.lo[2 * g]); }
+  int gld(int g) { return (int)t.m(2 * g); }
+
+  void leaf(int v, const std::vector<int>& groups) {
+    const int j = v - t.nleaf();
+    LeafJob J{};
+    J.D = F.leaves.hview[j].D;
+    J.m = (int)t.m(v);
+    J.Tleaf = F.tleaves.hview[j].D;
+    J.ngroups = (int)groups.size();
+    for (size_t i = 0; i < groups.size(); ++i) {
+      const int g = groups[i];
+      J.g[i] = LeafGroup{F.lo.hview[g].V, gld(g), (int)(t.lo[v] - t.lo[2 * g]), F.rank_lo(g)};
+    }
+    const int jid = (int)P.lj.size();
+    P.lj.push_back(J);
+    const int m = J.m, np = (m + NB - 1) / NB;
+    P.ops.push_back(Op{OP_LGATHER, 0, m, jid});
+    for (int p = 0; p <= np; ++p) {
+      if (p < np) P.ops.push_back(Op{OP_LPANEL, 0, 1, jid, p});
+      const int nstrip = p < np ? np - p - 1 : 0, ngram = p < np ? p : 0, ntile = p >= 1 ? p - 1 : 0;
+      const int cnt = nstrip + ngram + ntile;
+      if (cnt > 0) P.ops.push_back(Op{OP_LUPDATE, 0, cnt, jid, p});
+    }
+    P.ops.push_back(Op{OP_LSCATTER, 0, m, jid});
+  }
+
+  TrSpec trspec(Seg l0, Seg l1, Seg r0, Seg r1, int mL, int mR, double tau, double* oL, double* oR,
+                int ldL, int ldR, int* orank, int fc, int flags = 0) {
+    TrSpec s;
+    s.seg[0][0] = l0;
+    s.seg[0][1] = l1;
+    s.seg[1][0] = r0;
+    s.seg[1][1] = r1;
+    s.m[0] = mL;
+    s.m[1] = mR;
+    s.tau = tau;
+    s.flags = flags;
+    s.out[0] = oL;
+    s.out[1] = oR;
+    s.ldout[0] = ldL;
+    s.ldout[1] = ldR;
+    s.cap = cap;
+    s.out_rank = orank;
+    s.fc = fc;
+    return s;
+  }
+
+  void node(int v, const std::vector<int>& groups) {
+    if (t.is_leaf(v)) {
+      leaf(v, groups);
+      return;
+    }
+    const int Lc = 2 * v, Rc = 2 * v + 1;
+    const int mL = (int)t.m(Lc), mR = (int)t.m(Rc);
+    const HBlk& A12 = F.up.hview[v];
+    const HBlk& A21 = F.lo.hview[v];
+    int* k12 = F.rank_up(v);
+    int* k21 = F.rank_lo(v);
+    int* rS = F.rank_s();
+    // first block column: hQR(A11, A21, [B_R1; C1])
+    std::vector<int> gl;
+    gl.push_back(v);
+    gl.insert(gl.end(), groups.begin(), groups.end());
+    node(Lc, gl);
+    // S~ terms: Z1 = Y_A11^T U12 and Z2 = A22^T U21 (one launch pair)
+    P.mm(t, {mmspec(F.view_y(), false, true, Lc, 1, A12.U, mL, k12, F.Z1, mL, 1.0, 0.0, 1),
+             mmspec(F.view_gen(), true, true, Rc, 1, A21.U, mR, k21, F.Z2, mR, 1.0, 0.0, 0)});
+    // S~ = T(Y_A11^T A12 + Y_A21^T A22 + sum over groups), term by term
+    P.trunc({trspec(mkseg(F.Z1, mL, k12), mkseg(A21.V, mL, k21), mkseg(A12.V, mR, k12),
+                    mkseg(F.Z2, mR, k21), mL, mR, F.tauA, F.SL, F.SR, mL, mR, rS, FC_TRUNC)});
+    for (int g : groups)
+      P.trunc({trspec(mkseg(F.SL, mL, rS), mkseg(gslice(g, Lc), gld(g), F.rank_lo(g)),
+                      mkseg(F.SR, mR, rS), mkseg(gslice(g, Rc), gld(g), F.rank_lo(g)), mL, mR, F.tauA,
+                      F.SL, F.SR, mL, mR, rS, FC_TRUNC)});
+    // S = T1^T S~  (left factor only)
+    P.mm(t, {mmspec(F.view_t(), true, false, Lc, 1, F.SL, mL, rS, F.SLt, mL, 1.0, 0.0, 1)});
+    // Y_A11 S_L for the new upper block
+    P.mm(t, {mmspec(F.view_y(), false, true, Lc, 0, F.SLt, mL, rS, F.Z4, mL, 1.0, 0.0, 1)});
+    // W = Y~_B21 S_L (k21 x s) and M_g = S_L^T Y_C1g^T (s x k_g)
+    {
+      std::vector<GSpec> red;
+      red.push_back(GSpec{gjob(1, 0, 0, k21, 0, rS, mL, nullptr, A21.V, mL, F.SLt, mL, F.Wm, KCAP,
+                               1.0, 0.0, FC_DENSE),
+                          KCAP, KCAP, mL});
+      for (size_t i = 0; i < groups.size(); ++i) {
+        const int g = groups[i];
+        red.push_back(GSpec{gjob(1, 0, 0, rS, 0, F.rank_lo(g), mL, nullptr, F.SLt, mL, gslice(g, Lc),
+                                 gld(g), F.Mg + i * KCAP * KCAP, KCAP, 1.0, 0.0, FC_DENSE),
+                            KCAP, KCAP, mL});
+      }
+      P.gemm_red(red);
+    }
+    // SRW = S_R W^T (mR x k21);  C_2g -= S_R M_g  (B^_R2 and C^2 of the update)
+    {
+      std::vector<GSpec> tall;
+      tall.push_back(GSpec{gjob(0, 1, mR, nullptr, 0, k21, 0, rS, F.SR, mR, F.Wm, KCAP, F.SRW, mR, 1.0,
+                                0.0, FC_DENSE),
+                           mR, cap, 0});
+      for (size_t i = 0; i < groups.size(); ++i) {
+        const int g = groups[i];
+        tall.push_back(GSpec{gjob(0, 0, mR, nullptr, 0, F.rank_lo(g), 0, rS, F.SR, mR,
+                                  F.Mg + i * KCAP * KCAP, KCAP, gslice(g, Rc), gld(g), -1.0, 1.0,
+                                  FC_DENSE),
+                             mR, cap, 0});
+      }
+      P.gemm_tall(tall);
+    }
+    // A^12 = T([U12 | -Y_A11 S_L] [V12 | S_R]^T) and A^22 = A22 -_H U21 W S_R^T:
+    // every off-diagonal block of the trailing sub-HODLR, one batch
+    {
+      std::vector<TrSpec> sp;
+      sp.push_back(trspec(mkseg(A12.U, mL, k12), mkseg(F.Z4, mL, rS, -1.0), mkseg(A12.V, mR, k12),
+                          mkseg(F.SR, mR, rS), mL, mR, F.tauA, A12.U, A12.V, mL, mR, k12, FC_TRUNC));
+      std::vector<int> sub;
+      t.subtree_internal(Rc, sub);
+      for (int u : sub) {
+        for (int kind = 0; kind < 2; ++kind) {
+          const HBlk& b = kind == 0 ? F.up.hview[u] : F.lo.hview[u];
+          int* kb = kind == 0 ? F.rank_up(u) : F.rank_lo(u);
+          const int64_t ri = b.r0 - t.lo[Rc], cj = b.c0 - t.lo[Rc];
+          sp.push_back(trspec(mkseg(b.U, b.ldU, kb), mkseg(A21.U + ri, mR, k21), mkseg(b.V, b.ldV, kb),
+                              mkseg(F.SRW + cj, mR, k21, -1.0), b.rows, b.cols, F.tauA, b.U, b.V, b.ldU,
+                              b.ldV, kb, FC_TRUNC));
+        }
+      }
+      P.trunc(sp);
+      // leaves of the trailing part: D -= U21(I) (S_R W^T)(I)^T
+      std::vector<int> leaves;
+      t.subtree_leaves(Rc, leaves);
+      std::vector<GSpec> lu;
+      for (int j : leaves) {
+        const int lv = t.nleaf() + j;
+        const int m = (int)t.m(lv);
+        const int64_t ri = t.lo[lv] - t.lo[Rc];
+        lu.push_back(GSpec{gjob(0, 1, m, nullptr, m, nullptr, 0, k21, A21.U + ri, mR, F.SRW + ri, mR,
+                                F.leaves.hview[j].D, m, -1.0, 1.0, FC_UPDATE),
+                           m, m, 0});
+      }
+      P.gemm_tall(lu);
+    }
+    // second block column: hQR(A^22, [], [B^_R2; C^2])
+    node(Rc, groups);
+    // T~12 = T_eps(Y_A21^T Y_A22 + sum over groups of Y_g1^T Y_g2)
+    P.mm(t, {mmspec(F.view_y(), false, true, Rc, 1, A21.U, mR, k21, F.Z5, mR, 1.0, 0.0, 1)});
+    int* rt = F.rank_t(v);
+    if (groups.empty()) {
+      P.trunc({trspec(mkseg(A21.V, mL, k21), noseg(), mkseg(F.Z5, mR, k21), noseg(), mL, mR, F.tauT,
+                      F.TL, F.TR, mL, mR, rt, FC_TRUNC)});
+    } else {
+      for (size_t i = 0; i < groups.size(); ++i) {
+        const int g = groups[i];
+        const Seg l0 = i == 0 ? mkseg(A21.V, mL, k21) : mkseg(F.TL, mL, rt);
+        const Seg r0 = i == 0 ? mkseg(F.Z5, mR, k21) : mkseg(F.TR, mR, rt);
+        P.trunc({trspec(l0, mkseg(gslice(g, Lc), gld(g), F.rank_lo(g)), r0,
+                        mkseg(gslice(g, Rc), gld(g), F.rank_lo(g)), mL, mR, F.tauT, F.TL, F.TR, mL, mR,
+                        rt, FC_TRUNC)});
+      }
+    }
+    // T12 = -T1 T~12 T2 = (-T1 T~_L)(T2^T T~_R)^T
+    const HBlk& T12 = F.tup.hview[v];
+    P.mm(t, {mmspec(F.view_t(), true, false, Lc, 0, F.TL, mL, rt, T12.U, mL, -1.0, 0.0, 1),
+             mmspec(F.view_t(), true, false, Rc, 1, F.TR, mR, rt, T12.V, mR, 1.0, 0.0, 1)});
+  }
+
+  void build() {
+    // make every lower block left-orthogonal (the B_L of each block column)
+    std::vector<TrSpec> orth;
+    for (int v = 1; v < t.nleaf(); ++v) {
+      const HBlk& b = F.lo.hview[v];
+      orth.push_back(trspec(mkseg(b.U, b.ldU, F.rank_lo(v)), noseg(), mkseg(b.V, b.ldV, F.rank_lo(v)),
+                            noseg(), b.rows, b.cols, 0.0, b.U, b.V, b.ldU, b.ldV, F.rank_lo(v), FC_ORTH,
+                            TR_ORTH));
+    }
+    P.trunc(orth);
+    node(1, {});
+  }
+};
+
+hodlr_status check_finite(const double* p, size_t n, const char* what) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return fail(HODLR_ENONFINITE, std::string("non-finite value in ") + what);
+  return HODLR_OK;
+}
+
+// copies A's storage into F's and resets ranks / counters / flags
+hodlr_status reset_factor(hodlr_qr_s& F, const hodlr_s& A, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(F.leaves.D, A.leaves.D, F.leaves.size * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(F.up.U, A.up.U, F.up.usz * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(F.up.V, A.up.V, F.up.vsz * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(F.lo.U, A.lo.U, F.lo.usz * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(F.lo.V, A.lo.V, F.lo.vsz * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(F.ranks, A.ranks, 2 * (size_t)(1 << A.t.L) * sizeof(int), hipMemcpyDeviceToDevice, st));
+  k_fill<<<1, 64, 0, st>>>(F.work.fc, 8, 0.0);
+  return HODLR_OK;
+}
+
+hodlr_status make_factor(const hodlr_s& A, double eps, double anorm, hipStream_t st,
+                         std::unique_ptr<hodlr_qr_s>& out) {
+  auto F = std::make_unique<hodlr_qr_s>();
+  F->t = A.t;
+  F->cap = A.cap;
+  F->anorm = anorm;
+  F->eps = eps;
+  F->tauA = eps * anorm;
+  F->tauT = eps;
+  const Tree& t = F->t;
+  const int nn = 1 << t.L;
+  TRY(F->mem.alloc(&F->ranks, 3 * (size_t)nn + 8));
+  HIPCHK(hipMemsetAsync(F->ranks, 0, (3 * (size_t)nn + 8) * sizeof(int), st));
+  TRY(make_leaves(F->mem, t, F->leaves));
+  TRY(make_leaves(F->mem, t, F->tleaves));
+  TRY(make_blocks(F->mem, t, F->cap, BK_UP, F->ranks, F->up));
+  TRY(make_blocks(F->mem, t, F->cap, BK_LO, F->ranks + nn, F->lo));
+  TRY(make_blocks(F->mem, t, F->cap, BK_UP, F->ranks + 2 * nn, F->tup));
+  TRY(upload(F->mem, &F->up.dview, F->up.hview, st));
+  TRY(upload(F->mem, &F->lo.dview, F->lo.hview, st));
+  TRY(upload(F->mem, &F->tup.dview, F->tup.hview, st));
+  TRY(upload(F->mem, &F->leaves.dview, F->leaves.hview, st));
+  TRY(upload(F->mem, &F->tleaves.dview, F->tleaves.hview, st));
+  const size_t nc = (size_t)t.n * F->cap;
+  for (double** p : {&F->SL, &F->SR, &F->SLt, &F->Z1, &F->Z2, &F->Z4, &F->SRW, &F->TL, &F->TR, &F->Z5})
+    TRY(F->mem.alloc(p, nc));
+  TRY(F->mem.alloc(&F->Wm, (size_t)KCAP * KCAP));
+  TRY(F->mem.alloc(&F->Mg, (size_t)KCAP * KCAP * (t.L + 1)));
+  TRY(F->mem.alloc(&F->X1, (size_t)t.n * SMAX));
+  TRY(F->mem.alloc(&F->X2, (size_t)t.n * SMAX));
+  if (t.L > MAXGROUPS) return fail(HODLR_EINVAL, "too many levels");
+  QRBuilder qb(*F);
+  qb.build();
+  TRY(F->plan.upload_all(F->mem, st));
+  TRY(ensure_work(F->mem, F->work, F->plan.ws_need, F->plan.cnt_need, true, st));
+  F->n_launch = (int64_t)F->plan.ops.size();
+  out = std::move(F);
+  return HODLR_OK;
+}
+
+hodlr_status run_factor(hodlr_qr_s& F, const hodlr_s& A, bool use_graph, hipStream_t st) {
+  if (!use_graph) {
+    TRY(reset_factor(F, A, st));
+    return run_ops(F.plan, F.work, st);
+  }
+  if (F.graph == nullptr) {
+    // capture on a private stream so that the caller's stream state is untouched
+    hipStream_t cs;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    // prime function attributes outside capture
+    if (!g_attr_done) {
+      HIPCHK(hipFuncSetAttribute((const void*)k_tr_qr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TR_QR_LDS));
+      HIPCHK(hipFuncSetAttribute((const void*)k_tr_form, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TR_FORM_LDS));
+      HIPCHK(hipFuncSetAttribute((const void*)k_leaf_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LEAF_PANEL_LDS));
+      g_attr_done = true;
+    }
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hodlr_status s1 = reset_factor(F, A, cs);
+    hodlr_status s2 = s1 == HODLR_OK ? run_ops(F.plan, F.work, cs) : s1;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (s2 != HODLR_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s2;
+    }
+    if (e != hipSuccess) return fail(HODLR_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&F.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      F.graph = nullptr;
+      return fail(HODLR_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+  }
+  HIPCHK(hipGraphLaunch(F.graph, st));
+  return HODLR_OK;
+}
+
+hodlr_status finish_factor(hodlr_qr_s& F, hipStream_t st) {
+  int err = 0;
+  HIPCHK(hipMemcpyAsync(&err, F.work.err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (err & ERR_STACK) return fail(HODLR_ECAPACITY, "stacked leaf column exceeds 1024 rows");
+  if (err & ERR_WIDTH) return fail(HODLR_ECAPACITY, "a recompression width exceeded 128 columns");
+  if (err & ERR_CAPACITY) return fail(HODLR_ECAPACITY, "an off-diagonal rank exceeded rank_cap");
+  return HODLR_OK;
+}
+
+// power iteration on A^T A with HODLR products
+hodlr_status norm2_est_impl(hodlr_s& A, int iters, hipStream_t st, double* out) {
+  const Tree& t = A.t;
+  const int64_t n = t.n;
+  double *x, *y, *z, *res;
+  DMem tmp;
+  TRY(tmp.alloc(&x, n));
+  TRY(tmp.alloc(&y, n));
+  TRY(tmp.alloc(&z, n));
+  TRY(tmp.alloc(&res, 1));
+  HView V{t.L, A.up.dview, A.lo.dview, A.leaves.dview, LEAF_FULL};
+  Plan P;
+  Op fill{OP_FILL};
+  fill.p1 = x;
+  fill.n = n;
+  fill.d0 = 1.0 / std::sqrt((double)n);
+  P.ops.push_back(fill);
+  auto norm = [&](const double* src, double* dst) {
+    Op o{OP_NORMALIZE};
+    o.p0 = src;
+    o.p1 = dst;
+    o.n = n;
+    o.a0 = 0;
+    P.ops.push_back(o);
+  };
+  for (int it = 0; it < iters; ++it) {
+    P.mm(t, {mmspec(V, true, true, 1, 0, x, (int)n, nullptr, y, (int)n, 1.0, 0.0, 0, 1)});
+    P.mm(t, {mmspec(V, true, true, 1, 1, y, (int)n, nullptr, z, (int)n, 1.0, 0.0, 0, 1)});
+    norm(z, x);
+  }
+  P.mm(t, {mmspec(V, true, true, 1, 0, x, (int)n, nullptr, y, (int)n, 1.0, 0.0, 0, 1)});
+  {
+    Op o{OP_NORMALIZE};
+    o.p0 = y;
+    o.p1 = nullptr;
+    o.n = n;
+    o.a0 = 0;
+    P.ops.push_back(o);
+  }
+  TRY(P.upload_all(tmp, st));
+  TRY(ensure_work(A.mem, A.work, P.ws_need, P.cnt_need, false, st));
+  TRY(run_ops(P, A.work, st));
+  // the last normalize wrote |A x| nowhere: compute it into res
+  k_normalize<<<1, 1024, 0, st>>>(y, nullptr, n, res);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return HODLR_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+const char* hodlr_last_error(void) { return g_err.c_str(); }
+const char* hodlr_version(void) { return "hodlr-qr-gfx950 0.1"; }
+
+hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t* leaf_off, const double* leaves,
+                         const int64_t* leaf_data_off, const double* U, const int64_t* u_off,
+                         const double* V, const int64_t* v_off, const int32_t* ranks, int32_t rank_cap,
+                         hodlr_stream_t stream, hodlr_t** out) {
+  g_err.clear();
+  if (out == nullptr) return fail(HODLR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (levels < 0 || levels > MAXGROUPS) return fail(HODLR_EINVAL, "levels out of range");
+  if (n <= 0 || leaf_off == nullptr || leaves == nullptr || leaf_data_off == nullptr)
+    return fail(HODLR_EINVAL, "bad size or NULL array");
+  if (rank_cap < 1 || rank_cap > KCAP) return fail(HODLR_EINVAL, "rank_cap must be in 1..64");
+  const int nl = 1 << levels;
+  const int nb = 2 * (nl - 1);
+  if (nb > 0 && (U == nullptr || V == nullptr || u_off == nullptr || v_off == nullptr || ranks == nullptr))
+    return fail(HODLR_EINVAL, "NULL block array");
+  if (leaf_off[0] != 0 || leaf_off[nl] != n) return fail(HODLR_EINVAL, "leaf_off must run from 0 to n");
+  for (int j = 0; j < nl; ++j) {
+    const int64_t m = leaf_off[j + 1] - leaf_off[j];
+    if (m < 1) return fail(HODLR_EINVAL, "empty leaf");
+    if (m > MAXLEAF) return fail(HODLR_EINVAL, "leaf larger than 512");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  auto A = std::make_unique<hodlr_s>();
+  A->t.init(levels, leaf_off);
+  A->cap = rank_cap;
+  const Tree& t = A->t;
+  // validate ranks and finiteness
+  int bi = 0;
+  for (int d = 0; d < levels; ++d)
+    for (int v = 1 << d; v < (2 << d); ++v)
+      for (int kind = 0; kind < 2; ++kind, ++bi) {
+        const int64_t rows = kind == 0 ? t.m(2 * v) : t.m(2 * v + 1);
+        const int64_t cols = kind == 0 ? t.m(2 * v + 1) : t.m(2 * v);
+        const int k = ranks[bi];
+        if (k < 0 || k > rows || k > cols || k > rank_cap)
+          return fail(HODLR_EINVAL, "block " + std::to_string(bi) + ": rank out of range");
+        TRY(check_finite(U + u_off[bi], (size_t)(rows * k), "U"));
+        TRY(check_finite(V + v_off[bi], (size_t)(cols * k), "V"));
+      }
+  for (int j = 0; j < nl; ++j) {
+    const int64_t m = t.m(nl + j);
+    TRY(check_finite(leaves + leaf_data_off[j], (size_t)(m * m), "leaves"));
+  }
+  TRY(A->mem.alloc(&A->ranks, 2 * (size_t)nl + 8));
+  TRY(make_leaves(A->mem, t, A->leaves));
+  TRY(make_blocks(A->mem, t, rank_cap, BK_UP, A->ranks, A->up));
+  TRY(make_blocks(A->mem, t, rank_cap, BK_LO, A->ranks + nl, A->lo));
+  TRY(upload(A->mem, &A->up.dview, A->up.hview, st));
+  TRY(upload(A->mem, &A->lo.dview, A->lo.hview, st));
+  TRY(upload(A->mem, &A->leaves.dview, A->leaves.hview, st));
+  // pack into the capacity layout on the host, then one copy per array
+  std::vector<double> hl((size_t)A->leaves.size);
+  for (int j = 0; j < nl; ++j) {
+    const int64_t m = t.m(nl + j);
+    std::memcpy(hl.data() + A->leaves.off[j], leaves + leaf_data_off[j], (size_t)(m * m) * sizeof(double));
+  }
+  std::vector<double> uu((size_t)A->up.usz, 0.0), uv((size_t)A->up.vsz, 0.0), lu((size_t)A->lo.usz, 0.0),
+      lv((size_t)A->lo.vsz, 0.0);
+  std::vector<int> hr(2 * (size_t)nl + 8, 0);
+  bi = 0;
+  for (int d = 0; d < levels; ++d)
+    for (int v = 1 << d; v < (2 << d); ++v)
+      for (int kind = 0; kind < 2; ++kind, ++bi) {
+        BlockSet& B = kind == 0 ? A->up : A->lo;
+        std::vector<double>& bu = kind == 0 ? uu : lu;
+        std::vector<double>& bv = kind == 0 ? uv : lv;
+        const int64_t rows = kind == 0 ? t.m(2 * v) : t.m(2 * v + 1);
+        const int64_t cols = kind == 0 ? t.m(2 * v + 1) : t.m(2 * v);
+        const int k = ranks[bi];
+        std::memcpy(bu.data() + B.uoff[v], U + u_off[bi], (size_t)(rows * k) * sizeof(double));
+        std::memcpy(bv.data() + B.voff[v], V + v_off[bi], (size_t)(cols * k) * sizeof(double));
+        hr[(kind == 0 ? 0 : nl) + v] = k;
+      }
+  A->h_ranks_in = hr;
+  HIPCHK(hipMemcpyAsync(A->leaves.D, hl.data(), hl.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(A->up.U, uu.data(), uu.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(A->up.V, uv.data(), uv.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(A->lo.U, lu.data(), lu.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(A->lo.V, lv.data(), lv.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(A->ranks, hr.data(), hr.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *out = A.release();
+  return HODLR_OK;
+}
+
+void hodlr_free(hodlr_t* A) { delete A; }
+void hodlr_qr_free(hodlr_qr_t* F) { delete F; }
+
+hodlr_status hodlr_norm2_est(const hodlr_t* A, int32_t iters, hodlr_stream_t stream, double* out) {
+  g_err.clear();
+  if (A == nullptr || out == nullptr || iters < 0) return fail(HODLR_EINVAL, "bad argument");
+  return norm2_est_impl(*const_cast<hodlr_t*>(A), iters, (hipStream_t)stream, out);
+}
+
+hodlr_status hodlr_qr(const hodlr_t* A, double eps, double anorm, uint32_t flags, hodlr_stream_t stream,
+                      hodlr_qr_t** out) {
+  g_err.clear();
+  if (A == nullptr || out == nullptr) return fail(HODLR_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(HODLR_EINVAL, "eps must be finite and >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  if (!(anorm > 0.0)) TRY(norm2_est_impl(*const_cast<hodlr_t*>(A), 50, st, &anorm));
+  std::unique_ptr<hodlr_qr_s> F;
+  TRY(make_factor(*A, eps, anorm, st, F));
+  TRY(run_factor(*F, *A, !(flags & HODLR_QR_NO_GRAPH), st));
+  TRY(finish_factor(*F, st));
+  *out = F.release();
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_qr_time(const hodlr_t* A, double eps, double anorm, uint32_t flags, int32_t warmup,
+                           int32_t reps, hodlr_stream_t stream, double* ms) {
+  g_err.clear();
+  if (A == nullptr || ms == nullptr || reps < 1 || warmup < 0) return fail(HODLR_EINVAL, "bad argument");
+  hipStream_t st = (hipStream_t)stream;
+  if (!(anorm > 0.0)) TRY(norm2_est_impl(*const_cast<hodlr_t*>(A), 50, st, &anorm));
+  std::unique_ptr<hodlr_qr_s> F;
+  TRY(make_factor(*A, eps, anorm, st, F));
+  const bool g = !(flags & HODLR_QR_NO_GRAPH);
+  for (int i = 0; i < warmup; ++i) TRY(run_factor(*F, *A, g, st));
+  TRY(finish_factor(*F, st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (int i = 0; i < reps; ++i) {
+    HIPCHK(hipEventRecord(e0, st));
+    TRY(run_factor(*F, *A, g, st));
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    ms[i] = t;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return finish_factor(*F, st);
+}
+
+static hodlr_status matmul_view(const Tree& t, HView V, bool up, bool lo, int tri, Work& W, DMem& mem,
+                                int32_t trans, int64_t nrhs, const double* X, int64_t ldx, double* Z,
+                                int64_t ldz, double alpha, double beta, hipStream_t st) {
+  if (X == nullptr || Z == nullptr || nrhs < 0 || ldx < t.n || ldz < t.n)
+    return fail(HODLR_EINVAL, "bad operand");
+  if (nrhs == 0) return HODLR_OK;
+  Plan P;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += SMAX) {
+    const int s = (int)std::min<int64_t>(SMAX, nrhs - c0);
+    P.mm(t, {mmspec(V, up, lo, 1, trans ? 1 : 0, X + c0 * ldx, (int)ldx, nullptr, Z + c0 * ldz, (int)ldz,
+                    alpha, beta, tri, s)});
+  }
+  DMem tmp;
+  TRY(P.upload_all(tmp, st));
+  TRY(ensure_work(mem, W, P.ws_need, P.cnt_need, false, st));
+  TRY(run_ops(P, W, st));
+  HIPCHK(hipStreamSynchronize(st));  // the plan's descriptor memory is released on return
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_matmul(const hodlr_t* A, int32_t trans, int64_t nrhs, const double* X, int64_t ldx,
+                          double* Z, int64_t ldz, hodlr_stream_t stream) {
+  g_err.clear();
+  if (A == nullptr) return fail(HODLR_EINVAL, "NULL matrix");
+  hodlr_t* a = const_cast<hodlr_t*>(A);
+  HView V{a->t.L, a->up.dview, a->lo.dview, a->leaves.dview, LEAF_FULL};
+  return matmul_view(a->t, V, true, true, 0, a->work, a->mem, trans, nrhs, X, ldx, Z, ldz, 1.0, 0.0,
+                     (hipStream_t)stream);
+}
+
+hodlr_status hodlr_qr_matmul(const hodlr_qr_t* F, char which, int32_t trans, int64_t nrhs, const double* X,
+                             int64_t ldx, double* Z, int64_t ldz, hodlr_stream_t stream) {
+  g_err.clear();
+  if (F == nullptr) return fail(HODLR_EINVAL, "NULL factors");
+  hodlr_qr_t* f = const_cast<hodlr_qr_t*>(F);
+  HView V;
+  bool up, lo;
+  switch (which) {
+    case 'Y': V = f->view_y(); up = false; lo = true; break;
+    case 'T': V = f->view_t(); up = true; lo = false; break;
+    case 'R': V = f->view_r(); up = true; lo = false; break;
+    default: return fail(HODLR_EINVAL, "which must be 'Y', 'T' or 'R'");
+  }
+  return matmul_view(f->t, V, up, lo, 1, f->work, f->mem, trans, nrhs, X, ldx, Z, ldz, 1.0, 0.0,
+                     (hipStream_t)stream);
+}
+
+hodlr_status hodlr_apply_q(const hodlr_qr_t* F, int32_t trans, int64_t nrhs, double* X, int64_t ldx,
+                           hodlr_stream_t stream) {
+  g_err.clear();
+  if (F == nullptr || X == nullptr || nrhs < 0 || ldx < F->t.n) return fail(HODLR_EINVAL, "bad argument");
+  hodlr_qr_t* f = const_cast<hodlr_qr_t*>(F);
+  const Tree& t = f->t;
+  hipStream_t st = (hipStream_t)stream;
+  const int n = (int)t.n;
+  Plan P;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += SMAX) {
+    const int s = (int)std::min<int64_t>(SMAX, nrhs - c0);
+    double* Xc = X + c0 * ldx;
+    // W1 = Y^T X ; W2 = op(T) W1 ; X -= Y W2   (Q = I - Y T Y^T, Q^T = I - Y T^T Y^T)
+    P.mm(t, {mmspec(f->view_y(), false, true, 1, 1, Xc, (int)ldx, nullptr, f->X1, n, 1.0, 0.0, 1, s)});
+    P.mm(t, {mmspec(f->view_t(), true, false, 1, trans ? 1 : 0, f->X1, n, nullptr, f->X2, n, 1.0, 0.0, 1, s)});
+    P.mm(t, {mmspec(f->view_y(), false, true, 1, 0, f->X2, n, nullptr, Xc, (int)ldx, -1.0, 1.0, 1, s)});
+  }
+  DMem tmp;
+  TRY(P.upload_all(tmp, st));
+  TRY(ensure_work(f->mem, f->work, P.ws_need, P.cnt_need, false, st));
+  TRY(run_ops(P, f->work, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_solve(const hodlr_qr_t* F, int64_t nrhs, double* B, int64_t ldb, hodlr_stream_t stream) {
+  TRY(hodlr_apply_q(F, 1, nrhs, B, ldb, stream));
+  hodlr_qr_t* f = const_cast<hodlr_qr_t*>(F);
+  const Tree& t = f->t;
+  hipStream_t st = (hipStream_t)stream;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += SMAX) {
+    const int s = (int)std::min<int64_t>(SMAX, nrhs - c0);
+    double* Bc = B + c0 * ldb;
+    Plan P;
+    // back substitution, last leaf first: x2 = R22^{-1} c2; c1 -= R12 x2; x1 = R11^{-1} c1
+    struct Rec {
+      hodlr_qr_s& f;
+      Plan& P;
+      const Tree& t;
+      double* Bc;
+      int64_t ldb;
+      int s;
+      void go(int v) {
+        if (t.is_leaf(v)) {
+          const int j = v - t.nleaf();
+          Op o{OP_TRSM};
+          o.count = s;
+          o.a0 = (int)t.m(v);
+          o.p0 = f.leaves.hview[j].D;
+          o.p1 = Bc + t.lo[v];
+          o.n = ldb;
+          P.ops.push_back(o);
+          return;
+        }
+        go(2 * v + 1);
+        const HBlk& b = f.up.hview[v];
+        const int mL = (int)t.m(2 * v), mR = (int)t.m(2 * v + 1);
+        // Wt = V12^T x2 (k x s), c1 -= U12 Wt
+        P.gemm_red({GSpec{gjob(1, 0, 0, f.rank_up(v), s, nullptr, mR, nullptr, b.V, mR, Bc + t.lo[2 * v + 1],
+                               (int)ldb, f.Wm, KCAP, 1.0, 0.0, FC_DENSE),
+                          KCAP, KCAP, mR}});
+        P.gemm_tall({GSpec{gjob(0, 0, mL, nullptr, s, nullptr, 0, f.rank_up(v), b.U, mL, f.Wm, KCAP,
+                                Bc + t.lo[2 * v], (int)ldb, -1.0, 1.0, FC_DENSE),
+                           mL, s, 0}});
+        go(2 * v);
+      }
+    } rec{*f, P, t, Bc, ldb, s};
+    rec.go(1);
+    DMem tmp;
+    TRY(P.upload_all(tmp, st));
+    TRY(ensure_work(f->mem, f->work, P.ws_need, P.cnt_need, false, st));
+    TRY(run_ops(P, f->work, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_qr_info(const hodlr_qr_t* F, hodlr_qr_info_t* info) {
+  g_err.clear();
+  if (F == nullptr || info == nullptr) return fail(HODLR_EINVAL, "NULL argument");
+  const int nn = 1 << F->t.L;
+  std::vector<int> r(3 * (size_t)nn + 8);
+  double fc[8];
+  HIPCHK(hipMemcpy(r.data(), F->ranks, r.size() * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(fc, F->work.fc, sizeof(fc), hipMemcpyDeviceToHost));
+  std::memset(info, 0, sizeof(*info));
+  info->n = F->t.n;
+  info->levels = F->t.L;
+  info->rank_cap = F->cap;
+  for (int v = 1; v < nn; ++v) {
+    info->max_rank_r = std::max(info->max_rank_r, r[v]);
+    info->max_rank_y = std::max(info->max_rank_y, r[nn + v]);
+    info->max_rank_t = std::max(info->max_rank_t, r[2 * nn + v]);
+  }
+  info->anorm = F->anorm;
+  info->tau_a = F->tauA;
+  info->tau_t = F->tauT;
+  double tot = 0.0;
+  for (int c = 0; c < FC_N; ++c) tot += fc[c];
+  info->flops = tot;
+  info->n_truncations = F->plan.n_trunc;
+  info->n_launches = F->n_launch;
+  info->device_bytes = (int64_t)F->mem.bytes;
+  return HODLR_OK;
+}
+
+static hodlr_status export_impl(const Tree& t, int cap, const LeafSet& L, const BlockSet* up,
+                                const BlockSet* lo, const int* d_ranks_up, const int* d_ranks_lo,
+                                int leafmode, double* leaves, double* U, int64_t* u_off, double* V,
+                                int64_t* v_off, int32_t* ranks) {
+  if (leaves == nullptr || ranks == nullptr || u_off == nullptr || v_off == nullptr)
+    return fail(HODLR_EINVAL, "NULL output");
+  const int nl = t.nleaf();
+  std::vector<double> hl((size_t)L.size);
+  HIPCHK(hipMemcpy(hl.data(), L.D, hl.size() * sizeof(double), hipMemcpyDeviceToHost));
+  int64_t pos = 0;
+  for (int j = 0; j < nl; ++j) {
+    const int64_t m = t.m(nl + j);
+    for (int64_t c = 0; c < m; ++c)
+      for (int64_t r = 0; r < m; ++r) {
+        double x = hl[L.off[j] + r + c * m];
+        if (leafmode == 1) x = r > c ? x : (r == c ? 1.0 : 0.0);
+        if (leafmode == 2) x = r <= c ? x : 0.0;
+        leaves[pos + r + c * m] = x;
+      }
+    pos += m * m;
+  }
+  std::vector<int> rk(2 * (size_t)nl, 0);
+  if (d_ranks_up) HIPCHK(hipMemcpy(rk.data(), d_ranks_up, nl * sizeof(int), hipMemcpyDeviceToHost));
+  if (d_ranks_lo) HIPCHK(hipMemcpy(rk.data() + nl, d_ranks_lo, nl * sizeof(int), hipMemcpyDeviceToHost));
+  int64_t up_ = 0, vp_ = 0;
+  int bi = 0;
+  for (int d = 0; d < t.L; ++d)
+    for (int v = 1 << d; v < (2 << d); ++v)
+      for (int kind = 0; kind < 2; ++kind, ++bi) {
+        const BlockSet* B = kind == 0 ? up : lo;
+        const int64_t rows = kind == 0 ? t.m(2 * v) : t.m(2 * v + 1);
+        const int64_t cols = kind == 0 ? t.m(2 * v + 1) : t.m(2 * v);
+        const int k = B ? rk[(kind == 0 ? 0 : nl) + v] : 0;
+        ranks[bi] = k;
+        u_off[bi] = up_;
+        v_off[bi] = vp_;
+        if (k > 0) {
+          if (U == nullptr || V == nullptr) return fail(HODLR_EINVAL, "NULL U or V");
+          HIPCHK(hipMemcpy(U + up_, B->U + B->uoff[v], (size_t)(rows * k) * sizeof(double), hipMemcpyDeviceToHost));
+          HIPCHK(hipMemcpy(V + vp_, B->V + B->voff[v], (size_t)(cols * k) * sizeof(double), hipMemcpyDeviceToHost));
+        }
+        up_ += rows * k;
+        vp_ += cols * k;
+      }
+  (void)cap;
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_export(const hodlr_t* A, double* leaves, double* U, int64_t* u_off, double* V,
+                          int64_t* v_off, int32_t* ranks) {
+  g_err.clear();
+  if (A == nullptr) return fail(HODLR_EINVAL, "NULL matrix");
+  const int nl = A->t.nleaf();
+  return export_impl(A->t, A->cap, A->leaves, &A->up, &A->lo, A->ranks, A->ranks + nl, 0, leaves, U, u_off,
+                     V, v_off, ranks);
+}
+
+hodlr_status hodlr_qr_export(const hodlr_qr_t* F, char which, double* leaves, double* U, int64_t* u_off,
+                             double* V, int64_t* v_off, int32_t* ranks) {
+  g_err.clear();
+  if (F == nullptr) return fail(HODLR_EINVAL, "NULL factors");
+  const int nl = F->t.nleaf();
+  switch (which) {
+    case 'Y':
+      return export_impl(F->t, F->cap, F->leaves, nullptr, &F->lo, nullptr, F->ranks + nl, 1, leaves, U, u_off,
+                         V, v_off, ranks);
+    case 'T':
+      return export_impl(F->t, F->cap, F->tleaves, &F->tup, nullptr, F->ranks + 2 * nl, nullptr, 2, leaves, U,
+                         u_off, V, v_off, ranks);
+    case 'R':
+      return export_impl(F->t, F->cap, F->leaves, &F->up, nullptr, F->ranks, nullptr, 2, leaves, U, u_off, V,
+                         v_off, ranks);
+    default:
+      return fail(HODLR_EINVAL, "which must be 'Y', 'T' or 'R'");
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,1286 @@
+// Device kernels of the HODLR QR library (gfx950, wave64, FP64 throughout).
+//
+// Paper: Kressner & Susnjara, "Fast QR decomposition of HODLR matrices".
+//  * reg_qr / reg_formq : Householder QR of a register-resident tile (one
+//    reflector per column, Sec. 3's n = 1 case) and its explicit Q factor.
+//  * k_tr_qr / k_tr_form: recompression T_tau of Sec. 2.1.1 for a batch of
+//    blocks.  Both factors are reduced by a tall-skinny QR tree (chunks of CH
+//    rows, then stacked R factors), the last block of a job runs a one-sided
+//    Jacobi SVD of R1 R2^T, and the second kernel forms Q1 U_k and R (R1^T U_k).
+//  * k_mm_proj / k_mm_apply: HODLR matrix times a tall-skinny block (Table 1,
+//    matrix-vector product) for a whole sub-HODLR: all blocks of all levels in
+//    one launch per phase.
+//  * k_gemm_tall / k_gemm_red: small dense products of the update step.
+//  * k_leaf_*: blocked Householder QR with compact WY factor of the stacked
+//    leaf column (Alg. hQR at the lowest level, Alg. blockQR's T merge).
+#include "common.h"
+
+#include <float.h>
+
+namespace hq {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ double gsum(double x, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__device__ __forceinline__ int seg_n(const Seg& s) {
+  return s.p ? (s.ncols_dev ? *s.ncols_dev : s.ncols) : 0;
+}
+
+__device__ __forceinline__ int rel_node(int u, int v) {
+  const int du = 31 - __clz(u), dv = 31 - __clz(v);
+  const int d = du - dv;
+  return (1 << d) - 1 + (u - (v << d));
+}
+
+__device__ __forceinline__ void add_flops(double* fc, int cat, double f) {
+  if (fc && f != 0.0) atomicAdd(fc + cat, f);
+}
+
+__device__ __forceinline__ int tier_of(int w) {
+  return w <= 8 ? 8 : w <= 16 ? 16 : w <= 32 ? 32 : w <= 64 ? 64 : 128;
+}
+
+// Householder QR of a tile held in registers.  Thread (c, sub) owns column c
+// and rows r = sub + TPC*i (i < RPT) of a (TPC*RPT) x W tile; the valid part
+// is h x w (rows >= h are zero).  Reflector convention: for x = [alpha; x2]
+// with x2 != 0, beta = -sign(alpha)|x|, tau = (beta - alpha)/beta,
+// v = [1; x2/(alpha - beta)]; tau = 0 (identity) when x2 = 0.  On exit the
+// tile holds R on and above the diagonal and v below it, taus[j] = tau_j.
+// When `gram` is set, gram[c + j*gld] = v_c . v_j for c < j (used for T).
+template <int TPC, int RPT>
+__device__ __forceinline__ void reg_qr(double (&a)[RPT], int c, int sub, int h, int w, double* vbuf,
+                       double* taus, double* gram, int gld) {
+  constexpr int CHR = TPC * RPT;
+  const int jmax = min(h, w);
+  for (int j = 0; j < jmax; ++j) {
+    double* vb = vbuf + (j & 1) * CHR;
+    if (c == j) {
+      double ss = 0.0, al = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = sub + TPC * i;
+        if (r > j) ss += a[i] * a[i];
+        if (r == j) al = a[i];
+      }
+      ss = gsum(ss, TPC);
+      al = gsum(al, TPC);
+      double tau = 0.0, beta = al, scal = 0.0;
+      if (ss != 0.0) {
+        const double nrm = sqrt(al * al + ss);
+        beta = (al >= 0.0) ? -nrm : nrm;
+        tau = (beta - al) / beta;
+        scal = 1.0 / (al - beta);
+      }
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = sub + TPC * i;
+        if (r > j) {
+          if (ss != 0.0) a[i] *= scal;
+          vb[r] = a[i];
+        } else if (r == j) {
+          a[i] = beta;
+          vb[r] = 1.0;
+        } else {
+          vb[r] = 0.0;
+        }
+      }
+      if (sub == 0) taus[j] = tau;
+    }
+    __syncthreads();
+    const double tau = taus[j];
+    if (tau != 0.0 && c > j && c < w) {
+      double d = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) d += vb[sub + TPC * i] * a[i];
+      d = gsum(d, TPC);
+      const double f = tau * d;
+      asm volatile("" ::: "memory");  // re-read v from LDS instead of holding it in registers
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) a[i] -= f * vb[sub + TPC * i];
+    }
+    if (gram != nullptr && c < j) {
+      double d = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) d += vb[sub + TPC * i] * a[i];
+      d = gsum(d, TPC);
+      if (sub == 0) gram[c + j * gld] = d;
+    }
+  }
+}
+
+// Explicit Q = H_0 H_1 ... H_{jmax-1} [I; 0] (h x w) from reg_qr's output,
+// accumulated backwards; column c only changes under reflectors j <= c.
+template <int TPC, int RPT>
+__device__ __forceinline__ void reg_formq(const double (&a)[RPT], double (&q)[RPT], int c, int sub, int h, int w,
+                          double* vbuf, const double* taus) {
+  constexpr int CHR = TPC * RPT;
+  const int jmax = min(h, w);
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = sub + TPC * i;
+    q[i] = (r == c && r < h && c < w) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = jmax - 1; j >= 0; --j) {
+    double* vb = vbuf + (j & 1) * CHR;
+    if (c == j) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = sub + TPC * i;
+        vb[r] = (r < j) ? 0.0 : (r == j ? 1.0 : a[i]);
+      }
+    }
+    __syncthreads();
+    const double tau = taus[j];
+    if (tau != 0.0 && c >= j && c < w) {
+      double d = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) d += vb[sub + TPC * i] * q[i];
+      d = gsum(d, TPC);
+      const double f = tau * d;
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) q[i] -= f * vb[sub + TPC * i];
+    }
+  }
+}
+
+// As reg_formq, but the reflectors are read back from a column-major copy
+// (ld CH) in global memory instead of the owners' registers (widest tier).
+template <int TPC, int RPT>
+__device__ __forceinline__ void reg_formq_g(const double* Va, double (&q)[RPT], int c, int sub, int h, int w,
+                            double* vbuf, const double* taus) {
+  constexpr int CHR = TPC * RPT;
+  const int jmax = min(h, w);
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = sub + TPC * i;
+    q[i] = (r == c && r < h && c < w) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = jmax - 1; j >= 0; --j) {
+    double* vb = vbuf + (j & 1) * CHR;
+    if (c == j) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = sub + TPC * i;
+        vb[r] = (r < j) ? 0.0 : (r == j ? 1.0 : (r < h ? Va[r + (int64_t)j * CH] : 0.0));
+      }
+    }
+    __syncthreads();
+    const double tau = taus[j];
+    if (tau != 0.0 && c >= j && c < w) {
+      double d = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) d += vb[sub + TPC * i] * q[i];
+      d = gsum(d, TPC);
+      const double f = tau * d;
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) q[i] -= f * vb[sub + TPC * i];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ recompression
+// LDS layout of k_tr_qr (doubles)
+constexpr int TRS_VBUF = 0;
+constexpr int TRS_TAU = 2 * CH;
+constexpr int TRS_FLAG = TRS_TAU + WMAX;      // 16 doubles of int flags
+constexpr int TRS_X = TRS_FLAG + 16;
+constexpr int TRS_TOTAL = TRS_X + WMAX * WMAX + 2 * WMAX;   // X (+V for W<=64) + sig + perm
+constexpr size_t TR_QR_LDS = sizeof(double) * (size_t)TRS_TOTAL;
+
+__device__ __forceinline__ int tr_root_slot(int p0, int G) {
+  int s = 0, cnt = p0;
+  while (cnt > 1) {
+    s += cnt;
+    cnt = (cnt + G - 1) / G;
+  }
+  return s;
+}
+
+// One-sided Jacobi on the columns of X (w x w, ld lx), accumulating the
+// rotations in V (ld lv).  Round-robin pairing; one pair per group of TPP
+// lanes; a sweep ends when no pair needed a rotation.
+__device__ __forceinline__ void jacobi(double* X, int lx, double* V, int lv, int w, int* sflag) {
+  const int tid = threadIdx.x;
+  const int n = w + (w & 1);
+  if (n < 2) return;
+  const int P = n / 2;
+  int Pp = 1;
+  while (Pp < P) Pp <<= 1;
+  int TPP = NT_TR / Pp;
+  if (TPP > 64) TPP = 64;
+  const int p = tid / TPP, sub = tid % TPP;
+  const double tol = (double)w * DBL_EPSILON;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) *sflag = 0;
+    __syncthreads();
+    for (int r = 0; r < n - 1; ++r) {
+      if (p < P) {
+        int i, j;
+        if (p == 0) {
+          i = r;
+          j = n - 1;
+        } else {
+          i = (r + p) % (n - 1);
+          j = (r - p + n - 1) % (n - 1);
+        }
+        if (i > j) {
+          const int t = i;
+          i = j;
+          j = t;
+        }
+        const bool valid = j < w;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (valid) {
+          for (int row = sub; row < w; row += TPP) {
+            const double xi = X[row + i * lx], xj = X[row + j * lx];
+            al += xi * xi;
+            be += xj * xj;
+            ga += xi * xj;
+          }
+        }
+        al = gsum(al, TPP);
+        be = gsum(be, TPP);
+        ga = gsum(ga, TPP);
+        if (valid && ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          double t;
+          if (fabs(zeta) > 1e150)
+            t = 0.5 / zeta;
+          else
+            t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          for (int row = sub; row < w; row += TPP) {
+            const double xi = X[row + i * lx], xj = X[row + j * lx];
+            X[row + i * lx] = cs * xi - sn * xj;
+            X[row + j * lx] = sn * xi + cs * xj;
+            const double vi = V[row + i * lv], vj = V[row + j * lv];
+            V[row + i * lv] = cs * vi - sn * vj;
+            V[row + j * lv] = sn * vi + cs * vj;
+          }
+          if (sub == 0) *sflag = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int f = *sflag;
+    __syncthreads();
+    if (f == 0) break;
+  }
+}
+
+// Last block of a job: SVD of R1 R2^T and the small factors U_k, P = R1^T U_k.
+template <int W>
+__device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0a, int n0b, double* smem, int* err,
+                       double* fc) {
+  const int tid = threadIdx.x;
+  constexpr int G = CH / W;
+  double* hdr = ws + J.hdr;
+  double* Uk = hdr + 8;
+  double* P = Uk + WMAX * WMAX;
+  const double* R1 = ws + J.side[0].node0 + (int64_t)tr_root_slot(J.side[0].p0, G) * TR_NODE;
+  int* sflag = (int*)(smem + TRS_FLAG);
+  const int m0 = J.side[0].m, m1 = J.side[1].m;
+  int k;
+  if (J.flags & TR_ORTH) {
+    k = min(m0, w);
+    for (int e = tid; e < w * k; e += NT_TR) {
+      const int r = e % w, p = e / w;
+      Uk[r + p * WMAX] = (r == p) ? 1.0 : 0.0;
+      P[r + p * WMAX] = R1[p + r * WMAX];
+    }
+    if (tid == 0) {
+      const double pq = (double)min(m0, w);
+      add_flops(fc, J.fc, 2.0 * (2.0 * m0 * w * pq - 2.0 / 3.0 * pq * pq * pq) + 2.0 * w * w * m1);
+    }
+  } else {
+    const double* R2 = ws + J.side[1].node0 + (int64_t)tr_root_slot(J.side[1].p0, G) * TR_NODE;
+    constexpr int LX = W;
+    double* X = smem + TRS_X;
+    double* V;
+    int LV;
+    if (W <= 64) {
+      V = X + W * W;
+      LV = W;
+    } else {
+      V = hdr + 8 + 2 * WMAX * WMAX;
+      LV = WMAX;
+    }
+    double* sig = smem + TRS_X + WMAX * WMAX;
+    int* perm = (int*)(sig + WMAX);
+    // X = R2 R1^T  (both upper triangular, w x w)
+    for (int e = tid; e < w * w; e += NT_TR) {
+      const int i = e % w, j = e / w;
+      double s = 0.0;
+      for (int l = max(i, j); l < w; ++l) s += R2[i + l * WMAX] * R1[j + l * WMAX];
+      X[i + j * LX] = s;
+      V[i + j * LV] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    jacobi(X, LX, V, LV, w, sflag);
+    for (int cc = tid; cc < w; cc += NT_TR) {
+      double s = 0.0;
+      for (int r = 0; r < w; ++r) s += X[r + cc * LX] * X[r + cc * LX];
+      sig[cc] = sqrt(s);
+    }
+    __syncthreads();
+    for (int cc = tid; cc < w; cc += NT_TR) {
+      int pos = 0;
+      const double sc = sig[cc];
+      for (int j = 0; j < w; ++j) {
+        const double sj = sig[j];
+        pos += (sj > sc || (sj == sc && j < cc)) ? 1 : 0;
+      }
+      perm[pos] = cc;
+    }
+    __syncthreads();
+    k = 0;
+    for (int j = 0; j < w; ++j) k += (sig[j] > J.tau) ? 1 : 0;
+    if (k > J.cap) {
+      if (tid == 0) atomicOr(err, ERR_CAPACITY);
+      k = J.cap;
+    }
+    for (int e = tid; e < w * k; e += NT_TR) {
+      const int r = e % w, p = e / w;
+      Uk[r + p * WMAX] = V[r + perm[p] * LV];
+    }
+    __syncthreads();
+    for (int e = tid; e < w * k; e += NT_TR) {
+      const int r = e % w, p = e / w;
+      double s = 0.0;
+      for (int l = 0; l <= r; ++l) s += R1[l + r * WMAX] * Uk[l + p * WMAX];
+      P[r + p * WMAX] = s;
+    }
+    if (tid == 0) {
+      const double p1 = min(m0, w), p2 = min(m1, w);
+      const double qf = [](double m, double n) {
+        const double pp = fmin(m, n);
+        return m >= n ? 2.0 * m * n * pp - 2.0 / 3.0 * pp * pp * pp
+                      : 2.0 * n * m * m - 2.0 / 3.0 * m * m * m;
+      }(m0, w) + [](double m, double n) {
+        const double pp = fmin(m, n);
+        return m >= n ? 2.0 * m * n * pp - 2.0 / 3.0 * pp * pp * pp
+                      : 2.0 * n * m * m - 2.0 / 3.0 * m * m * m;
+      }(m1, w);
+      const double mp = fmax(p1, p2);
+      add_flops(fc, J.fc,
+                qf + 2.0 * p1 * p2 * w + 21.0 * mp * mp * mp + 4.0 * m0 * p1 * k + 2.0 * m1 * w * k);
+    }
+  }
+  if (tid == 0) {
+    hdr[0] = (double)w;
+    hdr[1] = (double)k;
+    hdr[2] = (double)n0a;
+    hdr[3] = (double)n0b;
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void tr_chunk(const TrJob& J, int side, int chunk, double* ws, int* counters, int* err,
+                         double* fc, double* smem, int w, int n0a, int n0b) {
+  constexpr int TPC = NT_TR / W;
+  constexpr int RPT = CH / TPC;
+  constexpr int G = CH / W;
+  const int tid = threadIdx.x, c = tid / TPC, sub = tid % TPC;
+  double* vbuf = smem + TRS_VBUF;
+  double* taus = smem + TRS_TAU;
+  int* sflag = (int*)(smem + TRS_FLAG);
+  const TrSide& S = J.side[side];
+  const int n0 = side == 0 ? n0a : n0b;
+  const Seg s0 = J.seg[side][0], s1 = J.seg[side][1];
+
+  double a[RPT];
+  int idx = chunk, count = S.p0;
+  int64_t base = 0;  // first slot of the current level
+  int row0 = (int)((int64_t)idx * S.m / S.p0);
+  int h = (int)((int64_t)(idx + 1) * S.m / S.p0) - row0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = sub + TPC * i;
+    double x = 0.0;
+    if (r < h && c < w) {
+      const int64_t gr = row0 + r;
+      x = (c < n0) ? s0.scale * s0.p[gr + (int64_t)c * s0.ld]
+                   : s1.scale * s1.p[gr + (int64_t)(c - n0) * s1.ld];
+    }
+    a[i] = x;
+  }
+  int64_t slot = idx;
+  while (true) {
+    reg_qr<TPC, RPT>(a, c, sub, h, w, vbuf, taus, nullptr, 0);
+    double* node = ws + S.node0 + slot * TR_NODE;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = sub + TPC * i;
+      if (c < w && r < w) node[r + c * WMAX] = (r <= c && r < h) ? a[i] : 0.0;
+    }
+    if (side == 0) {
+      double q[RPT];
+      double* Qa = node + WMAX * WMAX;
+      if constexpr (W <= 64) {
+        __syncthreads();
+        reg_formq<TPC, RPT>(a, q, c, sub, h, w, vbuf, taus);
+      } else {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const int r = sub + TPC * i;
+          if (r < h && c < w) Qa[r + c * CH] = a[i];
+        }
+        __threadfence_block();
+        __syncthreads();
+        reg_formq_g<TPC, RPT>(Qa, q, c, sub, h, w, vbuf, taus);
+      }
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = sub + TPC * i;
+        if (r < h && c < w) Qa[r + c * CH] = q[i];
+      }
+    }
+    if (count == 1) break;
+    const int pidx = idx / G;
+    const int pcount = (count + G - 1) / G;
+    const int nchild = min(G, count - pidx * G);
+    const int64_t pbase = base + count;
+    const int64_t pslot = pbase + pidx;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      int* cnt = counters + S.cnt0 + (int)(pslot - S.p0);
+      const int old = atomicAdd(cnt, 1);
+      const int last = (old == nchild - 1) ? 1 : 0;
+      if (last) atomicExch(cnt, 0);
+      sflag[0] = last;
+    }
+    __syncthreads();
+    const int last = sflag[0];
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // become the parent: stack the children's R factors
+    const int64_t cbase = base;
+    const int cfirst = pidx * G;
+    base = pbase;
+    idx = pidx;
+    count = pcount;
+    slot = pslot;
+    h = nchild * w;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = sub + TPC * i;
+      double x = 0.0;
+      if (r < h && c < w) {
+        const int ch = r / w, rr = r % w;
+        x = ws[S.node0 + (cbase + cfirst + ch) * TR_NODE + rr + c * WMAX];
+      }
+      a[i] = x;
+    }
+  }
+  // this side is reduced; join the two sides
+  if (!(J.flags & TR_ORTH)) {
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      int* cnt = counters + J.jcounter;
+      const int old = atomicAdd(cnt, 1);
+      const int last = (old == 1) ? 1 : 0;
+      if (last) atomicExch(cnt, 0);
+      sflag[0] = last;
+    }
+    __syncthreads();
+    const int last = sflag[0];
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+  }
+  tr_svd<W>(J, ws, w, n0a, n0b, smem, err, fc);
+}
+
+__global__ void __launch_bounds__(NT_TR) k_tr_qr(const TrJob* __restrict__ jobs,
+                                                  const TrChunk* __restrict__ items, int first,
+                                                  double* ws, int* counters, int* err, double* fc) {
+  extern __shared__ double smem[];
+  const TrChunk it = items[first + blockIdx.x];
+  const TrJob& J = jobs[it.job];
+  const int n0a = seg_n(J.seg[0][0]);
+  const int w = n0a + seg_n(J.seg[0][1]);
+  const int n0b = seg_n(J.seg[1][0]);
+  if (w == 0 || w > WMAX) {
+    if (it.side == 0 && it.chunk == 0 && threadIdx.x == 0) {
+      double* hdr = ws + J.hdr;
+      hdr[0] = 0.0;
+      hdr[1] = 0.0;
+      if (w > WMAX) atomicOr(err, ERR_WIDTH);
+    }
+    return;
+  }
+  switch (tier_of(w)) {
+    case 8: tr_chunk<8>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b); break;
+    case 16: tr_chunk<16>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b); break;
+    case 32: tr_chunk<32>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b); break;
+    case 64: tr_chunk<64>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b); break;
+    default: tr_chunk<128>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b); break;
+  }
+}
+
+constexpr size_t TR_FORM_LDS = sizeof(double) * (size_t)WMAX * WMAX;
+
+__global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ jobs,
+                                                    const TrForm* __restrict__ items, int first,
+                                                    const double* __restrict__ ws) {
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x;
+  const TrForm it = items[first + blockIdx.x];
+  const TrJob& J = jobs[it.job];
+  const double* hdr = ws + J.hdr;
+  const int w = (int)hdr[0], k = (int)hdr[1];
+  if (it.leader && tid == 0) *J.out_rank = k;
+  if (w == 0 || k == 0) return;
+  const double* Uk = hdr + 8;
+  const double* P = Uk + WMAX * WMAX;
+  const int G = CH / tier_of(w);
+  if (it.side == 0) {
+    const TrSide& S = J.side[0];
+    // path of tree indices from the chunk to the root
+    int idxs[16], bases[16];
+    int lvl = 0, idx = it.chunk, count = S.p0, base = 0;
+    idxs[0] = idx;
+    bases[0] = 0;
+    while (count > 1) {
+      base += count;
+      idx /= G;
+      count = (count + G - 1) / G;
+      ++lvl;
+      idxs[lvl] = idx;
+      bases[lvl] = base;
+    }
+    double* Z = smem;  // w x k, ld WMAX
+    for (int e = tid; e < w * k; e += NT_MM) {
+      const int r = e % w, p = e / w;
+      Z[r + p * WMAX] = Uk[r + p * WMAX];
+    }
+    __syncthreads();
+    for (int l = lvl; l >= 1; --l) {
+      const int cslot = idxs[l - 1] - idxs[l] * G;
+      const double* Qn = ws + S.node0 + (int64_t)(bases[l] + idxs[l]) * TR_NODE + WMAX * WMAX;
+      double zn[64];
+      int cnt = 0;
+      for (int e = tid; e < w * k; e += NT_MM, ++cnt) {
+        const int r = e % w, p = e / w;
+        double s = 0.0;
+        for (int cc = 0; cc < w; ++cc) s += Qn[(cslot * w + r) + cc * CH] * Z[cc + p * WMAX];
+        zn[cnt] = s;
+      }
+      __syncthreads();
+      cnt = 0;
+      for (int e = tid; e < w * k; e += NT_MM, ++cnt) {
+        const int r = e % w, p = e / w;
+        Z[r + p * WMAX] = zn[cnt];
+      }
+      __syncthreads();
+    }
+    const int row0 = (int)((int64_t)it.chunk * S.m / S.p0);
+    const int h = (int)((int64_t)(it.chunk + 1) * S.m / S.p0) - row0;
+    const double* Qc = ws + S.node0 + (int64_t)it.chunk * TR_NODE + WMAX * WMAX;
+    double* out = J.out[0];
+    const int ldo = J.ldout[0];
+    for (int e = tid; e < h * k; e += NT_MM) {
+      const int r = e % h, p = e / h;
+      double s = 0.0;
+      for (int cc = 0; cc < w; ++cc) s += Qc[r + cc * CH] * Z[cc + p * WMAX];
+      out[(int64_t)(row0 + r) + (int64_t)p * ldo] = s;
+    }
+  } else {
+    const int n0 = (int)hdr[3];
+    const Seg s0 = J.seg[1][0], s1 = J.seg[1][1];
+    double* In = smem;  // rows x w, ld 64
+    const int rows = it.rows;
+    for (int e = tid; e < rows * w; e += NT_MM) {
+      const int r = e % rows, cc = e / rows;
+      const int64_t gr = it.row0 + r;
+      In[r + cc * 64] = (cc < n0) ? s0.scale * s0.p[gr + (int64_t)cc * s0.ld]
+                                  : s1.scale * s1.p[gr + (int64_t)(cc - n0) * s1.ld];
+    }
+    __syncthreads();
+    double* out = J.out[1];
+    const int ldo = J.ldout[1];
+    for (int e = tid; e < rows * k; e += NT_MM) {
+      const int r = e % rows, p = e / rows;
+      double s = 0.0;
+      for (int cc = 0; cc < w; ++cc) s += In[r + cc * 64] * P[cc + p * WMAX];
+      out[(int64_t)(it.row0 + r) + (int64_t)p * ldo] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ HODLR x tall-skinny
+__device__ __forceinline__ int mm_s(const MmJob& J) { return J.s_dev ? *J.s_dev : J.s; }
+
+// Phase A: partial projections P_b = F_b^T X (F = V for op N, U for op T) over
+// one chunk of CH rows; the last chunk of a block sums the partials in order.
+__global__ void __launch_bounds__(NT_MM) k_mm_proj(const MmJob* __restrict__ jobs,
+                                                    const MmProj* __restrict__ items, int first,
+                                                    double* ws, int* counters, double* fc) {
+  __shared__ double Ft[64][KCAP + 1];
+  __shared__ double Xt[64][SMAX + 1];
+  __shared__ int lastf;
+  const int tid = threadIdx.x;
+  const MmProj it = items[first + blockIdx.x];
+  const MmJob& J = jobs[it.job];
+  const int s = mm_s(J);
+  const HBlk& b = (it.kind == 0 ? J.M.up : J.M.lo)[it.node];
+  const int k = *b.rank;
+  if (k == 0 || s == 0) return;
+  const int len = J.trans ? b.rows : b.cols;
+  const double* F = J.trans ? b.U : b.V;
+  const int ldF = J.trans ? b.ldU : b.ldV;
+  const int64_t xr0 = (J.trans ? b.r0 : b.c0) - J.row0;
+  const int c0 = it.chunk * CH;
+  const int cn = min(CH, len - c0);
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  const int nout = k * s;
+  for (int t0 = 0; t0 < cn; t0 += 64) {
+    const int tn = min(64, cn - t0);
+    for (int e = tid; e < 64 * k; e += NT_MM) {
+      const int r = e % 64, j = e / 64;
+      Ft[r][j] = (r < tn) ? F[(int64_t)(c0 + t0 + r) + (int64_t)j * ldF] : 0.0;
+    }
+    for (int e = tid; e < 64 * s; e += NT_MM) {
+      const int r = e % 64, cc = e / 64;
+      Xt[r][cc] = (r < tn) ? J.X[xr0 + c0 + t0 + r + (int64_t)cc * J.ldX] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + q * NT_MM;
+      if (e < nout) {
+        const int j = e % k, cc = e / k;
+        double sacc = acc[q];
+        for (int r = 0; r < tn; ++r) sacc += Ft[r][j] * Xt[r][cc];
+        acc[q] = sacc;
+      }
+    }
+    __syncthreads();
+  }
+  double* red = ws + J.red0 + (int64_t)(2 * rel_node(it.node, J.v) + it.kind) * (KCAP * SMAX);
+  if (it.nchunk == 1) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + q * NT_MM;
+      if (e < nout) red[(e % k) + (e / k) * KCAP] = acc[q];
+    }
+  } else {
+    double* part = ws + it.part;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + q * NT_MM;
+      if (e < nout) part[(e % k) + (e / k) * KCAP] = acc[q];
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      const int old = atomicAdd(counters + it.counter, 1);
+      lastf = (old == it.nchunk - 1) ? 1 : 0;
+      if (lastf) atomicExch(counters + it.counter, 0);
+    }
+    __syncthreads();
+    if (lastf) {
+      __threadfence();
+      const double* part0 = ws + it.part - (int64_t)it.chunk * (KCAP * SMAX);
+      for (int e = tid; e < nout; e += NT_MM) {
+        const int j = e % k, cc = e / k;
+        double sacc = 0.0;
+        for (int ch = 0; ch < it.nchunk; ++ch)
+          sacc += part0[(int64_t)ch * (KCAP * SMAX) + j + cc * KCAP];
+        red[j + cc * KCAP] = sacc;
+      }
+    }
+  }
+  if (tid == 0) add_flops(fc, FC_HMAT, 2.0 * k * cn * s);
+}
+
+// Phase B: Z rows of one leaf = leaf part + the low-rank parts of every level.
+__global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jobs,
+                                                     const MmApply* __restrict__ items, int first,
+                                                     const double* __restrict__ ws, double* fc) {
+  __shared__ double Dt[64][33];
+  __shared__ double Xt[32][SMAX + 1];
+  __shared__ double Pt[KCAP * SMAX];
+  const int tid = threadIdx.x;
+  const MmApply it = items[first + blockIdx.x];
+  const MmJob& J = jobs[it.job];
+  const int s = mm_s(J);
+  if (s == 0) return;
+  const HLeaf lf = J.M.leaf[it.leaf];
+  const int r = tid & 63, cg = tid >> 6;
+  const int kind = J.M.leaf_kind;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  // leaf part
+  for (int k0 = 0; k0 < lf.m; k0 += 32) {
+    const int kn = min(32, lf.m - k0);
+    for (int e = tid; e < 64 * 32; e += NT_MM) {
+      int rr, kk;
+      if (J.trans) {
+        kk = e % 32;
+        rr = e / 32;
+      } else {
+        rr = e % 64;
+        kk = e / 64;
+      }
+      double x = 0.0;
+      if (rr < it.rows && kk < kn) {
+        const int R = it.row0 + rr, Kc = k0 + kk;
+        const int i = J.trans ? Kc : R, j = J.trans ? R : Kc;  // element D(i, j)
+        if (kind == LEAF_FULL)
+          x = lf.D[i + (int64_t)j * lf.ld];
+        else if (kind == LEAF_UNIT_LOWER)
+          x = (i > j) ? lf.D[i + (int64_t)j * lf.ld] : (i == j ? 1.0 : 0.0);
+        else
+          x = (i <= j) ? lf.D[i + (int64_t)j * lf.ld] : 0.0;
+      }
+      Dt[rr][kk] = x;
+    }
+    for (int e = tid; e < 32 * s; e += NT_MM) {
+      const int kk = e % 32, cc = e / 32;
+      Xt[kk][cc] = (kk < kn) ? J.X[(lf.r0 - J.row0 + k0 + kk) + (int64_t)cc * J.ldX] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int cc = cg + 4 * q;
+      if (cc < s) {
+        double sacc = acc[q];
+        for (int kk = 0; kk < kn; ++kk) sacc += Dt[r][kk] * Xt[kk][cc];
+        acc[q] = sacc;
+      }
+    }
+    __syncthreads();
+  }
+  double flops = 2.0 * it.rows * lf.m * s * (J.tri ? 0.5 : 1.0);
+  // low-rank parts, one block per ancestor level
+  const int hleaf = (1 << J.M.levels) + it.leaf;
+  int child = hleaf, u = hleaf >> 1;
+  const int64_t grow = lf.r0 + it.row0 + r;  // global row of this thread
+  while (child != J.v && u >= 1) {
+    const bool left = (child == 2 * u);
+    const int bk = J.trans ? (left ? 1 : 0) : (left ? 0 : 1);
+    const HBlk* arr = bk == 0 ? J.M.up : J.M.lo;
+    if (arr != nullptr) {
+      const HBlk& b = arr[u];
+      const int kb = *b.rank;
+      if (kb > 0) {
+        const double* red = ws + J.red0 + (int64_t)(2 * rel_node(u, J.v) + bk) * (KCAP * SMAX);
+        for (int e = tid; e < kb * s; e += NT_MM) Pt[(e % kb) + (e / kb) * KCAP] = red[(e % kb) + (e / kb) * KCAP];
+        __syncthreads();
+        const double* F = J.trans ? b.V : b.U;
+        const int ldF = J.trans ? b.ldV : b.ldU;
+        const int64_t f0 = J.trans ? b.c0 : b.r0;
+        if (r < it.rows) {
+          for (int j = 0; j < kb; ++j) {
+            const double fv = F[(grow - f0) + (int64_t)j * ldF];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+              const int cc = cg + 4 * q;
+              if (cc < s) acc[q] += fv * Pt[j + cc * KCAP];
+            }
+          }
+        }
+        __syncthreads();
+        flops += 2.0 * it.rows * kb * s;
+      }
+    }
+    child = u;
+    u >>= 1;
+  }
+  if (r < it.rows) {
+    const int64_t zr = lf.r0 - J.row0 + it.row0 + r;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int cc = cg + 4 * q;
+      if (cc < s) {
+        double* zp = J.Z + zr + (int64_t)cc * J.ldZ;
+        const double v = J.alpha * acc[q];
+        *zp = (J.beta == 0.0) ? v : v + J.beta * (*zp);
+      }
+    }
+  }
+  if (tid == 0) add_flops(fc, FC_HMAT, flops);
+}
+
+// ------------------------------------------------------------------ small GEMMs
+__device__ __forceinline__ double gA(const GemmJob& J, int r, int kk) {
+  return J.ta ? J.A[kk + (int64_t)r * J.lda] : J.A[r + (int64_t)kk * J.lda];
+}
+__device__ __forceinline__ double gB(const GemmJob& J, int kk, int c) {
+  return J.tb ? J.B[c + (int64_t)kk * J.ldb] : J.B[kk + (int64_t)c * J.ldb];
+}
+
+__global__ void __launch_bounds__(NT_MM) k_gemm_tall(const GemmJob* __restrict__ jobs,
+                                                      const GemmTile* __restrict__ items, int first,
+                                                      double* fc) {
+  __shared__ double At[64][33];
+  __shared__ double Bt[32][65];
+  const int tid = threadIdx.x;
+  const GemmTile it = items[first + blockIdx.x];
+  const GemmJob& J = jobs[it.job];
+  const int M = J.Md ? *J.Md : J.M, N = J.Nd ? *J.Nd : J.N, K = J.Kd ? *J.Kd : J.K;
+  if (it.row0 >= M || it.col0 >= N) return;
+  const int mr = min(64, M - it.row0), nc = min(64, N - it.col0);
+  const int r = tid & 63, cg = tid >> 6;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int kn = min(32, K - k0);
+    for (int e = tid; e < 64 * 32; e += NT_MM) {
+      int rr, kk;
+      if (J.ta) {
+        kk = e % 32;
+        rr = e / 32;
+      } else {
+        rr = e % 64;
+        kk = e / 64;
+      }
+      At[rr][kk] = (rr < mr && kk < kn) ? gA(J, it.row0 + rr, k0 + kk) : 0.0;
+    }
+    for (int e = tid; e < 32 * 64; e += NT_MM) {
+      int kk, cc;
+      if (J.tb) {
+        cc = e % 64;
+        kk = e / 64;
+      } else {
+        kk = e % 32;
+        cc = e / 32;
+      }
+      Bt[kk][cc] = (kk < kn && cc < nc) ? gB(J, k0 + kk, it.col0 + cc) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int cc = cg + 4 * q;
+      double sacc = acc[q];
+      for (int kk = 0; kk < kn; ++kk) sacc += At[r][kk] * Bt[kk][cc];
+      acc[q] = sacc;
+    }
+    __syncthreads();
+  }
+  if (r < mr) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int cc = cg + 4 * q;
+      if (cc < nc) {
+        double* cp = J.C + (int64_t)(it.row0 + r) + (int64_t)(it.col0 + cc) * J.ldc;
+        const double v = J.alpha * acc[q];
+        *cp = (J.beta == 0.0) ? v : v + J.beta * (*cp);
+      }
+    }
+  }
+  if (tid == 0) add_flops(fc, J.fc, 2.0 * mr * nc * K);
+}
+
+// C (M x N, both <= KCAP) from a long K, split into chunks; the last chunk sums.
+__global__ void __launch_bounds__(NT_MM) k_gemm_red(const GemmJob* __restrict__ jobs,
+                                                     const GemmRed* __restrict__ items, int first,
+                                                     double* ws, int* counters, double* fc) {
+  __shared__ double At[32][KCAP + 1];
+  __shared__ double Bt[32][KCAP + 1];
+  __shared__ int lastf;
+  const int tid = threadIdx.x;
+  const GemmRed it = items[first + blockIdx.x];
+  const GemmJob& J = jobs[it.job];
+  const int M = J.Md ? *J.Md : J.M, N = J.Nd ? *J.Nd : J.N;
+  if (M == 0 || N == 0) return;
+  const int nout = M * N;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int k0 = it.k0; k0 < it.k0 + it.kn; k0 += 32) {
+    const int kn = min(32, it.k0 + it.kn - k0);
+    for (int e = tid; e < 32 * KCAP; e += NT_MM) {
+      const int kk = e % 32, rr = e / 32;
+      At[kk][rr] = (kk < kn && rr < M) ? gA(J, rr, k0 + kk) : 0.0;
+      Bt[kk][rr] = (kk < kn && rr < N) ? gB(J, k0 + kk, rr) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + q * NT_MM;
+      if (e < nout) {
+        const int rr = e % M, cc = e / M;
+        double sacc = acc[q];
+        for (int kk = 0; kk < kn; ++kk) sacc += At[kk][rr] * Bt[kk][cc];
+        acc[q] = sacc;
+      }
+    }
+    __syncthreads();
+  }
+  if (it.nchunk == 1) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + q * NT_MM;
+      if (e < nout) {
+        double* cp = J.C + (int64_t)(e % M) + (int64_t)(e / M) * J.ldc;
+        const double v = J.alpha * acc[q];
+        *cp = (J.beta == 0.0) ? v : v + J.beta * (*cp);
+      }
+    }
+  } else {
+    double* part = ws + it.part;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + q * NT_MM;
+      if (e < nout) part[(e % M) + (e / M) * KCAP] = acc[q];
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      const int old = atomicAdd(counters + it.counter, 1);
+      lastf = (old == it.nchunk - 1) ? 1 : 0;
+      if (lastf) atomicExch(counters + it.counter, 0);
+    }
+    __syncthreads();
+    if (lastf) {
+      __threadfence();
+      const double* part0 = ws + it.part - (int64_t)it.chunk * (KCAP * KCAP);
+      for (int e = tid; e < nout; e += NT_MM) {
+        const int rr = e % M, cc = e / M;
+        double sacc = 0.0;
+        for (int ch = 0; ch < it.nchunk; ++ch) sacc += part0[(int64_t)ch * (KCAP * KCAP) + rr + cc * KCAP];
+        double* cp = J.C + (int64_t)rr + (int64_t)cc * J.ldc;
+        const double v = J.alpha * sacc;
+        *cp = (J.beta == 0.0) ? v : v + J.beta * (*cp);
+      }
+    }
+  }
+  if (tid == 0) add_flops(fc, J.fc, 2.0 * M * N * it.kn);
+}
+
+// ------------------------------------------------------------------ leaf QR
+__device__ __forceinline__ int leaf_rows(const LeafJob& J) {
+  int M = J.m;
+  for (int g = 0; g < J.ngroups; ++g) M += *J.g[g].rank;
+  return M;
+}
+
+// H = [A_leaf; C_g1; ...] (one column per block)
+__global__ void __launch_bounds__(NT_MM) k_leaf_gather(const LeafJob* __restrict__ jobs, int jidx,
+                                                        LeafWs W, int* err) {
+  const LeafJob& J = jobs[jidx];
+  const int c = blockIdx.x;
+  const int M = leaf_rows(J);
+  if (M > MAXSTACK) {
+    if (c == 0 && threadIdx.x == 0) atomicOr(err, ERR_STACK);
+    return;
+  }
+  double* h = W.H + (int64_t)c * MAXSTACK;
+  for (int r = threadIdx.x; r < J.m; r += NT_MM) h[r] = J.D[r + (int64_t)c * J.m];
+  int off = J.m;
+  for (int g = 0; g < J.ngroups; ++g) {
+    const int k = *J.g[g].rank;
+    const double* V = J.g[g].V + J.g[g].row0 + c;
+    for (int t = threadIdx.x; t < k; t += NT_MM) h[off + t] = V[(int64_t)t * J.g[g].ld];
+    off += k;
+  }
+}
+
+template <int RPT>
+__device__ __forceinline__ void leaf_panel_body(const LeafJob& J, LeafWs W, int p, int M, double* smem) {
+  constexpr int TPC = NT_TR / NB;  // 32 columns x 16 threads
+  const int tid = threadIdx.x, c = tid / TPC, sub = tid % TPC;
+  const int c0 = p * NB;
+  const int pw = min(NB, J.m - c0);
+  const int h = M - c0;
+  double* vbuf = smem;                      // 2 * TPC*RPT
+  double* taus = vbuf + 2 * TPC * RPT;      // NB
+  double* gram = taus + NB;                 // NB x NB
+  double* Tp = gram + NB * NB;              // NB x NB
+  double a[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = sub + TPC * i;
+    a[i] = (r < h && c < pw) ? W.H[(int64_t)(c0 + r) + (int64_t)(c0 + c) * MAXSTACK] : 0.0;
+  }
+  reg_qr<TPC, RPT>(a, c, sub, h, pw, vbuf, taus, gram, NB);
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = sub + TPC * i;
+    if (r < h && c < pw) W.H[(int64_t)(c0 + r) + (int64_t)(c0 + c) * MAXSTACK] = a[i];
+  }
+  __syncthreads();
+  // T of the panel: T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] (Y^T y_j)
+  for (int e = tid; e < NB * NB; e += NT_TR) Tp[e] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < pw; ++j) {
+    const double tj = taus[j];
+    if (tid < j) {
+      double s = 0.0;
+      for (int l = tid; l < j; ++l) s += Tp[tid + l * NB] * gram[l + j * NB];
+      Tp[tid + j * NB] = -tj * s;
+    }
+    if (tid == j) Tp[j + j * NB] = tj;
+    __syncthreads();
+  }
+  for (int e = tid; e < NB * NB; e += NT_TR) {
+    const int i = e % NB, j = e / NB;
+    if (i < pw && j < pw) W.T[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] = Tp[e];
+  }
+}
+
+constexpr size_t LEAF_PANEL_LDS = sizeof(double) * (2 * MAXSTACK + NB + 2 * NB * NB);
+
+__global__ void __launch_bounds__(NT_TR) k_leaf_panel(const LeafJob* __restrict__ jobs, int jidx,
+                                                       LeafWs W, int p, const int* err) {
+  extern __shared__ double smem[];
+  if (*err & ERR_STACK) return;
+  const LeafJob& J = jobs[jidx];
+  const int M = leaf_rows(J);
+  const int h = M - p * NB;
+  if (h <= 320)
+    leaf_panel_body<20>(J, W, p, M, smem);
+  else if (h <= 512)
+    leaf_panel_body<32>(J, W, p, M, smem);
+  else if (h <= 768)
+    leaf_panel_body<48>(J, W, p, M, smem);
+  else
+    leaf_panel_body<64>(J, W, p, M, smem);
+}
+
+// Y_p(r, j) for rows r >= c0 (unit lower trapezoidal panel of H)
+__device__ __forceinline__ double leaf_y(const LeafWs& W, int c0, int r, int j) {
+  const int rr = r - c0;
+  return rr < j ? 0.0 : (rr == j ? 1.0 : W.H[(int64_t)r + (int64_t)(c0 + j) * MAXSTACK]);
+}
+
+// After panel p: (a) trailing strips  A_s -= Y_p T_p^T (Y_p^T A_s),
+// (b) Gram tiles G[i-block, p-block] = Y_i^T Y_p (i < p),
+// (c) T block of panel q = p-1:  T[0:32q, q] = -T[0:32q, 0:32q] G[0:32q, q] T_qq
+// (eq. recqrcombined, one row tile per block).
+__global__ void __launch_bounds__(NT_MM) k_leaf_update(const LeafJob* __restrict__ jobs, int jidx,
+                                                        LeafWs W, int p, const int* err) {
+  __shared__ double Yt[64][33];
+  __shared__ double Bt[64][33];
+  __shared__ double Wt[32][33];
+  __shared__ double Tt[32][33];
+  if (*err & ERR_STACK) return;
+  const LeafJob& J = jobs[jidx];
+  const int tid = threadIdx.x;
+  const int m = J.m;
+  const int np = (m + NB - 1) / NB;
+  const int M = leaf_rows(J);
+  const int c0 = p * NB;
+  const int nstrip = (p < np) ? np - p - 1 : 0;
+  const int ngram = (p < np) ? p : 0;
+  int b = blockIdx.x;
+  if (b < nstrip) {
+    // ---- (a) trailing strip s
+    const int s = p + 1 + b;
+    const int cs = s * NB, sw = min(NB, m - cs);
+    const int pw = min(NB, m - c0);
+    const int jj = tid % 32, cg = tid / 32;  // W[jj][cg + 8q]
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = c0; r0 < M; r0 += 64) {
+      const int rn = min(64, M - r0);
+      for (int e = tid; e < 64 * 32; e += NT_MM) {
+        const int rr = e % 64, j = e / 64;
+        Yt[rr][j] = (rr < rn && j < pw) ? leaf_y(W, c0, r0 + rr, j) : 0.0;
+        Bt[rr][j] = (rr < rn && j < sw) ? W.H[(int64_t)(r0 + rr) + (int64_t)(cs + j) * MAXSTACK] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int cc = cg + 8 * q;
+        double sacc = acc[q];
+        for (int rr = 0; rr < rn; ++rr) sacc += Yt[rr][jj] * Bt[rr][cc];
+        acc[q] = sacc;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Wt[jj][cg + 8 * q] = acc[q];
+    for (int e = tid; e < 32 * 32; e += NT_MM) {
+      const int i = e % 32, j = e / 32;
+      Tt[i][j] = (i < pw && j < pw) ? W.T[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] : 0.0;
+    }
+    __syncthreads();
+    // W <- T^T W
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int cc = cg + 8 * q;
+      double sacc = 0.0;
+      for (int l = 0; l <= jj; ++l) sacc += Tt[l][jj] * Wt[l][cc];
+      acc[q] = sacc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Wt[jj][cg + 8 * q] = acc[q];
+    __syncthreads();
+    // A_s -= Y W
+    for (int r = c0 + tid; r < M; r += NT_MM) {
+      double y[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) y[j] = (j < pw) ? leaf_y(W, c0, r, j) : 0.0;
+      for (int cc = 0; cc < sw; ++cc) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) sacc += y[j] * Wt[j][cc];
+        W.H[(int64_t)r + (int64_t)(cs + cc) * MAXSTACK] -= sacc;
+      }
+    }
+    return;
+  }
+  b -= nstrip;
+  if (b < ngram) {
+    // ---- (b) G[32b : 32b+32, c0 : c0+pw] = Y_b^T Y_p over rows >= c0
+    const int i0 = b * NB;
+    const int pw = min(NB, m - c0);
+    const int jj = tid % 32, cg = tid / 32;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = c0; r0 < M; r0 += 64) {
+      const int rn = min(64, M - r0);
+      for (int e = tid; e < 64 * 32; e += NT_MM) {
+        const int rr = e % 64, j = e / 64;
+        Yt[rr][j] = (rr < rn) ? W.H[(int64_t)(r0 + rr) + (int64_t)(i0 + j) * MAXSTACK] : 0.0;
+        Bt[rr][j] = (rr < rn && j < pw) ? leaf_y(W, c0, r0 + rr, j) : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int cc = cg + 8 * q;
+        double sacc = acc[q];
+        for (int rr = 0; rr < rn; ++rr) sacc += Yt[rr][jj] * Bt[rr][cc];
+        acc[q] = sacc;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int cc = cg + 8 * q;
+      if (cc < pw) W.G[(int64_t)(i0 + jj) + (int64_t)(c0 + cc) * MAXLEAF] = acc[q];
+    }
+    return;
+  }
+  b -= ngram;
+  // ---- (c) T block of panel q = p - 1, row tile b
+  const int q = p - 1;
+  const int cq = q * NB, qw = min(NB, m - cq);
+  const int i0 = b * NB;
+  const int ii = tid % 32, cg = tid / 32;
+  // X = T[i0:i0+32, i0:cq] G[i0:cq, cq:cq+qw]
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int l0 = i0; l0 < cq; l0 += 32) {
+    for (int e = tid; e < 32 * 32; e += NT_MM) {
+      const int a = e % 32, l = e / 32;
+      Yt[a][l] = (l0 + l >= i0 + a) ? W.T[(int64_t)(i0 + a) + (int64_t)(l0 + l) * MAXLEAF] : 0.0;
+      Bt[l][a] = (a < qw) ? W.G[(int64_t)(l0 + l) + (int64_t)(cq + a) * MAXLEAF] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int cc = cg + 8 * t;
+      double sacc = acc[t];
+      for (int l = 0; l < 32; ++l) sacc += Yt[ii][l] * Bt[l][cc];
+      acc[t] = sacc;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) Wt[ii][cg + 8 * t] = acc[t];
+  for (int e = tid; e < 32 * 32; e += NT_MM) {
+    const int i = e % 32, j = e / 32;
+    Tt[i][j] = (i < qw && j < qw) ? W.T[(int64_t)(cq + i) + (int64_t)(cq + j) * MAXLEAF] : 0.0;
+  }
+  __syncthreads();
+  // T[i0 + ii, cq + cc] = - sum_l X[ii][l] T_qq[l][cc]
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int cc = cg + 8 * t;
+    if (cc < qw) {
+      double sacc = 0.0;
+      for (int l = 0; l <= cc; ++l) sacc += Wt[ii][l] * Tt[l][cc];
+      W.T[(int64_t)(i0 + ii) + (int64_t)(cq + cc) * MAXLEAF] = -sacc;
+    }
+  }
+}
+
+// R + Y back into the leaf, Y rows back into the ancestors' right factors, T out.
+__global__ void __launch_bounds__(NT_MM) k_leaf_scatter(const LeafJob* __restrict__ jobs, int jidx,
+                                                         LeafWs W, const int* err, double* fc) {
+  if (*err & ERR_STACK) return;
+  const LeafJob& J = jobs[jidx];
+  const int c = blockIdx.x;
+  const int m = J.m;
+  const double* h = W.H + (int64_t)c * MAXSTACK;
+  for (int r = threadIdx.x; r < m; r += NT_MM) {
+    J.D[r + (int64_t)c * m] = h[r];
+    J.Tleaf[r + (int64_t)c * m] = (r <= c) ? W.T[r + (int64_t)c * MAXLEAF] : 0.0;
+  }
+  int off = m;
+  for (int g = 0; g < J.ngroups; ++g) {
+    const int k = *J.g[g].rank;
+    double* V = J.g[g].V + J.g[g].row0 + c;
+    for (int t = threadIdx.x; t < k; t += NT_MM) V[(int64_t)t * J.g[g].ld] = h[off + t];
+    off += k;
+  }
+  if (c == 0 && threadIdx.x == 0) {
+    const double M = off, n = m;
+    add_flops(fc, FC_LEAF, 2.0 * M * n * n - 2.0 / 3.0 * n * n * n + M * n * n - n * n * n / 3.0);
+  }
+}
+
+// ------------------------------------------------------------------ vectors
+// x <- z / |z|, out[0] = |z|  (one block)
+__global__ void __launch_bounds__(1024) k_normalize(const double* z, double* x, int64_t n,
+                                                     double* out) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) s += z[i] * z[i];
+  s = gsum(s, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < 16; ++i) t += red[i];
+  const double nrm = sqrt(t);
+  if (x != nullptr) {
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) x[i] = z[i] * inv;
+  }
+  if (threadIdx.x == 0 && out != nullptr) out[0] = nrm;
+}
+
+__global__ void k_fill(double* x, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+// Back substitution with one upper triangular leaf: X <- R^{-1} X (m x nrhs).
+__global__ void __launch_bounds__(NT_MM) k_leaf_trsm(const double* __restrict__ D, int m, int ld,
+                                                      double* X, int ldx, int nrhs) {
+  __shared__ double xs[MAXLEAF];
+  __shared__ double red[4];
+  const int c = blockIdx.x;  // one column per block
+  if (c >= nrhs) return;
+  double* x = X + (int64_t)c * ldx;
+  for (int r = threadIdx.x; r < m; r += NT_MM) xs[r] = x[r];
+  __syncthreads();
+  for (int i = m - 1; i >= 0; --i) {
+    double s = 0.0;
+    for (int j = i + 1 + threadIdx.x; j < m; j += NT_MM) s += D[i + (int64_t)j * ld] * xs[j];
+    s = gsum(s, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) xs[i] = (xs[i] - (red[0] + red[1] + red[2] + red[3])) / D[i + (int64_t)i * ld];
+    __syncthreads();
+  }
+  for (int r = threadIdx.x; r < m; r += NT_MM) x[r] = xs[r];
+}
+
+}  // namespace hq
