@@ -93,7 +93,8 @@ hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t *leaf_off,
  *         HODLR part) keep singular values > eps*anorm; the off-diagonal blocks
  *         of T keep singular values > eps (as written in the algorithm).
  *  anorm  |A|_2 used for the threshold; if anorm <= 0 it is estimated on the
- *         device by 50 steps of power iteration on A^T A (see hodlr_norm2_est).
+ *         device, as the first step of the factorisation's launch sequence, by
+ *         50 steps of power iteration on A^T A (see hodlr_norm2_est).
  *  flags  0 or HODLR_QR_NO_GRAPH.
  *  out    receives the factors (release with hodlr_qr_free).  A is not modified.
  * Returns HODLR_ECAPACITY if a rank outgrew rank_cap (or a recompression width
@@ -180,6 +181,20 @@ hodlr_status hodlr_qr_export(const hodlr_qr_t *F, char which, double *leaves, do
  */
 hodlr_status hodlr_qr_time(const hodlr_t *A, double eps, double anorm, uint32_t flags,
                            int32_t warmup, int32_t reps, hodlr_stream_t stream, double *ms);
+
+/*
+ * hodlr_qr_profile - diagnostic: run one factorisation launch by launch,
+ * bracketing every launch with HIP events on `stream`, and accumulate per
+ * kernel type (index = type, names from hodlr_op_name, hodlr_op_count types):
+ * ms[type] total duration, counts[type] launches, flops[type] algorithmic FP64
+ * flops credited to that kernel type (same counting rules as hodlr_qr_info).
+ * Host arrays of ntypes entries.  Synchronous and much slower than hodlr_qr.
+ */
+hodlr_status hodlr_qr_profile(const hodlr_t *A, double eps, double anorm, int32_t ntypes,
+                              double *ms, int64_t *counts, double *flops,
+                              hodlr_stream_t stream);
+const char *hodlr_op_name(int32_t type);
+int32_t hodlr_op_count(void);
 
 void hodlr_free(hodlr_t *A);        /* NULL-safe */
 void hodlr_qr_free(hodlr_qr_t *F);  /* NULL-safe */

@@ -19,7 +19,7 @@ from ._lib import HODLR_QR_NO_GRAPH, HodlrError, QRInfo
 __all__ = [
     "hodlr_build", "hodlr_qr", "hodlr_apply_q", "hodlr_solve", "hodlr_matmul", "hodlr_qr_matmul",
     "hodlr_norm2_est", "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time",
-    "HodlrMatrix", "QRFactors", "HodlrError", "colmajor", "HODLR_QR_NO_GRAPH", "load",
+    "hodlr_qr_profile", "HodlrMatrix", "QRFactors", "HodlrError", "colmajor", "HODLR_QR_NO_GRAPH", "load",
 ]
 
 load = _lib.load
@@ -189,3 +189,17 @@ def hodlr_qr_time(A: HodlrMatrix, eps: float, anorm: float = 0.0, flags: int = 0
     _lib.check(load().hodlr_qr_time(A.handle, float(eps), float(anorm), int(flags), int(warmup), int(reps),
                                     _stream(stream), _ptr(ms, C.c_double)))
     return ms
+
+
+def hodlr_qr_profile(A: HodlrMatrix, eps: float, anorm: float = 0.0, stream=None) -> dict:
+    """Per-kernel-type totals of one factorisation run launch by launch:
+    {name: {"ms": total, "count": launches, "flops": algorithmic flops}}."""
+    lib = load()
+    nt = lib.hodlr_op_count()
+    ms = np.zeros(nt)
+    cnt = np.zeros(nt, dtype=np.int64)
+    fl = np.zeros(nt)
+    _lib.check(lib.hodlr_qr_profile(A.handle, float(eps), float(anorm), nt, _ptr(ms, C.c_double),
+                                    _ptr(cnt, C.c_int64), _ptr(fl, C.c_double), _stream(stream)))
+    return {lib.hodlr_op_name(i).decode(): {"ms": float(ms[i]), "count": int(cnt[i]), "flops": float(fl[i])}
+            for i in range(nt) if cnt[i] > 0}

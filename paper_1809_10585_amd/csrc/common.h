@@ -60,7 +60,7 @@ struct TrSide {
 struct TrJob {
   Seg seg[2][2];
   TrSide side[2];
-  double tau;
+  const double* tau;  // threshold (device scalar: eps*|A|_2 or eps)
   int flags;
   double* out[2];
   int ldout[2];

@@ -199,8 +199,11 @@ hodlr_status make_leaves(DMem& mem, const Tree& t, LeafSet& S) {
 // ------------------------------------------------------------------ schedule
 enum OpType {
   OP_TRQR, OP_TRFORM, OP_MMPROJ, OP_MMAPPLY, OP_GTALL, OP_GRED, OP_LGATHER, OP_LPANEL,
-  OP_LUPDATE, OP_LSCATTER, OP_FILL, OP_NORMALIZE, OP_TRSM
+  OP_LUPDATE, OP_LSCATTER, OP_FILL, OP_NORMALIZE, OP_TRSM, OP_SETSCAL, OP_NTYPES
 };
+const char* const OP_NAMES[OP_NTYPES] = {
+  "tr_qr", "tr_form", "mm_proj", "mm_apply", "gemm_tall", "gemm_red", "leaf_gather", "leaf_panel",
+  "leaf_update", "leaf_scatter", "fill", "normalize", "leaf_trsm", "set_scal"};
 
 struct Op {
   int type;
@@ -211,12 +214,14 @@ struct Op {
   double* p1;
   double d0;
   int64_t n;
+  double* pout;
+  double d1;
 };
 
 struct TrSpec {
   Seg seg[2][2];
   int m[2];
-  double tau;
+  const double* tau;
   int flags;
   double* out[2];
   int ldout[2];
@@ -271,6 +276,7 @@ struct Plan {
   int64_t ws_need = 0;
   int cnt_need = 1;
   int64_t n_trunc = 0;
+  int wtop = WMAX;  // widest recompression this plan can produce
   // device copies
   TrJob* d_trj = nullptr;
   TrChunk* d_trc = nullptr;
@@ -476,64 +482,82 @@ hodlr_status ensure_work(DMem& mem, Work& W, int64_t ws_need, int cnt_need, bool
 
 bool g_attr_done = false;
 
-hodlr_status run_ops(const Plan& P, const Work& W, hipStream_t st) {
-  if (!g_attr_done) {
-    HIPCHK(hipFuncSetAttribute((const void*)k_tr_qr, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)TR_QR_LDS));
-    HIPCHK(hipFuncSetAttribute((const void*)k_tr_form, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)TR_FORM_LDS));
-    HIPCHK(hipFuncSetAttribute((const void*)k_leaf_panel,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)LEAF_PANEL_LDS));
-    g_attr_done = true;
-  }
-  for (const Op& o : P.ops) {
-    if (o.count <= 0 && o.type != OP_FILL && o.type != OP_NORMALIZE && o.type != OP_LPANEL) continue;
-    switch (o.type) {
-      case OP_TRQR:
-        k_tr_qr<<<o.count, NT_TR, TR_QR_LDS, st>>>(P.d_trj, P.d_trc, o.first, W.ws, W.counters, W.err,
-                                                    W.fc);
-        break;
-      case OP_TRFORM:
-        k_tr_form<<<o.count, NT_MM, TR_FORM_LDS, st>>>(P.d_trj, P.d_trf, o.first, W.ws);
-        break;
-      case OP_MMPROJ:
-        k_mm_proj<<<o.count, NT_MM, 0, st>>>(P.d_mmj, P.d_mmp, o.first, W.ws, W.counters, W.fc);
-        break;
-      case OP_MMAPPLY:
-        k_mm_apply<<<o.count, NT_MM, 0, st>>>(P.d_mmj, P.d_mma, o.first, W.ws, W.fc);
-        break;
-      case OP_GTALL:
-        k_gemm_tall<<<o.count, NT_MM, 0, st>>>(P.d_gj, P.d_gt, o.first, W.fc);
-        break;
-      case OP_GRED:
-        k_gemm_red<<<o.count, NT_MM, 0, st>>>(P.d_gj, P.d_gr, o.first, W.ws, W.counters, W.fc);
-        break;
-      case OP_LGATHER:
-        k_leaf_gather<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, W.err);
-        break;
-      case OP_LPANEL:
-        k_leaf_panel<<<1, NT_TR, LEAF_PANEL_LDS, st>>>(P.d_lj, o.a0, W.leaf, o.a1, W.err);
-        break;
-      case OP_LUPDATE:
-        k_leaf_update<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, o.a1, W.err);
-        break;
-      case OP_LSCATTER:
-        k_leaf_scatter<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, W.err, W.fc);
-        break;
-      case OP_FILL:
-        k_fill<<<(unsigned)((o.n + 255) / 256), 256, 0, st>>>(o.p1, o.n, o.d0);
-        break;
-      case OP_NORMALIZE:
-        k_normalize<<<1, 1024, 0, st>>>(o.p0, o.p1, o.n, o.a0 ? W.fc + 7 : nullptr);
-        break;
-      case OP_TRSM:
-        k_leaf_trsm<<<o.count, NT_MM, 0, st>>>(o.p0, o.a0, o.a0, o.p1, (int)o.n, o.count);
-        break;
+hodlr_status set_attrs() {
+  if (g_attr_done) return HODLR_OK;
+  for (const void* f : {(const void*)k_tr_qr<16>, (const void*)k_tr_qr<32>, (const void*)k_tr_qr<64>,
+                        (const void*)k_tr_qr<128>})
+    HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TR_QR_LDS));
+  HIPCHK(hipFuncSetAttribute((const void*)k_tr_form, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)TR_FORM_LDS));
+  HIPCHK(hipFuncSetAttribute((const void*)k_leaf_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)LEAF_PANEL_LDS));
+  g_attr_done = true;
+  return HODLR_OK;
+}
+
+void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st) {
+  if (o.count <= 0 && o.type != OP_FILL && o.type != OP_NORMALIZE && o.type != OP_LPANEL &&
+      o.type != OP_SETSCAL)
+    return;
+  switch (o.type) {
+    case OP_TRQR: {
+      const int wt = P.wtop;
+      auto kern = wt <= 16 ? k_tr_qr<16> : wt <= 32 ? k_tr_qr<32> : wt <= 64 ? k_tr_qr<64> : k_tr_qr<128>;
+      kern<<<o.count, NT_TR, TR_QR_LDS, st>>>(P.d_trj, P.d_trc, o.first, W.ws, W.counters, W.err, W.fc);
+      break;
     }
+    case OP_TRFORM:
+      k_tr_form<<<o.count, NT_MM, TR_FORM_LDS, st>>>(P.d_trj, P.d_trf, o.first, W.ws);
+      break;
+    case OP_MMPROJ:
+      k_mm_proj<<<o.count, NT_MM, 0, st>>>(P.d_mmj, P.d_mmp, o.first, W.ws, W.counters, W.fc);
+      break;
+    case OP_MMAPPLY:
+      k_mm_apply<<<o.count, NT_MM, 0, st>>>(P.d_mmj, P.d_mma, o.first, W.ws, W.fc);
+      break;
+    case OP_GTALL:
+      k_gemm_tall<<<o.count, NT_MM, 0, st>>>(P.d_gj, P.d_gt, o.first, W.fc);
+      break;
+    case OP_GRED:
+      k_gemm_red<<<o.count, NT_MM, 0, st>>>(P.d_gj, P.d_gr, o.first, W.ws, W.counters, W.fc);
+      break;
+    case OP_LGATHER:
+      k_leaf_gather<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, W.err);
+      break;
+    case OP_LPANEL:
+      k_leaf_panel<<<1, NT_TR, LEAF_PANEL_LDS, st>>>(P.d_lj, o.a0, W.leaf, o.a1, W.err);
+      break;
+    case OP_LUPDATE:
+      k_leaf_update<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, o.a1, W.err);
+      break;
+    case OP_LSCATTER:
+      k_leaf_scatter<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, W.err, W.fc);
+      break;
+    case OP_FILL:
+      k_fill<<<(unsigned)((o.n + 255) / 256), 256, 0, st>>>(o.p1, o.n, o.d0);
+      break;
+    case OP_NORMALIZE:
+      k_normalize<<<1, 1024, 0, st>>>(o.p0, o.p1, o.n, o.pout);
+      break;
+    case OP_SETSCAL:
+      k_set_scal<<<1, 64, 0, st>>>(o.p1, o.d0, o.d1);
+      break;
+    case OP_TRSM:
+      k_leaf_trsm<<<o.count, NT_MM, 0, st>>>(o.p0, o.a0, o.a0, o.p1, (int)o.n, o.count);
+      break;
   }
+}
+
+hodlr_status run_ops(const Plan& P, const Work& W, hipStream_t st) {
+  TRY(set_attrs());
+  for (const Op& o : P.ops) run_op(P, W, o, st);
   HIPCHK(hipGetLastError());
   return HODLR_OK;
 }
+
+// power-iteration estimate of |M|_2 (50 steps on M^T M from x0 = 1/sqrt(n));
+// writes the result to *out (device).  x, y, z: device vectors of length n.
+void plan_norm2(Plan& P, const Tree& t, HView V, int iters, double* x, double* y, double* z, double* out);
 
 }  // namespace
 
@@ -557,6 +581,7 @@ struct hodlr_qr_s {
   BlockSet up, lo, tup;
   int* ranks = nullptr;  // up | lo | t | scalars
   double anorm = 0, eps = 0, tauA = 0, tauT = 0;
+  double* scal = nullptr;  // device: |A|_2, eps*|A|_2, eps
   Work work;
   // temporaries of the node steps (n x cap each)
   double *SL = nullptr, *SR = nullptr, *SLt = nullptr, *Z1 = nullptr, *Z2 = nullptr, *Z4 = nullptr,
@@ -660,7 +685,7 @@ struct QRBuilder {
     P.ops.push_back(Op{OP_LSCATTER, 0, m, jid});
   }
 
-  TrSpec trspec(Seg l0, Seg l1, Seg r0, Seg r1, int mL, int mR, double tau, double* oL, double* oR,
+  TrSpec trspec(Seg l0, Seg l1, Seg r0, Seg r1, int mL, int mR, const double* tau, double* oL, double* oR,
                 int ldL, int ldR, int* orank, int fc, int flags = 0) {
     TrSpec s;
     s.seg[0][0] = l0;
@@ -703,10 +728,10 @@ struct QRBuilder {
              mmspec(F.view_gen(), true, true, Rc, 1, A21.U, mR, k21, F.Z2, mR, 1.0, 0.0, 0)});
     // S~ = T(Y_A11^T A12 + Y_A21^T A22 + sum over groups), term by term
     P.trunc({trspec(mkseg(F.Z1, mL, k12), mkseg(A21.V, mL, k21), mkseg(A12.V, mR, k12),
-                    mkseg(F.Z2, mR, k21), mL, mR, F.tauA, F.SL, F.SR, mL, mR, rS, FC_TRUNC)});
+                    mkseg(F.Z2, mR, k21), mL, mR, F.scal + 1, F.SL, F.SR, mL, mR, rS, FC_TRUNC)});
     for (int g : groups)
       P.trunc({trspec(mkseg(F.SL, mL, rS), mkseg(gslice(g, Lc), gld(g), F.rank_lo(g)),
-                      mkseg(F.SR, mR, rS), mkseg(gslice(g, Rc), gld(g), F.rank_lo(g)), mL, mR, F.tauA,
+                      mkseg(F.SR, mR, rS), mkseg(gslice(g, Rc), gld(g), F.rank_lo(g)), mL, mR, F.scal + 1,
                       F.SL, F.SR, mL, mR, rS, FC_TRUNC)});
     // S = T1^T S~  (left factor only)
     P.mm(t, {mmspec(F.view_t(), true, false, Lc, 1, F.SL, mL, rS, F.SLt, mL, 1.0, 0.0, 1)});
@@ -746,7 +771,7 @@ struct QRBuilder {
     {
       std::vector<TrSpec> sp;
       sp.push_back(trspec(mkseg(A12.U, mL, k12), mkseg(F.Z4, mL, rS, -1.0), mkseg(A12.V, mR, k12),
-                          mkseg(F.SR, mR, rS), mL, mR, F.tauA, A12.U, A12.V, mL, mR, k12, FC_TRUNC));
+                          mkseg(F.SR, mR, rS), mL, mR, F.scal + 1, A12.U, A12.V, mL, mR, k12, FC_TRUNC));
       std::vector<int> sub;
       t.subtree_internal(Rc, sub);
       for (int u : sub) {
@@ -755,7 +780,7 @@ struct QRBuilder {
           int* kb = kind == 0 ? F.rank_up(u) : F.rank_lo(u);
           const int64_t ri = b.r0 - t.lo[Rc], cj = b.c0 - t.lo[Rc];
           sp.push_back(trspec(mkseg(b.U, b.ldU, kb), mkseg(A21.U + ri, mR, k21), mkseg(b.V, b.ldV, kb),
-                              mkseg(F.SRW + cj, mR, k21, -1.0), b.rows, b.cols, F.tauA, b.U, b.V, b.ldU,
+                              mkseg(F.SRW + cj, mR, k21, -1.0), b.rows, b.cols, F.scal + 1, b.U, b.V, b.ldU,
                               b.ldV, kb, FC_TRUNC));
         }
       }
@@ -780,7 +805,7 @@ struct QRBuilder {
     P.mm(t, {mmspec(F.view_y(), false, true, Rc, 1, A21.U, mR, k21, F.Z5, mR, 1.0, 0.0, 1)});
     int* rt = F.rank_t(v);
     if (groups.empty()) {
-      P.trunc({trspec(mkseg(A21.V, mL, k21), noseg(), mkseg(F.Z5, mR, k21), noseg(), mL, mR, F.tauT,
+      P.trunc({trspec(mkseg(A21.V, mL, k21), noseg(), mkseg(F.Z5, mR, k21), noseg(), mL, mR, F.scal + 2,
                       F.TL, F.TR, mL, mR, rt, FC_TRUNC)});
     } else {
       for (size_t i = 0; i < groups.size(); ++i) {
@@ -788,7 +813,7 @@ struct QRBuilder {
         const Seg l0 = i == 0 ? mkseg(A21.V, mL, k21) : mkseg(F.TL, mL, rt);
         const Seg r0 = i == 0 ? mkseg(F.Z5, mR, k21) : mkseg(F.TR, mR, rt);
         P.trunc({trspec(l0, mkseg(gslice(g, Lc), gld(g), F.rank_lo(g)), r0,
-                        mkseg(gslice(g, Rc), gld(g), F.rank_lo(g)), mL, mR, F.tauT, F.TL, F.TR, mL, mR,
+                        mkseg(gslice(g, Rc), gld(g), F.rank_lo(g)), mL, mR, F.scal + 2, F.TL, F.TR, mL, mR,
                         rt, FC_TRUNC)});
       }
     }
@@ -804,13 +829,38 @@ struct QRBuilder {
     for (int v = 1; v < t.nleaf(); ++v) {
       const HBlk& b = F.lo.hview[v];
       orth.push_back(trspec(mkseg(b.U, b.ldU, F.rank_lo(v)), noseg(), mkseg(b.V, b.ldV, F.rank_lo(v)),
-                            noseg(), b.rows, b.cols, 0.0, b.U, b.V, b.ldU, b.ldV, F.rank_lo(v), FC_ORTH,
+                            noseg(), b.rows, b.cols, F.scal + 2, b.U, b.V, b.ldU, b.ldV, F.rank_lo(v), FC_ORTH,
                             TR_ORTH));
     }
     P.trunc(orth);
     node(1, {});
   }
 };
+
+void plan_norm2(Plan& P, const Tree& t, HView V, int iters, double* x, double* y, double* z, double* out) {
+  const int64_t n = t.n;
+  Op fill{OP_FILL};
+  fill.p1 = x;
+  fill.n = n;
+  fill.d0 = 1.0 / std::sqrt((double)n);
+  P.ops.push_back(fill);
+  for (int it = 0; it < iters; ++it) {
+    P.mm(t, {mmspec(V, true, true, 1, 0, x, (int)n, nullptr, y, (int)n, 1.0, 0.0, 0, 1)});
+    P.mm(t, {mmspec(V, true, true, 1, 1, y, (int)n, nullptr, z, (int)n, 1.0, 0.0, 0, 1)});
+    Op o{OP_NORMALIZE};
+    o.p0 = z;
+    o.p1 = x;
+    o.n = n;
+    P.ops.push_back(o);
+  }
+  P.mm(t, {mmspec(V, true, true, 1, 0, x, (int)n, nullptr, y, (int)n, 1.0, 0.0, 0, 1)});
+  Op o{OP_NORMALIZE};
+  o.p0 = y;
+  o.p1 = nullptr;
+  o.n = n;
+  o.pout = out;
+  P.ops.push_back(o);
+}
 
 hodlr_status check_finite(const double* p, size_t n, const char* what) {
   for (size_t i = 0; i < n; ++i)
@@ -841,6 +891,8 @@ hodlr_status make_factor(const hodlr_s& A, double eps, double anorm, hipStream_t
   F->tauT = eps;
   const Tree& t = F->t;
   const int nn = 1 << t.L;
+  TRY(F->mem.alloc(&F->scal, 8));
+  HIPCHK(hipMemsetAsync(F->scal, 0, 8 * sizeof(double), st));
   TRY(F->mem.alloc(&F->ranks, 3 * (size_t)nn + 8));
   HIPCHK(hipMemsetAsync(F->ranks, 0, (3 * (size_t)nn + 8) * sizeof(int), st));
   TRY(make_leaves(F->mem, t, F->leaves));
@@ -862,6 +914,17 @@ hodlr_status make_factor(const hodlr_s& A, double eps, double anorm, hipStream_t
   TRY(F->mem.alloc(&F->X2, (size_t)t.n * SMAX));
   if (t.L > MAXGROUPS) return fail(HODLR_EINVAL, "too many levels");
   QRBuilder qb(*F);
+  F->plan.wtop = 2 * F->cap;
+  // thresholds: |A|_2 from the power iteration unless given, then tau_A, tau_T
+  if (!(anorm > 0.0))
+    plan_norm2(F->plan, t, F->view_gen(), 50, F->X1, F->X1 + t.n, F->X2, F->scal);
+  {
+    Op o{OP_SETSCAL};
+    o.p1 = F->scal;
+    o.d0 = eps;
+    o.d1 = anorm > 0.0 ? anorm : -1.0;
+    F->plan.ops.push_back(o);
+  }
   qb.build();
   TRY(F->plan.upload_all(F->mem, st));
   TRY(ensure_work(F->mem, F->work, F->plan.ws_need, F->plan.cnt_need, true, st));
@@ -879,13 +942,7 @@ hodlr_status run_factor(hodlr_qr_s& F, const hodlr_s& A, bool use_graph, hipStre
     // capture on a private stream so that the caller's stream state is untouched
     hipStream_t cs;
     HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    // prime function attributes outside capture
-    if (!g_attr_done) {
-      HIPCHK(hipFuncSetAttribute((const void*)k_tr_qr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TR_QR_LDS));
-      HIPCHK(hipFuncSetAttribute((const void*)k_tr_form, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TR_FORM_LDS));
-      HIPCHK(hipFuncSetAttribute((const void*)k_leaf_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LEAF_PANEL_LDS));
-      g_attr_done = true;
-    }
+    TRY(set_attrs());
     HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hodlr_status s1 = reset_factor(F, A, cs);
     hodlr_status s2 = s1 == HODLR_OK ? run_ops(F.plan, F.work, cs) : s1;
@@ -910,8 +967,13 @@ hodlr_status run_factor(hodlr_qr_s& F, const hodlr_s& A, bool use_graph, hipStre
 
 hodlr_status finish_factor(hodlr_qr_s& F, hipStream_t st) {
   int err = 0;
+  double sc[3];
   HIPCHK(hipMemcpyAsync(&err, F.work.err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(sc, F.scal, sizeof(sc), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  F.anorm = sc[0];
+  F.tauA = sc[1];
+  F.tauT = sc[2];
   if (err & ERR_STACK) return fail(HODLR_ECAPACITY, "stacked leaf column exceeds 1024 rows");
   if (err & ERR_WIDTH) return fail(HODLR_ECAPACITY, "a recompression width exceeded 128 columns");
   if (err & ERR_CAPACITY) return fail(HODLR_ECAPACITY, "an off-diagonal rank exceeded rank_cap");
@@ -930,39 +992,10 @@ hodlr_status norm2_est_impl(hodlr_s& A, int iters, hipStream_t st, double* out) 
   TRY(tmp.alloc(&res, 1));
   HView V{t.L, A.up.dview, A.lo.dview, A.leaves.dview, LEAF_FULL};
   Plan P;
-  Op fill{OP_FILL};
-  fill.p1 = x;
-  fill.n = n;
-  fill.d0 = 1.0 / std::sqrt((double)n);
-  P.ops.push_back(fill);
-  auto norm = [&](const double* src, double* dst) {
-    Op o{OP_NORMALIZE};
-    o.p0 = src;
-    o.p1 = dst;
-    o.n = n;
-    o.a0 = 0;
-    P.ops.push_back(o);
-  };
-  for (int it = 0; it < iters; ++it) {
-    P.mm(t, {mmspec(V, true, true, 1, 0, x, (int)n, nullptr, y, (int)n, 1.0, 0.0, 0, 1)});
-    P.mm(t, {mmspec(V, true, true, 1, 1, y, (int)n, nullptr, z, (int)n, 1.0, 0.0, 0, 1)});
-    norm(z, x);
-  }
-  P.mm(t, {mmspec(V, true, true, 1, 0, x, (int)n, nullptr, y, (int)n, 1.0, 0.0, 0, 1)});
-  {
-    Op o{OP_NORMALIZE};
-    o.p0 = y;
-    o.p1 = nullptr;
-    o.n = n;
-    o.a0 = 0;
-    P.ops.push_back(o);
-  }
+  plan_norm2(P, t, V, iters, x, y, z, res);
   TRY(P.upload_all(tmp, st));
   TRY(ensure_work(A.mem, A.work, P.ws_need, P.cnt_need, false, st));
   TRY(run_ops(P, A.work, st));
-  // the last normalize wrote |A x| nowhere: compute it into res
-  k_normalize<<<1, 1024, 0, st>>>(y, nullptr, n, res);
-  HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   return HODLR_OK;
@@ -1077,7 +1110,6 @@ hodlr_status hodlr_qr(const hodlr_t* A, double eps, double anorm, uint32_t flags
   *out = nullptr;
   if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(HODLR_EINVAL, "eps must be finite and >= 0");
   hipStream_t st = (hipStream_t)stream;
-  if (!(anorm > 0.0)) TRY(norm2_est_impl(*const_cast<hodlr_t*>(A), 50, st, &anorm));
   std::unique_ptr<hodlr_qr_s> F;
   TRY(make_factor(*A, eps, anorm, st, F));
   TRY(run_factor(*F, *A, !(flags & HODLR_QR_NO_GRAPH), st));
@@ -1091,7 +1123,6 @@ hodlr_status hodlr_qr_time(const hodlr_t* A, double eps, double anorm, uint32_t 
   g_err.clear();
   if (A == nullptr || ms == nullptr || reps < 1 || warmup < 0) return fail(HODLR_EINVAL, "bad argument");
   hipStream_t st = (hipStream_t)stream;
-  if (!(anorm > 0.0)) TRY(norm2_est_impl(*const_cast<hodlr_t*>(A), 50, st, &anorm));
   std::unique_ptr<hodlr_qr_s> F;
   TRY(make_factor(*A, eps, anorm, st, F));
   const bool g = !(flags & HODLR_QR_NO_GRAPH);
@@ -1237,6 +1268,52 @@ hodlr_status hodlr_solve(const hodlr_qr_t* F, int64_t nrhs, double* B, int64_t l
   }
   return HODLR_OK;
 }
+
+hodlr_status hodlr_qr_profile(const hodlr_t* A, double eps, double anorm, int32_t ntypes, double* ms,
+                              int64_t* counts, double* flops, hodlr_stream_t stream) {
+  g_err.clear();
+  if (A == nullptr || ms == nullptr || counts == nullptr || flops == nullptr || ntypes < 1)
+    return fail(HODLR_EINVAL, "bad argument");
+  hipStream_t st = (hipStream_t)stream;
+  std::unique_ptr<hodlr_qr_s> F;
+  TRY(make_factor(*A, eps, anorm, st, F));
+  TRY(set_attrs());
+  for (int i = 0; i < ntypes; ++i) {
+    ms[i] = 0.0;
+    counts[i] = 0;
+    flops[i] = 0.0;
+  }
+  TRY(reset_factor(*F, *A, st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double prev = 0.0;
+  for (const Op& o : F->plan.ops) {
+    HIPCHK(hipEventRecord(e0, st));
+    run_op(F->plan, F->work, o, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    double fcv[8];
+    HIPCHK(hipMemcpy(fcv, F->work.fc, sizeof(fcv), hipMemcpyDeviceToHost));
+    double tot = 0.0;
+    for (int c = 0; c < FC_N; ++c) tot += fcv[c];
+    if (o.type < ntypes) {
+      ms[o.type] += t;
+      counts[o.type] += 1;
+      flops[o.type] += tot - prev;
+    }
+    prev = tot;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return finish_factor(*F, st);
+}
+
+const char* hodlr_op_name(int32_t type) { return (type >= 0 && type < OP_NTYPES) ? OP_NAMES[type] : ""; }
+int32_t hodlr_op_count(void) { return OP_NTYPES; }
 
 hodlr_status hodlr_qr_info(const hodlr_qr_t* F, hodlr_qr_info_t* info) {
   g_err.clear();

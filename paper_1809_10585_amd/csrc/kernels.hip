@@ -20,9 +20,52 @@
 namespace hq {
 
 // ------------------------------------------------------------------ helpers
-__device__ __forceinline__ double gsum(double x, int width) {
-  for (int o = width >> 1; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+// Cross-lane moves of a double through DPP (VALU, a few cycles) instead of
+// ds_bpermute round trips.  CTRL is a gfx9 DPP control word.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi2, lo2);
+}
+
+__device__ __forceinline__ double swz_xor16(double x) {  // lane ^ 16 within 32 lanes
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const int lo2 = __builtin_amdgcn_ds_swizzle(lo, 0x401F);
+  const int hi2 = __builtin_amdgcn_ds_swizzle(hi, 0x401F);
+  return __hiloint2double(hi2, lo2);
+}
+
+__device__ __forceinline__ double lane_read(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of W lanes (W = 1, 2, ..., 64); every lane of the
+// group receives the group sum.  The 64-lane case needs the whole wave active.
+template <int W>
+__device__ __forceinline__ double gsumt(double x) {
+  if constexpr (W >= 2) x += dpp_mov<0xB1>(x);   // quad_perm [1,0,3,2]
+  if constexpr (W >= 4) x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1]
+  if constexpr (W >= 8) x += dpp_mov<0x141>(x);  // row_half_mirror
+  if constexpr (W >= 16) x += dpp_mov<0x140>(x); // row_mirror
+  if constexpr (W >= 32) x += swz_xor16(x);
+  if constexpr (W >= 64) x = lane_read(x, 0) + lane_read(x, 32);
   return x;
+}
+
+__device__ __forceinline__ double gsum(double x, int width) {
+  switch (width) {
+    case 1: return x;
+    case 2: return gsumt<2>(x);
+    case 4: return gsumt<4>(x);
+    case 8: return gsumt<8>(x);
+    case 16: return gsumt<16>(x);
+    case 32: return gsumt<32>(x);
+    default: return gsumt<64>(x);
+  }
 }
 
 __device__ __forceinline__ int seg_n(const Seg& s) {
@@ -65,8 +108,8 @@ __device__ __forceinline__ void reg_qr(double (&a)[RPT], int c, int sub, int h, 
         if (r > j) ss += a[i] * a[i];
         if (r == j) al = a[i];
       }
-      ss = gsum(ss, TPC);
-      al = gsum(al, TPC);
+      ss = gsumt<TPC>(ss);
+      al = gsumt<TPC>(al);
       double tau = 0.0, beta = al, scal = 0.0;
       if (ss != 0.0) {
         const double nrm = sqrt(al * al + ss);
@@ -95,7 +138,7 @@ __device__ __forceinline__ void reg_qr(double (&a)[RPT], int c, int sub, int h, 
       double d = 0.0;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) d += vb[sub + TPC * i] * a[i];
-      d = gsum(d, TPC);
+      d = gsumt<TPC>(d);
       const double f = tau * d;
       asm volatile("" ::: "memory");  // re-read v from LDS instead of holding it in registers
 #pragma unroll
@@ -105,7 +148,7 @@ __device__ __forceinline__ void reg_qr(double (&a)[RPT], int c, int sub, int h, 
       double d = 0.0;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) d += vb[sub + TPC * i] * a[i];
-      d = gsum(d, TPC);
+      d = gsumt<TPC>(d);
       if (sub == 0) gram[c + j * gld] = d;
     }
   }
@@ -139,7 +182,7 @@ __device__ __forceinline__ void reg_formq(const double (&a)[RPT], double (&q)[RP
       double d = 0.0;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) d += vb[sub + TPC * i] * q[i];
-      d = gsum(d, TPC);
+      d = gsumt<TPC>(d);
       const double f = tau * d;
       asm volatile("" ::: "memory");
 #pragma unroll
@@ -176,7 +219,7 @@ __device__ __forceinline__ void reg_formq_g(const double* Va, double (&q)[RPT], 
       double d = 0.0;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) d += vb[sub + TPC * i] * q[i];
-      d = gsum(d, TPC);
+      d = gsumt<TPC>(d);
       const double f = tau * d;
       asm volatile("" ::: "memory");
 #pragma unroll
@@ -287,6 +330,8 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
   const double* R1 = ws + J.side[0].node0 + (int64_t)tr_root_slot(J.side[0].p0, G) * TR_NODE;
   int* sflag = (int*)(smem + TRS_FLAG);
   const int m0 = J.side[0].m, m1 = J.side[1].m;
+  const double tau = *J.tau;
+  const int capk = J.cap, fcat = J.fc;
   int k;
   if (J.flags & TR_ORTH) {
     k = min(m0, w);
@@ -297,37 +342,54 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
     }
     if (tid == 0) {
       const double pq = (double)min(m0, w);
-      add_flops(fc, J.fc, 2.0 * (2.0 * m0 * w * pq - 2.0 / 3.0 * pq * pq * pq) + 2.0 * w * w * m1);
+      add_flops(fc, fcat, 2.0 * (2.0 * m0 * w * pq - 2.0 / 3.0 * pq * pq * pq) + 2.0 * w * w * m1);
     }
   } else {
     const double* R2 = ws + J.side[1].node0 + (int64_t)tr_root_slot(J.side[1].p0, G) * TR_NODE;
-    constexpr int LX = W;
+    const int LX = w;
     double* X = smem + TRS_X;
     double* V;
     int LV;
-    if (W <= 64) {
-      V = X + W * W;
-      LV = W;
+    if (2 * w * w <= WMAX * WMAX) {  // X and V both in LDS
+      V = X + w * w;
+      LV = w;
     } else {
       V = hdr + 8 + 2 * WMAX * WMAX;
       LV = WMAX;
     }
     double* sig = smem + TRS_X + WMAX * WMAX;
     int* perm = (int*)(sig + WMAX);
+    // stage R1 and R2 in LDS when they fit next to X and V
+    const double* R1s = R1;
+    const double* R2s = R2;
+    int lr = WMAX;
+    if (4 * w * w <= WMAX * WMAX) {
+      double* r1 = X + 2 * w * w;
+      double* r2 = r1 + w * w;
+      for (int e = tid; e < w * w; e += NT_TR) {
+        const int i = e % w, j = e / w;
+        r1[e] = R1[i + j * WMAX];
+        r2[e] = R2[i + j * WMAX];
+      }
+      R1s = r1;
+      R2s = r2;
+      lr = w;
+      __syncthreads();
+    }
     // X = R2 R1^T  (both upper triangular, w x w)
     for (int e = tid; e < w * w; e += NT_TR) {
       const int i = e % w, j = e / w;
-      double s = 0.0;
-      for (int l = max(i, j); l < w; ++l) s += R2[i + l * WMAX] * R1[j + l * WMAX];
-      X[i + j * LX] = s;
+      double sacc = 0.0;
+      for (int l = max(i, j); l < w; ++l) sacc += R2s[i + l * lr] * R1s[j + l * lr];
+      X[i + j * LX] = sacc;
       V[i + j * LV] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
     jacobi(X, LX, V, LV, w, sflag);
     for (int cc = tid; cc < w; cc += NT_TR) {
-      double s = 0.0;
-      for (int r = 0; r < w; ++r) s += X[r + cc * LX] * X[r + cc * LX];
-      sig[cc] = sqrt(s);
+      double sacc = 0.0;
+      for (int r = 0; r < w; ++r) sacc += X[r + cc * LX] * X[r + cc * LX];
+      sig[cc] = sqrt(sacc);
     }
     __syncthreads();
     for (int cc = tid; cc < w; cc += NT_TR) {
@@ -341,21 +403,18 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
     }
     __syncthreads();
     k = 0;
-    for (int j = 0; j < w; ++j) k += (sig[j] > J.tau) ? 1 : 0;
-    if (k > J.cap) {
+    for (int j = 0; j < w; ++j) k += (sig[j] > tau) ? 1 : 0;
+    if (k > capk) {
       if (tid == 0) atomicOr(err, ERR_CAPACITY);
-      k = J.cap;
+      k = capk;
     }
     for (int e = tid; e < w * k; e += NT_TR) {
       const int r = e % w, p = e / w;
-      Uk[r + p * WMAX] = V[r + perm[p] * LV];
-    }
-    __syncthreads();
-    for (int e = tid; e < w * k; e += NT_TR) {
-      const int r = e % w, p = e / w;
-      double s = 0.0;
-      for (int l = 0; l <= r; ++l) s += R1[l + r * WMAX] * Uk[l + p * WMAX];
-      P[r + p * WMAX] = s;
+      const int pc = perm[p];
+      Uk[r + p * WMAX] = V[r + pc * LV];
+      double sacc = 0.0;
+      for (int l = 0; l <= r; ++l) sacc += R1s[l + r * lr] * V[l + pc * LV];
+      P[r + p * WMAX] = sacc;
     }
     if (tid == 0) {
       const double p1 = min(m0, w), p2 = min(m1, w);
@@ -369,7 +428,7 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
                       : 2.0 * n * m * m - 2.0 / 3.0 * m * m * m;
       }(m1, w);
       const double mp = fmax(p1, p2);
-      add_flops(fc, J.fc,
+      add_flops(fc, fcat,
                 qf + 2.0 * p1 * p2 * w + 21.0 * mp * mp * mp + 4.0 * m0 * p1 * k + 2.0 * m1 * w * k);
     }
   }
@@ -391,7 +450,7 @@ __device__ __forceinline__ void tr_chunk(const TrJob& J, int side, int chunk, do
   double* vbuf = smem + TRS_VBUF;
   double* taus = smem + TRS_TAU;
   int* sflag = (int*)(smem + TRS_FLAG);
-  const TrSide& S = J.side[side];
+  const TrSide S = J.side[side];
   const int n0 = side == 0 ? n0a : n0b;
   const Seg s0 = J.seg[side][0], s1 = J.seg[side][1];
 
@@ -423,7 +482,7 @@ __device__ __forceinline__ void tr_chunk(const TrJob& J, int side, int chunk, do
     if (side == 0) {
       double q[RPT];
       double* Qa = node + WMAX * WMAX;
-      if constexpr (W <= 64) {
+      if constexpr (W <= 32) {
         __syncthreads();
         reg_formq<TPC, RPT>(a, q, c, sub, h, w, vbuf, taus);
       } else {
@@ -501,6 +560,9 @@ __device__ __forceinline__ void tr_chunk(const TrJob& J, int side, int chunk, do
   tr_svd<W>(J, ws, w, n0a, n0b, smem, err, fc);
 }
 
+// WTOP: widest tier compiled into this instantiation (the host picks it from
+// the rank capacity: a recompression is at most twice as wide as a block).
+template <int WTOP>
 __global__ void __launch_bounds__(NT_TR) k_tr_qr(const TrJob* __restrict__ jobs,
                                                   const TrChunk* __restrict__ items, int first,
                                                   double* ws, int* counters, int* err, double* fc) {
@@ -510,25 +572,55 @@ __global__ void __launch_bounds__(NT_TR) k_tr_qr(const TrJob* __restrict__ jobs,
   const int n0a = seg_n(J.seg[0][0]);
   const int w = n0a + seg_n(J.seg[0][1]);
   const int n0b = seg_n(J.seg[1][0]);
-  if (w == 0 || w > WMAX) {
+  if (w == 0 || w > WTOP) {
     if (it.side == 0 && it.chunk == 0 && threadIdx.x == 0) {
       double* hdr = ws + J.hdr;
       hdr[0] = 0.0;
       hdr[1] = 0.0;
-      if (w > WMAX) atomicOr(err, ERR_WIDTH);
+      if (w > WTOP) atomicOr(err, ERR_WIDTH);
     }
     return;
   }
-  switch (tier_of(w)) {
-    case 8: tr_chunk<8>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b); break;
-    case 16: tr_chunk<16>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b); break;
-    case 32: tr_chunk<32>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b); break;
-    case 64: tr_chunk<64>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b); break;
-    default: tr_chunk<128>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b); break;
+  const int t = tier_of(w);
+  if (t == 8) {
+    tr_chunk<8>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b);
+  } else if (t == 16) {
+    if constexpr (WTOP >= 16) tr_chunk<16>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b);
+  } else if (t == 32) {
+    if constexpr (WTOP >= 32) tr_chunk<32>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b);
+  } else if (t == 64) {
+    if constexpr (WTOP >= 64) tr_chunk<64>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b);
+  } else {
+    if constexpr (WTOP >= 128) tr_chunk<128>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b);
   }
 }
 
 constexpr size_t TR_FORM_LDS = sizeof(double) * (size_t)WMAX * WMAX;
+
+// out[r, p] = sum_c A(r, c) B[c + p*ldb] for r < rows, p < k; thread = row,
+// 16 output columns at a time in registers.  A(r, c) = a[r + c*lda].
+__device__ __forceinline__ void rows_times_small(const double* a, int64_t lda, int rows, int w,
+                                                 const double* B, int ldb, int k, double* out,
+                                                 int64_t ldo) {
+  const int tid = threadIdx.x;
+  for (int r = tid; r < rows; r += NT_MM) {
+    for (int p0 = 0; p0 < k; p0 += 16) {
+      double acc[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+#pragma unroll 4
+      for (int c = 0; c < w; ++c) {
+        const double x = a[r + (int64_t)c * lda];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (p0 + q < k) acc[q] += x * B[c + (p0 + q) * ldb];
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (p0 + q < k) out[r + (int64_t)(p0 + q) * ldo] = acc[q];
+    }
+  }
+}
 
 __global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ jobs,
                                                     const TrForm* __restrict__ items, int first,
@@ -545,7 +637,9 @@ __global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ job
   const double* P = Uk + WMAX * WMAX;
   const int G = CH / tier_of(w);
   if (it.side == 0) {
-    const TrSide& S = J.side[0];
+    const TrSide S = J.side[0];
+    double* out = J.out[0];
+    const int ldo = J.ldout[0];
     // path of tree indices from the chunk to the root
     int idxs[16], bases[16];
     int lvl = 0, idx = it.chunk, count = S.p0, base = 0;
@@ -559,46 +653,44 @@ __global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ job
       idxs[lvl] = idx;
       bases[lvl] = base;
     }
-    double* Z = smem;  // w x k, ld WMAX
-    for (int e = tid; e < w * k; e += NT_MM) {
-      const int r = e % w, p = e / w;
-      Z[r + p * WMAX] = Uk[r + p * WMAX];
-    }
+    // Z = U_k (w x k, ld w), then Z <- Q_node[slot rows] Z down the path
+    double* Z = smem;
+    double* Zn = smem + w * k;
+    const bool fits = 2 * w * k <= WMAX * WMAX;
+    for (int e = tid; e < w * k; e += NT_MM) Z[e] = Uk[(e % w) + (e / w) * WMAX];
     __syncthreads();
     for (int l = lvl; l >= 1; --l) {
       const int cslot = idxs[l - 1] - idxs[l] * G;
-      const double* Qn = ws + S.node0 + (int64_t)(bases[l] + idxs[l]) * TR_NODE + WMAX * WMAX;
-      double zn[64];
-      int cnt = 0;
-      for (int e = tid; e < w * k; e += NT_MM, ++cnt) {
-        const int r = e % w, p = e / w;
-        double s = 0.0;
-        for (int cc = 0; cc < w; ++cc) s += Qn[(cslot * w + r) + cc * CH] * Z[cc + p * WMAX];
-        zn[cnt] = s;
+      const double* Qn = ws + S.node0 + (int64_t)(bases[l] + idxs[l]) * TR_NODE + WMAX * WMAX + cslot * w;
+      if (fits) {
+        rows_times_small(Qn, CH, w, w, Z, w, k, Zn, w);
+        __syncthreads();
+        for (int e = tid; e < w * k; e += NT_MM) Z[e] = Zn[e];
+        __syncthreads();
+      } else {
+        // wide case: one column of Z at a time through registers
+        for (int p = 0; p < k; ++p) {
+          double zr = 0.0;
+          if (tid < w)
+            for (int c = 0; c < w; ++c) zr += Qn[tid + (int64_t)c * CH] * Z[c + p * w];
+          __syncthreads();
+          if (tid < w) Z[tid + p * w] = zr;
+          __syncthreads();
+        }
       }
-      __syncthreads();
-      cnt = 0;
-      for (int e = tid; e < w * k; e += NT_MM, ++cnt) {
-        const int r = e % w, p = e / w;
-        Z[r + p * WMAX] = zn[cnt];
-      }
-      __syncthreads();
     }
     const int row0 = (int)((int64_t)it.chunk * S.m / S.p0);
     const int h = (int)((int64_t)(it.chunk + 1) * S.m / S.p0) - row0;
     const double* Qc = ws + S.node0 + (int64_t)it.chunk * TR_NODE + WMAX * WMAX;
-    double* out = J.out[0];
-    const int ldo = J.ldout[0];
-    for (int e = tid; e < h * k; e += NT_MM) {
-      const int r = e % h, p = e / h;
-      double s = 0.0;
-      for (int cc = 0; cc < w; ++cc) s += Qc[r + cc * CH] * Z[cc + p * WMAX];
-      out[(int64_t)(row0 + r) + (int64_t)p * ldo] = s;
-    }
+    rows_times_small(Qc, CH, h, w, Z, w, k, out + row0, ldo);
   } else {
     const int n0 = (int)hdr[3];
     const Seg s0 = J.seg[1][0], s1 = J.seg[1][1];
-    double* In = smem;  // rows x w, ld 64
+    double* out = J.out[1];
+    const int ldo = J.ldout[1];
+    double* In = smem;                 // rows x w, ld 64
+    double* Ps = smem + 64 * w;        // w x k, ld w
+    const bool fits = 64 * w + w * k <= WMAX * WMAX;
     const int rows = it.rows;
     for (int e = tid; e < rows * w; e += NT_MM) {
       const int r = e % rows, cc = e / rows;
@@ -606,15 +698,13 @@ __global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ job
       In[r + cc * 64] = (cc < n0) ? s0.scale * s0.p[gr + (int64_t)cc * s0.ld]
                                   : s1.scale * s1.p[gr + (int64_t)(cc - n0) * s1.ld];
     }
+    if (fits)
+      for (int e = tid; e < w * k; e += NT_MM) Ps[e] = P[(e % w) + (e / w) * WMAX];
     __syncthreads();
-    double* out = J.out[1];
-    const int ldo = J.ldout[1];
-    for (int e = tid; e < rows * k; e += NT_MM) {
-      const int r = e % rows, p = e / rows;
-      double s = 0.0;
-      for (int cc = 0; cc < w; ++cc) s += In[r + cc * 64] * P[cc + p * WMAX];
-      out[(int64_t)(it.row0 + r) + (int64_t)p * ldo] = s;
-    }
+    if (fits)
+      rows_times_small(In, 64, rows, w, Ps, w, k, out + it.row0, ldo);
+    else
+      rows_times_small(In, 64, rows, w, P, WMAX, k, out + it.row0, ldo);
   }
 }
 
@@ -631,9 +721,9 @@ __global__ void __launch_bounds__(NT_MM) k_mm_proj(const MmJob* __restrict__ job
   __shared__ int lastf;
   const int tid = threadIdx.x;
   const MmProj it = items[first + blockIdx.x];
-  const MmJob& J = jobs[it.job];
+  const MmJob J = jobs[it.job];
   const int s = mm_s(J);
-  const HBlk& b = (it.kind == 0 ? J.M.up : J.M.lo)[it.node];
+  const HBlk b = (it.kind == 0 ? J.M.up : J.M.lo)[it.node];
   const int k = *b.rank;
   if (k == 0 || s == 0) return;
   const int len = J.trans ? b.rows : b.cols;
@@ -663,7 +753,8 @@ __global__ void __launch_bounds__(NT_MM) k_mm_proj(const MmJob* __restrict__ job
       if (e < nout) {
         const int j = e % k, cc = e / k;
         double sacc = acc[q];
-        for (int r = 0; r < tn; ++r) sacc += Ft[r][j] * Xt[r][cc];
+#pragma unroll 16
+        for (int r = 0; r < 64; ++r) sacc += Ft[r][j] * Xt[r][cc];
         acc[q] = sacc;
       }
     }
@@ -710,12 +801,14 @@ __global__ void __launch_bounds__(NT_MM) k_mm_proj(const MmJob* __restrict__ job
 __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jobs,
                                                      const MmApply* __restrict__ items, int first,
                                                      const double* __restrict__ ws, double* fc) {
-  __shared__ double Dt[64][33];
-  __shared__ double Xt[32][SMAX + 1];
-  __shared__ double Pt[KCAP * SMAX];
+  __shared__ double shm[64 * 33 + 32 * (SMAX + 1) + KCAP * SMAX];
+  double (*Dt)[33] = reinterpret_cast<double (*)[33]>(shm);
+  double (*Xt)[SMAX + 1] = reinterpret_cast<double (*)[SMAX + 1]>(shm + 64 * 33);
+  double (*Ft)[KCAP + 1] = reinterpret_cast<double (*)[KCAP + 1]>(shm);  // aliases Dt/Xt
+  double* Pt = shm + 64 * 33 + 32 * (SMAX + 1);
   const int tid = threadIdx.x;
   const MmApply it = items[first + blockIdx.x];
-  const MmJob& J = jobs[it.job];
+  const MmJob J = jobs[it.job];
   const int s = mm_s(J);
   if (s == 0) return;
   const HLeaf lf = J.M.leaf[it.leaf];
@@ -759,7 +852,8 @@ __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jo
       const int cc = cg + 4 * q;
       if (cc < s) {
         double sacc = acc[q];
-        for (int kk = 0; kk < kn; ++kk) sacc += Dt[r][kk] * Xt[kk][cc];
+#pragma unroll 8
+        for (int kk = 0; kk < 32; ++kk) sacc += Dt[r][kk] * Xt[kk][cc];
         acc[q] = sacc;
       }
     }
@@ -769,29 +863,30 @@ __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jo
   // low-rank parts, one block per ancestor level
   const int hleaf = (1 << J.M.levels) + it.leaf;
   int child = hleaf, u = hleaf >> 1;
-  const int64_t grow = lf.r0 + it.row0 + r;  // global row of this thread
   while (child != J.v && u >= 1) {
     const bool left = (child == 2 * u);
     const int bk = J.trans ? (left ? 1 : 0) : (left ? 0 : 1);
     const HBlk* arr = bk == 0 ? J.M.up : J.M.lo;
     if (arr != nullptr) {
-      const HBlk& b = arr[u];
+      const HBlk b = arr[u];
       const int kb = *b.rank;
       if (kb > 0) {
         const double* red = ws + J.red0 + (int64_t)(2 * rel_node(u, J.v) + bk) * (KCAP * SMAX);
-        for (int e = tid; e < kb * s; e += NT_MM) Pt[(e % kb) + (e / kb) * KCAP] = red[(e % kb) + (e / kb) * KCAP];
-        __syncthreads();
         const double* F = J.trans ? b.V : b.U;
         const int ldF = J.trans ? b.ldV : b.ldU;
-        const int64_t f0 = J.trans ? b.c0 : b.r0;
-        if (r < it.rows) {
-          for (int j = 0; j < kb; ++j) {
-            const double fv = F[(grow - f0) + (int64_t)j * ldF];
+        const int64_t frow = lf.r0 + it.row0 - (J.trans ? b.c0 : b.r0);  // first F row of this tile
+        for (int e = tid; e < kb * s; e += NT_MM) Pt[(e % kb) + (e / kb) * KCAP] = red[(e % kb) + (e / kb) * KCAP];
+        for (int e = tid; e < 64 * kb; e += NT_MM) {
+          const int rr = e % 64, j = e / 64;
+          Ft[rr][j] = (rr < it.rows) ? F[frow + rr + (int64_t)j * ldF] : 0.0;
+        }
+        __syncthreads();
+        for (int j = 0; j < kb; ++j) {
+          const double fv = Ft[r][j];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-              const int cc = cg + 4 * q;
-              if (cc < s) acc[q] += fv * Pt[j + cc * KCAP];
-            }
+          for (int q = 0; q < 16; ++q) {
+            const int cc = cg + 4 * q;
+            if (cc < s) acc[q] += fv * Pt[j + cc * KCAP];
           }
         }
         __syncthreads();
@@ -831,7 +926,7 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_tall(const GemmJob* __restrict__
   __shared__ double Bt[32][65];
   const int tid = threadIdx.x;
   const GemmTile it = items[first + blockIdx.x];
-  const GemmJob& J = jobs[it.job];
+  const GemmJob J = jobs[it.job];
   const int M = J.Md ? *J.Md : J.M, N = J.Nd ? *J.Nd : J.N, K = J.Kd ? *J.Kd : J.K;
   if (it.row0 >= M || it.col0 >= N) return;
   const int mr = min(64, M - it.row0), nc = min(64, N - it.col0);
@@ -868,7 +963,8 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_tall(const GemmJob* __restrict__
     for (int q = 0; q < 16; ++q) {
       const int cc = cg + 4 * q;
       double sacc = acc[q];
-      for (int kk = 0; kk < kn; ++kk) sacc += At[r][kk] * Bt[kk][cc];
+#pragma unroll 8
+      for (int kk = 0; kk < 32; ++kk) sacc += At[r][kk] * Bt[kk][cc];
       acc[q] = sacc;
     }
     __syncthreads();
@@ -896,7 +992,7 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_red(const GemmJob* __restrict__ 
   __shared__ int lastf;
   const int tid = threadIdx.x;
   const GemmRed it = items[first + blockIdx.x];
-  const GemmJob& J = jobs[it.job];
+  const GemmJob J = jobs[it.job];
   const int M = J.Md ? *J.Md : J.M, N = J.Nd ? *J.Nd : J.N;
   if (M == 0 || N == 0) return;
   const int nout = M * N;
@@ -917,7 +1013,8 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_red(const GemmJob* __restrict__ 
       if (e < nout) {
         const int rr = e % M, cc = e / M;
         double sacc = acc[q];
-        for (int kk = 0; kk < kn; ++kk) sacc += At[kk][rr] * Bt[kk][cc];
+#pragma unroll 8
+        for (int kk = 0; kk < 32; ++kk) sacc += At[kk][rr] * Bt[kk][cc];
         acc[q] = sacc;
       }
     }
@@ -1019,15 +1116,23 @@ __device__ __forceinline__ void leaf_panel_body(const LeafJob& J, LeafWs W, int 
   // T of the panel: T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] (Y^T y_j)
   for (int e = tid; e < NB * NB; e += NT_TR) Tp[e] = 0.0;
   __syncthreads();
-  for (int j = 0; j < pw; ++j) {
-    const double tj = taus[j];
-    if (tid < j) {
+  {
+    // T[0:j, j] = -tau_j T[0:j, 0:j] gram[0:j, j]: thread (i, l-pair) and a
+    // 16-lane reduction per row, one barrier per column
+    const int ti = tid >> 4, tl = tid & 15;
+    for (int j = 0; j < pw; ++j) {
+      const double tj = taus[j];
       double s = 0.0;
-      for (int l = tid; l < j; ++l) s += Tp[tid + l * NB] * gram[l + j * NB];
-      Tp[tid + j * NB] = -tj * s;
+      if (ti < j) {
+        const int l0 = tl, l1 = tl + 16;
+        if (l0 >= ti && l0 < j) s += Tp[ti + l0 * NB] * gram[l0 + j * NB];
+        if (l1 >= ti && l1 < j) s += Tp[ti + l1 * NB] * gram[l1 + j * NB];
+      }
+      s = gsumt<16>(s);
+      if (ti < j && tl == 0) Tp[ti + j * NB] = -tj * s;
+      if (tid == 0) Tp[j + j * NB] = tj;
+      __syncthreads();
     }
-    if (tid == j) Tp[j + j * NB] = tj;
-    __syncthreads();
   }
   for (int e = tid; e < NB * NB; e += NT_TR) {
     const int i = e % NB, j = e / NB;
@@ -1099,7 +1204,8 @@ __global__ void __launch_bounds__(NT_MM) k_leaf_update(const LeafJob* __restrict
       for (int q = 0; q < 4; ++q) {
         const int cc = cg + 8 * q;
         double sacc = acc[q];
-        for (int rr = 0; rr < rn; ++rr) sacc += Yt[rr][jj] * Bt[rr][cc];
+#pragma unroll 16
+        for (int rr = 0; rr < 64; ++rr) sacc += Yt[rr][jj] * Bt[rr][cc];
         acc[q] = sacc;
       }
       __syncthreads();
@@ -1116,7 +1222,8 @@ __global__ void __launch_bounds__(NT_MM) k_leaf_update(const LeafJob* __restrict
     for (int q = 0; q < 4; ++q) {
       const int cc = cg + 8 * q;
       double sacc = 0.0;
-      for (int l = 0; l <= jj; ++l) sacc += Tt[l][jj] * Wt[l][cc];
+#pragma unroll 8
+      for (int l = 0; l < 32; ++l) sacc += Tt[l][jj] * Wt[l][cc];
       acc[q] = sacc;
     }
     __syncthreads();
@@ -1156,7 +1263,8 @@ __global__ void __launch_bounds__(NT_MM) k_leaf_update(const LeafJob* __restrict
       for (int q = 0; q < 4; ++q) {
         const int cc = cg + 8 * q;
         double sacc = acc[q];
-        for (int rr = 0; rr < rn; ++rr) sacc += Yt[rr][jj] * Bt[rr][cc];
+#pragma unroll 16
+        for (int rr = 0; rr < 64; ++rr) sacc += Yt[rr][jj] * Bt[rr][cc];
         acc[q] = sacc;
       }
       __syncthreads();
@@ -1254,6 +1362,16 @@ __global__ void __launch_bounds__(1024) k_normalize(const double* z, double* x, 
     for (int64_t i = threadIdx.x; i < n; i += 1024) x[i] = z[i] * inv;
   }
   if (threadIdx.x == 0 && out != nullptr) out[0] = nrm;
+}
+
+// thresholds of one factorisation: scal = [|A|_2, eps*|A|_2, eps]
+__global__ void k_set_scal(double* scal, double eps, double anorm) {
+  if (threadIdx.x == 0) {
+    const double a = anorm > 0.0 ? anorm : scal[0];
+    scal[0] = a;
+    scal[1] = eps * a;
+    scal[2] = eps;
+  }
 }
 
 __global__ void k_fill(double* x, int64_t n, double v) {
