@@ -15,7 +15,8 @@ constexpr int SMAX = 64;       // widest tall-skinny operand of a HODLR product
 constexpr int KCAP = 64;       // largest rank capacity of a stored block
 constexpr int NT_TR = 512;     // threads of the recompression kernels
 constexpr int NT_MM = 256;     // threads of the product / GEMM / leaf kernels
-constexpr int NB = 32;         // leaf QR panel width
+constexpr int NB = 16;         // leaf QR panel width (one wavefront per column)
+constexpr int NT_LEAF = 1024;  // threads of the leaf QR kernels (16 wavefronts)
 constexpr int MAXLEAF = 512;   // largest leaf order
 constexpr int MAXSTACK = 1024; // largest stacked leaf column (leaf + group rows)
 constexpr int MAXGROUPS = 24;

@@ -489,8 +489,8 @@ hodlr_status set_attrs() {
     HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TR_QR_LDS));
   HIPCHK(hipFuncSetAttribute((const void*)k_tr_form, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)TR_FORM_LDS));
-  HIPCHK(hipFuncSetAttribute((const void*)k_leaf_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)LEAF_PANEL_LDS));
+  HIPCHK(hipFuncSetAttribute((const void*)k_leaf_step, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)LEAF_LDS));
   g_attr_done = true;
   return HODLR_OK;
 }
@@ -525,10 +525,8 @@ void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st) {
       k_leaf_gather<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, W.err);
       break;
     case OP_LPANEL:
-      k_leaf_panel<<<1, NT_TR, LEAF_PANEL_LDS, st>>>(P.d_lj, o.a0, W.leaf, o.a1, W.err);
-      break;
     case OP_LUPDATE:
-      k_leaf_update<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, o.a1, W.err);
+      k_leaf_step<<<o.count, NT_LEAF, LEAF_LDS, st>>>(P.d_lj, o.a0, W.leaf, o.a1, W.err);
       break;
     case OP_LSCATTER:
       k_leaf_scatter<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, W.err, W.fc);
@@ -676,8 +674,8 @@ struct QRBuilder {
     P.lj.push_back(J);
     const int m = J.m, np = (m + NB - 1) / NB;
     P.ops.push_back(Op{OP_LGATHER, 0, m, jid});
+    P.ops.push_back(Op{OP_LPANEL, 0, 1, jid, -1});  // panel 0
     for (int p = 0; p <= np; ++p) {
-      if (p < np) P.ops.push_back(Op{OP_LPANEL, 0, 1, jid, p});
       const int nstrip = p < np ? np - p - 1 : 0, ngram = p < np ? p : 0, ntile = p >= 1 ? p - 1 : 0;
       const int cnt = nstrip + ngram + ntile;
       if (cnt > 0) P.ops.push_back(Op{OP_LUPDATE, 0, cnt, jid, p});

@@ -51,9 +51,54 @@ __device__ __forceinline__ double gsumt(double x) {
   if constexpr (W >= 4) x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1]
   if constexpr (W >= 8) x += dpp_mov<0x141>(x);  // row_half_mirror
   if constexpr (W >= 16) x += dpp_mov<0x140>(x); // row_mirror
-  if constexpr (W >= 32) x += swz_xor16(x);
-  if constexpr (W >= 64) x = lane_read(x, 0) + lane_read(x, 32);
+  if constexpr (W == 32) {
+    const double r0 = lane_read(x, 0), r1 = lane_read(x, 16), r2 = lane_read(x, 32), r3 = lane_read(x, 48);
+    x = ((int)(__lane_id()) < 32) ? r0 + r1 : r2 + r3;
+  }
+  if constexpr (W >= 64) x = (lane_read(x, 0) + lane_read(x, 16)) + (lane_read(x, 32) + lane_read(x, 48));
   return x;
+}
+
+// 1/x and sqrt(x) from the hardware estimates refined by Newton steps (a few
+// ulp), much shorter dependency chains than the correctly rounded sequences.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ __forceinline__ double sqrt_nr(double x) {  // x > 0
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  const double sq = x * y;
+  return fma(0.5 * y, fma(-sq, sq, x), sq);
+}
+
+// Householder reflector of x = [alpha; x2] from alpha and ss = |x2|^2:
+// beta = -sign(alpha) |x|, tau = (beta - alpha)/beta, scal = 1/(alpha - beta).
+__device__ __forceinline__ void house_scalars(double al, double ss, double& beta, double& tau,
+                                              double& scal) {
+  if (ss == 0.0) {
+    beta = al;
+    tau = 0.0;
+    scal = 0.0;
+    return;
+  }
+  const double nrm = sqrt_nr(al * al + ss);
+  beta = (al >= 0.0) ? -nrm : nrm;
+  const double d = beta - al;  // never 0: |beta| >= |alpha| and opposite sign
+  tau = d * rcp_nr(beta);
+  scal = -rcp_nr(d);
+}
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+// D += A B for A 16x4, B 4x16 (FP64 MFMA).  Lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; D[i][j] lives in lane j + 16*(i%4), element i/4.
+__device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ double gsum(double x, int width) {
@@ -110,13 +155,8 @@ __device__ __forceinline__ void reg_qr(double (&a)[RPT], int c, int sub, int h, 
       }
       ss = gsumt<TPC>(ss);
       al = gsumt<TPC>(al);
-      double tau = 0.0, beta = al, scal = 0.0;
-      if (ss != 0.0) {
-        const double nrm = sqrt(al * al + ss);
-        beta = (al >= 0.0) ? -nrm : nrm;
-        tau = (beta - al) / beta;
-        scal = 1.0 / (al - beta);
-      }
+      double tau, beta, scal;
+      house_scalars(al, ss, beta, tau, scal);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         const int r = sub + TPC * i;
@@ -1062,6 +1102,14 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_red(const GemmJob* __restrict__ 
 }
 
 // ------------------------------------------------------------------ leaf QR
+// Blocked right-looking Householder QR of the stacked leaf column H (M x m,
+// ld MAXSTACK) with its compact WY factor T, in 16-column panels.  A panel is
+// factorised by one 1024-thread block, one wavefront per column, so every
+// column reduction stays inside a wavefront.  Launch p (the "step") updates the
+// trailing strips with panel p's reflectors; its first block updates panel
+// p+1's columns and then factorises panel p+1 (look-ahead), while other blocks
+// form the Gram blocks Y_i^T Y_p and the T block of panel p-1:
+//   T[0:c_q, q] = -T[0:c_q, 0:c_q] (Y_{0:c_q}^T Y_q) T_qq     (eq. recqrcombined)
 __device__ __forceinline__ int leaf_rows(const LeafJob& J) {
   int M = J.m;
   for (int g = 0; g < J.ngroups; ++g) M += *J.g[g].rank;
@@ -1078,244 +1126,340 @@ __global__ void __launch_bounds__(NT_MM) k_leaf_gather(const LeafJob* __restrict
     if (c == 0 && threadIdx.x == 0) atomicOr(err, ERR_STACK);
     return;
   }
+  const int m = J.m;
   double* h = W.H + (int64_t)c * MAXSTACK;
-  for (int r = threadIdx.x; r < J.m; r += NT_MM) h[r] = J.D[r + (int64_t)c * J.m];
-  int off = J.m;
+  for (int r = threadIdx.x; r < m; r += NT_MM) h[r] = J.D[r + (int64_t)c * m];
+  int off = m;
   for (int g = 0; g < J.ngroups; ++g) {
     const int k = *J.g[g].rank;
     const double* V = J.g[g].V + J.g[g].row0 + c;
-    for (int t = threadIdx.x; t < k; t += NT_MM) h[off + t] = V[(int64_t)t * J.g[g].ld];
+    const int ld = J.g[g].ld;
+    for (int t = threadIdx.x; t < k; t += NT_MM) h[off + t] = V[(int64_t)t * ld];
     off += k;
   }
 }
 
+// LDS layout of the leaf kernels (doubles)
+constexpr int LF_VBUF = 0;                       // 2 x MAXSTACK reflector broadcast
+constexpr int LF_TAU = 2 * MAXSTACK;             // NB
+constexpr int LF_GRAM = LF_TAU + NB;             // NB x NB
+constexpr int LF_TP = LF_GRAM + NB * NB;         // NB x NB
+constexpr int LF_CH = 320;                       // rows per staged strip chunk
+constexpr int LF_LD = LF_CH + 4;                 // leading dimension of staged strips
+constexpr int LF_A = LF_TP + NB * NB;            // staged Y_p and strip: 2 x LF_LD x NB
+constexpr int LF_PART = LF_A + 2 * LF_LD * NB;   // 16 wave partial tiles (16 x 256)
+constexpr int LF_W = LF_PART + 16 * NB * NB;     // 3 tiles of NB x NB
+constexpr int LF_TOTAL = LF_W + 3 * NB * NB;
+constexpr size_t LEAF_LDS = sizeof(double) * (size_t)LF_TOTAL;
+
+// Unblocked Householder QR of panel columns [c0, c0+pw) over rows [c0, M):
+// wavefront w owns column c0 + w, lane l owns rows c0 + l + 64 t.
 template <int RPT>
-__device__ __forceinline__ void leaf_panel_body(const LeafJob& J, LeafWs W, int p, int M, double* smem) {
-  constexpr int TPC = NT_TR / NB;  // 32 columns x 16 threads
-  const int tid = threadIdx.x, c = tid / TPC, sub = tid % TPC;
-  const int c0 = p * NB;
-  const int pw = min(NB, J.m - c0);
+__device__ __forceinline__ void leaf_panel_rows(LeafWs W, int c0, int pw, int M, double* sm) {
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int h = M - c0;
-  double* vbuf = smem;                      // 2 * TPC*RPT
-  double* taus = vbuf + 2 * TPC * RPT;      // NB
-  double* gram = taus + NB;                 // NB x NB
-  double* Tp = gram + NB * NB;              // NB x NB
+  double* taus = sm + LF_TAU;
+  double* gram = sm + LF_GRAM;
+  double* Tp = sm + LF_TP;
+  double* col = W.H + (int64_t)(c0 + w) * MAXSTACK + c0;
   double a[RPT];
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int r = sub + TPC * i;
-    a[i] = (r < h && c < pw) ? W.H[(int64_t)(c0 + r) + (int64_t)(c0 + c) * MAXSTACK] : 0.0;
+  for (int t = 0; t < RPT; ++t) {
+    const int r = lane + 64 * t;
+    a[t] = (w < pw && r < h) ? col[r] : 0.0;
   }
-  reg_qr<TPC, RPT>(a, c, sub, h, pw, vbuf, taus, gram, NB);
+  for (int j = 0; j < pw; ++j) {
+    double* vb = sm + LF_VBUF + (j & 1) * MAXSTACK;
+    if (w == j) {
+      double ss0 = 0.0, ss1 = 0.0;
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int r = sub + TPC * i;
-    if (r < h && c < pw) W.H[(int64_t)(c0 + r) + (int64_t)(c0 + c) * MAXSTACK] = a[i];
+      for (int t = 0; t < RPT; ++t) {
+        const int r = lane + 64 * t;
+        const double x = (r > j) ? a[t] : 0.0;
+        if (t & 1) ss1 += x * x; else ss0 += x * x;
+      }
+      const double ss = gsumt<64>(ss0 + ss1);
+      const double al = lane_read(a[0], j);  // row j < 16 sits in t = 0
+      double tau, beta, scal;
+      house_scalars(al, ss, beta, tau, scal);
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int r = lane + 64 * t;
+        double v;
+        if (r > j) {
+          if (ss != 0.0) a[t] *= scal;
+          v = a[t];
+        } else if (r == j) {
+          a[t] = beta;
+          v = 1.0;
+        } else {
+          v = 0.0;
+        }
+        vb[r] = v;
+      }
+      if (lane == 0) taus[j] = tau;
+    }
+    __syncthreads();
+    const double tau = taus[j];
+    if (w > j && w < pw) {
+      if (tau != 0.0) {
+        double v[RPT];
+        double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          v[t] = vb[lane + 64 * t];
+          if (t & 1) d1 += v[t] * a[t]; else d0 += v[t] * a[t];
+        }
+        const double f = tau * gsumt<64>(d0 + d1);
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) a[t] -= f * v[t];
+      }
+    } else if (w < j) {
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const double x = vb[lane + 64 * t] * a[t];
+        if (t & 1) d1 += x; else d0 += x;
+      }
+      const double d = gsumt<64>(d0 + d1);
+      if (lane == 0) gram[w + j * NB] = d;
+    }
   }
-  __syncthreads();
-  // T of the panel: T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] (Y^T y_j)
-  for (int e = tid; e < NB * NB; e += NT_TR) Tp[e] = 0.0;
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int r = lane + 64 * t;
+    if (w < pw && r < h) col[r] = a[t];
+  }
+  // T of the panel: T[0:j, j] = -tau_j T[0:j, 0:j] gram[0:j, j], T[j, j] = tau_j
+  for (int e = tid; e < NB * NB; e += NT_LEAF) Tp[e] = 0.0;
   __syncthreads();
   {
-    // T[0:j, j] = -tau_j T[0:j, 0:j] gram[0:j, j]: thread (i, l-pair) and a
-    // 16-lane reduction per row, one barrier per column
-    const int ti = tid >> 4, tl = tid & 15;
+    const int ti = (tid >> 4) & 15, tl = tid & 15;
     for (int j = 0; j < pw; ++j) {
-      const double tj = taus[j];
-      double s = 0.0;
-      if (ti < j) {
-        const int l0 = tl, l1 = tl + 16;
-        if (l0 >= ti && l0 < j) s += Tp[ti + l0 * NB] * gram[l0 + j * NB];
-        if (l1 >= ti && l1 < j) s += Tp[ti + l1 * NB] * gram[l1 + j * NB];
+      if (tid < 256) {
+        double sacc = 0.0;
+        if (ti < j && tl >= ti && tl < j) sacc = Tp[ti + tl * NB] * gram[tl + j * NB];
+        sacc = gsumt<16>(sacc);
+        if (ti < j && tl == 0) Tp[ti + j * NB] = -taus[j] * sacc;
+        if (tid == 0) Tp[j + j * NB] = taus[j];
       }
-      s = gsumt<16>(s);
-      if (ti < j && tl == 0) Tp[ti + j * NB] = -tj * s;
-      if (tid == 0) Tp[j + j * NB] = tj;
       __syncthreads();
     }
   }
-  for (int e = tid; e < NB * NB; e += NT_TR) {
+  for (int e = tid; e < NB * NB; e += NT_LEAF) {
     const int i = e % NB, j = e / NB;
     if (i < pw && j < pw) W.T[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] = Tp[e];
   }
 }
 
-constexpr size_t LEAF_PANEL_LDS = sizeof(double) * (2 * MAXSTACK + NB + 2 * NB * NB);
-
-__global__ void __launch_bounds__(NT_TR) k_leaf_panel(const LeafJob* __restrict__ jobs, int jidx,
-                                                       LeafWs W, int p, const int* err) {
-  extern __shared__ double smem[];
-  if (*err & ERR_STACK) return;
-  const LeafJob& J = jobs[jidx];
-  const int M = leaf_rows(J);
-  const int h = M - p * NB;
+__device__ __forceinline__ void leaf_panel(LeafWs W, int c0, int pw, int M, double* sm) {
+  const int h = M - c0;
   if (h <= 320)
-    leaf_panel_body<20>(J, W, p, M, smem);
-  else if (h <= 512)
-    leaf_panel_body<32>(J, W, p, M, smem);
-  else if (h <= 768)
-    leaf_panel_body<48>(J, W, p, M, smem);
+    leaf_panel_rows<5>(W, c0, pw, M, sm);
+  else if (h <= 576)
+    leaf_panel_rows<9>(W, c0, pw, M, sm);
   else
-    leaf_panel_body<64>(J, W, p, M, smem);
+    leaf_panel_rows<16>(W, c0, pw, M, sm);
 }
 
-// Y_p(r, j) for rows r >= c0 (unit lower trapezoidal panel of H)
+// Y_p(r, j), panel p starting at column/row c0, for rows r >= c0
 __device__ __forceinline__ double leaf_y(const LeafWs& W, int c0, int r, int j) {
   const int rr = r - c0;
   return rr < j ? 0.0 : (rr == j ? 1.0 : W.H[(int64_t)r + (int64_t)(c0 + j) * MAXSTACK]);
 }
 
-// After panel p: (a) trailing strips  A_s -= Y_p T_p^T (Y_p^T A_s),
-// (b) Gram tiles G[i-block, p-block] = Y_i^T Y_p (i < p),
-// (c) T block of panel q = p-1:  T[0:32q, q] = -T[0:32q, 0:32q] G[0:32q, q] T_qq
-// (eq. recqrcombined, one row tile per block).
-__global__ void __launch_bounds__(NT_MM) k_leaf_update(const LeafJob* __restrict__ jobs, int jidx,
+// Stage rows [r0, r0 + rn) of Y_p (unit lower panel at c0) and of the B
+// columns [cb, cb + bw) (unmasked) into LDS, zero-padded to LF_CH rows.
+__device__ __forceinline__ void leaf_stage(const LeafWs& W, int c0, int pw, int r0, int rn, int cb,
+                                           int bw, double* Ys, double* Bs) {
+  for (int e = threadIdx.x; e < LF_CH * NB; e += NT_LEAF) {
+    const int rr = e % LF_CH, jj = e / LF_CH;
+    const int r = r0 + rr;
+    double y = 0.0, bv = 0.0;
+    if (rr < rn) {
+      if (jj < pw) y = leaf_y(W, c0, r, jj);
+      if (jj < bw) bv = W.H[(int64_t)r + (int64_t)(cb + jj) * MAXSTACK];
+    }
+    Ys[rr + jj * LF_LD] = y;
+    Bs[rr + jj * LF_LD] = bv;
+  }
+}
+
+// acc += (Y^T B) over the staged rows: wavefront w takes 4-row steps w, w+16, ...
+__device__ __forceinline__ d4_t leaf_ytb_acc(const double* Ys, const double* Bs, int rn, d4_t acc) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int nk = (rn + 3) >> 2;
+  for (int ks = w; ks < nk; ks += 16) {
+    const int r = 4 * ks + (l >> 4);
+    acc = mfma16(Ys[r + (l & 15) * LF_LD], Bs[r + (l & 15) * LF_LD], acc);
+  }
+  return acc;
+}
+
+// Sum the 16 wavefronts' 16 x 16 tiles into out (ld NB).
+__device__ __forceinline__ void leaf_reduce_tile(d4_t acc, double* part, double* out) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = 4 * e + (l >> 4), j = l & 15;
+    part[w * 256 + i + NB * j] = acc[e];
+  }
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    double sacc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sacc += part[q * 256 + threadIdx.x];
+    out[threadIdx.x] = sacc;
+  }
+  __syncthreads();
+}
+
+// S = Y_p^T B over rows [c0, M) into sm[LF_W] (16 x 16, ld NB).
+__device__ __forceinline__ void leaf_ytb(const LeafWs& W, int c0, int pw, int M, int cb, int bw,
+                                         double* sm) {
+  double* Ys = sm + LF_A;
+  double* Bs = Ys + LF_LD * NB;
+  d4_t acc = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = c0; r0 < M; r0 += LF_CH) {
+    const int rn = min(LF_CH, M - r0);
+    leaf_stage(W, c0, pw, r0, rn, cb, bw, Ys, Bs);
+    __syncthreads();
+    acc = leaf_ytb_acc(Ys, Bs, rn, acc);
+    __syncthreads();
+  }
+  leaf_reduce_tile(acc, sm + LF_PART, sm + LF_W);
+}
+
+// Strip [cs, cs+sw) -= Y_p T_pp^T (Y_p^T strip)  (the block reflector of panel p),
+// all three products on FP64 MFMA.
+__device__ __forceinline__ void leaf_strip(const LeafWs& W, int c0, int pw, int M, int cs, int sw,
+                                           double* sm) {
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  double* Ys = sm + LF_A;
+  double* Bs = Ys + LF_LD * NB;
+  double* Wt = sm + LF_W;
+  double* W2 = Wt + NB * NB;
+  double* Tt = W2 + NB * NB;
+  if (tid < 256) {
+    const int i = tid & 15, j = tid >> 4;
+    Tt[tid] = (i <= j && i < pw && j < pw) ? W.T[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] : 0.0;
+  }
+  d4_t acc = {0.0, 0.0, 0.0, 0.0};
+  const bool one_chunk = (M - c0) <= LF_CH;
+  for (int r0 = c0; r0 < M; r0 += LF_CH) {
+    const int rn = min(LF_CH, M - r0);
+    leaf_stage(W, c0, pw, r0, rn, cs, sw, Ys, Bs);
+    __syncthreads();
+    acc = leaf_ytb_acc(Ys, Bs, rn, acc);
+    __syncthreads();
+  }
+  leaf_reduce_tile(acc, sm + LF_PART, Wt);
+  if (tid < 256) {  // W2 = T^T W
+    const int i = tid & 15, j = tid >> 4;
+    double sacc = 0.0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) sacc += Tt[q + NB * i] * Wt[q + NB * j];
+    W2[i + NB * j] = sacc;
+  }
+  __syncthreads();
+  for (int r0 = c0; r0 < M; r0 += LF_CH) {
+    const int rn = min(LF_CH, M - r0);
+    if (!one_chunk) {
+      leaf_stage(W, c0, pw, r0, rn, cs, sw, Ys, Bs);
+      __syncthreads();
+    }
+    const int nt = (rn + 15) >> 4;
+    for (int t = w; t < nt; t += 16) {
+      d4_t d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k0 = 0; k0 < NB; k0 += 4)
+        d = mfma16(Ys[(16 * t + (l & 15)) + (k0 + (l >> 4)) * LF_LD], W2[(k0 + (l >> 4)) + NB * (l & 15)], d);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = 16 * t + 4 * e + (l >> 4);
+        Bs[row + (l & 15) * LF_LD] -= d[e];
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < LF_CH * NB; e += NT_LEAF) {
+      const int rr = e % LF_CH, jj = e / LF_CH;
+      if (rr < rn && jj < sw) W.H[(int64_t)(r0 + rr) + (int64_t)(cs + jj) * MAXSTACK] = Bs[rr + jj * LF_LD];
+    }
+    __syncthreads();
+  }
+}
+
+constexpr size_t LEAF_PANEL_LDS = LEAF_LDS;
+
+// One step of the blocked leaf QR (see the section comment).  p = -1 only
+// factorises panel 0; p = np only forms the last T block.
+__global__ void __launch_bounds__(NT_LEAF) k_leaf_step(const LeafJob* __restrict__ jobs, int jidx,
                                                         LeafWs W, int p, const int* err) {
-  __shared__ double Yt[64][33];
-  __shared__ double Bt[64][33];
-  __shared__ double Wt[32][33];
-  __shared__ double Tt[32][33];
+  extern __shared__ double sm[];
   if (*err & ERR_STACK) return;
   const LeafJob& J = jobs[jidx];
   const int tid = threadIdx.x;
   const int m = J.m;
   const int np = (m + NB - 1) / NB;
   const int M = leaf_rows(J);
-  const int c0 = p * NB;
+  if (p < 0) {
+    leaf_panel(W, 0, min(NB, m), M, sm);
+    return;
+  }
+  const int c0 = p * NB, pw = min(NB, m - c0);
   const int nstrip = (p < np) ? np - p - 1 : 0;
   const int ngram = (p < np) ? p : 0;
   int b = blockIdx.x;
   if (b < nstrip) {
-    // ---- (a) trailing strip s
     const int s = p + 1 + b;
     const int cs = s * NB, sw = min(NB, m - cs);
-    const int pw = min(NB, m - c0);
-    const int jj = tid % 32, cg = tid / 32;  // W[jj][cg + 8q]
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int r0 = c0; r0 < M; r0 += 64) {
-      const int rn = min(64, M - r0);
-      for (int e = tid; e < 64 * 32; e += NT_MM) {
-        const int rr = e % 64, j = e / 64;
-        Yt[rr][j] = (rr < rn && j < pw) ? leaf_y(W, c0, r0 + rr, j) : 0.0;
-        Bt[rr][j] = (rr < rn && j < sw) ? W.H[(int64_t)(r0 + rr) + (int64_t)(cs + j) * MAXSTACK] : 0.0;
-      }
+    leaf_strip(W, c0, pw, M, cs, sw, sm);
+    if (b == 0) {  // look-ahead: the next panel is ready, factorise it
+      __threadfence_block();
       __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int cc = cg + 8 * q;
-        double sacc = acc[q];
-#pragma unroll 16
-        for (int rr = 0; rr < 64; ++rr) sacc += Yt[rr][jj] * Bt[rr][cc];
-        acc[q] = sacc;
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) Wt[jj][cg + 8 * q] = acc[q];
-    for (int e = tid; e < 32 * 32; e += NT_MM) {
-      const int i = e % 32, j = e / 32;
-      Tt[i][j] = (i < pw && j < pw) ? W.T[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] : 0.0;
-    }
-    __syncthreads();
-    // W <- T^T W
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int cc = cg + 8 * q;
-      double sacc = 0.0;
-#pragma unroll 8
-      for (int l = 0; l < 32; ++l) sacc += Tt[l][jj] * Wt[l][cc];
-      acc[q] = sacc;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) Wt[jj][cg + 8 * q] = acc[q];
-    __syncthreads();
-    // A_s -= Y W
-    for (int r = c0 + tid; r < M; r += NT_MM) {
-      double y[NB];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) y[j] = (j < pw) ? leaf_y(W, c0, r, j) : 0.0;
-      for (int cc = 0; cc < sw; ++cc) {
-        double sacc = 0.0;
-#pragma unroll
-        for (int j = 0; j < NB; ++j) sacc += y[j] * Wt[j][cc];
-        W.H[(int64_t)r + (int64_t)(cs + cc) * MAXSTACK] -= sacc;
-      }
+      leaf_panel(W, cs, sw, M, sm);
     }
     return;
   }
   b -= nstrip;
   if (b < ngram) {
-    // ---- (b) G[32b : 32b+32, c0 : c0+pw] = Y_b^T Y_p over rows >= c0
-    const int i0 = b * NB;
-    const int pw = min(NB, m - c0);
-    const int jj = tid % 32, cg = tid / 32;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int r0 = c0; r0 < M; r0 += 64) {
-      const int rn = min(64, M - r0);
-      for (int e = tid; e < 64 * 32; e += NT_MM) {
-        const int rr = e % 64, j = e / 64;
-        Yt[rr][j] = (rr < rn) ? W.H[(int64_t)(r0 + rr) + (int64_t)(i0 + j) * MAXSTACK] : 0.0;
-        Bt[rr][j] = (rr < rn && j < pw) ? leaf_y(W, c0, r0 + rr, j) : 0.0;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int cc = cg + 8 * q;
-        double sacc = acc[q];
-#pragma unroll 16
-        for (int rr = 0; rr < 64; ++rr) sacc += Yt[rr][jj] * Bt[rr][cc];
-        acc[q] = sacc;
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int cc = cg + 8 * q;
-      if (cc < pw) W.G[(int64_t)(i0 + jj) + (int64_t)(c0 + cc) * MAXLEAF] = acc[q];
+    // G[16b : 16b+16, c0 : c0+pw] = Y_b^T Y_p over rows >= c0 (Y_b has no mask there)
+    leaf_ytb(W, c0, pw, M, b * NB, NB, sm);
+    // leaf_ytb computed Y_p^T Y_b; store its transpose
+    if (tid < 256) {
+      const int i = tid & 15, j = tid >> 4;  // (Y_p^T Y_b)[i][j] = G[b*16 + j][c0 + i]
+      if (i < pw) W.G[(int64_t)(b * NB + j) + (int64_t)(c0 + i) * MAXLEAF] = sm[LF_W + i + j * NB];
     }
     return;
   }
   b -= ngram;
-  // ---- (c) T block of panel q = p - 1, row tile b
+  // T block of panel q = p - 1, row tile b: T[16b : 16b+16, cq : cq+qw]
   const int q = p - 1;
   const int cq = q * NB, qw = min(NB, m - cq);
   const int i0 = b * NB;
-  const int ii = tid % 32, cg = tid / 32;
-  // X = T[i0:i0+32, i0:cq] G[i0:cq, cq:cq+qw]
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int l0 = i0; l0 < cq; l0 += 32) {
-    for (int e = tid; e < 32 * 32; e += NT_MM) {
-      const int a = e % 32, l = e / 32;
-      Yt[a][l] = (l0 + l >= i0 + a) ? W.T[(int64_t)(i0 + a) + (int64_t)(l0 + l) * MAXLEAF] : 0.0;
-      Bt[l][a] = (a < qw) ? W.G[(int64_t)(l0 + l) + (int64_t)(cq + a) * MAXLEAF] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int cc = cg + 8 * t;
-      double sacc = acc[t];
-      for (int l = 0; l < 32; ++l) sacc += Yt[ii][l] * Bt[l][cc];
-      acc[t] = sacc;
-    }
-    __syncthreads();
+  const int w = tid >> 6, l = tid & 63;
+  double* X = sm + LF_W;
+  double* Tq = X + NB * NB;
+  if (tid < 256) {
+    const int i = tid & 15, j = tid >> 4;
+    Tq[tid] = (i <= j && i < qw && j < qw) ? W.T[(int64_t)(cq + i) + (int64_t)(cq + j) * MAXLEAF] : 0.0;
   }
-#pragma unroll
-  for (int t = 0; t < 4; ++t) Wt[ii][cg + 8 * t] = acc[t];
-  for (int e = tid; e < 32 * 32; e += NT_MM) {
-    const int i = e % 32, j = e / 32;
-    Tt[i][j] = (i < qw && j < qw) ? W.T[(int64_t)(cq + i) + (int64_t)(cq + j) * MAXLEAF] : 0.0;
+  // X = T[i0:i0+16, i0:cq] G[i0:cq, cq:cq+16]  (T upper: zero left of its diagonal)
+  d4_t acc = {0.0, 0.0, 0.0, 0.0};
+  const int nk = (cq - i0) >> 2;
+  for (int ks = w; ks < nk; ks += 16) {
+    const int row = i0 + (l & 15), colT = i0 + 4 * ks + (l >> 4);
+    const double a = (colT >= row) ? W.T[(int64_t)row + (int64_t)colT * MAXLEAF] : 0.0;
+    const double g = W.G[(int64_t)(i0 + 4 * ks + (l >> 4)) + (int64_t)(cq + (l & 15)) * MAXLEAF];
+    acc = mfma16(a, g, acc);
   }
-  __syncthreads();
-  // T[i0 + ii, cq + cc] = - sum_l X[ii][l] T_qq[l][cc]
+  leaf_reduce_tile(acc, sm + LF_PART, X);
+  if (tid < 256) {
+    const int i = tid & 15, j = tid >> 4;
+    double sacc = 0.0;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int cc = cg + 8 * t;
-    if (cc < qw) {
-      double sacc = 0.0;
-      for (int l = 0; l <= cc; ++l) sacc += Wt[ii][l] * Tt[l][cc];
-      W.T[(int64_t)(i0 + ii) + (int64_t)(cq + cc) * MAXLEAF] = -sacc;
-    }
+    for (int q2 = 0; q2 < NB; ++q2) sacc += X[i + NB * q2] * Tq[q2 + NB * j];
+    if (j < qw) W.T[(int64_t)(i0 + i) + (int64_t)(cq + j) * MAXLEAF] = -sacc;
   }
 }
 
@@ -1335,12 +1479,13 @@ __global__ void __launch_bounds__(NT_MM) k_leaf_scatter(const LeafJob* __restric
   for (int g = 0; g < J.ngroups; ++g) {
     const int k = *J.g[g].rank;
     double* V = J.g[g].V + J.g[g].row0 + c;
-    for (int t = threadIdx.x; t < k; t += NT_MM) V[(int64_t)t * J.g[g].ld] = h[off + t];
+    const int ld = J.g[g].ld;
+    for (int t = threadIdx.x; t < k; t += NT_MM) V[(int64_t)t * ld] = h[off + t];
     off += k;
   }
   if (c == 0 && threadIdx.x == 0) {
-    const double M = off, n = m;
-    add_flops(fc, FC_LEAF, 2.0 * M * n * n - 2.0 / 3.0 * n * n * n + M * n * n - n * n * n / 3.0);
+    const double Mr = off, n = m;
+    add_flops(fc, FC_LEAF, 2.0 * Mr * n * n - 2.0 / 3.0 * n * n * n + Mr * n * n - n * n * n / 3.0);
   }
 }
 
