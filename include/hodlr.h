@@ -53,9 +53,14 @@ typedef enum {
   HODLR_ENOTBUILT = -6   /* the library was loaded without device code            */
 } hodlr_status;
 
-/* hodlr_qr flags */
-#define HODLR_QR_NO_GRAPH 1u  /* launch the schedule directly instead of replaying
-                                 a captured HIP graph                              */
+/* hodlr_qr / hodlr_qr_time flags.  By default the launches are issued directly,
+ * with the T-factor steps of every node (T~12 and T12, Alg. hQR) on a second
+ * stream beside the main chain, joined back into the caller's stream. */
+#define HODLR_QR_GRAPH 1u       /* capture the launch sequence once per call (per
+                                   handle for hodlr_qr_time) in its serial order
+                                   on one stream and replay it as a HIP graph     */
+#define HODLR_QR_ONE_STREAM 2u  /* direct launches, all on the caller's stream in
+                                   the serial order                                */
 
 /*
  * hodlr_build - copy a HODLR matrix to the device.
@@ -95,7 +100,8 @@ hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t *leaf_off,
  *  anorm  |A|_2 used for the threshold; if anorm <= 0 it is estimated on the
  *         device, as the first step of the factorisation's launch sequence, by
  *         50 steps of power iteration on A^T A (see hodlr_norm2_est).
- *  flags  0 or HODLR_QR_NO_GRAPH.
+ *  flags  0, HODLR_QR_GRAPH or HODLR_QR_ONE_STREAM; every choice gives
+ *         bitwise identical factors.
  *  out    receives the factors (release with hodlr_qr_free).  A is not modified.
  * Returns HODLR_ECAPACITY if a rank outgrew rank_cap (or a recompression width
  * exceeded 128); the partial factors are then released.
@@ -183,8 +189,10 @@ hodlr_status hodlr_qr_time(const hodlr_t *A, double eps, double anorm, uint32_t 
                            int32_t warmup, int32_t reps, hodlr_stream_t stream, double *ms);
 
 /*
- * hodlr_qr_profile - diagnostic: run one factorisation launch by launch,
- * bracketing every launch with HIP events on `stream`, and accumulate per
+ * hodlr_qr_profile - diagnostic: run one factorisation launch by launch on
+ * `stream`, each launch issued through hipExtLaunchKernel with a pair of HIP
+ * events that the dispatch itself stamps at its start and end (so a duration
+ * excludes launch gaps and matches a kernel trace), and accumulate per
  * kernel type (index = type, names from hodlr_op_name, hodlr_op_count types):
  * ms[type] total duration, counts[type] launches, flops[type] algorithmic FP64
  * flops credited to that kernel type (same counting rules as hodlr_qr_info).

@@ -14,12 +14,12 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import HODLR_QR_NO_GRAPH, HodlrError, QRInfo
+from ._lib import HODLR_QR_GRAPH, HODLR_QR_ONE_STREAM, HodlrError, QRInfo
 
 __all__ = [
     "hodlr_build", "hodlr_qr", "hodlr_apply_q", "hodlr_solve", "hodlr_matmul", "hodlr_qr_matmul",
     "hodlr_norm2_est", "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time",
-    "hodlr_qr_profile", "HodlrMatrix", "QRFactors", "HodlrError", "colmajor", "HODLR_QR_NO_GRAPH", "load",
+    "hodlr_qr_profile", "HodlrMatrix", "QRFactors", "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "load",
 ]
 
 load = _lib.load

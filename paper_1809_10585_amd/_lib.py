@@ -13,7 +13,8 @@ LIB_PATH = os.path.join(HERE, "libhodlr.so")
 HODLR_OK = 0
 STATUS = {0: "HODLR_OK", -1: "HODLR_EINVAL", -2: "HODLR_ENOMEM", -3: "HODLR_ENONFINITE",
           -4: "HODLR_ECAPACITY", -5: "HODLR_EDEVICE", -6: "HODLR_ENOTBUILT"}
-HODLR_QR_NO_GRAPH = 1
+HODLR_QR_GRAPH = 1
+HODLR_QR_ONE_STREAM = 2
 
 # every symbol include/hodlr.h declares
 EXPORTS = [

@@ -14,12 +14,16 @@
 //  * T block v     : T12 = -T1 T~12 T2 in factored form.
 #include "kernels.hip"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <memory>
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "hodlr.h"
@@ -199,11 +203,14 @@ hodlr_status make_leaves(DMem& mem, const Tree& t, LeafSet& S) {
 // ------------------------------------------------------------------ schedule
 enum OpType {
   OP_TRQR, OP_TRFORM, OP_MMPROJ, OP_MMAPPLY, OP_GTALL, OP_GRED, OP_LGATHER, OP_LPANEL,
-  OP_LUPDATE, OP_LSCATTER, OP_FILL, OP_NORMALIZE, OP_TRSM, OP_SETSCAL, OP_NTYPES
+  OP_LUPDATE, OP_LSCATTER, OP_FILL, OP_NORMALIZE, OP_TRSM, OP_SETSCAL,
+  OP_SIGNAL,  // record event a0 on the op's lane (no kernel)
+  OP_WAIT,    // the op's lane waits for event a0 (no kernel)
+  OP_NTYPES
 };
 const char* const OP_NAMES[OP_NTYPES] = {
   "tr_qr", "tr_form", "mm_proj", "mm_apply", "gemm_tall", "gemm_red", "leaf_gather", "leaf_panel",
-  "leaf_update", "leaf_scatter", "fill", "normalize", "leaf_trsm", "set_scal"};
+  "leaf_update", "leaf_scatter", "fill", "normalize", "leaf_trsm", "set_scal", "signal", "wait"};
 
 struct Op {
   int type;
@@ -216,6 +223,7 @@ struct Op {
   int64_t n;
   double* pout;
   double d1;
+  int lane = 0;  // 0: main chain, 1: the T-factor chain (runs beside it)
 };
 
 struct TrSpec {
@@ -273,8 +281,31 @@ struct Plan {
   std::vector<GemmRed> gr;
   std::vector<LeafJob> lj;
   std::vector<Op> ops;
-  int64_t ws_need = 0;
-  int cnt_need = 1;
+  // Workspace and counters are reused by consecutive ops of one lane; the two
+  // lanes get disjoint regions because their ops may run at the same time.
+  int64_t ws_lane[2] = {0, 0};
+  int cnt_lane[2] = {1, 1};
+  int lane = 0;  // lane of the ops being added
+  int n_events = 0;
+  int64_t ws_need() const { return ws_lane[0] + ws_lane[1]; }
+  int cnt_need() const { return cnt_lane[0] + cnt_lane[1]; }
+  int64_t ws_off(int l) const { return l == 0 ? 0 : ws_lane[0]; }
+  int cnt_off(int l) const { return l == 0 ? 0 : cnt_lane[0]; }
+  void push(Op o) {
+    o.lane = lane;
+    ops.push_back(o);
+  }
+  int signal() {
+    Op o{OP_SIGNAL};
+    o.a0 = n_events++;
+    push(o);
+    return o.a0;
+  }
+  void wait(int ev) {
+    Op o{OP_WAIT};
+    o.a0 = ev;
+    push(o);
+  }
   int64_t n_trunc = 0;
   int wtop = WMAX;  // widest recompression this plan can produce
   // device copies
@@ -338,10 +369,10 @@ struct Plan {
         trf.push_back(TrForm{jid, 1, 0, r0, std::min(64, J.side[1].m - r0), 0});
       ++n_trunc;
     }
-    ops.push_back(Op{OP_TRQR, c_first, (int)trc.size() - c_first});
-    ops.push_back(Op{OP_TRFORM, f_first, (int)trf.size() - f_first});
-    ws_need = std::max(ws_need, off);
-    cnt_need = std::max(cnt_need, cnt);
+    push(Op{OP_TRQR, c_first, (int)trc.size() - c_first});
+    push(Op{OP_TRFORM, f_first, (int)trf.size() - f_first});
+    ws_lane[lane] = std::max(ws_lane[lane], off);
+    cnt_lane[lane] = std::max(cnt_lane[lane], cnt);
   }
 
   void mm(const Tree& t, const std::vector<MmSpec>& specs) {
@@ -390,10 +421,10 @@ struct Plan {
         for (int r0 = 0; r0 < m; r0 += 64) mma.push_back(MmApply{jid, j, r0, std::min(64, m - r0)});
       }
     }
-    if ((int)mmp.size() > p_first) ops.push_back(Op{OP_MMPROJ, p_first, (int)mmp.size() - p_first});
-    ops.push_back(Op{OP_MMAPPLY, a_first, (int)mma.size() - a_first});
-    ws_need = std::max(ws_need, off);
-    cnt_need = std::max(cnt_need, cnt);
+    if ((int)mmp.size() > p_first) push(Op{OP_MMPROJ, p_first, (int)mmp.size() - p_first});
+    push(Op{OP_MMAPPLY, a_first, (int)mma.size() - a_first});
+    ws_lane[lane] = std::max(ws_lane[lane], off);
+    cnt_lane[lane] = std::max(cnt_lane[lane], cnt);
   }
 
   void gemm_tall(const std::vector<GSpec>& specs) {
@@ -405,7 +436,7 @@ struct Plan {
       for (int r0 = 0; r0 < g.Mcap; r0 += 64)
         for (int c0 = 0; c0 < g.Ncap; c0 += 64) gt.push_back(GemmTile{jid, r0, c0});
     }
-    if ((int)gt.size() > t_first) ops.push_back(Op{OP_GTALL, t_first, (int)gt.size() - t_first});
+    if ((int)gt.size() > t_first) push(Op{OP_GTALL, t_first, (int)gt.size() - t_first});
   }
 
   void gemm_red(const std::vector<GSpec>& specs) {
@@ -424,9 +455,9 @@ struct Plan {
                              counter});
       if (nch > 1) off += (int64_t)nch * KCAP * KCAP;
     }
-    ops.push_back(Op{OP_GRED, r_first, (int)gr.size() - r_first});
-    ws_need = std::max(ws_need, off);
-    cnt_need = std::max(cnt_need, cnt);
+    push(Op{OP_GRED, r_first, (int)gr.size() - r_first});
+    ws_lane[lane] = std::max(ws_lane[lane], off);
+    cnt_lane[lane] = std::max(cnt_lane[lane], cnt);
   }
 
   hodlr_status upload_all(DMem& mem, hipStream_t st) {
@@ -495,60 +526,108 @@ hodlr_status set_attrs() {
   return HODLR_OK;
 }
 
-void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st) {
-  if (o.count <= 0 && o.type != OP_FILL && o.type != OP_NORMALIZE && o.type != OP_LPANEL &&
-      o.type != OP_SETSCAL)
+// Launch a kernel; with events set (diagnostic profiling) through hipExtLaunchKernel,
+// which stamps the two events at the dispatch's own start and end.
+struct Launch {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+template <typename... P, typename... A>
+void launch(const Launch& L, void (*kern)(P...), dim3 g, dim3 b, size_t sh, hipStream_t st, A&&... a) {
+  if (L.e0 == nullptr) {
+    kern<<<g, b, sh, st>>>(std::forward<A>(a)...);
     return;
+  }
+  std::tuple<std::decay_t<P>...> t(std::forward<A>(a)...);
+  void* args[sizeof...(P) + 1];
+  std::apply([&](auto&... x) {
+    int i = 0;
+    ((args[i++] = (void*)&x), ...);
+  }, t);
+  (void)hipExtLaunchKernel((const void*)kern, g, b, args, sh, st, L.e0, L.e1, 0);
+}
+
+bool op_launches(const Op& o) {
+  return o.count > 0 || o.type == OP_FILL || o.type == OP_NORMALIZE || o.type == OP_LPANEL ||
+         o.type == OP_SETSCAL;
+}
+
+void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st, const Launch& L = Launch()) {
+  if (!op_launches(o)) return;
+  double* ws = W.ws + P.ws_off(o.lane);
+  int* cnt = W.counters + P.cnt_off(o.lane);
   switch (o.type) {
     case OP_TRQR: {
       const int wt = P.wtop;
       auto kern = wt <= 16 ? k_tr_qr<16> : wt <= 32 ? k_tr_qr<32> : wt <= 64 ? k_tr_qr<64> : k_tr_qr<128>;
-      kern<<<o.count, NT_TR, TR_QR_LDS, st>>>(P.d_trj, P.d_trc, o.first, W.ws, W.counters, W.err, W.fc);
+      launch(L, kern, o.count, NT_TR, TR_QR_LDS, st, P.d_trj, P.d_trc, o.first, ws, cnt, W.err, W.fc);
       break;
     }
     case OP_TRFORM:
-      k_tr_form<<<o.count, NT_MM, TR_FORM_LDS, st>>>(P.d_trj, P.d_trf, o.first, W.ws);
+      launch(L, k_tr_form, o.count, NT_MM, TR_FORM_LDS, st, P.d_trj, P.d_trf, o.first, ws);
       break;
     case OP_MMPROJ:
-      k_mm_proj<<<o.count, NT_MM, 0, st>>>(P.d_mmj, P.d_mmp, o.first, W.ws, W.counters, W.fc);
+      launch(L, k_mm_proj, o.count, NT_MM, 0, st, P.d_mmj, P.d_mmp, o.first, ws, cnt, W.fc);
       break;
     case OP_MMAPPLY:
-      k_mm_apply<<<o.count, NT_MM, 0, st>>>(P.d_mmj, P.d_mma, o.first, W.ws, W.fc);
+      launch(L, k_mm_apply, o.count, NT_MM, 0, st, P.d_mmj, P.d_mma, o.first, ws, W.fc);
       break;
     case OP_GTALL:
-      k_gemm_tall<<<o.count, NT_MM, 0, st>>>(P.d_gj, P.d_gt, o.first, W.fc);
+      launch(L, k_gemm_tall, o.count, NT_MM, 0, st, P.d_gj, P.d_gt, o.first, W.fc);
       break;
     case OP_GRED:
-      k_gemm_red<<<o.count, NT_MM, 0, st>>>(P.d_gj, P.d_gr, o.first, W.ws, W.counters, W.fc);
+      launch(L, k_gemm_red, o.count, NT_MM, 0, st, P.d_gj, P.d_gr, o.first, ws, cnt, W.fc);
       break;
     case OP_LGATHER:
-      k_leaf_gather<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, W.err);
+      launch(L, k_leaf_gather, o.count, NT_MM, 0, st, P.d_lj, o.a0, W.leaf, W.err);
       break;
     case OP_LPANEL:
     case OP_LUPDATE:
-      k_leaf_step<<<o.count, NT_LEAF, LEAF_LDS, st>>>(P.d_lj, o.a0, W.leaf, o.a1, W.err);
+      launch(L, k_leaf_step, o.count, NT_LEAF, LEAF_LDS, st, P.d_lj, o.a0, W.leaf, o.a1, W.err, W.fc);
       break;
     case OP_LSCATTER:
-      k_leaf_scatter<<<o.count, NT_MM, 0, st>>>(P.d_lj, o.a0, W.leaf, W.err, W.fc);
+      launch(L, k_leaf_scatter, o.count, NT_MM, 0, st, P.d_lj, o.a0, W.leaf, W.err, W.fc);
       break;
     case OP_FILL:
-      k_fill<<<(unsigned)((o.n + 255) / 256), 256, 0, st>>>(o.p1, o.n, o.d0);
+      launch(L, k_fill, (unsigned)((o.n + 255) / 256), 256, 0, st, o.p1, o.n, o.d0);
       break;
     case OP_NORMALIZE:
-      k_normalize<<<1, 1024, 0, st>>>(o.p0, o.p1, o.n, o.pout);
+      launch(L, k_normalize, 1, 1024, 0, st, o.p0, o.p1, o.n, o.pout);
       break;
     case OP_SETSCAL:
-      k_set_scal<<<1, 64, 0, st>>>(o.p1, o.d0, o.d1);
+      launch(L, k_set_scal, 1, 64, 0, st, o.p1, o.d0, o.d1);
       break;
     case OP_TRSM:
-      k_leaf_trsm<<<o.count, NT_MM, 0, st>>>(o.p0, o.a0, o.a0, o.p1, (int)o.n, o.count);
+      launch(L, k_leaf_trsm, o.count, NT_MM, 0, st, o.p0, o.a0, o.a0, o.p1, (int)o.n, o.count);
       break;
   }
 }
 
-hodlr_status run_ops(const Plan& P, const Work& W, hipStream_t st) {
+// Issue a plan.  With `aux` set, lane-1 ops go to `aux`, forked from and joined
+// back into `st` with events ev[n_events] and ev[n_events + 1]; SIGNAL/WAIT ops
+// become event records and waits.  Without it every op runs on `st` in list
+// order, which is a valid serial order of the same work.
+hodlr_status run_ops(const Plan& P, const Work& W, hipStream_t st, hipStream_t aux = nullptr,
+                     const hipEvent_t* ev = nullptr) {
   TRY(set_attrs());
-  for (const Op& o : P.ops) run_op(P, W, o, st);
+  if (aux != nullptr) {
+    HIPCHK(hipEventRecord(ev[P.n_events], st));
+    HIPCHK(hipStreamWaitEvent(aux, ev[P.n_events], 0));
+  }
+  for (const Op& o : P.ops) {
+    hipStream_t s = (aux != nullptr && o.lane == 1) ? aux : st;
+    if (o.type == OP_SIGNAL) {
+      if (aux != nullptr) HIPCHK(hipEventRecord(ev[o.a0], s));
+    } else if (o.type == OP_WAIT) {
+      if (aux != nullptr) HIPCHK(hipStreamWaitEvent(s, ev[o.a0], 0));
+    } else {
+      run_op(P, W, o, s);
+    }
+  }
+  if (aux != nullptr) {
+    HIPCHK(hipEventRecord(ev[P.n_events + 1], aux));
+    HIPCHK(hipStreamWaitEvent(st, ev[P.n_events + 1], 0));
+  }
   HIPCHK(hipGetLastError());
   return HODLR_OK;
 }
@@ -587,9 +666,13 @@ struct hodlr_qr_s {
   double *X1 = nullptr, *X2 = nullptr;  // n x SMAX scratch of apply_q / solve
   Plan plan;
   hipGraphExec_t graph = nullptr;
+  hipStream_t aux = nullptr;        // stream of the T-factor lane
+  std::vector<hipEvent_t> events;   // plan events + fork + join
   int64_t n_launch = 0;
   ~hodlr_qr_s() {
     if (graph) (void)hipGraphExecDestroy(graph);
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (aux) (void)hipStreamDestroy(aux);
   }
   HView view_gen() const { return HView{t.L, up.dview, lo.dview, leaves.dview, LEAF_FULL}; }
   HView view_y() const { return HView{t.L, nullptr, lo.dview, leaves.dview, LEAF_UNIT_LOWER}; }
@@ -673,14 +756,14 @@ struct QRBuilder {
     const int jid = (int)P.lj.size();
     P.lj.push_back(J);
     const int m = J.m, np = (m + NB - 1) / NB;
-    P.ops.push_back(Op{OP_LGATHER, 0, m, jid});
-    P.ops.push_back(Op{OP_LPANEL, 0, 1, jid, -1});  // panel 0
+    P.push(Op{OP_LGATHER, 0, m, jid});
+    P.push(Op{OP_LPANEL, 0, 1, jid, -1});  // panel 0
     for (int p = 0; p <= np; ++p) {
       const int nstrip = p < np ? np - p - 1 : 0, ngram = p < np ? p : 0, ntile = p >= 1 ? p - 1 : 0;
       const int cnt = nstrip + ngram + ntile;
-      if (cnt > 0) P.ops.push_back(Op{OP_LUPDATE, 0, cnt, jid, p});
+      if (cnt > 0) P.push(Op{OP_LUPDATE, 0, cnt, jid, p});
     }
-    P.ops.push_back(Op{OP_LSCATTER, 0, m, jid});
+    P.push(Op{OP_LSCATTER, 0, m, jid});
   }
 
   TrSpec trspec(Seg l0, Seg l1, Seg r0, Seg r1, int mL, int mR, const double* tau, double* oL, double* oR,
@@ -704,10 +787,15 @@ struct QRBuilder {
     return s;
   }
 
-  void node(int v, const std::vector<int>& groups) {
+  // Ops of the subtree at v.  The T-factor steps (T~12, T12) of every node run
+  // on lane 1 beside the main chain: they wait for the node's right subtree and
+  // are only read again by the parent's S = T1^T S~ (main chain: it waits for
+  // the returned event) or by the parent's own T steps (later on lane 1).
+  // Returns the event signalled once T of the subtree is complete, -1 for a leaf.
+  int node(int v, const std::vector<int>& groups) {
     if (t.is_leaf(v)) {
       leaf(v, groups);
-      return;
+      return -1;
     }
     const int Lc = 2 * v, Rc = 2 * v + 1;
     const int mL = (int)t.m(Lc), mR = (int)t.m(Rc);
@@ -720,7 +808,7 @@ struct QRBuilder {
     std::vector<int> gl;
     gl.push_back(v);
     gl.insert(gl.end(), groups.begin(), groups.end());
-    node(Lc, gl);
+    const int evL = node(Lc, gl);
     // S~ terms: Z1 = Y_A11^T U12 and Z2 = A22^T U21 (one launch pair)
     P.mm(t, {mmspec(F.view_y(), false, true, Lc, 1, A12.U, mL, k12, F.Z1, mL, 1.0, 0.0, 1),
              mmspec(F.view_gen(), true, true, Rc, 1, A21.U, mR, k21, F.Z2, mR, 1.0, 0.0, 0)});
@@ -731,7 +819,8 @@ struct QRBuilder {
       P.trunc({trspec(mkseg(F.SL, mL, rS), mkseg(gslice(g, Lc), gld(g), F.rank_lo(g)),
                       mkseg(F.SR, mR, rS), mkseg(gslice(g, Rc), gld(g), F.rank_lo(g)), mL, mR, F.scal + 1,
                       F.SL, F.SR, mL, mR, rS, FC_TRUNC)});
-    // S = T1^T S~  (left factor only)
+    // S = T1^T S~  (left factor only); T1 must be complete
+    if (evL >= 0) P.wait(evL);
     P.mm(t, {mmspec(F.view_t(), true, false, Lc, 1, F.SL, mL, rS, F.SLt, mL, 1.0, 0.0, 1)});
     // Y_A11 S_L for the new upper block
     P.mm(t, {mmspec(F.view_y(), false, true, Lc, 0, F.SLt, mL, rS, F.Z4, mL, 1.0, 0.0, 1)});
@@ -799,6 +888,9 @@ struct QRBuilder {
     }
     // second block column: hQR(A^22, [], [B^_R2; C^2])
     node(Rc, groups);
+    const int evM = P.signal();
+    P.lane = 1;
+    P.wait(evM);
     // T~12 = T_eps(Y_A21^T Y_A22 + sum over groups of Y_g1^T Y_g2)
     P.mm(t, {mmspec(F.view_y(), false, true, Rc, 1, A21.U, mR, k21, F.Z5, mR, 1.0, 0.0, 1)});
     int* rt = F.rank_t(v);
@@ -819,6 +911,9 @@ struct QRBuilder {
     const HBlk& T12 = F.tup.hview[v];
     P.mm(t, {mmspec(F.view_t(), true, false, Lc, 0, F.TL, mL, rt, T12.U, mL, -1.0, 0.0, 1),
              mmspec(F.view_t(), true, false, Rc, 1, F.TR, mR, rt, T12.V, mR, 1.0, 0.0, 1)});
+    const int evT = P.signal();
+    P.lane = 0;
+    return evT;
   }
 
   void build() {
@@ -841,7 +936,7 @@ void plan_norm2(Plan& P, const Tree& t, HView V, int iters, double* x, double* y
   fill.p1 = x;
   fill.n = n;
   fill.d0 = 1.0 / std::sqrt((double)n);
-  P.ops.push_back(fill);
+  P.push(fill);
   for (int it = 0; it < iters; ++it) {
     P.mm(t, {mmspec(V, true, true, 1, 0, x, (int)n, nullptr, y, (int)n, 1.0, 0.0, 0, 1)});
     P.mm(t, {mmspec(V, true, true, 1, 1, y, (int)n, nullptr, z, (int)n, 1.0, 0.0, 0, 1)});
@@ -849,7 +944,7 @@ void plan_norm2(Plan& P, const Tree& t, HView V, int iters, double* x, double* y
     o.p0 = z;
     o.p1 = x;
     o.n = n;
-    P.ops.push_back(o);
+    P.push(o);
   }
   P.mm(t, {mmspec(V, true, true, 1, 0, x, (int)n, nullptr, y, (int)n, 1.0, 0.0, 0, 1)});
   Op o{OP_NORMALIZE};
@@ -857,7 +952,7 @@ void plan_norm2(Plan& P, const Tree& t, HView V, int iters, double* x, double* y
   o.p1 = nullptr;
   o.n = n;
   o.pout = out;
-  P.ops.push_back(o);
+  P.push(o);
 }
 
 hodlr_status check_finite(const double* p, size_t n, const char* what) {
@@ -921,20 +1016,39 @@ hodlr_status make_factor(const hodlr_s& A, double eps, double anorm, hipStream_t
     o.p1 = F->scal;
     o.d0 = eps;
     o.d1 = anorm > 0.0 ? anorm : -1.0;
-    F->plan.ops.push_back(o);
+    F->plan.push(o);
   }
   qb.build();
   TRY(F->plan.upload_all(F->mem, st));
-  TRY(ensure_work(F->mem, F->work, F->plan.ws_need, F->plan.cnt_need, true, st));
-  F->n_launch = (int64_t)F->plan.ops.size();
+  TRY(ensure_work(F->mem, F->work, F->plan.ws_need(), F->plan.cnt_need(), true, st));
+  F->n_launch = 0;
+  for (const Op& o : F->plan.ops) F->n_launch += op_launches(o) ? 1 : 0;
   out = std::move(F);
   return HODLR_OK;
 }
 
-hodlr_status run_factor(hodlr_qr_s& F, const hodlr_s& A, bool use_graph, hipStream_t st) {
-  if (!use_graph) {
+hodlr_status lane_streams(hodlr_qr_s& F) {
+  if (F.aux == nullptr) HIPCHK(hipStreamCreateWithFlags(&F.aux, hipStreamNonBlocking));
+  while ((int)F.events.size() < F.plan.n_events + 2) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    F.events.push_back(e);
+  }
+  return HODLR_OK;
+}
+
+// Run the whole factorisation on `st`.  Default: direct launches, the T-factor
+// lane on a second stream.  HODLR_QR_ONE_STREAM: direct launches in the serial
+// order.  HODLR_QR_GRAPH: replay a HIP graph captured (once per handle) from the
+// serial order on one stream; a graph captured from the two-stream form ran
+// with wrong results on ROCm 7.2 although every edge of it was present, so the
+// graph keeps the serial order.
+hodlr_status run_factor(hodlr_qr_s& F, const hodlr_s& A, uint32_t flags, hipStream_t st) {
+  TRY(lane_streams(F));
+  if (!(flags & HODLR_QR_GRAPH)) {
     TRY(reset_factor(F, A, st));
-    return run_ops(F.plan, F.work, st);
+    hipStream_t aux = (flags & HODLR_QR_ONE_STREAM) ? nullptr : F.aux;
+    return run_ops(F.plan, F.work, st, aux, F.events.data());
   }
   if (F.graph == nullptr) {
     // capture on a private stream so that the caller's stream state is untouched
@@ -992,7 +1106,7 @@ hodlr_status norm2_est_impl(hodlr_s& A, int iters, hipStream_t st, double* out) 
   Plan P;
   plan_norm2(P, t, V, iters, x, y, z, res);
   TRY(P.upload_all(tmp, st));
-  TRY(ensure_work(A.mem, A.work, P.ws_need, P.cnt_need, false, st));
+  TRY(ensure_work(A.mem, A.work, P.ws_need(), P.cnt_need(), false, st));
   TRY(run_ops(P, A.work, st));
   HIPCHK(hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1110,7 +1224,7 @@ hodlr_status hodlr_qr(const hodlr_t* A, double eps, double anorm, uint32_t flags
   hipStream_t st = (hipStream_t)stream;
   std::unique_ptr<hodlr_qr_s> F;
   TRY(make_factor(*A, eps, anorm, st, F));
-  TRY(run_factor(*F, *A, !(flags & HODLR_QR_NO_GRAPH), st));
+  TRY(run_factor(*F, *A, flags, st));
   TRY(finish_factor(*F, st));
   *out = F.release();
   return HODLR_OK;
@@ -1123,15 +1237,14 @@ hodlr_status hodlr_qr_time(const hodlr_t* A, double eps, double anorm, uint32_t 
   hipStream_t st = (hipStream_t)stream;
   std::unique_ptr<hodlr_qr_s> F;
   TRY(make_factor(*A, eps, anorm, st, F));
-  const bool g = !(flags & HODLR_QR_NO_GRAPH);
-  for (int i = 0; i < warmup; ++i) TRY(run_factor(*F, *A, g, st));
+  for (int i = 0; i < warmup; ++i) TRY(run_factor(*F, *A, flags, st));
   TRY(finish_factor(*F, st));
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   for (int i = 0; i < reps; ++i) {
     HIPCHK(hipEventRecord(e0, st));
-    TRY(run_factor(*F, *A, g, st));
+    TRY(run_factor(*F, *A, flags, st));
     HIPCHK(hipEventRecord(e1, st));
     HIPCHK(hipEventSynchronize(e1));
     float t = 0.0f;
@@ -1157,7 +1270,7 @@ static hodlr_status matmul_view(const Tree& t, HView V, bool up, bool lo, int tr
   }
   DMem tmp;
   TRY(P.upload_all(tmp, st));
-  TRY(ensure_work(mem, W, P.ws_need, P.cnt_need, false, st));
+  TRY(ensure_work(mem, W, P.ws_need(), P.cnt_need(), false, st));
   TRY(run_ops(P, W, st));
   HIPCHK(hipStreamSynchronize(st));  // the plan's descriptor memory is released on return
   return HODLR_OK;
@@ -1209,7 +1322,7 @@ hodlr_status hodlr_apply_q(const hodlr_qr_t* F, int32_t trans, int64_t nrhs, dou
   }
   DMem tmp;
   TRY(P.upload_all(tmp, st));
-  TRY(ensure_work(f->mem, f->work, P.ws_need, P.cnt_need, false, st));
+  TRY(ensure_work(f->mem, f->work, P.ws_need(), P.cnt_need(), false, st));
   TRY(run_ops(P, f->work, st));
   HIPCHK(hipStreamSynchronize(st));
   return HODLR_OK;
@@ -1241,7 +1354,7 @@ hodlr_status hodlr_solve(const hodlr_qr_t* F, int64_t nrhs, double* B, int64_t l
           o.p0 = f.leaves.hview[j].D;
           o.p1 = Bc + t.lo[v];
           o.n = ldb;
-          P.ops.push_back(o);
+          P.push(o);
           return;
         }
         go(2 * v + 1);
@@ -1260,7 +1373,7 @@ hodlr_status hodlr_solve(const hodlr_qr_t* F, int64_t nrhs, double* B, int64_t l
     rec.go(1);
     DMem tmp;
     TRY(P.upload_all(tmp, st));
-    TRY(ensure_work(f->mem, f->work, P.ws_need, P.cnt_need, false, st));
+    TRY(ensure_work(f->mem, f->work, P.ws_need(), P.cnt_need(), false, st));
     TRY(run_ops(P, f->work, st));
     HIPCHK(hipStreamSynchronize(st));
   }
@@ -1287,10 +1400,12 @@ hodlr_status hodlr_qr_profile(const hodlr_t* A, double eps, double anorm, int32_
   HIPCHK(hipEventCreate(&e1));
   double prev = 0.0;
   for (const Op& o : F->plan.ops) {
-    HIPCHK(hipEventRecord(e0, st));
-    run_op(F->plan, F->work, o, st);
+    if (!op_launches(o)) continue;
+    Launch L;
+    L.e0 = e0;
+    L.e1 = e1;
+    run_op(F->plan, F->work, o, st, L);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(e1, st));
     HIPCHK(hipEventSynchronize(e1));
     float t = 0.0f;
     HIPCHK(hipEventElapsedTime(&t, e0, e1));

@@ -671,6 +671,8 @@ __global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ job
   const TrJob& J = jobs[it.job];
   const double* hdr = ws + J.hdr;
   const int w = (int)hdr[0], k = (int)hdr[1];
+  // the header is written by k_tr_qr for every job; refuse anything else
+  if (w < 0 || w > WMAX || k < 0 || k > w || k > J.cap) return;
   if (it.leader && tid == 0) *J.out_rank = k;
   if (w == 0 || k == 0) return;
   const double* Uk = hdr + 8;
@@ -1394,7 +1396,8 @@ constexpr size_t LEAF_PANEL_LDS = LEAF_LDS;
 // One step of the blocked leaf QR (see the section comment).  p = -1 only
 // factorises panel 0; p = np only forms the last T block.
 __global__ void __launch_bounds__(NT_LEAF) k_leaf_step(const LeafJob* __restrict__ jobs, int jidx,
-                                                        LeafWs W, int p, const int* err) {
+                                                        LeafWs W, int p, const int* err,
+                                                        double* fc) {
   extern __shared__ double sm[];
   if (*err & ERR_STACK) return;
   const LeafJob& J = jobs[jidx];
@@ -1403,6 +1406,12 @@ __global__ void __launch_bounds__(NT_LEAF) k_leaf_step(const LeafJob* __restrict
   const int np = (m + NB - 1) / NB;
   const int M = leaf_rows(J);
   if (p < 0) {
+    // the whole leaf's flops (Householder QR of M x m, Table 1, plus forming T
+    // by eq. recqrcombined) are credited to this kernel's first launch
+    if (tid == 0) {
+      const double Mr = M, n = m;
+      add_flops(fc, FC_LEAF, 2.0 * Mr * n * n - 2.0 / 3.0 * n * n * n + Mr * n * n - n * n * n / 3.0);
+    }
     leaf_panel(W, 0, min(NB, m), M, sm);
     return;
   }
@@ -1482,10 +1491,6 @@ __global__ void __launch_bounds__(NT_MM) k_leaf_scatter(const LeafJob* __restric
     const int ld = J.g[g].ld;
     for (int t = threadIdx.x; t < k; t += NT_MM) V[(int64_t)t * ld] = h[off + t];
     off += k;
-  }
-  if (c == 0 && threadIdx.x == 0) {
-    const double Mr = off, n = m;
-    add_flops(fc, FC_LEAF, 2.0 * Mr * n * n - 2.0 / 3.0 * n * n * n + Mr * n * n - n * n * n / 3.0);
   }
 }
 

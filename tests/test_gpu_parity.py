@@ -122,15 +122,19 @@ def test_config0_anorm_on_device(H):
     assert _rel(H.hodlr_qr_matmul(F, "R", H.colmajor(X)).cpu().numpy(), O.rmat(ref, X)) <= 1e-8
 
 
-def test_graph_and_direct_launch_agree_bitwise(H):
-    inp = G.config(0)
-    A = H.hodlr_build(inp, rank_cap=64)
-    X = H.colmajor(np.random.default_rng(3).standard_normal((inp.n, 8)))
+@pytest.mark.parametrize("n,leaf", [(512, 64), (16384, 256)])
+def test_launch_modes_agree_bitwise(H, n, leaf):
+    """Two streams (default), one stream and graph replay give the same bits."""
+    inp = G.config(0) if n == 512 else G.expkernel_hodlr(n, leaf, 2)
+    A = H.hodlr_build(inp, rank_cap=64 if n == 512 else 16)
+    X = np.random.default_rng(3).standard_normal((inp.n, 8))
     outs = []
-    for flags in (0, H.HODLR_QR_NO_GRAPH, 0):
+    for flags in (0, H.HODLR_QR_ONE_STREAM, H.HODLR_QR_GRAPH, 0):
         F = H.hodlr_qr(A, EPS, anorm=17.6, flags=flags)
-        outs.append(H.hodlr_qr_matmul(F, "R", X).cpu().numpy())
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+        outs.append((H.hodlr_qr_matmul(F, "R", H.colmajor(X)).cpu().numpy(),
+                     H.hodlr_apply_q(F, H.colmajor(X)).cpu().numpy()))
+    for o in outs[1:]:
+        assert np.array_equal(outs[0][0], o[0]) and np.array_equal(outs[0][1], o[1])
 
 
 def test_flop_count_matches_oracle(H):
