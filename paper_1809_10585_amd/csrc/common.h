@@ -10,6 +10,7 @@
 namespace hq {
 
 constexpr int CH = 256;        // rows of one tall-skinny QR chunk (TSQR leaf)
+constexpr int MM_CH = 1024;    // rows of one projection chunk of a HODLR product
 constexpr int WMAX = 128;      // widest recompression handled on the device
 constexpr int SMAX = 64;       // widest tall-skinny operand of a HODLR product
 constexpr int KCAP = 64;       // largest rank capacity of a stored block
@@ -32,6 +33,9 @@ enum : int { ERR_CAPACITY = 1, ERR_WIDTH = 2, ERR_STACK = 4 };
 // flop counter categories (same counting conventions as the CPU oracle)
 enum : int { FC_LEAF = 0, FC_HMAT = 1, FC_TRUNC = 2, FC_DENSE = 3, FC_UPDATE = 4, FC_ORTH = 5,
              FC_N = 6 };
+// flop counters: FC_N categories x FC_STRIPE stripes (summed on the host)
+constexpr int FC_STRIPE = 64;
+constexpr int FC_SIZE = 8 * FC_STRIPE;
 
 // Columns [0, ncols) of a column-major array, scaled by `scale`.  ncols is
 // *ncols_dev when that pointer is set.  p == nullptr means an empty segment.
@@ -135,8 +139,8 @@ struct MmProj {      // phase A: one row chunk of one block projection
   int node;
   int kind;          // 0 = upper block, 1 = lower block
   int chunk, nchunk;
-  int64_t part;      // this chunk's partial (KCAP x SMAX, ld KCAP)
-  int counter;
+  int64_t part;      // this chunk's partial (KCAP x SMAX, ld KCAP); for k_mm_red
+                     // items the first chunk's partial
 };
 
 struct MmApply {     // phase B: rows of one leaf of the output

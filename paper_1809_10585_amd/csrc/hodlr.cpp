@@ -204,13 +204,14 @@ hodlr_status make_leaves(DMem& mem, const Tree& t, LeafSet& S) {
 enum OpType {
   OP_TRQR, OP_TRFORM, OP_MMPROJ, OP_MMAPPLY, OP_GTALL, OP_GRED, OP_LGATHER, OP_LPANEL,
   OP_LUPDATE, OP_LSCATTER, OP_FILL, OP_NORMALIZE, OP_TRSM, OP_SETSCAL,
+  OP_MMRED,
   OP_SIGNAL,  // record event a0 on the op's lane (no kernel)
   OP_WAIT,    // the op's lane waits for event a0 (no kernel)
   OP_NTYPES
 };
 const char* const OP_NAMES[OP_NTYPES] = {
   "tr_qr", "tr_form", "mm_proj", "mm_apply", "gemm_tall", "gemm_red", "leaf_gather", "leaf_panel",
-  "leaf_update", "leaf_scatter", "fill", "normalize", "leaf_trsm", "set_scal", "signal", "wait"};
+  "leaf_update", "leaf_scatter", "fill", "normalize", "leaf_trsm", "set_scal", "mm_red", "signal", "wait"};
 
 struct Op {
   int type;
@@ -308,6 +309,7 @@ struct Plan {
   }
   int64_t n_trunc = 0;
   int wtop = WMAX;  // widest recompression this plan can produce
+  int mleaf = 0;    // largest leaf any product of this plan touches
   // device copies
   TrJob* d_trj = nullptr;
   TrChunk* d_trc = nullptr;
@@ -375,10 +377,25 @@ struct Plan {
     cnt_lane[lane] = std::max(cnt_lane[lane], cnt);
   }
 
+  static int rel_node_h(int u, int v) {
+    int du = 0, dv = 0;
+    while ((u >> du) > 1) ++du;
+    while ((v >> dv) > 1) ++dv;
+    const int d = du - dv;
+    return (1 << d) - 1 + (u - (v << d));
+  }
+
+  // Z = alpha op(M_v) X + beta Z for every spec: projections of all blocks in one
+  // launch (plus a summing launch if some block spans several chunks), then the
+  // leaf rows in one launch.
   void mm(const Tree& t, const std::vector<MmSpec>& specs) {
     int64_t off = 0;
-    int cnt = 0;
-    const int p_first = (int)mmp.size(), a_first = (int)mma.size();
+    const int p_first = (int)mmp.size();
+    std::vector<MmProj> reds;
+    int64_t rows_total = 0;
+    for (const MmSpec& sp : specs) rows_total += t.m(sp.v);
+    const int RT = rows_total >= 32768 ? 64 : 16;
+    std::vector<MmApply> apply;
     for (const MmSpec& sp : specs) {
       MmJob J{};
       J.M = sp.M;
@@ -394,6 +411,8 @@ struct Plan {
       J.beta = sp.beta;
       J.row0 = t.lo[sp.v];
       J.tri = sp.tri;
+      J.red0 = off;
+      off += 2 * (int64_t)t.subtree_size(sp.v) * KCAP * SMAX;
       const int jid = (int)mmj.size();
       std::vector<int> nodes;
       t.subtree_internal(sp.v, nodes);
@@ -403,28 +422,36 @@ struct Plan {
           const int64_t rows = kind == 0 ? t.m(2 * u) : t.m(2 * u + 1);
           const int64_t cols = kind == 0 ? t.m(2 * u + 1) : t.m(2 * u);
           const int64_t len = sp.trans ? rows : cols;
-          const int nch = (int)((len + CH - 1) / CH);
-          const int counter = cnt++;
-          for (int c = 0; c < nch; ++c) {
-            mmp.push_back(MmProj{jid, u, kind, c, nch, off + (int64_t)c * KCAP * SMAX, counter});
+          const int nch = (int)((len + MM_CH - 1) / MM_CH);
+          if (nch == 1) {
+            const int64_t red = J.red0 + (int64_t)(2 * rel_node_h(u, sp.v) + kind) * KCAP * SMAX;
+            mmp.push_back(MmProj{jid, u, kind, 0, 1, red});
+          } else {
+            for (int c = 0; c < nch; ++c) mmp.push_back(MmProj{jid, u, kind, c, nch, off + (int64_t)c * KCAP * SMAX});
+            reds.push_back(MmProj{jid, u, kind, 0, nch, off});
+            off += (int64_t)nch * KCAP * SMAX;
           }
-          if (nch > 1) off += (int64_t)nch * KCAP * SMAX;
         }
       }
-      J.red0 = off;
-      off += 2 * (int64_t)t.subtree_size(sp.v) * KCAP * SMAX;
       mmj.push_back(J);
       std::vector<int> leaves;
       t.subtree_leaves(sp.v, leaves);
       for (int j : leaves) {
         const int m = (int)t.m(t.nleaf() + j);
-        for (int r0 = 0; r0 < m; r0 += 64) mma.push_back(MmApply{jid, j, r0, std::min(64, m - r0)});
+        mleaf = std::max(mleaf, m);
+        for (int r0 = 0; r0 < m; r0 += RT) apply.push_back(MmApply{jid, j, r0, std::min(RT, m - r0)});
       }
     }
     if ((int)mmp.size() > p_first) push(Op{OP_MMPROJ, p_first, (int)mmp.size() - p_first});
-    push(Op{OP_MMAPPLY, a_first, (int)mma.size() - a_first});
+    if (!reds.empty()) {
+      const int r_first = (int)mmp.size();
+      mmp.insert(mmp.end(), reds.begin(), reds.end());
+      push(Op{OP_MMRED, r_first, (int)reds.size()});
+    }
+    const int a_first = (int)mma.size();
+    mma.insert(mma.end(), apply.begin(), apply.end());
+    push(Op{OP_MMAPPLY, a_first, (int)apply.size(), 0, RT});
     ws_lane[lane] = std::max(ws_lane[lane], off);
-    cnt_lane[lane] = std::max(cnt_lane[lane], cnt);
   }
 
   void gemm_tall(const std::vector<GSpec>& specs) {
@@ -486,13 +513,23 @@ struct Work {
   LeafWs leaf{};
 };
 
+// sum of the striped device flop counters (synchronous); -1 on failure
+double flop_total(const double* fc) {
+  std::vector<double> h(FC_SIZE);
+  if (hipMemcpy(h.data(), fc, FC_SIZE * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return -1.0;
+  double tot = 0.0;
+  for (int c = 0; c < FC_N; ++c)
+    for (int k = 0; k < FC_STRIPE; ++k) tot += h[c * FC_STRIPE + k];
+  return tot;
+}
+
 hodlr_status ensure_work(DMem& mem, Work& W, int64_t ws_need, int cnt_need, bool leafws,
                          hipStream_t st) {
   if (W.err == nullptr) {
     TRY(mem.alloc(&W.err, 4));
-    TRY(mem.alloc(&W.fc, 8));
+    TRY(mem.alloc(&W.fc, FC_SIZE));
     HIPCHK(hipMemsetAsync(W.err, 0, 4 * sizeof(int), st));
-    HIPCHK(hipMemsetAsync(W.fc, 0, 8 * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(W.fc, 0, FC_SIZE * sizeof(double), st));
   }
   if (ws_need > W.ws_size) {
     TRY(mem.alloc(&W.ws, (size_t)ws_need));
@@ -520,6 +557,8 @@ hodlr_status set_attrs() {
     HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TR_QR_LDS));
   HIPCHK(hipFuncSetAttribute((const void*)k_tr_form, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)TR_FORM_LDS));
+  for (const void* f : {(const void*)k_mm_apply<16>, (const void*)k_mm_apply<64>})
+    HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mm_apply_lds(MAXLEAF)));
   HIPCHK(hipFuncSetAttribute((const void*)k_leaf_step, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)LEAF_LDS));
   g_attr_done = true;
@@ -567,10 +606,14 @@ void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st, const Lau
       launch(L, k_tr_form, o.count, NT_MM, TR_FORM_LDS, st, P.d_trj, P.d_trf, o.first, ws);
       break;
     case OP_MMPROJ:
-      launch(L, k_mm_proj, o.count, NT_MM, 0, st, P.d_mmj, P.d_mmp, o.first, ws, cnt, W.fc);
+      launch(L, k_mm_proj, o.count, NT_MM, 0, st, P.d_mmj, P.d_mmp, o.first, ws, W.fc);
+      break;
+    case OP_MMRED:
+      launch(L, k_mm_red, o.count, NT_MM, 0, st, P.d_mmj, P.d_mmp, o.first, ws);
       break;
     case OP_MMAPPLY:
-      launch(L, k_mm_apply, o.count, NT_MM, 0, st, P.d_mmj, P.d_mma, o.first, ws, W.fc);
+      launch(L, o.a1 == 64 ? k_mm_apply<64> : k_mm_apply<16>, o.count, NT_MM, mm_apply_lds(P.mleaf), st,
+             P.d_mmj, P.d_mma, o.first, (const double*)ws, W.fc);
       break;
     case OP_GTALL:
       launch(L, k_gemm_tall, o.count, NT_MM, 0, st, P.d_gj, P.d_gt, o.first, W.fc);
@@ -969,7 +1012,7 @@ hodlr_status reset_factor(hodlr_qr_s& F, const hodlr_s& A, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(F.lo.U, A.lo.U, F.lo.usz * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(F.lo.V, A.lo.V, F.lo.vsz * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(F.ranks, A.ranks, 2 * (size_t)(1 << A.t.L) * sizeof(int), hipMemcpyDeviceToDevice, st));
-  k_fill<<<1, 64, 0, st>>>(F.work.fc, 8, 0.0);
+  k_fill<<<(FC_SIZE + 255) / 256, 256, 0, st>>>(F.work.fc, FC_SIZE, 0.0);
   return HODLR_OK;
 }
 
@@ -1409,10 +1452,8 @@ hodlr_status hodlr_qr_profile(const hodlr_t* A, double eps, double anorm, int32_
     HIPCHK(hipEventSynchronize(e1));
     float t = 0.0f;
     HIPCHK(hipEventElapsedTime(&t, e0, e1));
-    double fcv[8];
-    HIPCHK(hipMemcpy(fcv, F->work.fc, sizeof(fcv), hipMemcpyDeviceToHost));
-    double tot = 0.0;
-    for (int c = 0; c < FC_N; ++c) tot += fcv[c];
+    const double tot = flop_total(F->work.fc);
+    if (tot < 0.0) return fail(HODLR_EDEVICE, "reading the flop counters failed");
     if (o.type < ntypes) {
       ms[o.type] += t;
       counts[o.type] += 1;
@@ -1433,9 +1474,9 @@ hodlr_status hodlr_qr_info(const hodlr_qr_t* F, hodlr_qr_info_t* info) {
   if (F == nullptr || info == nullptr) return fail(HODLR_EINVAL, "NULL argument");
   const int nn = 1 << F->t.L;
   std::vector<int> r(3 * (size_t)nn + 8);
-  double fc[8];
+
   HIPCHK(hipMemcpy(r.data(), F->ranks, r.size() * sizeof(int), hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(fc, F->work.fc, sizeof(fc), hipMemcpyDeviceToHost));
+
   std::memset(info, 0, sizeof(*info));
   info->n = F->t.n;
   info->levels = F->t.L;
@@ -1448,9 +1489,7 @@ hodlr_status hodlr_qr_info(const hodlr_qr_t* F, hodlr_qr_info_t* info) {
   info->anorm = F->anorm;
   info->tau_a = F->tauA;
   info->tau_t = F->tauT;
-  double tot = 0.0;
-  for (int c = 0; c < FC_N; ++c) tot += fc[c];
-  info->flops = tot;
+  info->flops = flop_total(F->work.fc);
   info->n_truncations = F->plan.n_trunc;
   info->n_launches = F->n_launch;
   info->device_bytes = (int64_t)F->mem.bytes;

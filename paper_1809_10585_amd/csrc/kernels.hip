@@ -124,7 +124,8 @@ __device__ __forceinline__ int rel_node(int u, int v) {
 }
 
 __device__ __forceinline__ void add_flops(double* fc, int cat, double f) {
-  if (fc && f != 0.0) atomicAdd(fc + cat, f);
+  // striped by block so that thousands of blocks do not queue on one address
+  if (fc && f != 0.0) atomicAdd(fc + cat * FC_STRIPE + (blockIdx.x % FC_STRIPE), f);
 }
 
 __device__ __forceinline__ int tier_of(int w) {
@@ -358,6 +359,91 @@ __device__ __forceinline__ void jacobi(double* X, int lx, double* V, int lv, int
   }
 }
 
+// The same one-sided Jacobi for w <= WS (WS = 8 or 16) inside one wavefront.
+// X (and V = X + WS*WS) are WS x WS in LDS with leading dimension WS, rows and
+// columns beyond w zero (rotations keep them zero), so a lane loads, rotates and
+// stores whole padded columns without branches.  Lane p rotates pair p of the
+// round-robin schedule; a round costs no block barrier and no cross-lane
+// reduction; the sweep test is a wavefront vote.  Same rotation and threshold as
+// jacobi() (|g| > tol sqrt(a b) is tested squared).  All threads of the block
+// call it; it ends with a block barrier.
+template <int WS>
+__device__ __forceinline__ void jacobi_small(double* X, int w) {
+  double* V = X + WS * WS;
+  const int tid = threadIdx.x;
+  const int n = w + (w & 1);
+  if (n >= 2 && tid < 64) {
+    const int P = n / 2;
+    const double tol = (double)w * DBL_EPSILON;
+    const double tol2 = tol * tol;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+      int rot = 0;
+      for (int r = 0; r < n - 1; ++r) {
+        int i = 0, j = 0;
+        if (tid == 0) {
+          i = r;
+          j = n - 1;
+        } else {
+          i = (r + tid) % (n - 1);
+          j = (r - tid + n - 1) % (n - 1);
+        }
+        if (i > j) {
+          const int t = i;
+          i = j;
+          j = t;
+        }
+        if (tid < P && j < w) {
+          double* xi = X + i * WS;
+          double* xj = X + j * WS;
+          double* vi = V + i * WS;
+          double* vj = V + j * WS;
+          double a[WS], b[WS], c[WS], d[WS];
+#pragma unroll
+          for (int row = 0; row < WS; ++row) {
+            a[row] = xi[row];
+            b[row] = xj[row];
+            c[row] = vi[row];
+            d[row] = vj[row];
+          }
+          double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+          for (int row = 0; row < WS; ++row) {
+            al = fma(a[row], a[row], al);
+            be = fma(b[row], b[row], be);
+            ga = fma(a[row], b[row], ga);
+          }
+          if (ga != 0.0 && ga * ga > tol2 * (al * be)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            double t;
+            if (fabs(zeta) > 1e150)
+              t = 0.5 / zeta;
+            else
+              t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + sqrt_nr(fma(zeta, zeta, 1.0)));
+            const double u = fma(t, t, 1.0);
+            double cs = __builtin_amdgcn_rsq(u);
+            cs = cs * fma(-0.5 * u * cs, cs, 1.5);
+            cs = cs * fma(-0.5 * u * cs, cs, 1.5);
+            const double sn = cs * t;
+#pragma unroll
+            for (int row = 0; row < WS; ++row) {
+              xi[row] = cs * a[row] - sn * b[row];
+              xj[row] = sn * a[row] + cs * b[row];
+              vi[row] = cs * c[row] - sn * d[row];
+              vj[row] = sn * c[row] + cs * d[row];
+            }
+            rot = 1;
+          }
+        }
+        // the next round reads columns other lanes of this wavefront wrote
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (__ballot(rot) == 0) break;
+    }
+  }
+  __syncthreads();
+}
+
 // Last block of a job: SVD of R1 R2^T and the small factors U_k, P = R1^T U_k.
 template <int W>
 __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0a, int n0b, double* smem, int* err,
@@ -386,11 +472,16 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
     }
   } else {
     const double* R2 = ws + J.side[1].node0 + (int64_t)tr_root_slot(J.side[1].p0, G) * TR_NODE;
-    const int LX = w;
+    // w <= 16: X and V padded to WS x WS (zeros beyond w) for jacobi_small
+    const int WSs = w <= 8 ? 8 : (w <= 16 ? 16 : 0);
+    const int LX = WSs ? WSs : w;
     double* X = smem + TRS_X;
     double* V;
     int LV;
-    if (2 * w * w <= WMAX * WMAX) {  // X and V both in LDS
+    if (WSs) {
+      V = X + LX * LX;
+      LV = LX;
+    } else if (2 * w * w <= WMAX * WMAX) {  // X and V both in LDS
       V = X + w * w;
       LV = w;
     } else {
@@ -403,8 +494,8 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
     const double* R1s = R1;
     const double* R2s = R2;
     int lr = WMAX;
-    if (4 * w * w <= WMAX * WMAX) {
-      double* r1 = X + 2 * w * w;
+    if (4 * LX * LX <= WMAX * WMAX) {
+      double* r1 = X + 2 * LX * LX;
       double* r2 = r1 + w * w;
       for (int e = tid; e < w * w; e += NT_TR) {
         const int i = e % w, j = e / w;
@@ -416,16 +507,23 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
       lr = w;
       __syncthreads();
     }
-    // X = R2 R1^T  (both upper triangular, w x w)
-    for (int e = tid; e < w * w; e += NT_TR) {
-      const int i = e % w, j = e / w;
+    // X = R2 R1^T  (both upper triangular, w x w; zero padding up to LX)
+    const int wx = WSs ? LX : w;
+    for (int e = tid; e < wx * wx; e += NT_TR) {
+      const int i = e % wx, j = e / wx;
       double sacc = 0.0;
-      for (int l = max(i, j); l < w; ++l) sacc += R2s[i + l * lr] * R1s[j + l * lr];
+      if (i < w && j < w)
+        for (int l = max(i, j); l < w; ++l) sacc += R2s[i + l * lr] * R1s[j + l * lr];
       X[i + j * LX] = sacc;
-      V[i + j * LV] = (i == j) ? 1.0 : 0.0;
+      V[i + j * LV] = (i == j && i < w) ? 1.0 : 0.0;
     }
     __syncthreads();
-    jacobi(X, LX, V, LV, w, sflag);
+    if (WSs == 8)
+      jacobi_small<8>(X, w);
+    else if (WSs == 16)
+      jacobi_small<16>(X, w);
+    else
+      jacobi(X, LX, V, LV, w, sflag);
     for (int cc = tid; cc < w; cc += NT_TR) {
       double sacc = 0.0;
       for (int r = 0; r < w; ++r) sacc += X[r + cc * LX] * X[r + cc * LX];
@@ -753,204 +851,226 @@ __global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ job
 // ------------------------------------------------------------------ HODLR x tall-skinny
 __device__ __forceinline__ int mm_s(const MmJob& J) { return J.s_dev ? *J.s_dev : J.s; }
 
-// Phase A: partial projections P_b = F_b^T X (F = V for op N, U for op T) over
-// one chunk of CH rows; the last chunk of a block sums the partials in order.
+// Phase A: projections P_b = F_b^T X (F = V for op N, U for op T) of every
+// block of the sub-HODLR, MM_CH rows per block of threads.  Thread t takes
+// output e = t % nout (nout = k s) and every Q-th row of the chunk
+// (Q = NT_MM / nout groups), so all loads of a block are in flight together;
+// the Q partial sums are added in a fixed order.  A block of one chunk writes
+// its projection directly, longer blocks write per-chunk partials that
+// k_mm_red sums (a separate launch: no cross-block fences).
 __global__ void __launch_bounds__(NT_MM) k_mm_proj(const MmJob* __restrict__ jobs,
                                                     const MmProj* __restrict__ items, int first,
-                                                    double* ws, int* counters, double* fc) {
-  __shared__ double Ft[64][KCAP + 1];
-  __shared__ double Xt[64][SMAX + 1];
-  __shared__ int lastf;
+                                                    double* ws, double* fc) {
+  __shared__ double part_s[NT_MM];
   const int tid = threadIdx.x;
   const MmProj it = items[first + blockIdx.x];
-  const MmJob J = jobs[it.job];
+  const MmJob& J = jobs[it.job];
   const int s = mm_s(J);
   const HBlk b = (it.kind == 0 ? J.M.up : J.M.lo)[it.node];
   const int k = *b.rank;
   if (k == 0 || s == 0) return;
-  const int len = J.trans ? b.rows : b.cols;
-  const double* F = J.trans ? b.U : b.V;
-  const int ldF = J.trans ? b.ldU : b.ldV;
-  const int64_t xr0 = (J.trans ? b.r0 : b.c0) - J.row0;
-  const int c0 = it.chunk * CH;
-  const int cn = min(CH, len - c0);
-  double acc[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  const int trans = J.trans;
+  const int len = trans ? b.rows : b.cols;
+  const double* F = trans ? b.U : b.V;
+  const int ldF = trans ? b.ldU : b.ldV;
+  const double* X = J.X + ((trans ? b.r0 : b.c0) - J.row0);
+  const int ldX = J.ldX;
+  const int c0 = it.chunk * MM_CH;
+  const int cn = min(MM_CH, len - c0);
   const int nout = k * s;
-  for (int t0 = 0; t0 < cn; t0 += 64) {
-    const int tn = min(64, cn - t0);
-    for (int e = tid; e < 64 * k; e += NT_MM) {
-      const int r = e % 64, j = e / 64;
-      Ft[r][j] = (r < tn) ? F[(int64_t)(c0 + t0 + r) + (int64_t)j * ldF] : 0.0;
+  double* dst = ws + it.part;
+  if (nout <= NT_MM) {
+    const int Q = NT_MM / nout;
+    const int e = tid % nout, q = tid / nout;
+    double acc = 0.0;
+    if (q < Q) {
+      const int j = e % k, c = e / k;
+      const double* f = F + c0 + (int64_t)j * ldF;
+      const double* x = X + c0 + (int64_t)c * ldX;
+      for (int r = q; r < cn; r += Q) acc += f[r] * x[r];
     }
-    for (int e = tid; e < 64 * s; e += NT_MM) {
-      const int r = e % 64, cc = e / 64;
-      Xt[r][cc] = (r < tn) ? J.X[xr0 + c0 + t0 + r + (int64_t)cc * J.ldX] : 0.0;
-    }
+    part_s[tid] = acc;
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = tid + q * NT_MM;
-      if (e < nout) {
-        const int j = e % k, cc = e / k;
-        double sacc = acc[q];
-#pragma unroll 16
-        for (int r = 0; r < 64; ++r) sacc += Ft[r][j] * Xt[r][cc];
-        acc[q] = sacc;
-      }
-    }
-    __syncthreads();
-  }
-  double* red = ws + J.red0 + (int64_t)(2 * rel_node(it.node, J.v) + it.kind) * (KCAP * SMAX);
-  if (it.nchunk == 1) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = tid + q * NT_MM;
-      if (e < nout) red[(e % k) + (e / k) * KCAP] = acc[q];
+    if (tid < nout) {
+      double sacc = 0.0;
+      for (int q2 = 0; q2 < Q; ++q2) sacc += part_s[tid + q2 * nout];
+      dst[(tid % k) + (tid / k) * KCAP] = sacc;
     }
   } else {
-    double* part = ws + it.part;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = tid + q * NT_MM;
-      if (e < nout) part[(e % k) + (e / k) * KCAP] = acc[q];
-    }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-      const int old = atomicAdd(counters + it.counter, 1);
-      lastf = (old == it.nchunk - 1) ? 1 : 0;
-      if (lastf) atomicExch(counters + it.counter, 0);
-    }
-    __syncthreads();
-    if (lastf) {
-      __threadfence();
-      const double* part0 = ws + it.part - (int64_t)it.chunk * (KCAP * SMAX);
-      for (int e = tid; e < nout; e += NT_MM) {
-        const int j = e % k, cc = e / k;
-        double sacc = 0.0;
-        for (int ch = 0; ch < it.nchunk; ++ch)
-          sacc += part0[(int64_t)ch * (KCAP * SMAX) + j + cc * KCAP];
-        red[j + cc * KCAP] = sacc;
-      }
+    for (int e = tid; e < nout; e += NT_MM) {
+      const int j = e % k, c = e / k;
+      const double* f = F + c0 + (int64_t)j * ldF;
+      const double* x = X + c0 + (int64_t)c * ldX;
+      double acc = 0.0;
+      for (int r = 0; r < cn; ++r) acc += f[r] * x[r];
+      dst[j + c * KCAP] = acc;
     }
   }
   if (tid == 0) add_flops(fc, FC_HMAT, 2.0 * k * cn * s);
 }
 
+// Sum the per-chunk partials of one block projection (chunk order fixed).
+__global__ void __launch_bounds__(NT_MM) k_mm_red(const MmJob* __restrict__ jobs,
+                                                   const MmProj* __restrict__ items, int first,
+                                                   double* ws) {
+  const MmProj it = items[first + blockIdx.x];
+  const MmJob& J = jobs[it.job];
+  const int s = mm_s(J);
+  const HBlk b = (it.kind == 0 ? J.M.up : J.M.lo)[it.node];
+  const int k = *b.rank;
+  const double* part0 = ws + it.part;
+  double* red = ws + J.red0 + (int64_t)(2 * rel_node(it.node, J.v) + it.kind) * (KCAP * SMAX);
+  for (int e = threadIdx.x; e < k * s; e += NT_MM) {
+    const int off = (e % k) + (e / k) * KCAP;
+    double acc = 0.0;
+    for (int ch = 0; ch < it.nchunk; ++ch) acc += part0[(int64_t)ch * (KCAP * SMAX) + off];
+    red[off] = acc;
+  }
+}
+
 // Phase B: Z rows of one leaf = leaf part + the low-rank parts of every level.
+// A block takes RT rows of one leaf; thread (r, g) = (tid % RT, tid / RT).
+// Group g adds the leaf columns of its share and the low-rank parts of the
+// ancestor levels g, g + G, ...; the groups' partial rows are then summed in a
+// fixed order.  X of the leaf rows is staged in LDS, 16 columns at a time.
+//  RT = 16: the group's leaf columns kk = g, g + 16, ... are loaded into
+//           registers up front (short launches: one round trip of loads);
+//  RT = 64: the group streams a contiguous quarter of the columns, so a wave
+//           reads whole 512-byte column pieces (long launches: bandwidth).
+// Dynamic LDS: max(m_leaf, 256) * 17 doubles.
+constexpr int MA_LD = 17;
+
+__host__ __device__ constexpr size_t mm_apply_lds(int mleaf) {
+  return sizeof(double) * (size_t)MA_LD * (size_t)(mleaf > 256 ? mleaf : 256);
+}
+
+template <int RT>
+__device__ __forceinline__ double leaf_elem(const HLeaf& lf, int kind, int trans, int R, int kk) {
+  const int ii = trans ? kk : R, jj = trans ? R : kk;  // element D(ii, jj)
+  if (kind == LEAF_FULL) return lf.D[ii + (int64_t)jj * lf.ld];
+  if (kind == LEAF_UNIT_LOWER) return (ii > jj) ? lf.D[ii + (int64_t)jj * lf.ld] : (ii == jj ? 1.0 : 0.0);
+  return (ii <= jj) ? lf.D[ii + (int64_t)jj * lf.ld] : 0.0;
+}
+
+template <int RT>
 __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jobs,
                                                      const MmApply* __restrict__ items, int first,
                                                      const double* __restrict__ ws, double* fc) {
-  __shared__ double shm[64 * 33 + 32 * (SMAX + 1) + KCAP * SMAX];
-  double (*Dt)[33] = reinterpret_cast<double (*)[33]>(shm);
-  double (*Xt)[SMAX + 1] = reinterpret_cast<double (*)[SMAX + 1]>(shm + 64 * 33);
-  double (*Ft)[KCAP + 1] = reinterpret_cast<double (*)[KCAP + 1]>(shm);  // aliases Dt/Xt
-  double* Pt = shm + 64 * 33 + 32 * (SMAX + 1);
+  constexpr int G = NT_MM / RT;
+  constexpr int DMAX = RT == 16 ? MAXLEAF / G : 1;
+  extern __shared__ double shm[];
   const int tid = threadIdx.x;
+  const int r = tid % RT, g = tid / RT;
   const MmApply it = items[first + blockIdx.x];
-  const MmJob J = jobs[it.job];
+  const MmJob& J = jobs[it.job];
   const int s = mm_s(J);
   if (s == 0) return;
   const HLeaf lf = J.M.leaf[it.leaf];
-  const int r = tid & 63, cg = tid >> 6;
   const int kind = J.M.leaf_kind;
-  double acc[16];
+  const int trans = J.trans;
+  const int m = lf.m;
+  const int R = it.row0 + r;  // row of this thread within the leaf
+  const bool live = r < it.rows;
+  double dv[DMAX];
+  if constexpr (RT == 16) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  // leaf part
-  for (int k0 = 0; k0 < lf.m; k0 += 32) {
-    const int kn = min(32, lf.m - k0);
-    for (int e = tid; e < 64 * 32; e += NT_MM) {
-      int rr, kk;
-      if (J.trans) {
-        kk = e % 32;
-        rr = e / 32;
-      } else {
-        rr = e % 64;
-        kk = e / 64;
-      }
-      double x = 0.0;
-      if (rr < it.rows && kk < kn) {
-        const int R = it.row0 + rr, Kc = k0 + kk;
-        const int i = J.trans ? Kc : R, j = J.trans ? R : Kc;  // element D(i, j)
-        if (kind == LEAF_FULL)
-          x = lf.D[i + (int64_t)j * lf.ld];
-        else if (kind == LEAF_UNIT_LOWER)
-          x = (i > j) ? lf.D[i + (int64_t)j * lf.ld] : (i == j ? 1.0 : 0.0);
-        else
-          x = (i <= j) ? lf.D[i + (int64_t)j * lf.ld] : 0.0;
-      }
-      Dt[rr][kk] = x;
+    for (int i = 0; i < DMAX; ++i) {
+      const int kk = g + G * i;
+      dv[i] = (live && kk < m) ? leaf_elem<RT>(lf, kind, trans, R, kk) : 0.0;
     }
-    for (int e = tid; e < 32 * s; e += NT_MM) {
-      const int kk = e % 32, cc = e / 32;
-      Xt[kk][cc] = (kk < kn) ? J.X[(lf.r0 - J.row0 + k0 + kk) + (int64_t)cc * J.ldX] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int cc = cg + 4 * q;
-      if (cc < s) {
-        double sacc = acc[q];
-#pragma unroll 8
-        for (int kk = 0; kk < 32; ++kk) sacc += Dt[r][kk] * Xt[kk][cc];
-        acc[q] = sacc;
-      }
-    }
-    __syncthreads();
   }
-  double flops = 2.0 * it.rows * lf.m * s * (J.tri ? 0.5 : 1.0);
-  // low-rank parts, one block per ancestor level
+  const int q = (m + G - 1) / G;  // RT = 64: columns [g q, g q + q) of this group
+  const int kb0 = min(m, g * q), kb1 = min(m, g * q + q);
   const int hleaf = (1 << J.M.levels) + it.leaf;
-  int child = hleaf, u = hleaf >> 1;
-  while (child != J.v && u >= 1) {
-    const bool left = (child == 2 * u);
-    const int bk = J.trans ? (left ? 1 : 0) : (left ? 0 : 1);
-    const HBlk* arr = bk == 0 ? J.M.up : J.M.lo;
-    if (arr != nullptr) {
-      const HBlk b = arr[u];
-      const int kb = *b.rank;
-      if (kb > 0) {
-        const double* red = ws + J.red0 + (int64_t)(2 * rel_node(u, J.v) + bk) * (KCAP * SMAX);
-        const double* F = J.trans ? b.V : b.U;
-        const int ldF = J.trans ? b.ldV : b.ldU;
-        const int64_t frow = lf.r0 + it.row0 - (J.trans ? b.c0 : b.r0);  // first F row of this tile
-        for (int e = tid; e < kb * s; e += NT_MM) Pt[(e % kb) + (e / kb) * KCAP] = red[(e % kb) + (e / kb) * KCAP];
-        for (int e = tid; e < 64 * kb; e += NT_MM) {
-          const int rr = e % 64, j = e / 64;
-          Ft[rr][j] = (rr < it.rows) ? F[frow + rr + (int64_t)j * ldF] : 0.0;
-        }
-        __syncthreads();
-        for (int j = 0; j < kb; ++j) {
-          const double fv = Ft[r][j];
+  const double* xl = J.X + (lf.r0 - J.row0);
+  double* Xs = shm;
+  for (int c0 = 0; c0 < s; c0 += 16) {
+    const int cn = min(16, s - c0);
+    for (int e = tid; e < m * 16; e += NT_MM) {
+      const int kk = e % m, c = e / m;
+      Xs[kk * MA_LD + c] = (c < cn) ? xl[kk + (int64_t)(c0 + c) * J.ldX] : 0.0;
+    }
+    __syncthreads();
+    double acc[16];
 #pragma unroll
-          for (int q = 0; q < 16; ++q) {
-            const int cc = cg + 4 * q;
-            if (cc < s) acc[q] += fv * Pt[j + cc * KCAP];
+    for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+    if constexpr (RT == 16) {
+#pragma unroll
+      for (int i = 0; i < DMAX; ++i) {
+        const int kk = g + G * i;
+        if (kk < m) {
+          const double d = dv[i];
+#pragma unroll
+          for (int c = 0; c < 16; ++c) acc[c] += d * Xs[kk * MA_LD + c];
+        }
+      }
+    } else {
+      if (live) {
+#pragma unroll 8
+        for (int kk = kb0; kk < kb1; ++kk) {
+          const double d = leaf_elem<RT>(lf, kind, trans, R, kk);
+#pragma unroll
+          for (int c = 0; c < 16; ++c) acc[c] += d * Xs[kk * MA_LD + c];
+        }
+      }
+    }
+    // low-rank parts
+    int child = hleaf, u = hleaf >> 1, li = 0;
+    while (child != J.v && u >= 1) {
+      if (li % G == g) {
+        const bool left = (child == 2 * u);
+        const int bk = trans ? (left ? 1 : 0) : (left ? 0 : 1);
+        const HBlk* arr = bk == 0 ? J.M.up : J.M.lo;
+        if (arr != nullptr) {
+          const HBlk& b = arr[u];
+          const int kb = *b.rank;
+          const double* red = ws + J.red0 + (int64_t)(2 * rel_node(u, J.v) + bk) * (KCAP * SMAX) +
+                              (int64_t)c0 * KCAP;
+          const double* F = trans ? b.V : b.U;
+          const int ldF = trans ? b.ldV : b.ldU;
+          const int64_t frow = lf.r0 + R - (trans ? b.c0 : b.r0);
+          for (int j = 0; j < kb; ++j) {
+            const double fv = live ? F[frow + (int64_t)j * ldF] : 0.0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+              if (c < cn) acc[c] += fv * red[j + c * KCAP];
           }
         }
-        __syncthreads();
-        flops += 2.0 * it.rows * kb * s;
       }
+      child = u;
+      u >>= 1;
+      ++li;
     }
-    child = u;
-    u >>= 1;
-  }
-  if (r < it.rows) {
-    const int64_t zr = lf.r0 - J.row0 + it.row0 + r;
+    __syncthreads();  // Xs is reused for the partial rows
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int cc = cg + 4 * q;
-      if (cc < s) {
-        double* zp = J.Z + zr + (int64_t)cc * J.ldZ;
-        const double v = J.alpha * acc[q];
+    for (int c = 0; c < 16; ++c) shm[(g * RT + r) * MA_LD + c] = acc[c];
+    __syncthreads();
+    for (int e = tid; e < RT * 16; e += NT_MM) {
+      const int rr = e % RT, c = e / RT;
+      if (rr < it.rows && c < cn) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int g2 = 0; g2 < G; ++g2) sacc += shm[(g2 * RT + rr) * MA_LD + c];
+        double* zp = J.Z + (lf.r0 - J.row0 + it.row0 + rr) + (int64_t)(c0 + c) * J.ldZ;
+        const double v = J.alpha * sacc;
         *zp = (J.beta == 0.0) ? v : v + J.beta * (*zp);
       }
     }
+    __syncthreads();
   }
-  if (tid == 0) add_flops(fc, FC_HMAT, flops);
+  if (tid == 0) {
+    double flops = 2.0 * it.rows * m * s * (J.tri ? 0.5 : 1.0);
+    int child2 = hleaf, u2 = hleaf >> 1;
+    while (child2 != J.v && u2 >= 1) {
+      const bool left = (child2 == 2 * u2);
+      const int bk = trans ? (left ? 1 : 0) : (left ? 0 : 1);
+      const HBlk* arr = bk == 0 ? J.M.up : J.M.lo;
+      if (arr != nullptr) flops += 2.0 * it.rows * (*arr[u2].rank) * s;
+      child2 = u2;
+      u2 >>= 1;
+    }
+    add_flops(fc, FC_HMAT, flops);
+  }
 }
 
 // ------------------------------------------------------------------ small GEMMs
