@@ -1274,139 +1274,6 @@ constexpr int LF_W = LF_PART + 16 * NB * NB;     // 3 tiles of NB x NB
 constexpr int LF_TOTAL = LF_W + 3 * NB * NB;
 constexpr size_t LEAF_LDS = sizeof(double) * (size_t)LF_TOTAL;
 
-// Unblocked Householder QR of panel columns [c0, c0+pw) over rows [c0, M):
-// wavefront w owns column c0 + w, lane l owns rows c0 + l + 64 t.
-template <int RPT>
-__device__ __forceinline__ void leaf_panel_rows(LeafWs W, int c0, int pw, int M, double* sm) {
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int h = M - c0;
-  double* taus = sm + LF_TAU;
-  double* gram = sm + LF_GRAM;
-  double* Tp = sm + LF_TP;
-  double* col = W.H + (int64_t)(c0 + w) * MAXSTACK + c0;
-  double a[RPT];
-#pragma unroll
-  for (int t = 0; t < RPT; ++t) {
-    const int r = lane + 64 * t;
-    a[t] = (w < pw && r < h) ? col[r] : 0.0;
-  }
-  for (int j = 0; j < pw; ++j) {
-    double* vb = sm + LF_VBUF + (j & 1) * MAXSTACK;
-    if (w == j) {
-      double ss0 = 0.0, ss1 = 0.0;
-#pragma unroll
-      for (int t = 0; t < RPT; ++t) {
-        const int r = lane + 64 * t;
-        const double x = (r > j) ? a[t] : 0.0;
-        if (t & 1) ss1 += x * x; else ss0 += x * x;
-      }
-      const double ss = gsumt<64>(ss0 + ss1);
-      const double al = lane_read(a[0], j);  // row j < 16 sits in t = 0
-      double tau, beta, scal;
-      house_scalars(al, ss, beta, tau, scal);
-#pragma unroll
-      for (int t = 0; t < RPT; ++t) {
-        const int r = lane + 64 * t;
-        double v;
-        if (r > j) {
-          if (ss != 0.0) a[t] *= scal;
-          v = a[t];
-        } else if (r == j) {
-          a[t] = beta;
-          v = 1.0;
-        } else {
-          v = 0.0;
-        }
-        vb[r] = v;
-      }
-      if (lane == 0) taus[j] = tau;
-    }
-    __syncthreads();
-    const double tau = taus[j];
-    if (w > j && w < pw) {
-      if (tau != 0.0) {
-        double v[RPT];
-        double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-        for (int t = 0; t < RPT; ++t) {
-          v[t] = vb[lane + 64 * t];
-          if (t & 1) d1 += v[t] * a[t]; else d0 += v[t] * a[t];
-        }
-        const double f = tau * gsumt<64>(d0 + d1);
-#pragma unroll
-        for (int t = 0; t < RPT; ++t) a[t] -= f * v[t];
-      }
-    } else if (w < j) {
-      double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-      for (int t = 0; t < RPT; ++t) {
-        const double x = vb[lane + 64 * t] * a[t];
-        if (t & 1) d1 += x; else d0 += x;
-      }
-      const double d = gsumt<64>(d0 + d1);
-      if (lane == 0) gram[w + j * NB] = d;
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < RPT; ++t) {
-    const int r = lane + 64 * t;
-    if (w < pw && r < h) col[r] = a[t];
-  }
-  // T of the panel: T[0:j, j] = -tau_j T[0:j, 0:j] gram[0:j, j], T[j, j] = tau_j
-  for (int e = tid; e < NB * NB; e += NT_LEAF) Tp[e] = 0.0;
-  __syncthreads();
-  {
-    const int ti = (tid >> 4) & 15, tl = tid & 15;
-    for (int j = 0; j < pw; ++j) {
-      if (tid < 256) {
-        double sacc = 0.0;
-        if (ti < j && tl >= ti && tl < j) sacc = Tp[ti + tl * NB] * gram[tl + j * NB];
-        sacc = gsumt<16>(sacc);
-        if (ti < j && tl == 0) Tp[ti + j * NB] = -taus[j] * sacc;
-        if (tid == 0) Tp[j + j * NB] = taus[j];
-      }
-      __syncthreads();
-    }
-  }
-  for (int e = tid; e < NB * NB; e += NT_LEAF) {
-    const int i = e % NB, j = e / NB;
-    if (i < pw && j < pw) W.T[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] = Tp[e];
-  }
-}
-
-__device__ __forceinline__ void leaf_panel(LeafWs W, int c0, int pw, int M, double* sm) {
-  const int h = M - c0;
-  if (h <= 320)
-    leaf_panel_rows<5>(W, c0, pw, M, sm);
-  else if (h <= 576)
-    leaf_panel_rows<9>(W, c0, pw, M, sm);
-  else
-    leaf_panel_rows<16>(W, c0, pw, M, sm);
-}
-
-// Y_p(r, j), panel p starting at column/row c0, for rows r >= c0
-__device__ __forceinline__ double leaf_y(const LeafWs& W, int c0, int r, int j) {
-  const int rr = r - c0;
-  return rr < j ? 0.0 : (rr == j ? 1.0 : W.H[(int64_t)r + (int64_t)(c0 + j) * MAXSTACK]);
-}
-
-// Stage rows [r0, r0 + rn) of Y_p (unit lower panel at c0) and of the B
-// columns [cb, cb + bw) (unmasked) into LDS, zero-padded to LF_CH rows.
-__device__ __forceinline__ void leaf_stage(const LeafWs& W, int c0, int pw, int r0, int rn, int cb,
-                                           int bw, double* Ys, double* Bs) {
-  for (int e = threadIdx.x; e < LF_CH * NB; e += NT_LEAF) {
-    const int rr = e % LF_CH, jj = e / LF_CH;
-    const int r = r0 + rr;
-    double y = 0.0, bv = 0.0;
-    if (rr < rn) {
-      if (jj < pw) y = leaf_y(W, c0, r, jj);
-      if (jj < bw) bv = W.H[(int64_t)r + (int64_t)(cb + jj) * MAXSTACK];
-    }
-    Ys[rr + jj * LF_LD] = y;
-    Bs[rr + jj * LF_LD] = bv;
-  }
-}
-
 // acc += (Y^T B) over the staged rows: wavefront w takes 4-row steps w, w+16, ...
 __device__ __forceinline__ d4_t leaf_ytb_acc(const double* Ys, const double* Bs, int rn, d4_t acc) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -1436,6 +1303,176 @@ __device__ __forceinline__ void leaf_reduce_tile(d4_t acc, double* part, double*
   __syncthreads();
 }
 
+// Unblocked Householder QR of panel columns [c0, c0+pw) over rows [c0, M):
+// wavefront w owns column c0 + w, lane l owns rows c0 + l + 64 t.  Step j: the
+// owner forms reflector j and broadcasts it through LDS, the wavefronts of the
+// later columns apply it.  Afterwards the Gram matrix G = Y^T Y of the panel
+// (FP64 MFMA) gives T by eq. recqrcombined row by row: lane i of wavefront 0
+// runs T[i, j] = -tau_j sum_{i <= k < j} T[i, k] G[k, j] over j, T[i, i] = tau_i.
+template <int RPT>
+__device__ __forceinline__ void leaf_panel_rows(LeafWs W, int c0, int pw, int M, double* sm) {
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int h = M - c0;
+  double* taus = sm + LF_TAU;
+  double* gram = sm + LF_GRAM;
+  double* col = W.H + (int64_t)(c0 + w) * MAXSTACK + c0;
+  double a[RPT];
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int r = lane + 64 * t;
+    a[t] = (w < pw && r < h) ? col[r] : 0.0;
+  }
+  for (int j = 0; j < pw; ++j) {
+    double* vb = sm + LF_VBUF + (j & 1) * MAXSTACK;
+    if (w == j) {
+      double ss0 = 0.0, ss1 = 0.0;
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int r = lane + 64 * t;
+        const double x = (r > j) ? a[t] : 0.0;
+        if (t & 1) ss1 += x * x; else ss0 += x * x;
+      }
+      const double ss = gsumt<64>(ss0 + ss1);
+      const double al = lane_read(a[0], j);  // row j < 16 sits in t = 0
+      double tau, beta, scal;
+      house_scalars(al, ss, beta, tau, scal);
+      const double sc = (ss != 0.0) ? scal : 1.0;
+      {  // t = 0 holds rows 0..63, the only ones that can be <= j
+        const int r = lane;
+        const double x = a[0];
+        const double v = (r > j) ? x * sc : (r == j ? 1.0 : 0.0);
+        a[0] = (r > j) ? x * sc : (r == j ? beta : x);
+        vb[r] = v;
+      }
+#pragma unroll
+      for (int t = 1; t < RPT; ++t) {
+        a[t] *= sc;
+        vb[lane + 64 * t] = a[t];
+      }
+      if (lane == 0) taus[j] = tau;
+    }
+    __syncthreads();
+    if (w > j && w < pw) {
+      const double tau = taus[j];
+      if (tau != 0.0) {
+        double v[RPT];
+        double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          v[t] = vb[lane + 64 * t];
+          if (t & 1) d1 += v[t] * a[t]; else d0 += v[t] * a[t];
+        }
+        const double f = tau * gsumt<64>(d0 + d1);
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) a[t] -= f * v[t];
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int r = lane + 64 * t;
+    if (w < pw && r < h) col[r] = a[t];
+  }
+  // G = Y^T Y over the panel rows, LF_CH rows at a time through LDS
+  double* Ys = sm + LF_A;
+  d4_t acc = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = 0; r0 < h; r0 += LF_CH) {
+    const int rn = min(LF_CH, h - r0);
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int r = lane + 64 * t;
+      if (r >= r0 && r < r0 + LF_CH) {
+        double y = 0.0;
+        if (w < pw && r < h) y = r > w ? a[t] : (r == w ? 1.0 : 0.0);
+        Ys[(r - r0) + w * LF_LD] = y;
+      }
+    }
+    if (tid < 4 * NB) Ys[LF_CH + (tid & 3) + (tid >> 2) * LF_LD] = 0.0;  // pad rows of the last k-step
+    __syncthreads();
+    acc = leaf_ytb_acc(Ys, Ys, rn, acc);
+    __syncthreads();
+  }
+  leaf_reduce_tile(acc, sm + LF_PART, gram);
+  // T by eq. recqrcombined, doubling the block size: on blocks B1 = [2ab, 2ab+b)
+  // and B2 = [2ab+b, 2ab+2b), T[B1, B2] = -T[B1, B1] (Y_B1^T Y_B2) T[B2, B2]
+  double* Tp = sm + LF_TP;
+  double* Xt = sm + LF_W;
+  if (tid < NB * NB) {
+    const int i = tid % NB, j = tid / NB;
+    Tp[tid] = (i == j && i < pw) ? taus[i] : 0.0;
+  }
+  __syncthreads();
+  for (int b = 1; b < NB; b *= 2) {
+    const int e = tid, bb = b * b;
+    const bool act = e < (NB / (2 * b)) * bb;
+    const int pa = e / bb, rc = e % bb, r = rc % b, c = rc / b;
+    const int i = 2 * pa * b + r, j = 2 * pa * b + b + c;
+    if (act) {
+      double x = 0.0;
+      for (int k = 2 * pa * b + b; k < 2 * pa * b + 2 * b; ++k) x += gram[i + NB * k] * Tp[k + NB * j];
+      Xt[i + NB * j] = x;
+    }
+    __syncthreads();
+    if (act) {
+      double y = 0.0;
+      for (int k = 2 * pa * b; k < 2 * pa * b + b; ++k) y += Tp[i + NB * k] * Xt[k + NB * j];
+      Tp[i + NB * j] = -y;
+    }
+    __syncthreads();
+  }
+  if (tid < NB * NB) {
+    const int i = tid % NB, j = tid / NB;
+    if (i < pw && j < pw) W.T[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] = Tp[tid];
+  }
+}
+
+__device__ __forceinline__ void leaf_panel(LeafWs W, int c0, int pw, int M, double* sm) {
+  const int h = M - c0;
+  if (h <= 320)
+    leaf_panel_rows<5>(W, c0, pw, M, sm);
+  else if (h <= 576)
+    leaf_panel_rows<9>(W, c0, pw, M, sm);
+  else
+    leaf_panel_rows<16>(W, c0, pw, M, sm);
+}
+
+// Y_p(r, j), panel p starting at column/row c0, for rows r >= c0
+__device__ __forceinline__ double leaf_y(const LeafWs& W, int c0, int r, int j) {
+  const int rr = r - c0;
+  return rr < j ? 0.0 : (rr == j ? 1.0 : W.H[(int64_t)r + (int64_t)(c0 + j) * MAXSTACK]);
+}
+
+// Stage rows [r0, r0 + rn) of Y_p (unit lower panel at c0) and of the B
+// columns [cb, cb + bw) (unmasked) into LDS, zero-padded to LF_CH rows.  All
+// loads of a thread are issued (from clamped, in-bounds addresses) before any
+// LDS store, so the staging costs one round trip to memory.
+__device__ __forceinline__ void leaf_stage(const LeafWs& W, int c0, int pw, int r0, int rn, int cb,
+                                           int bw, double* Ys, double* Bs) {
+  constexpr int PER = (LF_CH * NB + NT_LEAF - 1) / NT_LEAF;
+  double y[PER], bv[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * NT_LEAF;
+    const int rr = e % LF_CH, jj = e / LF_CH;
+    const bool row_ok = rr < rn && jj < NB;
+    const int r = row_ok ? r0 + rr : r0;
+    const int rel = r - c0;
+    const double yv = W.H[(int64_t)r + (int64_t)(c0 + (jj < pw ? jj : 0)) * MAXSTACK];
+    const double bb = W.H[(int64_t)r + (int64_t)(cb + (jj < bw ? jj : 0)) * MAXSTACK];
+    y[q] = (row_ok && jj < pw) ? (rel < jj ? 0.0 : (rel == jj ? 1.0 : yv)) : 0.0;
+    bv[q] = (row_ok && jj < bw) ? bb : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * NT_LEAF;
+    if (e < LF_CH * NB) {
+      const int rr = e % LF_CH, jj = e / LF_CH;
+      Ys[rr + jj * LF_LD] = y[q];
+      Bs[rr + jj * LF_LD] = bv[q];
+    }
+  }
+}
+
 // S = Y_p^T B over rows [c0, M) into sm[LF_W] (16 x 16, ld NB).
 __device__ __forceinline__ void leaf_ytb(const LeafWs& W, int c0, int pw, int M, int cb, int bw,
                                          double* sm) {
@@ -1462,9 +1499,10 @@ __device__ __forceinline__ void leaf_strip(const LeafWs& W, int c0, int pw, int 
   double* Wt = sm + LF_W;
   double* W2 = Wt + NB * NB;
   double* Tt = W2 + NB * NB;
+  double tval = 0.0;  // T_pp tile, loaded together with the first staging
   if (tid < 256) {
     const int i = tid & 15, j = tid >> 4;
-    Tt[tid] = (i <= j && i < pw && j < pw) ? W.T[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] : 0.0;
+    tval = (i <= j && i < pw && j < pw) ? W.T[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] : 0.0;
   }
   d4_t acc = {0.0, 0.0, 0.0, 0.0};
   const bool one_chunk = (M - c0) <= LF_CH;
@@ -1475,6 +1513,7 @@ __device__ __forceinline__ void leaf_strip(const LeafWs& W, int c0, int pw, int 
     acc = leaf_ytb_acc(Ys, Bs, rn, acc);
     __syncthreads();
   }
+  if (tid < 256) Tt[tid] = tval;
   leaf_reduce_tile(acc, sm + LF_PART, Wt);
   if (tid < 256) {  // W2 = T^T W
     const int i = tid & 15, j = tid >> 4;
