@@ -110,6 +110,29 @@ hodlr_status hodlr_qr(const hodlr_t *A, double eps, double anorm, uint32_t flags
                       hodlr_stream_t stream, hodlr_qr_t **out);
 
 /*
+ * hodlr_qr_batched - hodlr_qr of `count` independent matrices A[0..count-1] at
+ * once (Algorithm hQR for each).  Matrices with the same partition and
+ * rank_cap share one schedule: every launch of it carries the jobs of all of
+ * them, so they advance through the recursion in lockstep; groups of different
+ * shape run one after another.  Each factorisation computes exactly what
+ * hodlr_qr computes for that matrix alone (bitwise: no kernel mixes jobs).
+ *  anorm  host array of count values (<= 0: estimate) or NULL (estimate all).
+ *  out    host array of count handles, released with hodlr_qr_free one by one.
+ * On error no handle is returned; the message names the first failing matrix.
+ */
+hodlr_status hodlr_qr_batched(const hodlr_t *const *A, int32_t count, double eps,
+                              const double *anorm, uint32_t flags, hodlr_stream_t stream,
+                              hodlr_qr_t **out);
+
+/*
+ * hodlr_qr_batched_time - as hodlr_qr_time for hodlr_qr_batched: per-run
+ * durations (ms, host array of reps) of factorising the whole batch.
+ */
+hodlr_status hodlr_qr_batched_time(const hodlr_t *const *A, int32_t count, double eps,
+                                   const double *anorm, uint32_t flags, int32_t warmup,
+                                   int32_t reps, hodlr_stream_t stream, double *ms);
+
+/*
  * hodlr_apply_q - X <- Q X (trans = 0) or X <- Q^T X (trans = 1), with
  * Q = I - Y T Y^T (eq. compactwy).  X: device, n x nrhs, leading dimension
  * ldx >= n.  Asynchronous.

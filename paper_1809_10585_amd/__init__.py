@@ -19,7 +19,8 @@ from ._lib import HODLR_QR_GRAPH, HODLR_QR_ONE_STREAM, HodlrError, QRInfo
 __all__ = [
     "hodlr_build", "hodlr_qr", "hodlr_apply_q", "hodlr_solve", "hodlr_matmul", "hodlr_qr_matmul",
     "hodlr_norm2_est", "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time",
-    "hodlr_qr_profile", "HodlrMatrix", "QRFactors", "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "load",
+    "hodlr_qr_profile", "hodlr_qr_batched", "hodlr_qr_batched_time", "HodlrMatrix", "QRFactors",
+    "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "load",
 ]
 
 load = _lib.load
@@ -106,6 +107,41 @@ def hodlr_qr(A: HodlrMatrix, eps: float, anorm: float = 0.0, flags: int = 0, str
     h = C.c_void_p()
     _lib.check(lib.hodlr_qr(A.handle, float(eps), float(anorm), int(flags), _stream(stream), C.byref(h)))
     return QRFactors(h, A)
+
+
+def _handles(As):
+    arr = (C.c_void_p * len(As))(*[A.handle for A in As])
+    return C.cast(arr, C.POINTER(C.c_void_p)), arr
+
+
+def _anorms(anorm, count):
+    if anorm is None:
+        return None, None
+    a = np.ascontiguousarray(np.broadcast_to(np.asarray(anorm, dtype=np.float64), (count,)))
+    return _ptr(a, C.c_double), a
+
+
+def hodlr_qr_batched(As, eps: float, anorm=None, flags: int = 0, stream=None) -> list:
+    """hodlr_qr of every matrix of As in shared launches; anorm: None, a value
+    or one value per matrix (<= 0: estimate)."""
+    lib = load()
+    hp, keep = _handles(As)
+    ap, akeep = _anorms(anorm, len(As))
+    out = (C.c_void_p * len(As))()
+    _lib.check(lib.hodlr_qr_batched(hp, len(As), float(eps), ap, int(flags), _stream(stream),
+                                    C.cast(out, C.POINTER(C.c_void_p))))
+    return [QRFactors(C.c_void_p(out[i]), A) for i, A in enumerate(As)]
+
+
+def hodlr_qr_batched_time(As, eps: float, anorm=None, flags: int = 0, warmup: int = 1, reps: int = 3,
+                          stream=None):
+    """Per-run wall times (ms) of factorising the whole batch."""
+    hp, keep = _handles(As)
+    ap, akeep = _anorms(anorm, len(As))
+    ms = np.zeros(reps)
+    _lib.check(load().hodlr_qr_batched_time(hp, len(As), float(eps), ap, int(flags), int(warmup), int(reps),
+                                            _stream(stream), _ptr(ms, C.c_double)))
+    return ms
 
 
 def hodlr_apply_q(F: QRFactors, X, trans: bool = False, stream=None):

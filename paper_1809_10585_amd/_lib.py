@@ -20,7 +20,7 @@ HODLR_QR_ONE_STREAM = 2
 EXPORTS = [
     "hodlr_build", "hodlr_qr", "hodlr_apply_q", "hodlr_solve", "hodlr_matmul", "hodlr_qr_matmul",
     "hodlr_norm2_est", "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time",
-    "hodlr_qr_profile", "hodlr_op_name", "hodlr_op_count",
+    "hodlr_qr_profile", "hodlr_op_name", "hodlr_op_count", "hodlr_qr_batched", "hodlr_qr_batched_time",
     "hodlr_free", "hodlr_qr_free", "hodlr_last_error", "hodlr_version",
 ]
 
@@ -77,6 +77,8 @@ def load(path: str = LIB_PATH):
         "hodlr_qr_export": (I32, [P, C.c_char, PD, PD, PI64, PD, PI64, PI32]),
         "hodlr_qr_time": (I32, [P, D, D, C.c_uint32, I32, I32, P, PD]),
         "hodlr_qr_profile": (I32, [P, D, D, I32, PD, PI64, PD, P]),
+        "hodlr_qr_batched": (I32, [PP, I32, D, PD, C.c_uint32, P, PP]),
+        "hodlr_qr_batched_time": (I32, [PP, I32, D, PD, C.c_uint32, I32, I32, P, PD]),
         "hodlr_op_name": (C.c_char_p, [I32]),
         "hodlr_op_count": (I32, []),
         "hodlr_free": (None, [P]),

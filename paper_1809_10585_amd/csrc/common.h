@@ -74,6 +74,8 @@ struct TrJob {
   int jcounter;     // counter joining the two sides
   int fc;           // flop category
   int64_t hdr;      // offset (doubles) of the job header in the workspace
+  int* err;         // error word of the factorisation the job belongs to
+  double* flops;    // flop counters of that factorisation
 };
 
 struct TrChunk {    // one block of the first recompression kernel
@@ -132,6 +134,7 @@ struct MmJob {
   int64_t red0;        // reduced projection of node u, kind t at
                        // red0 + (2*(rel(u)) + t) * KCAP*SMAX
   int tri;             // triangular operand (halves the leaf flop count)
+  double* flops;
 };
 
 struct MmProj {      // phase A: one row chunk of one block projection
@@ -163,6 +166,7 @@ struct GemmJob {
   int ldc;
   double alpha, beta;
   int fc;
+  double* flops;
 };
 
 struct GemmTile {    // 64 x 64 output tile of a tall GEMM
@@ -187,18 +191,29 @@ struct LeafGroup {
   const int* rank;
 };
 
-struct LeafJob {
-  double* D;        // leaf (m x m, ld m): A on input, R + Y on output
-  int m;
-  double* Tleaf;    // T leaf output (m x m, ld m)
-  int ngroups;
-  LeafGroup g[MAXGROUPS];
-};
-
-struct LeafWs {     // shared workspace of the leaf QR (leaves run one at a time)
+struct LeafWs {     // workspace of one leaf QR (one per factorisation: its leaves run in turn)
   double* H;        // stacked matrix, ld MAXSTACK
   double* T;        // T (MAXLEAF x MAXLEAF, ld MAXLEAF)
   double* G;        // Y^T Y blocks above the panel diagonal (ld MAXLEAF)
 };
+struct LeafJob {
+  double* D;        // leaf (m x m, ld m): A on input, R + Y on output
+  int m;
+  double* Tleaf;    // T leaf output (m x m, ld m)
+  LeafWs ws;
+  int* err;
+  double* flops;
+  int ngroups;
+  LeafGroup g[MAXGROUPS];
+};
+struct VecJob {     // one vector of a batched fill / normalise / threshold op
+  const double* z;
+  double* x;
+  int64_t n;
+  double* out;
+  double d0, d1;
+};
+
+
 
 }  // namespace hq

@@ -237,6 +237,8 @@ struct TrSpec {
   int cap;
   int* out_rank;
   int fc;
+  int* err;
+  double* flops;
 };
 
 struct MmSpec {
@@ -251,6 +253,7 @@ struct MmSpec {
   int ldZ;
   double alpha, beta;
   int tri;
+  double* flops = nullptr;
 };
 
 struct GSpec {  // gemm job with host-side capacities for tiling
@@ -281,6 +284,7 @@ struct Plan {
   std::vector<GemmTile> gt;
   std::vector<GemmRed> gr;
   std::vector<LeafJob> lj;
+  std::vector<VecJob> vj;
   std::vector<Op> ops;
   // Workspace and counters are reused by consecutive ops of one lane; the two
   // lanes get disjoint regions because their ops may run at the same time.
@@ -307,6 +311,12 @@ struct Plan {
     o.a0 = ev;
     push(o);
   }
+  // one launch over vector items (fill / normalise / thresholds)
+  void vec(int type, const std::vector<VecJob>& items) {
+    const int first = (int)vj.size();
+    vj.insert(vj.end(), items.begin(), items.end());
+    push(Op{type, first, (int)items.size()});
+  }
   int64_t n_trunc = 0;
   int wtop = WMAX;  // widest recompression this plan can produce
   int mleaf = 0;    // largest leaf any product of this plan touches
@@ -321,6 +331,7 @@ struct Plan {
   GemmTile* d_gt = nullptr;
   GemmRed* d_gr = nullptr;
   LeafJob* d_lj = nullptr;
+  VecJob* d_vj = nullptr;
 
   void trunc(const std::vector<TrSpec>& specs) {
     if (specs.empty()) return;
@@ -340,6 +351,8 @@ struct Plan {
       J.cap = sp.cap;
       J.out_rank = sp.out_rank;
       J.fc = sp.fc;
+      J.err = sp.err;
+      J.flops = sp.flops;
       J.hdr = off;
       off += TR_HDR;
       for (int side = 0; side < 2; ++side) {
@@ -411,6 +424,7 @@ struct Plan {
       J.beta = sp.beta;
       J.row0 = t.lo[sp.v];
       J.tri = sp.tri;
+      J.flops = sp.flops;
       J.red0 = off;
       off += 2 * (int64_t)t.subtree_size(sp.v) * KCAP * SMAX;
       const int jid = (int)mmj.size();
@@ -498,6 +512,7 @@ struct Plan {
     TRY(upload(mem, &d_gt, gt, st));
     TRY(upload(mem, &d_gr, gr, st));
     TRY(upload(mem, &d_lj, lj, st));
+    TRY(upload(mem, &d_vj, vj, st));
     return HODLR_OK;
   }
 };
@@ -586,10 +601,7 @@ void launch(const Launch& L, void (*kern)(P...), dim3 g, dim3 b, size_t sh, hipS
   (void)hipExtLaunchKernel((const void*)kern, g, b, args, sh, st, L.e0, L.e1, 0);
 }
 
-bool op_launches(const Op& o) {
-  return o.count > 0 || o.type == OP_FILL || o.type == OP_NORMALIZE || o.type == OP_LPANEL ||
-         o.type == OP_SETSCAL;
-}
+bool op_launches(const Op& o) { return o.count > 0 && o.type != OP_SIGNAL && o.type != OP_WAIT; }
 
 void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st, const Launch& L = Launch()) {
   if (!op_launches(o)) return;
@@ -599,46 +611,46 @@ void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st, const Lau
     case OP_TRQR: {
       const int wt = P.wtop;
       auto kern = wt <= 16 ? k_tr_qr<16> : wt <= 32 ? k_tr_qr<32> : wt <= 64 ? k_tr_qr<64> : k_tr_qr<128>;
-      launch(L, kern, o.count, NT_TR, TR_QR_LDS, st, P.d_trj, P.d_trc, o.first, ws, cnt, W.err, W.fc);
+      launch(L, kern, o.count, NT_TR, TR_QR_LDS, st, P.d_trj, P.d_trc, o.first, ws, cnt);
       break;
     }
     case OP_TRFORM:
       launch(L, k_tr_form, o.count, NT_MM, TR_FORM_LDS, st, P.d_trj, P.d_trf, o.first, ws);
       break;
     case OP_MMPROJ:
-      launch(L, k_mm_proj, o.count, NT_MM, 0, st, P.d_mmj, P.d_mmp, o.first, ws, W.fc);
+      launch(L, k_mm_proj, o.count, NT_MM, 0, st, P.d_mmj, P.d_mmp, o.first, ws);
       break;
     case OP_MMRED:
       launch(L, k_mm_red, o.count, NT_MM, 0, st, P.d_mmj, P.d_mmp, o.first, ws);
       break;
     case OP_MMAPPLY:
       launch(L, o.a1 == 64 ? k_mm_apply<64> : k_mm_apply<16>, o.count, NT_MM, mm_apply_lds(P.mleaf), st,
-             P.d_mmj, P.d_mma, o.first, (const double*)ws, W.fc);
+             P.d_mmj, P.d_mma, o.first, (const double*)ws);
       break;
     case OP_GTALL:
-      launch(L, k_gemm_tall, o.count, NT_MM, 0, st, P.d_gj, P.d_gt, o.first, W.fc);
+      launch(L, k_gemm_tall, o.count, NT_MM, 0, st, P.d_gj, P.d_gt, o.first);
       break;
     case OP_GRED:
-      launch(L, k_gemm_red, o.count, NT_MM, 0, st, P.d_gj, P.d_gr, o.first, ws, cnt, W.fc);
+      launch(L, k_gemm_red, o.count, NT_MM, 0, st, P.d_gj, P.d_gr, o.first, ws, cnt);
       break;
     case OP_LGATHER:
-      launch(L, k_leaf_gather, o.count, NT_MM, 0, st, P.d_lj, o.a0, W.leaf, W.err);
+      launch(L, k_leaf_gather, o.count, NT_MM, 0, st, P.d_lj, o.first, (int)o.n);
       break;
     case OP_LPANEL:
     case OP_LUPDATE:
-      launch(L, k_leaf_step, o.count, NT_LEAF, LEAF_LDS, st, P.d_lj, o.a0, W.leaf, o.a1, W.err, W.fc);
+      launch(L, k_leaf_step, o.count, NT_LEAF, LEAF_LDS, st, P.d_lj, o.first, (int)o.n, o.a1);
       break;
     case OP_LSCATTER:
-      launch(L, k_leaf_scatter, o.count, NT_MM, 0, st, P.d_lj, o.a0, W.leaf, W.err, W.fc);
+      launch(L, k_leaf_scatter, o.count, NT_MM, 0, st, P.d_lj, o.first, (int)o.n);
       break;
     case OP_FILL:
-      launch(L, k_fill, (unsigned)((o.n + 255) / 256), 256, 0, st, o.p1, o.n, o.d0);
+      launch(L, k_fill_items, o.count, 256, 0, st, P.d_vj, o.first);
       break;
     case OP_NORMALIZE:
-      launch(L, k_normalize, 1, 1024, 0, st, o.p0, o.p1, o.n, o.pout);
+      launch(L, k_normalize, o.count, 1024, 0, st, P.d_vj, o.first);
       break;
     case OP_SETSCAL:
-      launch(L, k_set_scal, 1, 64, 0, st, o.p1, o.d0, o.d1);
+      launch(L, k_set_scal, (o.count + 63) / 64, 64, 0, st, P.d_vj, o.first, o.count);
       break;
     case OP_TRSM:
       launch(L, k_leaf_trsm, o.count, NT_MM, 0, st, o.p0, o.a0, o.a0, o.p1, (int)o.n, o.count);
@@ -693,6 +705,25 @@ struct hodlr_s {
   Work work;  // for products / norm estimates
 };
 
+// The launch schedule of one batch of factorisations that share a tree: one
+// plan whose every launch carries the jobs of all of them, the workspace of
+// that plan, the second stream and its events, and the captured graph.
+struct Batch {
+  Plan plan;
+  Work work;  // ws and counters of the plan (per-factorisation words live in each factor)
+  DMem mem;
+  hipGraphExec_t graph = nullptr;
+  hipStream_t aux = nullptr;       // stream of the T-factor lane
+  std::vector<hipEvent_t> events;  // plan events + fork + join
+  int64_t n_launch = 0;
+  int size = 0;
+  ~Batch() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (aux) (void)hipStreamDestroy(aux);
+  }
+};
+
 struct hodlr_qr_s {
   Tree t;
   int cap = 0;
@@ -701,22 +732,14 @@ struct hodlr_qr_s {
   BlockSet up, lo, tup;
   int* ranks = nullptr;  // up | lo | t | scalars
   double anorm = 0, eps = 0, tauA = 0, tauT = 0;
+  double anorm_in = 0;     // |A|_2 given by the caller (<= 0: estimated)
   double* scal = nullptr;  // device: |A|_2, eps*|A|_2, eps
-  Work work;
+  Work work;               // error word, flop counters, leaf workspace; ws of apply/solve
   // temporaries of the node steps (n x cap each)
   double *SL = nullptr, *SR = nullptr, *SLt = nullptr, *Z1 = nullptr, *Z2 = nullptr, *Z4 = nullptr,
          *SRW = nullptr, *TL = nullptr, *TR = nullptr, *Z5 = nullptr, *Wm = nullptr, *Mg = nullptr;
-  double *X1 = nullptr, *X2 = nullptr;  // n x SMAX scratch of apply_q / solve
-  Plan plan;
-  hipGraphExec_t graph = nullptr;
-  hipStream_t aux = nullptr;        // stream of the T-factor lane
-  std::vector<hipEvent_t> events;   // plan events + fork + join
-  int64_t n_launch = 0;
-  ~hodlr_qr_s() {
-    if (graph) (void)hipGraphExecDestroy(graph);
-    for (hipEvent_t e : events) (void)hipEventDestroy(e);
-    if (aux) (void)hipStreamDestroy(aux);
-  }
+  double *X1 = nullptr, *X2 = nullptr;  // n x SMAX scratch of apply_q / solve / the norm estimate
+  std::shared_ptr<Batch> batch;          // the schedule this factor was computed with
   HView view_gen() const { return HView{t.L, up.dview, lo.dview, leaves.dview, LEAF_FULL}; }
   HView view_y() const { return HView{t.L, nullptr, lo.dview, leaves.dview, LEAF_UNIT_LOWER}; }
   HView view_t() const { return HView{t.L, tup.dview, nullptr, tleaves.dview, LEAF_UPPER}; }
@@ -730,7 +753,7 @@ struct hodlr_qr_s {
 namespace {
 
 MmSpec mmspec(HView M, bool up, bool lo, int v, int trans, const double* X, int ldX, const int* s_dev,
-              double* Z, int ldZ, double alpha, double beta, int tri, int s = 0) {
+              double* Z, int ldZ, double alpha, double beta, int tri, int s = 0, double* flops = nullptr) {
   MmSpec m;
   m.M = M;
   m.has_up = up;
@@ -746,12 +769,13 @@ MmSpec mmspec(HView M, bool up, bool lo, int v, int trans, const double* X, int 
   m.alpha = alpha;
   m.beta = beta;
   m.tri = tri;
+  m.flops = flops;
   return m;
 }
 
 GemmJob gjob(int ta, int tb, int M, const int* Md, int N, const int* Nd, int K, const int* Kd,
              const double* A, int lda, const double* B, int ldb, double* C, int ldc, double alpha,
-             double beta, int fc) {
+             double beta, int fc, double* flops = nullptr) {
   GemmJob J;
   J.ta = ta;
   J.tb = tb;
@@ -770,47 +794,63 @@ GemmJob gjob(int ta, int tb, int M, const int* Md, int N, const int* Nd, int K, 
   J.alpha = alpha;
   J.beta = beta;
   J.fc = fc;
+  J.flops = flops;
   return J;
 }
 
-// Builds the launch list of one factorisation (Algorithm hQR, depth first).
+// Builds the launch list of a batch of factorisations with the same tree
+// (Algorithm hQR, depth first): every step issues one launch holding the jobs
+// of all factors of the batch, so the factors progress in lockstep.
 struct QRBuilder {
-  hodlr_qr_s& F;
+  std::vector<hodlr_qr_s*> Fs;
   Plan& P;
   const Tree& t;
   int cap;
-  QRBuilder(hodlr_qr_s& f) : F(f), P(f.plan), t(f.t), cap(f.cap) {}
+  QRBuilder(const std::vector<hodlr_qr_s*>& fs, Plan& plan)
+      : Fs(fs), P(plan), t(fs[0]->t), cap(fs[0]->cap) {}
 
   // right factor slice of ancestor g's lower block over node x's columns
-  double* gslice(int g, int x) { return F.lo.hview[g].V + (t.lo[x] - t.lo[2 * g]); }
+  double* gslice(hodlr_qr_s& F, int g, int x) { return F.lo.hview[g].V + (t.lo[x] - t.lo[2 * g]); }
   int gld(int g) { return (int)t.m(2 * g); }
 
   void leaf(int v, const std::vector<int>& groups) {
     const int j = v - t.nleaf();
-    LeafJob J{};
-    J.D = F.leaves.hview[j].D;
-    J.m = (int)t.m(v);
-    J.Tleaf = F.tleaves.hview[j].D;
-    J.ngroups = (int)groups.size();
-    for (size_t i = 0; i < groups.size(); ++i) {
-      const int g = groups[i];
-      J.g[i] = LeafGroup{F.lo.hview[g].V, gld(g), (int)(t.lo[v] - t.lo[2 * g]), F.rank_lo(g)};
+    const int first = (int)P.lj.size();
+    const int m = (int)t.m(v), np = (m + NB - 1) / NB;
+    for (hodlr_qr_s* Fp : Fs) {
+      hodlr_qr_s& F = *Fp;
+      LeafJob J{};
+      J.D = F.leaves.hview[j].D;
+      J.m = m;
+      J.Tleaf = F.tleaves.hview[j].D;
+      J.ws = F.work.leaf;
+      J.err = F.work.err;
+      J.flops = F.work.fc;
+      J.ngroups = (int)groups.size();
+      for (size_t i = 0; i < groups.size(); ++i) {
+        const int g = groups[i];
+        J.g[i] = LeafGroup{F.lo.hview[g].V, gld(g), (int)(t.lo[v] - t.lo[2 * g]), F.rank_lo(g)};
+      }
+      P.lj.push_back(J);
     }
-    const int jid = (int)P.lj.size();
-    P.lj.push_back(J);
-    const int m = J.m, np = (m + NB - 1) / NB;
-    P.push(Op{OP_LGATHER, 0, m, jid});
-    P.push(Op{OP_LPANEL, 0, 1, jid, -1});  // panel 0
+    const int nj = (int)Fs.size();
+    auto leafop = [&](int type, int nper, int p) {
+      Op o{type, first, nj * nper, 0, p};
+      o.n = nper;
+      P.push(o);
+    };
+    leafop(OP_LGATHER, m, 0);
+    leafop(OP_LPANEL, 1, -1);  // panel 0
     for (int p = 0; p <= np; ++p) {
       const int nstrip = p < np ? np - p - 1 : 0, ngram = p < np ? p : 0, ntile = p >= 1 ? p - 1 : 0;
       const int cnt = nstrip + ngram + ntile;
-      if (cnt > 0) P.push(Op{OP_LUPDATE, 0, cnt, jid, p});
+      if (cnt > 0) leafop(OP_LUPDATE, cnt, p);
     }
-    P.push(Op{OP_LSCATTER, 0, m, jid});
+    leafop(OP_LSCATTER, m, 0);
   }
 
-  TrSpec trspec(Seg l0, Seg l1, Seg r0, Seg r1, int mL, int mR, const double* tau, double* oL, double* oR,
-                int ldL, int ldR, int* orank, int fc, int flags = 0) {
+  TrSpec trspec(hodlr_qr_s& F, Seg l0, Seg l1, Seg r0, Seg r1, int mL, int mR, const double* tau,
+                double* oL, double* oR, int ldL, int ldR, int* orank, int fc, int flags = 0) {
     TrSpec s;
     s.seg[0][0] = l0;
     s.seg[0][1] = l1;
@@ -827,6 +867,8 @@ struct QRBuilder {
     s.cap = cap;
     s.out_rank = orank;
     s.fc = fc;
+    s.err = F.work.err;
+    s.flops = F.work.fc;
     return s;
   }
 
@@ -842,91 +884,140 @@ struct QRBuilder {
     }
     const int Lc = 2 * v, Rc = 2 * v + 1;
     const int mL = (int)t.m(Lc), mR = (int)t.m(Rc);
-    const HBlk& A12 = F.up.hview[v];
-    const HBlk& A21 = F.lo.hview[v];
-    int* k12 = F.rank_up(v);
-    int* k21 = F.rank_lo(v);
-    int* rS = F.rank_s();
     // first block column: hQR(A11, A21, [B_R1; C1])
     std::vector<int> gl;
     gl.push_back(v);
     gl.insert(gl.end(), groups.begin(), groups.end());
     const int evL = node(Lc, gl);
+    std::vector<MmSpec> mms;
+    std::vector<TrSpec> trs;
     // S~ terms: Z1 = Y_A11^T U12 and Z2 = A22^T U21 (one launch pair)
-    P.mm(t, {mmspec(F.view_y(), false, true, Lc, 1, A12.U, mL, k12, F.Z1, mL, 1.0, 0.0, 1),
-             mmspec(F.view_gen(), true, true, Rc, 1, A21.U, mR, k21, F.Z2, mR, 1.0, 0.0, 0)});
+    for (hodlr_qr_s* Fp : Fs) {
+      hodlr_qr_s& F = *Fp;
+      const HBlk& A12 = F.up.hview[v];
+      const HBlk& A21 = F.lo.hview[v];
+      mms.push_back(mmspec(F.view_y(), false, true, Lc, 1, A12.U, mL, F.rank_up(v), F.Z1, mL, 1.0, 0.0, 1, 0,
+                           F.work.fc));
+      mms.push_back(mmspec(F.view_gen(), true, true, Rc, 1, A21.U, mR, F.rank_lo(v), F.Z2, mR, 1.0, 0.0, 0,
+                           0, F.work.fc));
+    }
+    P.mm(t, mms);
     // S~ = T(Y_A11^T A12 + Y_A21^T A22 + sum over groups), term by term
-    P.trunc({trspec(mkseg(F.Z1, mL, k12), mkseg(A21.V, mL, k21), mkseg(A12.V, mR, k12),
-                    mkseg(F.Z2, mR, k21), mL, mR, F.scal + 1, F.SL, F.SR, mL, mR, rS, FC_TRUNC)});
-    for (int g : groups)
-      P.trunc({trspec(mkseg(F.SL, mL, rS), mkseg(gslice(g, Lc), gld(g), F.rank_lo(g)),
-                      mkseg(F.SR, mR, rS), mkseg(gslice(g, Rc), gld(g), F.rank_lo(g)), mL, mR, F.scal + 1,
-                      F.SL, F.SR, mL, mR, rS, FC_TRUNC)});
+    for (hodlr_qr_s* Fp : Fs) {
+      hodlr_qr_s& F = *Fp;
+      const HBlk& A12 = F.up.hview[v];
+      const HBlk& A21 = F.lo.hview[v];
+      int* k12 = F.rank_up(v);
+      int* k21 = F.rank_lo(v);
+      trs.push_back(trspec(F, mkseg(F.Z1, mL, k12), mkseg(A21.V, mL, k21), mkseg(A12.V, mR, k12),
+                           mkseg(F.Z2, mR, k21), mL, mR, F.scal + 1, F.SL, F.SR, mL, mR, F.rank_s(), FC_TRUNC));
+    }
+    P.trunc(trs);
+    for (int g : groups) {
+      trs.clear();
+      for (hodlr_qr_s* Fp : Fs) {
+        hodlr_qr_s& F = *Fp;
+        int* rS = F.rank_s();
+        trs.push_back(trspec(F, mkseg(F.SL, mL, rS), mkseg(gslice(F, g, Lc), gld(g), F.rank_lo(g)),
+                             mkseg(F.SR, mR, rS), mkseg(gslice(F, g, Rc), gld(g), F.rank_lo(g)), mL, mR,
+                             F.scal + 1, F.SL, F.SR, mL, mR, rS, FC_TRUNC));
+      }
+      P.trunc(trs);
+    }
     // S = T1^T S~  (left factor only); T1 must be complete
     if (evL >= 0) P.wait(evL);
-    P.mm(t, {mmspec(F.view_t(), true, false, Lc, 1, F.SL, mL, rS, F.SLt, mL, 1.0, 0.0, 1)});
+    mms.clear();
+    for (hodlr_qr_s* Fp : Fs) {
+      hodlr_qr_s& F = *Fp;
+      mms.push_back(mmspec(F.view_t(), true, false, Lc, 1, F.SL, mL, F.rank_s(), F.SLt, mL, 1.0, 0.0, 1, 0,
+                           F.work.fc));
+    }
+    P.mm(t, mms);
     // Y_A11 S_L for the new upper block
-    P.mm(t, {mmspec(F.view_y(), false, true, Lc, 0, F.SLt, mL, rS, F.Z4, mL, 1.0, 0.0, 1)});
+    mms.clear();
+    for (hodlr_qr_s* Fp : Fs) {
+      hodlr_qr_s& F = *Fp;
+      mms.push_back(mmspec(F.view_y(), false, true, Lc, 0, F.SLt, mL, F.rank_s(), F.Z4, mL, 1.0, 0.0, 1, 0,
+                           F.work.fc));
+    }
+    P.mm(t, mms);
     // W = Y~_B21 S_L (k21 x s) and M_g = S_L^T Y_C1g^T (s x k_g)
     {
       std::vector<GSpec> red;
-      red.push_back(GSpec{gjob(1, 0, 0, k21, 0, rS, mL, nullptr, A21.V, mL, F.SLt, mL, F.Wm, KCAP,
-                               1.0, 0.0, FC_DENSE),
-                          KCAP, KCAP, mL});
-      for (size_t i = 0; i < groups.size(); ++i) {
-        const int g = groups[i];
-        red.push_back(GSpec{gjob(1, 0, 0, rS, 0, F.rank_lo(g), mL, nullptr, F.SLt, mL, gslice(g, Lc),
-                                 gld(g), F.Mg + i * KCAP * KCAP, KCAP, 1.0, 0.0, FC_DENSE),
+      for (hodlr_qr_s* Fp : Fs) {
+        hodlr_qr_s& F = *Fp;
+        const HBlk& A21 = F.lo.hview[v];
+        int* rS = F.rank_s();
+        red.push_back(GSpec{gjob(1, 0, 0, F.rank_lo(v), 0, rS, mL, nullptr, A21.V, mL, F.SLt, mL, F.Wm, KCAP,
+                                 1.0, 0.0, FC_DENSE, F.work.fc),
                             KCAP, KCAP, mL});
+        for (size_t i = 0; i < groups.size(); ++i) {
+          const int g = groups[i];
+          red.push_back(GSpec{gjob(1, 0, 0, rS, 0, F.rank_lo(g), mL, nullptr, F.SLt, mL, gslice(F, g, Lc),
+                                   gld(g), F.Mg + i * KCAP * KCAP, KCAP, 1.0, 0.0, FC_DENSE, F.work.fc),
+                              KCAP, KCAP, mL});
+        }
       }
       P.gemm_red(red);
     }
     // SRW = S_R W^T (mR x k21);  C_2g -= S_R M_g  (B^_R2 and C^2 of the update)
     {
       std::vector<GSpec> tall;
-      tall.push_back(GSpec{gjob(0, 1, mR, nullptr, 0, k21, 0, rS, F.SR, mR, F.Wm, KCAP, F.SRW, mR, 1.0,
-                                0.0, FC_DENSE),
-                           mR, cap, 0});
-      for (size_t i = 0; i < groups.size(); ++i) {
-        const int g = groups[i];
-        tall.push_back(GSpec{gjob(0, 0, mR, nullptr, 0, F.rank_lo(g), 0, rS, F.SR, mR,
-                                  F.Mg + i * KCAP * KCAP, KCAP, gslice(g, Rc), gld(g), -1.0, 1.0,
-                                  FC_DENSE),
+      for (hodlr_qr_s* Fp : Fs) {
+        hodlr_qr_s& F = *Fp;
+        int* rS = F.rank_s();
+        tall.push_back(GSpec{gjob(0, 1, mR, nullptr, 0, F.rank_lo(v), 0, rS, F.SR, mR, F.Wm, KCAP, F.SRW, mR,
+                                  1.0, 0.0, FC_DENSE, F.work.fc),
                              mR, cap, 0});
+        for (size_t i = 0; i < groups.size(); ++i) {
+          const int g = groups[i];
+          tall.push_back(GSpec{gjob(0, 0, mR, nullptr, 0, F.rank_lo(g), 0, rS, F.SR, mR,
+                                    F.Mg + i * KCAP * KCAP, KCAP, gslice(F, g, Rc), gld(g), -1.0, 1.0,
+                                    FC_DENSE, F.work.fc),
+                               mR, cap, 0});
+        }
       }
       P.gemm_tall(tall);
     }
     // A^12 = T([U12 | -Y_A11 S_L] [V12 | S_R]^T) and A^22 = A22 -_H U21 W S_R^T:
     // every off-diagonal block of the trailing sub-HODLR, one batch
     {
-      std::vector<TrSpec> sp;
-      sp.push_back(trspec(mkseg(A12.U, mL, k12), mkseg(F.Z4, mL, rS, -1.0), mkseg(A12.V, mR, k12),
-                          mkseg(F.SR, mR, rS), mL, mR, F.scal + 1, A12.U, A12.V, mL, mR, k12, FC_TRUNC));
       std::vector<int> sub;
       t.subtree_internal(Rc, sub);
-      for (int u : sub) {
-        for (int kind = 0; kind < 2; ++kind) {
-          const HBlk& b = kind == 0 ? F.up.hview[u] : F.lo.hview[u];
-          int* kb = kind == 0 ? F.rank_up(u) : F.rank_lo(u);
-          const int64_t ri = b.r0 - t.lo[Rc], cj = b.c0 - t.lo[Rc];
-          sp.push_back(trspec(mkseg(b.U, b.ldU, kb), mkseg(A21.U + ri, mR, k21), mkseg(b.V, b.ldV, kb),
-                              mkseg(F.SRW + cj, mR, k21, -1.0), b.rows, b.cols, F.scal + 1, b.U, b.V, b.ldU,
-                              b.ldV, kb, FC_TRUNC));
-        }
-      }
-      P.trunc(sp);
-      // leaves of the trailing part: D -= U21(I) (S_R W^T)(I)^T
+      std::vector<TrSpec> sp;
       std::vector<int> leaves;
       t.subtree_leaves(Rc, leaves);
       std::vector<GSpec> lu;
-      for (int j : leaves) {
-        const int lv = t.nleaf() + j;
-        const int m = (int)t.m(lv);
-        const int64_t ri = t.lo[lv] - t.lo[Rc];
-        lu.push_back(GSpec{gjob(0, 1, m, nullptr, m, nullptr, 0, k21, A21.U + ri, mR, F.SRW + ri, mR,
-                                F.leaves.hview[j].D, m, -1.0, 1.0, FC_UPDATE),
-                           m, m, 0});
+      for (hodlr_qr_s* Fp : Fs) {
+        hodlr_qr_s& F = *Fp;
+        const HBlk& A12 = F.up.hview[v];
+        const HBlk& A21 = F.lo.hview[v];
+        int* k12 = F.rank_up(v);
+        int* k21 = F.rank_lo(v);
+        int* rS = F.rank_s();
+        sp.push_back(trspec(F, mkseg(A12.U, mL, k12), mkseg(F.Z4, mL, rS, -1.0), mkseg(A12.V, mR, k12),
+                            mkseg(F.SR, mR, rS), mL, mR, F.scal + 1, A12.U, A12.V, mL, mR, k12, FC_TRUNC));
+        for (int u : sub) {
+          for (int kind = 0; kind < 2; ++kind) {
+            const HBlk& b = kind == 0 ? F.up.hview[u] : F.lo.hview[u];
+            int* kb = kind == 0 ? F.rank_up(u) : F.rank_lo(u);
+            const int64_t ri = b.r0 - t.lo[Rc], cj = b.c0 - t.lo[Rc];
+            sp.push_back(trspec(F, mkseg(b.U, b.ldU, kb), mkseg(A21.U + ri, mR, k21), mkseg(b.V, b.ldV, kb),
+                                mkseg(F.SRW + cj, mR, k21, -1.0), b.rows, b.cols, F.scal + 1, b.U, b.V,
+                                b.ldU, b.ldV, kb, FC_TRUNC));
+          }
+        }
+        // leaves of the trailing part: D -= U21(I) (S_R W^T)(I)^T
+        for (int j : leaves) {
+          const int lv = t.nleaf() + j;
+          const int m = (int)t.m(lv);
+          const int64_t ri = t.lo[lv] - t.lo[Rc];
+          lu.push_back(GSpec{gjob(0, 1, m, nullptr, m, nullptr, 0, k21, A21.U + ri, mR, F.SRW + ri, mR,
+                                  F.leaves.hview[j].D, m, -1.0, 1.0, FC_UPDATE, F.work.fc),
+                             m, m, 0});
+        }
       }
+      P.trunc(sp);
       P.gemm_tall(lu);
     }
     // second block column: hQR(A^22, [], [B^_R2; C^2])
@@ -935,25 +1026,45 @@ struct QRBuilder {
     P.lane = 1;
     P.wait(evM);
     // T~12 = T_eps(Y_A21^T Y_A22 + sum over groups of Y_g1^T Y_g2)
-    P.mm(t, {mmspec(F.view_y(), false, true, Rc, 1, A21.U, mR, k21, F.Z5, mR, 1.0, 0.0, 1)});
-    int* rt = F.rank_t(v);
-    if (groups.empty()) {
-      P.trunc({trspec(mkseg(A21.V, mL, k21), noseg(), mkseg(F.Z5, mR, k21), noseg(), mL, mR, F.scal + 2,
-                      F.TL, F.TR, mL, mR, rt, FC_TRUNC)});
-    } else {
-      for (size_t i = 0; i < groups.size(); ++i) {
-        const int g = groups[i];
+    mms.clear();
+    for (hodlr_qr_s* Fp : Fs) {
+      hodlr_qr_s& F = *Fp;
+      mms.push_back(mmspec(F.view_y(), false, true, Rc, 1, F.lo.hview[v].U, mR, F.rank_lo(v), F.Z5, mR, 1.0,
+                           0.0, 1, 0, F.work.fc));
+    }
+    P.mm(t, mms);
+    const size_t nterm = groups.empty() ? 1 : groups.size();
+    for (size_t i = 0; i < nterm; ++i) {
+      trs.clear();
+      for (hodlr_qr_s* Fp : Fs) {
+        hodlr_qr_s& F = *Fp;
+        const HBlk& A21 = F.lo.hview[v];
+        int* k21 = F.rank_lo(v);
+        int* rt = F.rank_t(v);
         const Seg l0 = i == 0 ? mkseg(A21.V, mL, k21) : mkseg(F.TL, mL, rt);
         const Seg r0 = i == 0 ? mkseg(F.Z5, mR, k21) : mkseg(F.TR, mR, rt);
-        P.trunc({trspec(l0, mkseg(gslice(g, Lc), gld(g), F.rank_lo(g)), r0,
-                        mkseg(gslice(g, Rc), gld(g), F.rank_lo(g)), mL, mR, F.scal + 2, F.TL, F.TR, mL, mR,
-                        rt, FC_TRUNC)});
+        if (groups.empty()) {
+          trs.push_back(trspec(F, l0, noseg(), r0, noseg(), mL, mR, F.scal + 2, F.TL, F.TR, mL, mR, rt,
+                               FC_TRUNC));
+        } else {
+          const int g = groups[i];
+          trs.push_back(trspec(F, l0, mkseg(gslice(F, g, Lc), gld(g), F.rank_lo(g)), r0,
+                               mkseg(gslice(F, g, Rc), gld(g), F.rank_lo(g)), mL, mR, F.scal + 2, F.TL, F.TR,
+                               mL, mR, rt, FC_TRUNC));
+        }
       }
+      P.trunc(trs);
     }
     // T12 = -T1 T~12 T2 = (-T1 T~_L)(T2^T T~_R)^T
-    const HBlk& T12 = F.tup.hview[v];
-    P.mm(t, {mmspec(F.view_t(), true, false, Lc, 0, F.TL, mL, rt, T12.U, mL, -1.0, 0.0, 1),
-             mmspec(F.view_t(), true, false, Rc, 1, F.TR, mR, rt, T12.V, mR, 1.0, 0.0, 1)});
+    mms.clear();
+    for (hodlr_qr_s* Fp : Fs) {
+      hodlr_qr_s& F = *Fp;
+      const HBlk& T12 = F.tup.hview[v];
+      int* rt = F.rank_t(v);
+      mms.push_back(mmspec(F.view_t(), true, false, Lc, 0, F.TL, mL, rt, T12.U, mL, -1.0, 0.0, 1, 0, F.work.fc));
+      mms.push_back(mmspec(F.view_t(), true, false, Rc, 1, F.TR, mR, rt, T12.V, mR, 1.0, 0.0, 1, 0, F.work.fc));
+    }
+    P.mm(t, mms);
     const int evT = P.signal();
     P.lane = 0;
     return evT;
@@ -962,40 +1073,50 @@ struct QRBuilder {
   void build() {
     // make every lower block left-orthogonal (the B_L of each block column)
     std::vector<TrSpec> orth;
-    for (int v = 1; v < t.nleaf(); ++v) {
-      const HBlk& b = F.lo.hview[v];
-      orth.push_back(trspec(mkseg(b.U, b.ldU, F.rank_lo(v)), noseg(), mkseg(b.V, b.ldV, F.rank_lo(v)),
-                            noseg(), b.rows, b.cols, F.scal + 2, b.U, b.V, b.ldU, b.ldV, F.rank_lo(v), FC_ORTH,
-                            TR_ORTH));
+    for (hodlr_qr_s* Fp : Fs) {
+      hodlr_qr_s& F = *Fp;
+      for (int v = 1; v < t.nleaf(); ++v) {
+        const HBlk& b = F.lo.hview[v];
+        orth.push_back(trspec(F, mkseg(b.U, b.ldU, F.rank_lo(v)), noseg(), mkseg(b.V, b.ldV, F.rank_lo(v)),
+                              noseg(), b.rows, b.cols, F.scal + 2, b.U, b.V, b.ldU, b.ldV, F.rank_lo(v),
+                              FC_ORTH, TR_ORTH));
+      }
     }
     P.trunc(orth);
     node(1, {});
   }
 };
 
-void plan_norm2(Plan& P, const Tree& t, HView V, int iters, double* x, double* y, double* z, double* out) {
+// One power-iteration estimate of |M|_2 per item (50 steps on M^T M from
+// x0 = 1/sqrt(n)), all items in the same launches; writes each result to
+// its out (device).  x, y, z: device vectors of length n per item.
+struct NormItem {
+  HView V;
+  double *x, *y, *z, *out;
+  double* flops;
+};
+
+void plan_norm2(Plan& P, const Tree& t, const std::vector<NormItem>& items, int iters) {
   const int64_t n = t.n;
-  Op fill{OP_FILL};
-  fill.p1 = x;
-  fill.n = n;
-  fill.d0 = 1.0 / std::sqrt((double)n);
-  P.push(fill);
-  for (int it = 0; it < iters; ++it) {
-    P.mm(t, {mmspec(V, true, true, 1, 0, x, (int)n, nullptr, y, (int)n, 1.0, 0.0, 0, 1)});
-    P.mm(t, {mmspec(V, true, true, 1, 1, y, (int)n, nullptr, z, (int)n, 1.0, 0.0, 0, 1)});
-    Op o{OP_NORMALIZE};
-    o.p0 = z;
-    o.p1 = x;
-    o.n = n;
-    P.push(o);
+  std::vector<VecJob> fill, norm, last;
+  for (const NormItem& it : items) {
+    fill.push_back(VecJob{nullptr, it.x, n, nullptr, 1.0 / std::sqrt((double)n), 0.0});
+    norm.push_back(VecJob{it.z, it.x, n, nullptr, 0.0, 0.0});
+    last.push_back(VecJob{it.y, nullptr, n, it.out, 0.0, 0.0});
   }
-  P.mm(t, {mmspec(V, true, true, 1, 0, x, (int)n, nullptr, y, (int)n, 1.0, 0.0, 0, 1)});
-  Op o{OP_NORMALIZE};
-  o.p0 = y;
-  o.p1 = nullptr;
-  o.n = n;
-  o.pout = out;
-  P.push(o);
+  P.vec(OP_FILL, fill);
+  std::vector<MmSpec> a, b;
+  for (const NormItem& it : items) {
+    a.push_back(mmspec(it.V, true, true, 1, 0, it.x, (int)n, nullptr, it.y, (int)n, 1.0, 0.0, 0, 1, it.flops));
+    b.push_back(mmspec(it.V, true, true, 1, 1, it.y, (int)n, nullptr, it.z, (int)n, 1.0, 0.0, 0, 1, it.flops));
+  }
+  for (int i = 0; i < iters; ++i) {
+    P.mm(t, a);
+    P.mm(t, b);
+    P.vec(OP_NORMALIZE, norm);
+  }
+  P.mm(t, a);
+  P.vec(OP_NORMALIZE, last);
 }
 
 hodlr_status check_finite(const double* p, size_t n, const char* what) {
@@ -1004,7 +1125,7 @@ hodlr_status check_finite(const double* p, size_t n, const char* what) {
   return HODLR_OK;
 }
 
-// copies A's storage into F's and resets ranks / counters / flags
+// copies A's storage into F's and resets ranks / flop counters
 hodlr_status reset_factor(hodlr_qr_s& F, const hodlr_s& A, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(F.leaves.D, A.leaves.D, F.leaves.size * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(F.up.U, A.up.U, F.up.usz * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1016,16 +1137,19 @@ hodlr_status reset_factor(hodlr_qr_s& F, const hodlr_s& A, hipStream_t st) {
   return HODLR_OK;
 }
 
-hodlr_status make_factor(const hodlr_s& A, double eps, double anorm, hipStream_t st,
-                         std::unique_ptr<hodlr_qr_s>& out) {
+// device storage of the factors of A (no schedule yet)
+hodlr_status make_storage(const hodlr_s& A, double eps, double anorm, hipStream_t st,
+                          std::unique_ptr<hodlr_qr_s>& out) {
   auto F = std::make_unique<hodlr_qr_s>();
   F->t = A.t;
   F->cap = A.cap;
   F->anorm = anorm;
+  F->anorm_in = anorm;
   F->eps = eps;
   F->tauA = eps * anorm;
   F->tauT = eps;
   const Tree& t = F->t;
+  if (t.L > MAXGROUPS) return fail(HODLR_EINVAL, "too many levels");
   const int nn = 1 << t.L;
   TRY(F->mem.alloc(&F->scal, 8));
   HIPCHK(hipMemsetAsync(F->scal, 0, 8 * sizeof(double), st));
@@ -1048,59 +1172,80 @@ hodlr_status make_factor(const hodlr_s& A, double eps, double anorm, hipStream_t
   TRY(F->mem.alloc(&F->Mg, (size_t)KCAP * KCAP * (t.L + 1)));
   TRY(F->mem.alloc(&F->X1, (size_t)t.n * SMAX));
   TRY(F->mem.alloc(&F->X2, (size_t)t.n * SMAX));
-  if (t.L > MAXGROUPS) return fail(HODLR_EINVAL, "too many levels");
-  QRBuilder qb(*F);
-  F->plan.wtop = 2 * F->cap;
-  // thresholds: |A|_2 from the power iteration unless given, then tau_A, tau_T
-  if (!(anorm > 0.0))
-    plan_norm2(F->plan, t, F->view_gen(), 50, F->X1, F->X1 + t.n, F->X2, F->scal);
-  {
-    Op o{OP_SETSCAL};
-    o.p1 = F->scal;
-    o.d0 = eps;
-    o.d1 = anorm > 0.0 ? anorm : -1.0;
-    F->plan.push(o);
-  }
-  qb.build();
-  TRY(F->plan.upload_all(F->mem, st));
-  TRY(ensure_work(F->mem, F->work, F->plan.ws_need(), F->plan.cnt_need(), true, st));
-  F->n_launch = 0;
-  for (const Op& o : F->plan.ops) F->n_launch += op_launches(o) ? 1 : 0;
+  TRY(ensure_work(F->mem, F->work, 0, 1, true, st));  // error word, flop counters, leaf workspace
   out = std::move(F);
   return HODLR_OK;
 }
 
-hodlr_status lane_streams(hodlr_qr_s& F) {
-  if (F.aux == nullptr) HIPCHK(hipStreamCreateWithFlags(&F.aux, hipStreamNonBlocking));
-  while ((int)F.events.size() < F.plan.n_events + 2) {
+// the schedule of a batch of factors that share a tree and a capacity
+hodlr_status make_batch(const std::vector<hodlr_qr_s*>& Fs, hipStream_t st, std::shared_ptr<Batch>& out) {
+  auto B = std::make_shared<Batch>();
+  Plan& P = B->plan;
+  const Tree& t = Fs[0]->t;
+  P.wtop = 2 * Fs[0]->cap;
+  B->size = (int)Fs.size();
+  // thresholds: |A|_2 from the power iteration unless given, then tau_A, tau_T
+  std::vector<NormItem> est;
+  std::vector<VecJob> sc;
+  for (hodlr_qr_s* F : Fs) {
+    if (!(F->anorm_in > 0.0))
+      est.push_back(NormItem{F->view_gen(), F->X1, F->X1 + t.n, F->X2, F->scal, F->work.fc});
+    sc.push_back(VecJob{nullptr, F->scal, 3, nullptr, F->eps, F->anorm_in > 0.0 ? F->anorm_in : -1.0});
+  }
+  if (!est.empty()) plan_norm2(P, t, est, 50);
+  P.vec(OP_SETSCAL, sc);
+  QRBuilder qb(Fs, P);
+  qb.build();
+  TRY(P.upload_all(B->mem, st));
+  TRY(ensure_work(B->mem, B->work, P.ws_need(), P.cnt_need(), false, st));
+  B->n_launch = 0;
+  for (const Op& o : P.ops) B->n_launch += op_launches(o) ? 1 : 0;
+  out = std::move(B);
+  return HODLR_OK;
+}
+
+hodlr_status make_factor(const hodlr_s& A, double eps, double anorm, hipStream_t st,
+                         std::unique_ptr<hodlr_qr_s>& out) {
+  TRY(make_storage(A, eps, anorm, st, out));
+  std::shared_ptr<Batch> B;
+  TRY(make_batch({out.get()}, st, B));
+  out->batch = B;
+  return HODLR_OK;
+}
+
+hodlr_status lane_streams(Batch& B) {
+  if (B.aux == nullptr) HIPCHK(hipStreamCreateWithFlags(&B.aux, hipStreamNonBlocking));
+  while ((int)B.events.size() < B.plan.n_events + 2) {
     hipEvent_t e;
     HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    F.events.push_back(e);
+    B.events.push_back(e);
   }
   return HODLR_OK;
 }
 
-// Run the whole factorisation on `st`.  Default: direct launches, the T-factor
-// lane on a second stream.  HODLR_QR_ONE_STREAM: direct launches in the serial
-// order.  HODLR_QR_GRAPH: replay a HIP graph captured (once per handle) from the
-// serial order on one stream; a graph captured from the two-stream form ran
-// with wrong results on ROCm 7.2 although every edge of it was present, so the
-// graph keeps the serial order.
-hodlr_status run_factor(hodlr_qr_s& F, const hodlr_s& A, uint32_t flags, hipStream_t st) {
-  TRY(lane_streams(F));
+// Run the whole factorisation of every factor of a batch on `st`.  Default:
+// direct launches, the T-factor lane on a second stream.  HODLR_QR_ONE_STREAM:
+// direct launches in the serial order.  HODLR_QR_GRAPH: replay a HIP graph
+// captured (once per batch) from the serial order on one stream; a graph
+// captured from the two-stream form ran with wrong results on ROCm 7.2 although
+// every edge of it was present, so the graph keeps the serial order.
+hodlr_status run_batch(Batch& B, const std::vector<hodlr_qr_s*>& Fs, const std::vector<const hodlr_s*>& As,
+                       uint32_t flags, hipStream_t st) {
+  TRY(lane_streams(B));
   if (!(flags & HODLR_QR_GRAPH)) {
-    TRY(reset_factor(F, A, st));
-    hipStream_t aux = (flags & HODLR_QR_ONE_STREAM) ? nullptr : F.aux;
-    return run_ops(F.plan, F.work, st, aux, F.events.data());
+    for (size_t i = 0; i < Fs.size(); ++i) TRY(reset_factor(*Fs[i], *As[i], st));
+    hipStream_t aux = (flags & HODLR_QR_ONE_STREAM) ? nullptr : B.aux;
+    return run_ops(B.plan, B.work, st, aux, B.events.data());
   }
-  if (F.graph == nullptr) {
+  if (B.graph == nullptr) {
     // capture on a private stream so that the caller's stream state is untouched
     hipStream_t cs;
     HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     TRY(set_attrs());
     HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hodlr_status s1 = reset_factor(F, A, cs);
-    hodlr_status s2 = s1 == HODLR_OK ? run_ops(F.plan, F.work, cs) : s1;
+    hodlr_status s1 = HODLR_OK;
+    for (size_t i = 0; i < Fs.size() && s1 == HODLR_OK; ++i) s1 = reset_factor(*Fs[i], *As[i], cs);
+    hodlr_status s2 = s1 == HODLR_OK ? run_ops(B.plan, B.work, cs) : s1;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
@@ -1109,15 +1254,19 @@ hodlr_status run_factor(hodlr_qr_s& F, const hodlr_s& A, uint32_t flags, hipStre
       return s2;
     }
     if (e != hipSuccess) return fail(HODLR_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&F.graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&B.graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-      F.graph = nullptr;
+      B.graph = nullptr;
       return fail(HODLR_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
     }
   }
-  HIPCHK(hipGraphLaunch(F.graph, st));
+  HIPCHK(hipGraphLaunch(B.graph, st));
   return HODLR_OK;
+}
+
+hodlr_status run_factor(hodlr_qr_s& F, const hodlr_s& A, uint32_t flags, hipStream_t st) {
+  return run_batch(*F.batch, {&F}, {&A}, flags, st);
 }
 
 hodlr_status finish_factor(hodlr_qr_s& F, hipStream_t st) {
@@ -1147,7 +1296,7 @@ hodlr_status norm2_est_impl(hodlr_s& A, int iters, hipStream_t st, double* out) 
   TRY(tmp.alloc(&res, 1));
   HView V{t.L, A.up.dview, A.lo.dview, A.leaves.dview, LEAF_FULL};
   Plan P;
-  plan_norm2(P, t, V, iters, x, y, z, res);
+  plan_norm2(P, t, {NormItem{V, x, y, z, res, nullptr}}, iters);
   TRY(P.upload_all(tmp, st));
   TRY(ensure_work(A.mem, A.work, P.ws_need(), P.cnt_need(), false, st));
   TRY(run_ops(P, A.work, st));
@@ -1270,6 +1419,122 @@ hodlr_status hodlr_qr(const hodlr_t* A, double eps, double anorm, uint32_t flags
   TRY(run_factor(*F, *A, flags, st));
   TRY(finish_factor(*F, st));
   *out = F.release();
+  return HODLR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Factors of a set of matrices with one schedule per group of matrices that share
+// partition and rank capacity; groups are run one after the other.
+struct BatchSet {
+  std::vector<std::unique_ptr<hodlr_qr_s>> F;
+  std::vector<std::vector<int>> groups;  // indices into F / A
+};
+
+hodlr_status make_batch_set(const hodlr_t* const* A, int count, double eps, const double* anorm,
+                            hipStream_t st, BatchSet& S) {
+  S.F.resize(count);
+  for (int i = 0; i < count; ++i) {
+    TRY(make_storage(*A[i], eps, anorm ? anorm[i] : 0.0, st, S.F[i]));
+    bool placed = false;
+    for (auto& g : S.groups) {
+      const hodlr_s& B = *A[g[0]];
+      if (B.t.L == A[i]->t.L && B.t.n == A[i]->t.n && B.cap == A[i]->cap && B.t.lo == A[i]->t.lo &&
+          B.t.hi == A[i]->t.hi) {
+        g.push_back(i);
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) S.groups.push_back({i});
+  }
+  for (auto& g : S.groups) {
+    std::vector<hodlr_qr_s*> fs;
+    for (int i : g) fs.push_back(S.F[i].get());
+    std::shared_ptr<Batch> B;
+    TRY(make_batch(fs, st, B));
+    for (int i : g) S.F[i]->batch = B;
+  }
+  return HODLR_OK;
+}
+
+hodlr_status run_batch_set(BatchSet& S, const hodlr_t* const* A, uint32_t flags, hipStream_t st) {
+  for (auto& g : S.groups) {
+    std::vector<hodlr_qr_s*> fs;
+    std::vector<const hodlr_s*> as;
+    for (int i : g) {
+      fs.push_back(S.F[i].get());
+      as.push_back(A[i]);
+    }
+    TRY(run_batch(*S.F[g[0]]->batch, fs, as, flags, st));
+  }
+  return HODLR_OK;
+}
+
+hodlr_status check_batch_args(const hodlr_t* const* A, int count, double eps) {
+  if (A == nullptr || count < 1) return fail(HODLR_EINVAL, "need at least one matrix");
+  for (int i = 0; i < count; ++i)
+    if (A[i] == nullptr) return fail(HODLR_EINVAL, "NULL matrix in the batch");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(HODLR_EINVAL, "eps must be finite and >= 0");
+  return HODLR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hodlr_status hodlr_qr_batched(const hodlr_t* const* A, int32_t count, double eps, const double* anorm,
+                              uint32_t flags, hodlr_stream_t stream, hodlr_qr_t** out) {
+  g_err.clear();
+  if (out == nullptr) return fail(HODLR_EINVAL, "NULL argument");
+  TRY(check_batch_args(A, count, eps));
+  for (int i = 0; i < count; ++i) out[i] = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  BatchSet S;
+  TRY(make_batch_set(A, count, eps, anorm, st, S));
+  TRY(run_batch_set(S, A, flags, st));
+  hodlr_status first_err = HODLR_OK;
+  std::string msg;
+  for (int i = 0; i < count; ++i) {
+    const hodlr_status e = finish_factor(*S.F[i], st);
+    if (e != HODLR_OK && first_err == HODLR_OK) {
+      first_err = e;
+      msg = "matrix " + std::to_string(i) + ": " + g_err;
+    }
+  }
+  if (first_err != HODLR_OK) return fail(first_err, msg);
+  for (int i = 0; i < count; ++i) out[i] = S.F[i].release();
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_qr_batched_time(const hodlr_t* const* A, int32_t count, double eps, const double* anorm,
+                                   uint32_t flags, int32_t warmup, int32_t reps, hodlr_stream_t stream,
+                                   double* ms) {
+  g_err.clear();
+  if (ms == nullptr || reps < 1 || warmup < 0) return fail(HODLR_EINVAL, "bad argument");
+  TRY(check_batch_args(A, count, eps));
+  hipStream_t st = (hipStream_t)stream;
+  BatchSet S;
+  TRY(make_batch_set(A, count, eps, anorm, st, S));
+  for (int i = 0; i < warmup; ++i) TRY(run_batch_set(S, A, flags, st));
+  for (int i = 0; i < count; ++i) TRY(finish_factor(*S.F[i], st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (int r = 0; r < reps; ++r) {
+    HIPCHK(hipEventRecord(e0, st));
+    TRY(run_batch_set(S, A, flags, st));
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    ms[r] = t;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (int i = 0; i < count; ++i) TRY(finish_factor(*S.F[i], st));
   return HODLR_OK;
 }
 
@@ -1442,12 +1707,13 @@ hodlr_status hodlr_qr_profile(const hodlr_t* A, double eps, double anorm, int32_
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   double prev = 0.0;
-  for (const Op& o : F->plan.ops) {
+  const Batch& B = *F->batch;
+  for (const Op& o : B.plan.ops) {
     if (!op_launches(o)) continue;
     Launch L;
     L.e0 = e0;
     L.e1 = e1;
-    run_op(F->plan, F->work, o, st, L);
+    run_op(B.plan, B.work, o, st, L);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventSynchronize(e1));
     float t = 0.0f;
@@ -1490,8 +1756,8 @@ hodlr_status hodlr_qr_info(const hodlr_qr_t* F, hodlr_qr_info_t* info) {
   info->tau_a = F->tauA;
   info->tau_t = F->tauT;
   info->flops = flop_total(F->work.fc);
-  info->n_truncations = F->plan.n_trunc;
-  info->n_launches = F->n_launch;
+  info->n_truncations = F->batch ? F->batch->plan.n_trunc / F->batch->size : 0;
+  info->n_launches = F->batch ? F->batch->n_launch : 0;
   info->device_bytes = (int64_t)F->mem.bytes;
   return HODLR_OK;
 }

@@ -703,10 +703,12 @@ __device__ __forceinline__ void tr_chunk(const TrJob& J, int side, int chunk, do
 template <int WTOP>
 __global__ void __launch_bounds__(NT_TR) k_tr_qr(const TrJob* __restrict__ jobs,
                                                   const TrChunk* __restrict__ items, int first,
-                                                  double* ws, int* counters, int* err, double* fc) {
+                                                  double* ws, int* counters) {
   extern __shared__ double smem[];
   const TrChunk it = items[first + blockIdx.x];
   const TrJob& J = jobs[it.job];
+  int* err = J.err;
+  double* fc = J.flops;
   const int n0a = seg_n(J.seg[0][0]);
   const int w = n0a + seg_n(J.seg[0][1]);
   const int n0b = seg_n(J.seg[1][0]);
@@ -860,7 +862,7 @@ __device__ __forceinline__ int mm_s(const MmJob& J) { return J.s_dev ? *J.s_dev 
 // k_mm_red sums (a separate launch: no cross-block fences).
 __global__ void __launch_bounds__(NT_MM) k_mm_proj(const MmJob* __restrict__ jobs,
                                                     const MmProj* __restrict__ items, int first,
-                                                    double* ws, double* fc) {
+                                                    double* ws) {
   __shared__ double part_s[NT_MM];
   const int tid = threadIdx.x;
   const MmProj it = items[first + blockIdx.x];
@@ -906,7 +908,7 @@ __global__ void __launch_bounds__(NT_MM) k_mm_proj(const MmJob* __restrict__ job
       dst[j + c * KCAP] = acc;
     }
   }
-  if (tid == 0) add_flops(fc, FC_HMAT, 2.0 * k * cn * s);
+  if (tid == 0) add_flops(J.flops, FC_HMAT, 2.0 * k * cn * s);
 }
 
 // Sum the per-chunk partials of one block projection (chunk order fixed).
@@ -955,7 +957,7 @@ __device__ __forceinline__ double leaf_elem(const HLeaf& lf, int kind, int trans
 template <int RT>
 __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jobs,
                                                      const MmApply* __restrict__ items, int first,
-                                                     const double* __restrict__ ws, double* fc) {
+                                                     const double* __restrict__ ws) {
   constexpr int G = NT_MM / RT;
   constexpr int DMAX = RT == 16 ? MAXLEAF / G : 1;
   extern __shared__ double shm[];
@@ -1069,7 +1071,7 @@ __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jo
       child2 = u2;
       u2 >>= 1;
     }
-    add_flops(fc, FC_HMAT, flops);
+    add_flops(J.flops, FC_HMAT, flops);
   }
 }
 
@@ -1082,8 +1084,7 @@ __device__ __forceinline__ double gB(const GemmJob& J, int kk, int c) {
 }
 
 __global__ void __launch_bounds__(NT_MM) k_gemm_tall(const GemmJob* __restrict__ jobs,
-                                                      const GemmTile* __restrict__ items, int first,
-                                                      double* fc) {
+                                                      const GemmTile* __restrict__ items, int first) {
   __shared__ double At[64][33];
   __shared__ double Bt[32][65];
   const int tid = threadIdx.x;
@@ -1142,13 +1143,13 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_tall(const GemmJob* __restrict__
       }
     }
   }
-  if (tid == 0) add_flops(fc, J.fc, 2.0 * mr * nc * K);
+  if (tid == 0) add_flops(J.flops, J.fc, 2.0 * mr * nc * K);
 }
 
 // C (M x N, both <= KCAP) from a long K, split into chunks; the last chunk sums.
 __global__ void __launch_bounds__(NT_MM) k_gemm_red(const GemmJob* __restrict__ jobs,
                                                      const GemmRed* __restrict__ items, int first,
-                                                     double* ws, int* counters, double* fc) {
+                                                     double* ws, int* counters) {
   __shared__ double At[32][KCAP + 1];
   __shared__ double Bt[32][KCAP + 1];
   __shared__ int lastf;
@@ -1220,7 +1221,7 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_red(const GemmJob* __restrict__ 
       }
     }
   }
-  if (tid == 0) add_flops(fc, J.fc, 2.0 * M * N * it.kn);
+  if (tid == 0) add_flops(J.flops, J.fc, 2.0 * M * N * it.kn);
 }
 
 // ------------------------------------------------------------------ leaf QR
@@ -1239,10 +1240,15 @@ __device__ __forceinline__ int leaf_rows(const LeafJob& J) {
 }
 
 // H = [A_leaf; C_g1; ...] (one column per block)
-__global__ void __launch_bounds__(NT_MM) k_leaf_gather(const LeafJob* __restrict__ jobs, int jidx,
-                                                        LeafWs W, int* err) {
-  const LeafJob& J = jobs[jidx];
-  const int c = blockIdx.x;
+// Leaf kernels: a launch covers nper blocks of each of its jobs, job first +
+// blockIdx / nper (jobs of different factorisations of one batch).
+__global__ void __launch_bounds__(NT_MM) k_leaf_gather(const LeafJob* __restrict__ jobs, int first,
+                                                        int nper) {
+  const LeafJob& J = jobs[first + blockIdx.x / nper];
+  const LeafWs W = J.ws;
+  int* err = J.err;
+  const int c = blockIdx.x % nper;
+  if (c >= J.m) return;
   const int M = leaf_rows(J);
   if (M > MAXSTACK) {
     if (c == 0 && threadIdx.x == 0) atomicOr(err, ERR_STACK);
@@ -1554,12 +1560,13 @@ constexpr size_t LEAF_PANEL_LDS = LEAF_LDS;
 
 // One step of the blocked leaf QR (see the section comment).  p = -1 only
 // factorises panel 0; p = np only forms the last T block.
-__global__ void __launch_bounds__(NT_LEAF) k_leaf_step(const LeafJob* __restrict__ jobs, int jidx,
-                                                        LeafWs W, int p, const int* err,
-                                                        double* fc) {
+__global__ void __launch_bounds__(NT_LEAF) k_leaf_step(const LeafJob* __restrict__ jobs, int first,
+                                                        int nper, int p) {
   extern __shared__ double sm[];
-  if (*err & ERR_STACK) return;
-  const LeafJob& J = jobs[jidx];
+  const LeafJob& J = jobs[first + blockIdx.x / nper];
+  if (*J.err & ERR_STACK) return;
+  const LeafWs W = J.ws;
+  double* fc = J.flops;
   const int tid = threadIdx.x;
   const int m = J.m;
   const int np = (m + NB - 1) / NB;
@@ -1577,7 +1584,7 @@ __global__ void __launch_bounds__(NT_LEAF) k_leaf_step(const LeafJob* __restrict
   const int c0 = p * NB, pw = min(NB, m - c0);
   const int nstrip = (p < np) ? np - p - 1 : 0;
   const int ngram = (p < np) ? p : 0;
-  int b = blockIdx.x;
+  int b = blockIdx.x % nper;
   if (b < nstrip) {
     const int s = p + 1 + b;
     const int cs = s * NB, sw = min(NB, m - cs);
@@ -1632,11 +1639,13 @@ __global__ void __launch_bounds__(NT_LEAF) k_leaf_step(const LeafJob* __restrict
 }
 
 // R + Y back into the leaf, Y rows back into the ancestors' right factors, T out.
-__global__ void __launch_bounds__(NT_MM) k_leaf_scatter(const LeafJob* __restrict__ jobs, int jidx,
-                                                         LeafWs W, const int* err, double* fc) {
-  if (*err & ERR_STACK) return;
-  const LeafJob& J = jobs[jidx];
-  const int c = blockIdx.x;
+__global__ void __launch_bounds__(NT_MM) k_leaf_scatter(const LeafJob* __restrict__ jobs, int first,
+                                                         int nper) {
+  const LeafJob& J = jobs[first + blockIdx.x / nper];
+  if (*J.err & ERR_STACK) return;
+  const LeafWs W = J.ws;
+  const int c = blockIdx.x % nper;
+  if (c >= J.m) return;
   const int m = J.m;
   const double* h = W.H + (int64_t)c * MAXSTACK;
   for (int r = threadIdx.x; r < m; r += NT_MM) {
@@ -1654,10 +1663,12 @@ __global__ void __launch_bounds__(NT_MM) k_leaf_scatter(const LeafJob* __restric
 }
 
 // ------------------------------------------------------------------ vectors
-// x <- z / |z|, out[0] = |z|  (one block)
-__global__ void __launch_bounds__(1024) k_normalize(const double* z, double* x, int64_t n,
-                                                     double* out) {
+// x <- z / |z|, out[0] = |z|  (one block per item; x or out may be null)
+__global__ void __launch_bounds__(1024) k_normalize(const VecJob* __restrict__ items, int first) {
   __shared__ double red[16];
+  const VecJob it = items[first + blockIdx.x];
+  const double* z = it.z;
+  const int64_t n = it.n;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 1024) s += z[i] * z[i];
   s = gsum(s, 64);
@@ -1666,21 +1677,29 @@ __global__ void __launch_bounds__(1024) k_normalize(const double* z, double* x, 
   double t = 0.0;
   for (int i = 0; i < 16; ++i) t += red[i];
   const double nrm = sqrt(t);
-  if (x != nullptr) {
+  if (it.x != nullptr) {
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) x[i] = z[i] * inv;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) it.x[i] = z[i] * inv;
   }
-  if (threadIdx.x == 0 && out != nullptr) out[0] = nrm;
+  if (threadIdx.x == 0 && it.out != nullptr) it.out[0] = nrm;
 }
 
-// thresholds of one factorisation: scal = [|A|_2, eps*|A|_2, eps]
-__global__ void k_set_scal(double* scal, double eps, double anorm) {
-  if (threadIdx.x == 0) {
-    const double a = anorm > 0.0 ? anorm : scal[0];
-    scal[0] = a;
-    scal[1] = eps * a;
-    scal[2] = eps;
-  }
+// thresholds of one factorisation: x = [|A|_2, eps*|A|_2, eps] with eps = d0 and
+// |A|_2 = d1 if d1 > 0, else the estimate already in x[0]  (one thread per item)
+__global__ void k_set_scal(const VecJob* __restrict__ items, int first, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const VecJob it = items[first + i];
+  const double a = it.d1 > 0.0 ? it.d1 : it.x[0];
+  it.x[0] = a;
+  it.x[1] = it.d0 * a;
+  it.x[2] = it.d0;
+}
+
+// x[0:n] = d0, one block per item
+__global__ void k_fill_items(const VecJob* __restrict__ items, int first) {
+  const VecJob it = items[first + blockIdx.x];
+  for (int64_t i = threadIdx.x; i < it.n; i += blockDim.x) it.x[i] = it.d0;
 }
 
 __global__ void k_fill(double* x, int64_t n, double v) {

@@ -87,6 +87,15 @@ def test_invalid_arguments_are_rejected_on_host(lib):
     assert lib.hodlr_solve(None, 1, None, 64, None) == -1
     lib.hodlr_free(None)
     lib.hodlr_qr_free(None)
+    # batched: no matrices, NULL matrix, NULL output, bad eps
+    out = (C.c_void_p * 2)()
+    outp = C.cast(out, C.POINTER(C.c_void_p))
+    assert lib.hodlr_qr_batched(None, 0, 1e-10, None, 0, None, outp) == -1
+    arr = (C.c_void_p * 2)(None, None)
+    assert lib.hodlr_qr_batched(C.cast(arr, C.POINTER(C.c_void_p)), 2, 1e-10, None, 0, None, outp) == -1
+    assert lib.hodlr_qr_batched(C.cast(arr, C.POINTER(C.c_void_p)), 2, 1e-10, None, 0, None, None) == -1
+    ms = (C.c_double * 1)()
+    assert lib.hodlr_qr_batched_time(None, 1, 1e-10, None, 0, 0, 1, None, ms) == -1
 
 
 def test_header_documents_every_entry_point():

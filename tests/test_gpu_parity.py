@@ -269,3 +269,46 @@ def test_repeat_runs_are_deterministic(H):
     a = H.hodlr_apply_q(H.hodlr_qr(A, EPS), X.clone()).cpu().numpy()
     b = H.hodlr_apply_q(H.hodlr_qr(A, EPS), X.clone()).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+def _batch_inputs():
+    """A small batch of two shapes: three n=1024 and two n=2048 Gaussian HODLR
+    matrices (leaf 256) of different ranks."""
+    specs = [(1024, 1, 30), (2048, 3, 31), (1024, 4, 32), (2048, 2, 33), (1024, 2, 34)]
+    return [G.gaussian_hodlr(n, 256, k, seed=sd) for n, k, sd in specs]
+
+
+def test_batched_equals_one_at_a_time_bitwise(H):
+    """Each factorisation of a batch gives the bits hodlr_qr gives alone."""
+    inps = _batch_inputs()
+    As = [H.hodlr_build(inp, rank_cap=32) for inp in inps]
+    Fb = H.hodlr_qr_batched(As, EPS)
+    for inp, A, Fi in zip(inps, As, Fb):
+        X = np.random.default_rng(5).standard_normal((inp.n, 4))
+        F1 = H.hodlr_qr(A, EPS)
+        for which in "YTR":
+            a = H.hodlr_qr_matmul(Fi, which, H.colmajor(X)).cpu().numpy()
+            b = H.hodlr_qr_matmul(F1, which, H.colmajor(X)).cpu().numpy()
+            assert np.array_equal(a, b), which
+        assert H.hodlr_qr_info(Fi)["anorm"] == H.hodlr_qr_info(F1)["anorm"]
+
+
+def test_batched_parity_with_oracle(H):
+    """Batched factors against the oracle (same thresholds), well-conditioned inputs."""
+    inps = _batch_inputs()
+    As = [H.hodlr_build(inp, rank_cap=32) for inp in inps]
+    anorms = [H.hodlr_norm2_est(A, 50) for A in As]
+    Fb = H.hodlr_qr_batched(As, EPS, anorm=anorms)
+    for inp, Fi, an in list(zip(inps, Fb, anorms))[:3]:
+        ref = O.hqr(inp, EPS, anorm=an)
+        X = np.random.default_rng(6).standard_normal((inp.n, 8))
+        rR = _rel(H.hodlr_qr_matmul(Fi, "R", H.colmajor(X)).cpu().numpy(), O.rmat(ref, X))
+        rQ = _rel(H.hodlr_apply_q(Fi, H.colmajor(X)).cpu().numpy(), O.apply_q(ref, X), np.linalg.norm(X))
+        assert rR <= 1e-8 and rQ <= 1e-8, (inp.n, rR, rQ)
+
+
+def test_batched_time_runs(H):
+    inps = _batch_inputs()[:2]
+    As = [H.hodlr_build(inp, rank_cap=32) for inp in inps]
+    ms = H.hodlr_qr_batched_time(As, EPS, warmup=1, reps=2)
+    assert ms.shape == (2,) and (ms > 0).all()
