@@ -279,6 +279,23 @@ def cauchy_hodlr(n: int, n_min: int = 256, seed=1, eps: float = 1e-10,
     return H
 
 
+def batched_set(count: int = 256, seed: int = 3, dmin: int = 2, dmax: int = 6, kmin: int = 1,
+                kmax: int = 4, n_min: int = 256) -> list:
+    """The batch of independent matrices of the batched workload: for each of
+    `count` matrices in turn, d ~ U{dmin..dmax} and k ~ U{kmin..kmax} are drawn,
+    then a Gaussian HODLR matrix (gaussian_hodlr, shift 4I) of order
+    n_min * 2^d with exact off-diagonal rank k, all from one stream seeded
+    with `seed`."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        d = int(rng.integers(dmin, dmax + 1))
+        k = int(rng.integers(kmin, kmax + 1))
+        out.append(gaussian_hodlr(n_min * 2 ** d, n_min, k, seed=None, rng=rng,
+                                  name=f"batched(d={d},k={k})"))
+    return out
+
+
 def config(i: int, **kw) -> HodlrInput:
     """The benchmark workloads, seeded as documented:
     0: Gaussian, n=512, leaf 64, rank 8, shift 4I, seed 0.

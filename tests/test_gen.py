@@ -68,3 +68,14 @@ def test_perturb_is_roundoff_close():
     P = G.perturb(H, 3)
     d = np.linalg.norm(P.to_dense() - H.to_dense(), 2) / np.linalg.norm(H.to_dense(), 2)
     assert 0 < d < 1e-14
+
+
+def test_batched_set_draws():
+    s1 = G.batched_set(count=6, seed=3)
+    s2 = G.batched_set(count=6, seed=3)
+    assert [a.n for a in s1] == [b.n for b in s2]
+    assert all(a.n in (1024, 2048, 4096, 8192, 16384) for a in s1)
+    assert np.array_equal(s1[0].leaves[0], s2[0].leaves[0])
+    for a in s1:
+        ks = {U.shape[1] for (U, V) in a.blocks.values()}
+        assert len(ks) == 1 and 1 <= ks.pop() <= 4
