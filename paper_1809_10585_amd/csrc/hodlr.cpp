@@ -52,6 +52,10 @@ hodlr_status fail(hodlr_status s, const std::string& m) {
 struct DMem {
   std::vector<void*> ptrs;
   size_t bytes = 0;
+  // when set, every allocation is zero-filled on `zero_stream` (capacity padding
+  // of factors and temporaries then holds zeros, never recycled garbage)
+  bool zero = false;
+  hipStream_t zero_stream = nullptr;
   ~DMem() {
     for (void* p : ptrs) (void)hipFree(p);
   }
@@ -68,6 +72,10 @@ struct DMem {
     ptrs.push_back(p);
     bytes += count * sizeof(T);
     *out = static_cast<T*>(p);
+    if (zero && hipMemsetAsync(p, 0, count * sizeof(T), zero_stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(HODLR_EDEVICE, "hipMemsetAsync of a new allocation failed");
+    }
     return HODLR_OK;
   }
 };
@@ -739,7 +747,8 @@ struct hodlr_qr_s {
   double *SL = nullptr, *SR = nullptr, *SLt = nullptr, *Z1 = nullptr, *Z2 = nullptr, *Z4 = nullptr,
          *SRW = nullptr, *TL = nullptr, *TR = nullptr, *Z5 = nullptr, *Wm = nullptr, *Mg = nullptr;
   double *X1 = nullptr, *X2 = nullptr;  // n x SMAX scratch of apply_q / solve / the norm estimate
-  std::shared_ptr<Batch> batch;          // the schedule this factor was computed with
+  std::shared_ptr<Batch> batch;          // the schedule (dropped once the factors are final)
+  int64_t n_launch = 0, n_trunc = 0;     // counts of that schedule per factorisation
   HView view_gen() const { return HView{t.L, up.dview, lo.dview, leaves.dview, LEAF_FULL}; }
   HView view_y() const { return HView{t.L, nullptr, lo.dview, leaves.dview, LEAF_UNIT_LOWER}; }
   HView view_t() const { return HView{t.L, tup.dview, nullptr, tleaves.dview, LEAF_UPPER}; }
@@ -1141,6 +1150,8 @@ hodlr_status reset_factor(hodlr_qr_s& F, const hodlr_s& A, hipStream_t st) {
 hodlr_status make_storage(const hodlr_s& A, double eps, double anorm, hipStream_t st,
                           std::unique_ptr<hodlr_qr_s>& out) {
   auto F = std::make_unique<hodlr_qr_s>();
+  F->mem.zero = true;
+  F->mem.zero_stream = st;
   F->t = A.t;
   F->cap = A.cap;
   F->anorm = anorm;
@@ -1173,6 +1184,8 @@ hodlr_status make_storage(const hodlr_s& A, double eps, double anorm, hipStream_
   TRY(F->mem.alloc(&F->X1, (size_t)t.n * SMAX));
   TRY(F->mem.alloc(&F->X2, (size_t)t.n * SMAX));
   TRY(ensure_work(F->mem, F->work, 0, 1, true, st));  // error word, flop counters, leaf workspace
+  // later allocations (plans of apply_q / solve) are filled on their own streams
+  F->mem.zero = false;
   out = std::move(F);
   return HODLR_OK;
 }
@@ -1267,6 +1280,15 @@ hodlr_status run_batch(Batch& B, const std::vector<hodlr_qr_s*>& Fs, const std::
 
 hodlr_status run_factor(hodlr_qr_s& F, const hodlr_s& A, uint32_t flags, hipStream_t st) {
   return run_batch(*F.batch, {&F}, {&A}, flags, st);
+}
+
+// keep the schedule's counts, release its plan and workspace (the factors no
+// longer need them; apply_q / solve build their own small plans)
+void drop_schedule(hodlr_qr_s& F) {
+  if (!F.batch) return;
+  F.n_launch = F.batch->n_launch;
+  F.n_trunc = F.batch->plan.n_trunc / std::max(1, F.batch->size);
+  F.batch.reset();
 }
 
 hodlr_status finish_factor(hodlr_qr_s& F, hipStream_t st) {
@@ -1418,6 +1440,7 @@ hodlr_status hodlr_qr(const hodlr_t* A, double eps, double anorm, uint32_t flags
   TRY(make_factor(*A, eps, anorm, st, F));
   TRY(run_factor(*F, *A, flags, st));
   TRY(finish_factor(*F, st));
+  drop_schedule(*F);
   *out = F.release();
   return HODLR_OK;
 }
@@ -1505,7 +1528,10 @@ hodlr_status hodlr_qr_batched(const hodlr_t* const* A, int32_t count, double eps
     }
   }
   if (first_err != HODLR_OK) return fail(first_err, msg);
-  for (int i = 0; i < count; ++i) out[i] = S.F[i].release();
+  for (int i = 0; i < count; ++i) {
+    drop_schedule(*S.F[i]);
+    out[i] = S.F[i].release();
+  }
   return HODLR_OK;
 }
 
@@ -1756,8 +1782,8 @@ hodlr_status hodlr_qr_info(const hodlr_qr_t* F, hodlr_qr_info_t* info) {
   info->tau_a = F->tauA;
   info->tau_t = F->tauT;
   info->flops = flop_total(F->work.fc);
-  info->n_truncations = F->batch ? F->batch->plan.n_trunc / F->batch->size : 0;
-  info->n_launches = F->batch ? F->batch->n_launch : 0;
+  info->n_truncations = F->batch ? F->batch->plan.n_trunc / F->batch->size : F->n_trunc;
+  info->n_launches = F->batch ? F->batch->n_launch : F->n_launch;
   info->device_bytes = (int64_t)F->mem.bytes;
   return HODLR_OK;
 }
