@@ -1400,35 +1400,43 @@ __device__ __forceinline__ void leaf_panel_rows(LeafWs W, int c0, int pw, int M,
   }
   leaf_reduce_tile(acc, sm + LF_PART, gram);
   // T by eq. recqrcombined, doubling the block size: on blocks B1 = [2ab, 2ab+b)
-  // and B2 = [2ab+b, 2ab+2b), T[B1, B2] = -T[B1, B1] (Y_B1^T Y_B2) T[B2, B2]
+  // and B2 = [2ab+b, 2ab+2b), T[B1, B2] = -T[B1, B1] (Y_B1^T Y_B2) T[B2, B2].
+  // Wavefront 0 alone (at most 64 entries per step), ordered by wavefront fences.
   double* Tp = sm + LF_TP;
   double* Xt = sm + LF_W;
-  if (tid < NB * NB) {
-    const int i = tid % NB, j = tid / NB;
-    Tp[tid] = (i == j && i < pw) ? taus[i] : 0.0;
-  }
-  __syncthreads();
-  for (int b = 1; b < NB; b *= 2) {
-    const int e = tid, bb = b * b;
-    const bool act = e < (NB / (2 * b)) * bb;
-    const int pa = e / bb, rc = e % bb, r = rc % b, c = rc / b;
-    const int i = 2 * pa * b + r, j = 2 * pa * b + b + c;
-    if (act) {
-      double x = 0.0;
-      for (int k = 2 * pa * b + b; k < 2 * pa * b + 2 * b; ++k) x += gram[i + NB * k] * Tp[k + NB * j];
-      Xt[i + NB * j] = x;
+  if (tid < 64) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + 64 * e, i = idx % NB, j = idx / NB;
+      Tp[idx] = (i == j && i < pw) ? taus[i] : 0.0;
     }
-    __syncthreads();
-    if (act) {
-      double y = 0.0;
-      for (int k = 2 * pa * b; k < 2 * pa * b + b; ++k) y += Tp[i + NB * k] * Xt[k + NB * j];
-      Tp[i + NB * j] = -y;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int b = 1; b < NB; b *= 2) {
+      const int bb = b * b;
+      const bool act = tid < (NB / (2 * b)) * bb;
+      const int pa = tid / bb, rc = tid % bb, r = rc % b, c = rc / b;
+      const int i = 2 * pa * b + r, j = 2 * pa * b + b + c;
+      if (act) {
+        double x = 0.0;
+        for (int k = 2 * pa * b + b; k < 2 * pa * b + 2 * b; ++k) x += gram[i + NB * k] * Tp[k + NB * j];
+        Xt[i + NB * j] = x;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (act) {
+        double y = 0.0;
+        for (int k = 2 * pa * b; k < 2 * pa * b + b; ++k) y += Tp[i + NB * k] * Xt[k + NB * j];
+        Tp[i + NB * j] = -y;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
-  }
-  if (tid < NB * NB) {
-    const int i = tid % NB, j = tid / NB;
-    if (i < pw && j < pw) W.T[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] = Tp[tid];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + 64 * e, i = idx % NB, j = idx / NB;
+      if (i < pw && j < pw) W.T[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] = Tp[idx];
+    }
   }
 }
 
@@ -1496,15 +1504,17 @@ __device__ __forceinline__ void leaf_ytb(const LeafWs& W, int c0, int pw, int M,
 }
 
 // Strip [cs, cs+sw) -= Y_p T_pp^T (Y_p^T strip)  (the block reflector of panel p),
-// all three products on FP64 MFMA.
+// all three products on FP64 MFMA.  W = Y^T strip is summed over the
+// wavefronts through LDS; every wavefront then forms W2 = T^T W itself (four
+// MFMAs), whose result registers are already the B operand of the update
+// MFMA, and writes its updated rows straight to global memory.
 __device__ __forceinline__ void leaf_strip(const LeafWs& W, int c0, int pw, int M, int cs, int sw,
                                            double* sm) {
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   double* Ys = sm + LF_A;
   double* Bs = Ys + LF_LD * NB;
   double* Wt = sm + LF_W;
-  double* W2 = Wt + NB * NB;
-  double* Tt = W2 + NB * NB;
+  double* Tt = Wt + 2 * NB * NB;
   double tval = 0.0;  // T_pp tile, loaded together with the first staging
   if (tid < 256) {
     const int i = tid & 15, j = tid >> 4;
@@ -1517,18 +1527,17 @@ __device__ __forceinline__ void leaf_strip(const LeafWs& W, int c0, int pw, int 
     leaf_stage(W, c0, pw, r0, rn, cs, sw, Ys, Bs);
     __syncthreads();
     acc = leaf_ytb_acc(Ys, Bs, rn, acc);
-    __syncthreads();
+    if (!one_chunk) __syncthreads();
   }
   if (tid < 256) Tt[tid] = tval;
   leaf_reduce_tile(acc, sm + LF_PART, Wt);
-  if (tid < 256) {  // W2 = T^T W
-    const int i = tid & 15, j = tid >> 4;
-    double sacc = 0.0;
+  // W2 = T^T W: A[i][k] = T[k][i], B[k][j] = W[k][j]; D[i][j] sits in lane
+  // j + 16 (i % 4), element i / 4, i.e. element e of lane l is W2[4e + l/16][l%16]:
+  // the B operand of k-step e of the update below
+  d4_t w2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < NB; ++q) sacc += Tt[q + NB * i] * Wt[q + NB * j];
-    W2[i + NB * j] = sacc;
-  }
-  __syncthreads();
+  for (int k0 = 0; k0 < NB; k0 += 4)
+    w2 = mfma16(Tt[(k0 + (l >> 4)) + NB * (l & 15)], Wt[(k0 + (l >> 4)) + NB * (l & 15)], w2);
   for (int r0 = c0; r0 < M; r0 += LF_CH) {
     const int rn = min(LF_CH, M - r0);
     if (!one_chunk) {
@@ -1539,20 +1548,16 @@ __device__ __forceinline__ void leaf_strip(const LeafWs& W, int c0, int pw, int 
     for (int t = w; t < nt; t += 16) {
       d4_t d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int k0 = 0; k0 < NB; k0 += 4)
-        d = mfma16(Ys[(16 * t + (l & 15)) + (k0 + (l >> 4)) * LF_LD], W2[(k0 + (l >> 4)) + NB * (l & 15)], d);
+      for (int e = 0; e < 4; ++e)
+        d = mfma16(Ys[(16 * t + (l & 15)) + (4 * e + (l >> 4)) * LF_LD], w2[e], d);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = 16 * t + 4 * e + (l >> 4);
-        Bs[row + (l & 15) * LF_LD] -= d[e];
+        const int row = 16 * t + 4 * e + (l >> 4), col = l & 15;
+        if (row < rn && col < sw)
+          W.H[(int64_t)(r0 + row) + (int64_t)(cs + col) * MAXSTACK] = Bs[row + col * LF_LD] - d[e];
       }
     }
-    __syncthreads();
-    for (int e = tid; e < LF_CH * NB; e += NT_LEAF) {
-      const int rr = e % LF_CH, jj = e / LF_CH;
-      if (rr < rn && jj < sw) W.H[(int64_t)(r0 + rr) + (int64_t)(cs + jj) * MAXSTACK] = Bs[rr + jj * LF_LD];
-    }
-    __syncthreads();
+    if (!one_chunk) __syncthreads();
   }
 }
 
