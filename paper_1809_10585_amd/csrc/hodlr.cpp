@@ -212,14 +212,15 @@ hodlr_status make_leaves(DMem& mem, const Tree& t, LeafSet& S) {
 enum OpType {
   OP_TRQR, OP_TRFORM, OP_MMPROJ, OP_MMAPPLY, OP_GTALL, OP_GRED, OP_LGATHER, OP_LPANEL,
   OP_LUPDATE, OP_LSCATTER, OP_FILL, OP_NORMALIZE, OP_TRSM, OP_SETSCAL,
-  OP_MMRED,
+  OP_MMRED, OP_TRSMALL,
   OP_SIGNAL,  // record event a0 on the op's lane (no kernel)
   OP_WAIT,    // the op's lane waits for event a0 (no kernel)
   OP_NTYPES
 };
 const char* const OP_NAMES[OP_NTYPES] = {
   "tr_qr", "tr_form", "mm_proj", "mm_apply", "gemm_tall", "gemm_red", "leaf_gather", "leaf_panel",
-  "leaf_update", "leaf_scatter", "fill", "normalize", "leaf_trsm", "set_scal", "mm_red", "signal", "wait"};
+  "leaf_update", "leaf_scatter", "fill", "normalize", "leaf_trsm", "set_scal", "mm_red", "tr_small",
+  "signal", "wait"};
 
 struct Op {
   int type;
@@ -346,6 +347,7 @@ struct Plan {
     int64_t off = 0;
     int cnt = 0;
     const int c_first = (int)trc.size(), f_first = (int)trf.size();
+    std::vector<TrChunk> small;
     for (const TrSpec& sp : specs) {
       TrJob J{};
       for (int a = 0; a < 2; ++a)
@@ -381,6 +383,13 @@ struct Plan {
       J.jcounter = cnt++;
       const int jid = (int)trj.size();
       trj.push_back(J);
+      ++n_trunc;
+      // both factors within one chunk: the one-block kernel does the whole job
+      if (J.side[0].m <= CH && J.side[1].m <= CH) {
+        small.push_back(TrChunk{jid, 0, 0});
+        small.push_back(TrChunk{jid, 1, 0});
+        continue;
+      }
       for (int side = 0; side < 2; ++side)
         for (int c = 0; c < J.side[side].p0; ++c) trc.push_back(TrChunk{jid, side, c});
       bool leader = true;
@@ -390,10 +399,16 @@ struct Plan {
       }
       for (int r0 = 0; r0 < J.side[1].m; r0 += 64)
         trf.push_back(TrForm{jid, 1, 0, r0, std::min(64, J.side[1].m - r0), 0});
-      ++n_trunc;
     }
-    push(Op{OP_TRQR, c_first, (int)trc.size() - c_first});
-    push(Op{OP_TRFORM, f_first, (int)trf.size() - f_first});
+    if (!small.empty()) {
+      const int s_first = (int)trc.size();
+      trc.insert(trc.end(), small.begin(), small.end());
+      push(Op{OP_TRSMALL, s_first, (int)small.size()});
+    }
+    if ((int)trc.size() > c_first + (int)small.size()) {
+      push(Op{OP_TRQR, c_first, (int)trc.size() - c_first - (int)small.size()});
+      push(Op{OP_TRFORM, f_first, (int)trf.size() - f_first});
+    }
     ws_lane[lane] = std::max(ws_lane[lane], off);
     cnt_lane[lane] = std::max(cnt_lane[lane], cnt);
   }
@@ -576,7 +591,8 @@ bool g_attr_done = false;
 hodlr_status set_attrs() {
   if (g_attr_done) return HODLR_OK;
   for (const void* f : {(const void*)k_tr_qr<16>, (const void*)k_tr_qr<32>, (const void*)k_tr_qr<64>,
-                        (const void*)k_tr_qr<128>})
+                        (const void*)k_tr_qr<128>, (const void*)k_tr_small<16>, (const void*)k_tr_small<32>,
+                        (const void*)k_tr_small<64>, (const void*)k_tr_small<128>})
     HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TR_QR_LDS));
   HIPCHK(hipFuncSetAttribute((const void*)k_tr_form, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)TR_FORM_LDS));
@@ -619,6 +635,12 @@ void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st, const Lau
     case OP_TRQR: {
       const int wt = P.wtop;
       auto kern = wt <= 16 ? k_tr_qr<16> : wt <= 32 ? k_tr_qr<32> : wt <= 64 ? k_tr_qr<64> : k_tr_qr<128>;
+      launch(L, kern, o.count, NT_TR, TR_QR_LDS, st, P.d_trj, P.d_trc, o.first, ws, cnt);
+      break;
+    }
+    case OP_TRSMALL: {
+      const int wt = P.wtop;
+      auto kern = wt <= 16 ? k_tr_small<16> : wt <= 32 ? k_tr_small<32> : wt <= 64 ? k_tr_small<64> : k_tr_small<128>;
       launch(L, kern, o.count, NT_TR, TR_QR_LDS, st, P.d_trj, P.d_trc, o.first, ws, cnt);
       break;
     }

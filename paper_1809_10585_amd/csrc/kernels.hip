@@ -359,6 +359,35 @@ __device__ __forceinline__ void jacobi(double* X, int lx, double* V, int lv, int
   }
 }
 
+// Rotation of one-sided Jacobi for a column pair with a = |x_i|^2, b = |x_j|^2,
+// g = x_i . x_j: false when |g| <= tol sqrt(a b) (tested squared); otherwise
+// the (cs, sn) that makes the rotated pair orthogonal, the smaller angle with
+// tan(2 theta) = 2g / (b - a) (the rotation of jacobi()).  Short dependency
+// chain: with d = b - a and g2 = 2g scaled by a power of two (squares neither
+// overflow nor underflow), r = |(d, g2)|, s = r + |d| and q = 1/sqrt(2 r s),
+// cs = s q and sn = sign(d) g2 q (cs^2 + sn^2 = (s^2 + g2^2) / (2 r s) = 1).
+__device__ __forceinline__ bool jac_rot_fast(double al, double be, double ga, double tol2, double& cs,
+                                             double& sn) {
+  if (!(ga != 0.0 && ga * ga > tol2 * (al * be))) return false;
+  double d = be - al, g = 2.0 * ga;
+  const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(d), fabs(g)));
+  d = __builtin_ldexp(d, -e);
+  g = __builtin_ldexp(g, -e);
+  const double h2 = fma(d, d, g * g);  // in [1/4, 2]
+  double y = __builtin_amdgcn_rsq(h2);
+  y = y * fma(-0.5 * h2 * y, y, 1.5);
+  y = y * fma(-0.5 * h2 * y, y, 1.5);
+  const double r = h2 * y;
+  const double s = r + fabs(d);
+  const double u = 2.0 * r * s;
+  double q = __builtin_amdgcn_rsq(u);
+  q = q * fma(-0.5 * u * q, q, 1.5);
+  q = q * fma(-0.5 * u * q, q, 1.5);
+  cs = s * q;
+  sn = (d >= 0.0 ? g : -g) * q;
+  return true;
+}
+
 // The same one-sided Jacobi for w <= WS (WS = 8 or 16) inside one wavefront.
 // X (and V = X + WS*WS) are WS x WS in LDS with leading dimension WS, rows and
 // columns beyond w zero (rotations keep them zero), so a lane loads, rotates and
@@ -412,18 +441,8 @@ __device__ __forceinline__ void jacobi_small(double* X, int w) {
             be = fma(b[row], b[row], be);
             ga = fma(a[row], b[row], ga);
           }
-          if (ga != 0.0 && ga * ga > tol2 * (al * be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            double t;
-            if (fabs(zeta) > 1e150)
-              t = 0.5 / zeta;
-            else
-              t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + sqrt_nr(fma(zeta, zeta, 1.0)));
-            const double u = fma(t, t, 1.0);
-            double cs = __builtin_amdgcn_rsq(u);
-            cs = cs * fma(-0.5 * u * cs, cs, 1.5);
-            cs = cs * fma(-0.5 * u * cs, cs, 1.5);
-            const double sn = cs * t;
+          double cs, sn;
+          if (jac_rot_fast(al, be, ga, tol2, cs, sn)) {
 #pragma unroll
             for (int row = 0; row < WS; ++row) {
               xi[row] = cs * a[row] - sn * b[row];
@@ -442,6 +461,25 @@ __device__ __forceinline__ void jacobi_small(double* X, int w) {
     }
   }
   __syncthreads();
+}
+
+// Flops of one recompression (the oracle's counting: Householder QR of both
+// factors, the product of the R factors, the SVD as 21 p^3, forming the factors).
+__device__ __forceinline__ double qr_flops(double m, double n) {
+  const double pp = fmin(m, n);
+  return m >= n ? 2.0 * m * n * pp - 2.0 / 3.0 * pp * pp * pp : 2.0 * n * m * m - 2.0 / 3.0 * m * m * m;
+}
+
+__device__ __forceinline__ double tr_flops_full(int m0, int m1, int w, int k) {
+  const double p1 = min(m0, w), p2 = min(m1, w);
+  const double mp = fmax(p1, p2);
+  return qr_flops(m0, w) + qr_flops(m1, w) + 2.0 * p1 * p2 * w + 21.0 * mp * mp * mp +
+         4.0 * (double)m0 * p1 * k + 2.0 * (double)m1 * w * k;
+}
+
+__device__ __forceinline__ double tr_flops_orth(int m0, int m1, int w) {
+  const double pq = (double)min(m0, w);
+  return 2.0 * (2.0 * (double)m0 * w * pq - 2.0 / 3.0 * pq * pq * pq) + 2.0 * (double)w * w * m1;
 }
 
 // Last block of a job: SVD of R1 R2^T and the small factors U_k, P = R1^T U_k.
@@ -466,10 +504,7 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
       Uk[r + p * WMAX] = (r == p) ? 1.0 : 0.0;
       P[r + p * WMAX] = R1[p + r * WMAX];
     }
-    if (tid == 0) {
-      const double pq = (double)min(m0, w);
-      add_flops(fc, fcat, 2.0 * (2.0 * m0 * w * pq - 2.0 / 3.0 * pq * pq * pq) + 2.0 * w * w * m1);
-    }
+    if (tid == 0) add_flops(fc, fcat, tr_flops_orth(m0, m1, w));
   } else {
     const double* R2 = ws + J.side[1].node0 + (int64_t)tr_root_slot(J.side[1].p0, G) * TR_NODE;
     // w <= 16: X and V padded to WS x WS (zeros beyond w) for jacobi_small
@@ -554,21 +589,7 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
       for (int l = 0; l <= r; ++l) sacc += R1s[l + r * lr] * V[l + pc * LV];
       P[r + p * WMAX] = sacc;
     }
-    if (tid == 0) {
-      const double p1 = min(m0, w), p2 = min(m1, w);
-      const double qf = [](double m, double n) {
-        const double pp = fmin(m, n);
-        return m >= n ? 2.0 * m * n * pp - 2.0 / 3.0 * pp * pp * pp
-                      : 2.0 * n * m * m - 2.0 / 3.0 * m * m * m;
-      }(m0, w) + [](double m, double n) {
-        const double pp = fmin(m, n);
-        return m >= n ? 2.0 * m * n * pp - 2.0 / 3.0 * pp * pp * pp
-                      : 2.0 * n * m * m - 2.0 / 3.0 * m * m * m;
-      }(m1, w);
-      const double mp = fmax(p1, p2);
-      add_flops(fc, fcat,
-                qf + 2.0 * p1 * p2 * w + 21.0 * mp * mp * mp + 4.0 * m0 * p1 * k + 2.0 * m1 * w * k);
-    }
+    if (tid == 0) add_flops(fc, fcat, tr_flops_full(m0, m1, w, k));
   }
   if (tid == 0) {
     hdr[0] = (double)w;
@@ -579,7 +600,8 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
 }
 
 template <int W>
-__device__ __forceinline__ void tr_chunk(const TrJob& J, int side, int chunk, double* ws, int* counters, int* err,
+// Returns true in the block that ran the SVD (the job's last block).
+__device__ __forceinline__ bool tr_chunk(const TrJob& J, int side, int chunk, double* ws, int* counters, int* err,
                          double* fc, double* smem, int w, int n0a, int n0b) {
   constexpr int TPC = NT_TR / W;
   constexpr int RPT = CH / TPC;
@@ -657,7 +679,7 @@ __device__ __forceinline__ void tr_chunk(const TrJob& J, int side, int chunk, do
     __syncthreads();
     const int last = sflag[0];
     __syncthreads();
-    if (!last) return;
+    if (!last) return false;
     __threadfence();
     // become the parent: stack the children's R factors
     const int64_t cbase = base;
@@ -692,10 +714,11 @@ __device__ __forceinline__ void tr_chunk(const TrJob& J, int side, int chunk, do
     __syncthreads();
     const int last = sflag[0];
     __syncthreads();
-    if (!last) return;
+    if (!last) return false;
     __threadfence();
   }
   tr_svd<W>(J, ws, w, n0a, n0b, smem, err, fc);
+  return true;
 }
 
 // WTOP: widest tier compiled into this instantiation (the host picks it from
@@ -848,6 +871,433 @@ __global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ job
     else
       rows_times_small(In, 64, rows, w, P, WMAX, k, out + it.row0, ldo);
   }
+}
+
+// ------------------------------------------------------------------ one-block recompression
+// A recompression whose two factors have at most CH rows each, in one block
+// and one launch (no TSQR tree, no join across blocks, no forming kernel).
+// Width w <= 8: wavefront 0 factorises L and wavefront 1 factorises R in
+// registers (wave_qr), wavefront 0 runs the SVD of R2 R1^T in LDS
+// (jacobi_wave), then wavefront 0 applies Q1 to [U_k; 0] and wavefront 1 forms
+// R (R1^T U_k) from the rows it kept.  Wider jobs run the chunk code of
+// k_tr_qr for one chunk per side and then the forming step, in this block.
+
+// Load rows [0, h) of the factor [seg0 | seg1] (n0 columns in seg0) into a
+// wavefront's tile: lane l holds rows l + 64 i, columns < WT (zero beyond w, h).
+template <int WT>
+__device__ __forceinline__ void wave_load(double (&a)[4][WT], const Seg& s0, const Seg& s1, int n0, int h,
+                                          int w) {
+  const int lane = threadIdx.x & 63;
+  if (h <= 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < WT; ++c) a[i][c] = 0.0;
+    return;
+  }
+  // every load is issued (elements outside the tile read the factor's first
+  // element, which exists for w >= 1 and h >= 1) before any is used
+  const double* base = (n0 > 0) ? s0.p : s1.p;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t r = lane + 64 * i;
+#pragma unroll
+    for (int c = 0; c < WT; ++c) {
+      const bool ok = r < h && c < w;
+      const double* src = (c < n0) ? s0.p + r + (int64_t)c * s0.ld : s1.p + r + (int64_t)(c - n0) * s1.ld;
+      a[i][c] = *(ok ? src : base);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = lane + 64 * i;
+#pragma unroll
+    for (int c = 0; c < WT; ++c) a[i][c] = (r < h && c < w) ? ((c < n0) ? s0.scale : s1.scale) * a[i][c] : 0.0;
+  }
+}
+
+// Householder QR of the h x w tile of one wavefront (w <= WT, h <= 256), the
+// reflector convention of reg_qr.  On exit R is on and above the diagonal, v
+// below it, tau[j] in registers (0 past min(h, w)).  The products with the
+// later columns are independent and run interleaved (columns past w are zero
+// and stay zero).
+template <int WT>
+__device__ __forceinline__ void wave_qr(double (&a)[4][WT], int h, int w, double (&tau)[WT]) {
+  const int lane = threadIdx.x & 63;
+  const int jmax = min(h, w);
+#pragma unroll
+  for (int j = 0; j < WT; ++j) {
+    tau[j] = 0.0;
+    if (j < jmax) {
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double x = (lane + 64 * i > j) ? a[i][j] : 0.0;
+        if (i & 1) s1 += x * x; else s0 += x * x;
+      }
+      const double ss = gsumt<64>(s0 + s1);
+      const double al = lane_read(a[0][j], j);
+      double tj, beta, scal;
+      house_scalars(al, ss, beta, tj, scal);
+      const double sc = (ss != 0.0) ? scal : 1.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = lane + 64 * i;
+        a[i][j] = (r > j) ? a[i][j] * sc : (r == j ? beta : a[i][j]);
+      }
+      tau[j] = tj;
+      if (tj != 0.0) {
+        double f[WT];
+#pragma unroll
+        for (int c = j + 1; c < WT; ++c) {
+          double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double v = (lane + 64 * i > j) ? a[i][j] : 0.0;
+            if (i & 1) d1 += v * a[i][c]; else d0 += v * a[i][c];
+          }
+          f[c] = tj * (gsumt<64>(d0 + d1) + lane_read(a[0][c], j));
+        }
+#pragma unroll
+        for (int c = j + 1; c < WT; ++c) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = lane + 64 * i;
+            const double v = (r > j) ? a[i][j] : (r == j ? 1.0 : 0.0);
+            a[i][c] -= f[c] * v;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Z <- H_0 H_1 ... H_{jmax-1} Z for the reflectors of wave_qr (columns of a)
+// on the wavefront's tile Z (columns < WT).
+template <int WT>
+__device__ __forceinline__ void wave_apply_q(const double (&a)[4][WT], const double (&tau)[WT], int jmax,
+                                             double (&z)[4][WT]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = WT - 1; j >= 0; --j) {
+    if (j < jmax && tau[j] != 0.0) {
+      double f[WT];
+#pragma unroll
+      for (int c = 0; c < WT; ++c) {
+        double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = lane + 64 * i;
+          const double v = (r > j) ? a[i][j] : (r == j ? 1.0 : 0.0);
+          if (i & 1) d1 += v * z[i][c]; else d0 += v * z[i][c];
+        }
+        f[c] = tau[j] * gsumt<64>(d0 + d1);
+      }
+#pragma unroll
+      for (int c = 0; c < WT; ++c) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = lane + 64 * i;
+          const double v = (r > j) ? a[i][j] : (r == j ? 1.0 : 0.0);
+          z[i][c] -= f[c] * v;
+        }
+      }
+    }
+  }
+}
+
+// One-sided Jacobi (rotation and threshold of jacobi_small) on the w <= WT
+// columns of X (WT x WT, ld WT, zero beyond w), rotations accumulated in V, by
+// one wavefront: lane (p, r) = (lane / WT, lane % WT) holds row r of column
+// pair p of the round-robin schedule and the pair's sums are WT-lane reductions.
+template <int WT>
+__device__ __forceinline__ void jacobi_wave(double* X, double* V, int w) {
+  const int lane = threadIdx.x & 63;
+  const int n = w + (w & 1);
+  if (n < 2) return;
+  const int P = n / 2;
+  const int p = lane / WT, r = lane % WT;
+  const double tol = (double)w * DBL_EPSILON;
+  const double tol2 = tol * tol;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    int rot = 0;
+    for (int rd = 0; rd < n - 1; ++rd) {
+      int i = 0, j = 0;
+      if (p == 0) {
+        i = rd;
+        j = n - 1;
+      } else {  // (rd + p) mod (n - 1) and (rd - p) mod (n - 1), p < n/2
+        i = rd + p;
+        if (i >= n - 1) i -= n - 1;
+        j = rd - p;
+        if (j < 0) j += n - 1;
+      }
+      if (i > j) {
+        const int t = i;
+        i = j;
+        j = t;
+      }
+      const bool live = p < P;
+      double xi = 0.0, xj = 0.0, vi = 0.0, vj = 0.0;
+      if (live) {
+        xi = X[r + i * WT];
+        xj = X[r + j * WT];
+        vi = V[r + i * WT];
+        vj = V[r + j * WT];
+      }
+      const double al = gsumt<WT>(xi * xi), be = gsumt<WT>(xj * xj), ga = gsumt<WT>(xi * xj);
+      double cs, sn;
+      if (live && j < w && jac_rot_fast(al, be, ga, tol2, cs, sn)) {
+        X[r + i * WT] = cs * xi - sn * xj;
+        X[r + j * WT] = sn * xi + cs * xj;
+        V[r + i * WT] = cs * vi - sn * vj;
+        V[r + j * WT] = sn * vi + cs * vj;
+        rot = 1;
+      }
+      // the next round reads columns that other lanes wrote
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (__ballot(rot) == 0) break;
+  }
+}
+
+// LDS layout of the narrow path (doubles): R1, R2, X, V, U_k, P (WT x WT each), perm
+constexpr int TSM_R1 = 0, TSM_R2 = 64, TSM_X = 128, TSM_V = 192, TSM_U = 256, TSM_P = 320,
+              TSM_PERM = 384;
+
+template <int WT>
+__device__ __forceinline__ void tr_small_narrow(const TrJob& J, int w, int n0a, int n0b, double* sm) {
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const bool orth = (J.flags & TR_ORTH) != 0;
+  const int m0 = J.side[0].m, m1 = J.side[1].m;
+  double* R1 = sm + TSM_R1;
+  double* R2 = sm + TSM_R2;
+  double* X = sm + TSM_X;
+  double* V = sm + TSM_V;
+  double* Uk = sm + TSM_U;
+  double* P = sm + TSM_P;
+  int* perm = (int*)(sm + TSM_PERM);
+  double a[4][WT];  // wavefront 0: L's tile; wavefront 1: R's tile
+  double tau[WT];
+  if (wv == 0) {
+    wave_load<WT>(a, J.seg[0][0], J.seg[0][1], n0a, m0, w);
+    wave_qr<WT>(a, m0, w, tau);
+    if (lane < WT) {
+#pragma unroll
+      for (int c = 0; c < WT; ++c) R1[lane + c * WT] = (lane <= c) ? a[0][c] : 0.0;
+    }
+  } else if (wv == 1) {
+    if (!orth) {
+      wave_load<WT>(a, J.seg[1][0], J.seg[1][1], n0b, m1, w);
+      wave_qr<WT>(a, m1, w, tau);
+      if (lane < WT) {
+#pragma unroll
+        for (int c = 0; c < WT; ++c) R2[lane + c * WT] = (lane <= c) ? a[0][c] : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  int k = 0;
+  if (wv == 0) {
+    const double thr = *J.tau;
+    if (orth) {
+      k = min(m0, w);
+      if (lane < WT * WT) {
+        const int rr = lane % WT, pp = lane / WT;
+        Uk[lane] = (rr == pp && pp < k) ? 1.0 : 0.0;
+        P[lane] = (pp < k) ? R1[pp + rr * WT] : 0.0;  // P = R1^T [I_k; 0]
+      }
+    } else {
+      // X = R2 R1^T (upper triangular factors, zero beyond w), V = I
+      if (lane < WT * WT) {
+        const int ii = lane % WT, jj = lane / WT;
+        double s = 0.0;
+        for (int l = max(ii, jj); l < w; ++l) s += R2[ii + l * WT] * R1[jj + l * WT];
+        X[lane] = s;
+        V[lane] = (ii == jj && ii < w) ? 1.0 : 0.0;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      jacobi_wave<WT>(X, V, w);
+      // singular values (column norms), their descending order, and k (sig > tau)
+      double sg = -1.0;
+      if (lane < w) {
+        double s = 0.0;
+        for (int rr = 0; rr < WT; ++rr) s += X[rr + lane * WT] * X[rr + lane * WT];
+        sg = sqrt(s);
+      }
+      int pos = 0;
+#pragma unroll
+      for (int jj = 0; jj < WT; ++jj) {
+        const double sj = lane_read(sg, jj);
+        pos += (jj < w && (sj > sg || (sj == sg && jj < lane))) ? 1 : 0;
+      }
+      if (lane < w) perm[pos] = lane;
+      k = __popcll(__ballot(lane < w && sg > thr));
+      if (k > J.cap) {
+        if (lane == 0) atomicOr(J.err, ERR_CAPACITY);
+        k = J.cap;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // U_k = V[:, perm[:k]], P = R1^T U_k
+      if (lane < WT * WT) {
+        const int rr = lane % WT, pp = lane / WT;
+        Uk[lane] = (pp < k && rr < w) ? V[rr + perm[pp] * WT] : 0.0;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (lane < WT * WT) {
+        const int rr = lane % WT, pp = lane / WT;
+        double s = 0.0;
+        for (int l = 0; l <= rr; ++l) s += R1[l + rr * WT] * Uk[l + pp * WT];
+        P[lane] = (pp < k && rr < w) ? s : 0.0;
+      }
+    }
+    if (lane == 0) {
+      *J.out_rank = k;
+      perm[WT] = k;  // for the other wavefronts
+      add_flops(J.flops, J.fc, orth ? tr_flops_orth(m0, m1, w) : tr_flops_full(m0, m1, w, k));
+    }
+  }
+  __syncthreads();
+  k = perm[WT];
+  if (wv == 0) {
+    // L' = Q1 [U_k; 0] (rows past min(m0, w) of [U_k; 0] are zero)
+    double z[4][WT];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = lane + 64 * i;
+#pragma unroll
+      for (int c = 0; c < WT; ++c) z[i][c] = (i == 0 && r < WT && r < m0) ? Uk[r + c * WT] : 0.0;
+    }
+    wave_apply_q<WT>(a, tau, min(m0, w), z);
+    double* out = J.out[0];
+    const int ld = J.ldout[0];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = lane + 64 * i;
+#pragma unroll
+      for (int c = 0; c < WT; ++c)
+        if (r < m0 && c < k) out[r + (int64_t)c * ld] = z[i][c];
+    }
+  } else if (wv == 1) {
+    // R' = R P, row by row (R read again: it is cached, and wavefront 0's
+    // product with Q1 takes longer)
+    double b[4][WT];
+    wave_load<WT>(b, J.seg[1][0], J.seg[1][1], n0b, m1, w);
+    double* out = J.out[1];
+    const int ld = J.ldout[1];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = lane + 64 * i;
+#pragma unroll
+      for (int c = 0; c < WT; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < WT; ++l) s += b[i][l] * P[l + c * WT];
+        if (r < m1 && c < k) out[r + (int64_t)c * ld] = s;
+      }
+    }
+  }
+}
+
+// Forming step of a one-chunk job inside the block (k_tr_form for p0 = 1):
+// L' = Q_chunk U_k and R' = R P, from the header tr_svd wrote.
+__device__ __forceinline__ void tr_small_form(const TrJob& J, const double* ws, double* sm) {
+  const int tid = threadIdx.x;
+  const double* hdr = ws + J.hdr;
+  const int w = (int)hdr[0], k = (int)hdr[1];
+  if (w < 0 || w > WMAX || k < 0 || k > w || k > J.cap) return;
+  if (tid == 0) *J.out_rank = k;
+  if (w == 0 || k == 0) return;
+  const double* Uk = hdr + 8;
+  const double* P = Uk + WMAX * WMAX;
+  {
+    double* Z = sm;
+    for (int e = tid; e < w * k; e += NT_TR) Z[e] = Uk[(e % w) + (e / w) * WMAX];
+    __syncthreads();
+    const double* Qc = ws + J.side[0].node0 + WMAX * WMAX;
+    rows_times_small(Qc, CH, J.side[0].m, w, Z, w, k, J.out[0], J.ldout[0]);
+    __syncthreads();
+  }
+  const int n0 = (int)hdr[3];
+  const Seg s0 = J.seg[1][0], s1 = J.seg[1][1];
+  double* In = sm;           // rows x w, ld 64
+  double* Ps = sm + 64 * w;  // w x k, ld w
+  const bool fits = 64 * w + w * k <= WMAX * WMAX;
+  if (fits)
+    for (int e = tid; e < w * k; e += NT_TR) Ps[e] = P[(e % w) + (e / w) * WMAX];
+  for (int r0 = 0; r0 < J.side[1].m; r0 += 64) {
+    const int rows = min(64, J.side[1].m - r0);
+    for (int e = tid; e < rows * w; e += NT_TR) {
+      const int r = e % rows, cc = e / rows;
+      const int64_t gr = r0 + r;
+      In[r + cc * 64] = (cc < n0) ? s0.scale * s0.p[gr + (int64_t)cc * s0.ld]
+                                  : s1.scale * s1.p[gr + (int64_t)(cc - n0) * s1.ld];
+    }
+    __syncthreads();
+    if (fits)
+      rows_times_small(In, 64, rows, w, Ps, w, k, J.out[1] + r0, J.ldout[1]);
+    else
+      rows_times_small(In, 64, rows, w, P, WMAX, k, J.out[1] + r0, J.ldout[1]);
+    __syncthreads();
+  }
+}
+
+// Wider jobs: the chunk code of k_tr_qr, one chunk per side in each of the
+// job's two blocks (they join through the job counter); the block that ran
+// the SVD then forms both factors.
+template <int WTOP>
+__device__ __forceinline__ void tr_small_wide(const TrJob& J, int side, int w, int n0a, int n0b, double* ws,
+                                              int* counters, double* smem) {
+  const int t = tier_of(w);
+  bool last = false;
+  if (t == 16) {
+    if constexpr (WTOP >= 16) last = tr_chunk<16>(J, side, 0, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+  } else if (t == 32) {
+    if constexpr (WTOP >= 32) last = tr_chunk<32>(J, side, 0, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+  } else if (t == 64) {
+    if constexpr (WTOP >= 64) last = tr_chunk<64>(J, side, 0, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+  } else {
+    if constexpr (WTOP >= 128) last = tr_chunk<128>(J, side, 0, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+  }
+  if (!last) return;
+  __threadfence_block();
+  __syncthreads();
+  tr_small_form(J, ws, smem);
+}
+
+// Two blocks per job (its sides).  Width <= 8: the side-0 block does the
+// whole job and the side-1 block has nothing to do.
+template <int WTOP>
+__global__ void __launch_bounds__(NT_TR) k_tr_small(const TrJob* __restrict__ jobs,
+                                                     const TrChunk* __restrict__ items, int first,
+                                                     double* ws, int* counters) {
+  extern __shared__ double smem[];
+  const TrChunk it = items[first + blockIdx.x];
+  const TrJob& J = jobs[it.job];
+  const int n0a = seg_n(J.seg[0][0]);
+  const int w = n0a + seg_n(J.seg[0][1]);
+  const int n0b = seg_n(J.seg[1][0]);
+  if (w == 0 || w > WTOP) {
+    if (it.side == 0 && threadIdx.x == 0) {
+      *J.out_rank = 0;
+      if (w > WTOP) atomicOr(J.err, ERR_WIDTH);
+    }
+    return;
+  }
+  if (w <= 8) {
+    if (it.side != 0) return;
+    if (w <= 4)
+      tr_small_narrow<4>(J, w, n0a, n0b, smem);
+    else
+      tr_small_narrow<8>(J, w, n0a, n0b, smem);
+    return;
+  }
+  if (it.side == 1 && (J.flags & TR_ORTH)) return;
+  tr_small_wide<WTOP>(J, it.side, w, n0a, n0b, ws, counters, smem);
 }
 
 // ------------------------------------------------------------------ HODLR x tall-skinny
