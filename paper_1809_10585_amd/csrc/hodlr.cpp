@@ -384,10 +384,12 @@ struct Plan {
       const int jid = (int)trj.size();
       trj.push_back(J);
       ++n_trunc;
-      // both factors within one chunk: the one-block kernel does the whole job
-      if (J.side[0].m <= CH && J.side[1].m <= CH) {
-        small.push_back(TrChunk{jid, 0, 0});
-        small.push_back(TrChunk{jid, 1, 0});
+      // factors of a few chunks: k_tr_small (for wide jobs its forming step
+      // needs a tree of one combine level and w k doubles of LDS twice)
+      const int mx = std::max(J.side[0].m, J.side[1].m);
+      if (mx <= CH || (wtop <= 64 && mx <= TRS_MAXCH * CH)) {
+        for (int side = 0; side < 2; ++side)
+          for (int c = 0; c < J.side[side].p0; ++c) small.push_back(TrChunk{jid, side, c});
         continue;
       }
       for (int side = 0; side < 2; ++side)

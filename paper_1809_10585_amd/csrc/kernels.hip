@@ -874,19 +874,24 @@ __global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ job
 }
 
 // ------------------------------------------------------------------ one-block recompression
-// A recompression whose two factors have at most CH rows each, in one block
-// and one launch (no TSQR tree, no join across blocks, no forming kernel).
-// Width w <= 8: wavefront 0 factorises L and wavefront 1 factorises R in
-// registers (wave_qr), wavefront 0 runs the SVD of R2 R1^T in LDS
-// (jacobi_wave), then wavefront 0 applies Q1 to [U_k; 0] and wavefront 1 forms
-// R (R1^T U_k) from the rows it kept.  Wider jobs run the chunk code of
-// k_tr_qr for one chunk per side and then the forming step, in this block.
+// A recompression whose two factors have at most TRS_MAXCH chunks each (rows
+// split evenly, at most CH per chunk) in one launch, without the tree in
+// global memory or the forming kernel.  Width w <= 8: a TSQR inside one block.
+// Wavefront c < 4 factorises chunk c of L and wavefront 4 + c chunk c of R in
+// registers (wave_qr); wavefronts 4 and 5 factorise the stacked chunk R
+// factors; wavefront 4 runs the SVD of R2 R1^T (jacobi_wave) and applies the
+// stacked Q factor of L to [U_k; 0]; then wavefront c applies its chunk's Q to
+// its rows of that product (L' = Q1 U_k) and wavefront 4 + c forms its rows of
+// R (R1^T U_k).  Wider jobs run the chunk code of k_tr_qr in one block per
+// chunk and the block that ran the SVD forms both factors.
+constexpr int TRS_MAXCH = 4;
 
-// Load rows [0, h) of the factor [seg0 | seg1] (n0 columns in seg0) into a
-// wavefront's tile: lane l holds rows l + 64 i, columns < WT (zero beyond w, h).
+// Load rows [r0, r0 + h) of the factor [seg0 | seg1] (n0 columns in seg0)
+// into a wavefront's tile: lane l holds rows r0 + l + 64 i, columns < WT (zero
+// beyond w and h).
 template <int WT>
-__device__ __forceinline__ void wave_load(double (&a)[4][WT], const Seg& s0, const Seg& s1, int n0, int h,
-                                          int w) {
+__device__ __forceinline__ void wave_load(double (&a)[4][WT], const Seg& s0, const Seg& s1, int n0, int r0,
+                                          int h, int w) {
   const int lane = threadIdx.x & 63;
   if (h <= 0) {
 #pragma unroll
@@ -901,10 +906,11 @@ __device__ __forceinline__ void wave_load(double (&a)[4][WT], const Seg& s0, con
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t r = lane + 64 * i;
+    const int64_t gr = r0 + r;
 #pragma unroll
     for (int c = 0; c < WT; ++c) {
       const bool ok = r < h && c < w;
-      const double* src = (c < n0) ? s0.p + r + (int64_t)c * s0.ld : s1.p + r + (int64_t)(c - n0) * s1.ld;
+      const double* src = (c < n0) ? s0.p + gr + (int64_t)c * s0.ld : s1.p + gr + (int64_t)(c - n0) * s1.ld;
       a[i][c] = *(ok ? src : base);
     }
   }
@@ -1062,44 +1068,78 @@ __device__ __forceinline__ void jacobi_wave(double* X, double* V, int w) {
   }
 }
 
-// LDS layout of the narrow path (doubles): R1, R2, X, V, U_k, P (WT x WT each), perm
-constexpr int TSM_R1 = 0, TSM_R2 = 64, TSM_X = 128, TSM_V = 192, TSM_U = 256, TSM_P = 320,
-              TSM_PERM = 384;
+// LDS layout of the narrow path (doubles): the stacked chunk R factors of
+// both sides (TRS_MAXCH*WT x WT, ld 32), the stacked product Q_top [U_k; 0]
+// (ld 32), R1, R2, X, V, U_k, P (WT x WT, ld WT), then ints.
+constexpr int TSM_S0 = 0, TSM_S1 = 256, TSM_Z = 512, TSM_R1 = 768, TSM_R2 = 832, TSM_X = 896, TSM_V = 960,
+              TSM_U = 1024, TSM_P = 1088, TSM_INT = 1152;
+constexpr int TSM_LD = 32;
+
+// chunk c of nc over m rows: [row0, row0 + h)
+__device__ __forceinline__ void tr_chunk_rows(int m, int nc, int c, int& row0, int& h) {
+  row0 = (int)((int64_t)c * m / nc);
+  h = (int)((int64_t)(c + 1) * m / nc) - row0;
+}
 
 template <int WT>
 __device__ __forceinline__ void tr_small_narrow(const TrJob& J, int w, int n0a, int n0b, double* sm) {
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const bool orth = (J.flags & TR_ORTH) != 0;
   const int m0 = J.side[0].m, m1 = J.side[1].m;
+  const int nc0 = max(1, (m0 + CH - 1) / CH), nc1 = max(1, (m1 + CH - 1) / CH);
+  double* S0 = sm + TSM_S0;
+  double* S1 = sm + TSM_S1;
+  double* Zt = sm + TSM_Z;
   double* R1 = sm + TSM_R1;
   double* R2 = sm + TSM_R2;
   double* X = sm + TSM_X;
   double* V = sm + TSM_V;
   double* Uk = sm + TSM_U;
   double* P = sm + TSM_P;
-  int* perm = (int*)(sm + TSM_PERM);
-  double a[4][WT];  // wavefront 0: L's tile; wavefront 1: R's tile
+  int* perm = (int*)(sm + TSM_INT);
+  const int side = wv >> 2, c = wv & 3;  // this wavefront's chunk
+  int row0 = 0, h = 0;
+  if (side == 0 && c < nc0) tr_chunk_rows(m0, nc0, c, row0, h);
+  if (side == 1 && c < nc1) tr_chunk_rows(m1, nc1, c, row0, h);
+  double a[4][WT];  // the chunk's tile; wavefronts 4, 5 then the stacked R factors
   double tau[WT];
-  if (wv == 0) {
-    wave_load<WT>(a, J.seg[0][0], J.seg[0][1], n0a, m0, w);
-    wave_qr<WT>(a, m0, w, tau);
+#pragma unroll
+  for (int j = 0; j < WT; ++j) tau[j] = 0.0;
+  // chunk QRs; their R factors stacked in LDS
+  if (side == 0 ? c < nc0 : (!orth && c < nc1)) {
+    if (side == 0)
+      wave_load<WT>(a, J.seg[0][0], J.seg[0][1], n0a, row0, h, w);
+    else
+      wave_load<WT>(a, J.seg[1][0], J.seg[1][1], n0b, row0, h, w);
+    wave_qr<WT>(a, h, w, tau);
+    double* S = side == 0 ? S0 : S1;
     if (lane < WT) {
 #pragma unroll
-      for (int c = 0; c < WT; ++c) R1[lane + c * WT] = (lane <= c) ? a[0][c] : 0.0;
+      for (int q = 0; q < WT; ++q) S[c * WT + lane + q * TSM_LD] = (lane <= q) ? a[0][q] : 0.0;
     }
-  } else if (wv == 1) {
-    if (!orth) {
-      wave_load<WT>(a, J.seg[1][0], J.seg[1][1], n0b, m1, w);
-      wave_qr<WT>(a, m1, w, tau);
-      if (lane < WT) {
+  }
+  __syncthreads();
+  // R1 (wavefront 4) and R2 (wavefront 5): QR of the stacked chunk factors
+  // (their own chunk's reflectors are no longer needed)
+  const int ncs = (wv == 4) ? nc0 : nc1;
+  if (wv == 4 || (wv == 5 && !orth)) {
+    const double* S = (wv == 4) ? S0 : S1;
 #pragma unroll
-        for (int c = 0; c < WT; ++c) R2[lane + c * WT] = (lane <= c) ? a[0][c] : 0.0;
-      }
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < WT; ++q) a[i][q] = (i == 0 && lane < ncs * WT) ? S[lane + q * TSM_LD] : 0.0;
+#pragma unroll
+    for (int j = 0; j < WT; ++j) tau[j] = 0.0;
+    if (ncs > 1) wave_qr<WT>(a, ncs * WT, w, tau);
+    double* R = (wv == 4) ? R1 : R2;
+    if (lane < WT) {
+#pragma unroll
+      for (int q = 0; q < WT; ++q) R[lane + q * WT] = (lane <= q) ? a[0][q] : 0.0;
     }
   }
   __syncthreads();
   int k = 0;
-  if (wv == 0) {
+  if (wv == 4) {
     const double thr = *J.tau;
     if (orth) {
       k = min(m0, w);
@@ -1155,6 +1195,19 @@ __device__ __forceinline__ void tr_small_narrow(const TrJob& J, int w, int n0a, 
         P[lane] = (pp < k && rr < w) ? s : 0.0;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // Zt = Q_top [U_k; 0] (stacked rows; Q_top = I for one chunk)
+    double z[4][WT];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < WT; ++q) z[i][q] = (i == 0 && lane < WT) ? Uk[lane + q * WT] : 0.0;
+    if (nc0 > 1) wave_apply_q<WT>(a, tau, w, z);
+    if (lane < nc0 * WT) {
+#pragma unroll
+      for (int q = 0; q < WT; ++q) Zt[lane + q * TSM_LD] = z[0][q];
+    }
     if (lane == 0) {
       *J.out_rank = k;
       perm[WT] = k;  // for the other wavefronts
@@ -1163,48 +1216,48 @@ __device__ __forceinline__ void tr_small_narrow(const TrJob& J, int w, int n0a, 
   }
   __syncthreads();
   k = perm[WT];
-  if (wv == 0) {
-    // L' = Q1 [U_k; 0] (rows past min(m0, w) of [U_k; 0] are zero)
+  if (side == 0 && c < nc0) {
+    // rows of L' = Q_c [Zt rows of chunk c; 0] (rows past min(h, w) are zero)
     double z[4][WT];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = lane + 64 * i;
 #pragma unroll
-      for (int c = 0; c < WT; ++c) z[i][c] = (i == 0 && r < WT && r < m0) ? Uk[r + c * WT] : 0.0;
+      for (int q = 0; q < WT; ++q) z[i][q] = (i == 0 && r < WT && r < h) ? Zt[c * WT + r + q * TSM_LD] : 0.0;
     }
-    wave_apply_q<WT>(a, tau, min(m0, w), z);
+    wave_apply_q<WT>(a, tau, min(h, w), z);
     double* out = J.out[0];
     const int ld = J.ldout[0];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = lane + 64 * i;
 #pragma unroll
-      for (int c = 0; c < WT; ++c)
-        if (r < m0 && c < k) out[r + (int64_t)c * ld] = z[i][c];
+      for (int q = 0; q < WT; ++q)
+        if (r < h && q < k) out[row0 + r + (int64_t)q * ld] = z[i][q];
     }
-  } else if (wv == 1) {
-    // R' = R P, row by row (R read again: it is cached, and wavefront 0's
-    // product with Q1 takes longer)
+  } else if (side == 1 && c < nc1) {
+    // rows of R' = R P (R read again: it is cached)
     double b[4][WT];
-    wave_load<WT>(b, J.seg[1][0], J.seg[1][1], n0b, m1, w);
+    wave_load<WT>(b, J.seg[1][0], J.seg[1][1], n0b, row0, h, w);
     double* out = J.out[1];
     const int ld = J.ldout[1];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = lane + 64 * i;
 #pragma unroll
-      for (int c = 0; c < WT; ++c) {
+      for (int q = 0; q < WT; ++q) {
         double s = 0.0;
 #pragma unroll
-        for (int l = 0; l < WT; ++l) s += b[i][l] * P[l + c * WT];
-        if (r < m1 && c < k) out[r + (int64_t)c * ld] = s;
+        for (int l = 0; l < WT; ++l) s += b[i][l] * P[l + q * WT];
+        if (r < h && q < k) out[row0 + r + (int64_t)q * ld] = s;
       }
     }
   }
 }
 
-// Forming step of a one-chunk job inside the block (k_tr_form for p0 = 1):
-// L' = Q_chunk U_k and R' = R P, from the header tr_svd wrote.
+// Forming step inside the block that ran the SVD (k_tr_form for a tree of
+// at most one combine level): L' = Q_chunk (Q_root rows of the chunk) U_k for
+// each chunk of side 0, and R' = R P, from the header tr_svd wrote.
 __device__ __forceinline__ void tr_small_form(const TrJob& J, const double* ws, double* sm) {
   const int tid = threadIdx.x;
   const double* hdr = ws + J.hdr;
@@ -1214,12 +1267,23 @@ __device__ __forceinline__ void tr_small_form(const TrJob& J, const double* ws, 
   if (w == 0 || k == 0) return;
   const double* Uk = hdr + 8;
   const double* P = Uk + WMAX * WMAX;
-  {
-    double* Z = sm;
-    for (int e = tid; e < w * k; e += NT_TR) Z[e] = Uk[(e % w) + (e / w) * WMAX];
-    __syncthreads();
-    const double* Qc = ws + J.side[0].node0 + WMAX * WMAX;
-    rows_times_small(Qc, CH, J.side[0].m, w, Z, w, k, J.out[0], J.ldout[0]);
+  const TrSide S = J.side[0];
+  double* Z = sm;           // U_k (w x k, ld w)
+  double* Zc = sm + w * k;  // Q_root rows of a chunk times U_k
+  for (int e = tid; e < w * k; e += NT_TR) Z[e] = Uk[(e % w) + (e / w) * WMAX];
+  __syncthreads();
+  for (int c = 0; c < S.p0; ++c) {
+    int row0, h;
+    tr_chunk_rows(S.m, S.p0, c, row0, h);
+    const double* Zuse = Z;
+    if (S.p0 > 1) {
+      const double* Qn = ws + S.node0 + (int64_t)S.p0 * TR_NODE + WMAX * WMAX + c * w;
+      rows_times_small(Qn, CH, w, w, Z, w, k, Zc, w);
+      __syncthreads();
+      Zuse = Zc;
+    }
+    const double* Qc = ws + S.node0 + (int64_t)c * TR_NODE + WMAX * WMAX;
+    rows_times_small(Qc, CH, h, w, Zuse, w, k, J.out[0] + row0, J.ldout[0]);
     __syncthreads();
   }
   const int n0 = (int)hdr[3];
@@ -1246,22 +1310,23 @@ __device__ __forceinline__ void tr_small_form(const TrJob& J, const double* ws, 
   }
 }
 
-// Wider jobs: the chunk code of k_tr_qr, one chunk per side in each of the
-// job's two blocks (they join through the job counter); the block that ran
-// the SVD then forms both factors.
+// Wider jobs: the chunk code of k_tr_qr, one block per chunk (the chunks
+// and sides join through the job's counters); the block that ran the SVD
+// then forms both factors.
 template <int WTOP>
-__device__ __forceinline__ void tr_small_wide(const TrJob& J, int side, int w, int n0a, int n0b, double* ws,
-                                              int* counters, double* smem) {
+__device__ __forceinline__ void tr_small_wide(const TrJob& J, int side, int chunk, int w, int n0a, int n0b,
+                                              double* ws, int* counters, double* smem) {
   const int t = tier_of(w);
   bool last = false;
   if (t == 16) {
-    if constexpr (WTOP >= 16) last = tr_chunk<16>(J, side, 0, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+    if constexpr (WTOP >= 16) last = tr_chunk<16>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
   } else if (t == 32) {
-    if constexpr (WTOP >= 32) last = tr_chunk<32>(J, side, 0, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+    if constexpr (WTOP >= 32) last = tr_chunk<32>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
   } else if (t == 64) {
-    if constexpr (WTOP >= 64) last = tr_chunk<64>(J, side, 0, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+    if constexpr (WTOP >= 64) last = tr_chunk<64>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
   } else {
-    if constexpr (WTOP >= 128) last = tr_chunk<128>(J, side, 0, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+    if constexpr (WTOP >= 128)
+      last = tr_chunk<128>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
   }
   if (!last) return;
   __threadfence_block();
@@ -1269,8 +1334,10 @@ __device__ __forceinline__ void tr_small_wide(const TrJob& J, int side, int w, i
   tr_small_form(J, ws, smem);
 }
 
-// Two blocks per job (its sides).  Width <= 8: the side-0 block does the
-// whole job and the side-1 block has nothing to do.
+// One block per chunk of each side (the items of k_tr_qr).  Width <= 8: the
+// block of side 0, chunk 0 does the whole job and the others return.  The
+// host sends a job here only when each side has at most TRS_MAXCH chunks and
+// at most CH / WTOP of them (so that a wide job's tree has one combine level).
 template <int WTOP>
 __global__ void __launch_bounds__(NT_TR) k_tr_small(const TrJob* __restrict__ jobs,
                                                      const TrChunk* __restrict__ items, int first,
@@ -1281,23 +1348,27 @@ __global__ void __launch_bounds__(NT_TR) k_tr_small(const TrJob* __restrict__ jo
   const int n0a = seg_n(J.seg[0][0]);
   const int w = n0a + seg_n(J.seg[0][1]);
   const int n0b = seg_n(J.seg[1][0]);
+  const bool lead = it.side == 0 && it.chunk == 0;
   if (w == 0 || w > WTOP) {
-    if (it.side == 0 && threadIdx.x == 0) {
+    if (lead && threadIdx.x == 0) {
       *J.out_rank = 0;
       if (w > WTOP) atomicOr(J.err, ERR_WIDTH);
     }
     return;
   }
   if (w <= 8) {
-    if (it.side != 0) return;
+    if (!lead) return;
+    if (max(J.side[0].m, J.side[1].m) > TRS_MAXCH * CH) {  // not sent here by the host
+      if (threadIdx.x == 0) atomicOr(J.err, ERR_WIDTH);
+      return;
+    }
     if (w <= 4)
       tr_small_narrow<4>(J, w, n0a, n0b, smem);
     else
       tr_small_narrow<8>(J, w, n0a, n0b, smem);
     return;
   }
-  if (it.side == 1 && (J.flags & TR_ORTH)) return;
-  tr_small_wide<WTOP>(J, it.side, w, n0a, n0b, ws, counters, smem);
+  tr_small_wide<WTOP>(J, it.side, it.chunk, w, n0a, n0b, ws, counters, smem);
 }
 
 // ------------------------------------------------------------------ HODLR x tall-skinny
