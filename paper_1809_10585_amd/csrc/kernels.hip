@@ -7,6 +7,8 @@
 //    blocks.  Both factors are reduced by a tall-skinny QR tree (chunks of CH
 //    rows, then stacked R factors), the last block of a job runs a one-sided
 //    Jacobi SVD of R1 R2^T, and the second kernel forms Q1 U_k and R (R1^T U_k).
+//  * k_tr_small: the same recompression for factors of at most four chunks in
+//    one launch (for widths <= 8 a TSQR inside one block, in registers).
 //  * k_mm_proj / k_mm_apply: HODLR matrix times a tall-skinny block (Table 1,
 //    matrix-vector product) for a whole sub-HODLR: all blocks of all levels in
 //    one launch per phase.
