@@ -307,6 +307,36 @@ def test_batched_parity_with_oracle(H):
         assert rR <= 1e-8 and rQ <= 1e-8, (inp.n, rR, rQ)
 
 
+# Recompressions run in k_tr_small when both factors have at most four 256-row
+# chunks (narrow: w <= 8 inside one block; wide: one block per chunk and the
+# forming step in the block that ran the SVD), otherwise in k_tr_qr + k_tr_form.
+# n, leaf, k, rank_cap: 2048/256/2/16 has narrow jobs of 1, 2 and 4 even chunks;
+# 2048/256/5/32 wide jobs of several chunks (R ranks up to 30); 1500/200/3/32
+# uneven chunk splits (blocks of 750 and 375 rows).
+RECOMP_CASES = [(2048, 256, 2, 16, 40), (2048, 256, 5, 32, 41), (1500, 200, 3, 32, 42)]
+
+
+@pytest.mark.parametrize("n,leaf,k,cap,seed", RECOMP_CASES)
+def test_recompression_kernel_paths(H, n, leaf, k, cap, seed):
+    inp = G.gaussian_hodlr(n, leaf, k, seed=seed)
+    A = H.hodlr_build(inp, rank_cap=cap)
+    anorm = H.hodlr_norm2_est(A, 50)
+    F = H.hodlr_qr(A, EPS, anorm=anorm)
+    ref = O.hqr(inp, EPS, anorm=anorm)
+    X = np.random.default_rng(seed).standard_normal((n, 8))
+    rR = _rel(H.hodlr_qr_matmul(F, "R", H.colmajor(X)).cpu().numpy(), O.rmat(ref, X))
+    rQ = _rel(H.hodlr_apply_q(F, H.colmajor(X)).cpu().numpy(), O.apply_q(ref, X), np.linalg.norm(X))
+    assert rR <= 1e-8 and rQ <= 1e-8, (n, rR, rQ)
+    # the factorisation itself: |A X - Q R X| / (|A| |X|) and |Q^T Q X - X| / |X|
+    RX = H.hodlr_qr_matmul(F, "R", H.colmajor(X)).cpu().numpy()
+    AX = H.hodlr_matmul(A, H.colmajor(X)).cpu().numpy()
+    QRX = H.hodlr_apply_q(F, H.colmajor(RX)).cpu().numpy()
+    assert np.linalg.norm(AX - QRX) / (anorm * np.linalg.norm(X)) <= 10 * EPS
+    QX = H.hodlr_apply_q(F, H.colmajor(X)).cpu().numpy()
+    QtQX = H.hodlr_apply_q(F, H.colmajor(QX), trans=True).cpu().numpy()
+    assert np.linalg.norm(QtQX - X) / np.linalg.norm(X) <= 10 * EPS
+
+
 def test_batched_time_runs(H):
     inps = _batch_inputs()[:2]
     As = [H.hodlr_build(inp, rank_cap=32) for inp in inps]
