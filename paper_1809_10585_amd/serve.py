@@ -1,28 +1,31 @@
 """Served HODLR QR / solve requests with continuous batching on one GPU.
 
-A request stream (arrival times, kinds) is fed to a pool of `slots` workers,
-each owning its own HIP stream: a request that arrives while others are on the
-GPU starts as soon as a slot is free and its device-memory footprint fits the
-budget, so the launch sequences of several factorisations overlap on the
-device.  QR requests factorise a device-resident HODLR matrix with hodlr_qr and
-keep the factors resident; solve requests run hodlr_solve with a resident
-factor.  Resident factors beyond the budget are evicted least recently used.
+Requests (QR of a device-resident HODLR matrix, or a solve with the factor of
+an earlier QR request) arrive over time.  One host thread runs the loop: at
+every step it takes the requests that have arrived and are admissible, runs
+all their factorisations as one `hodlr_qr_batched` call (the library groups
+them by shape and runs each group as one launch sequence), then their solves;
+requests arriving meanwhile join the next step.  Factors stay resident for
+later solves; resident factors beyond the device-memory budget are evicted
+least recently used, sparing those a pending solve needs, and a solve whose
+factor was evicted factorises its matrix again first (counted in
+`refactored`).  `batching=False` serves one request per step in arrival order
+(the plain loop it is compared with).
 
-Every request computes exactly what it computes alone: the library's kernels
-never mix the jobs of two factorisations, so results are bitwise independent of
-what else runs (tested in tests/test_serve.py).
+Every library call is issued from the calling thread, one after the other.
+Each factorisation in a batch computes exactly what it computes alone: the
+library's kernels never mix the jobs of two factorisations (tested in
+tests/test_serve.py on the GPU, and in tests/test_gpu_parity.py for the batched
+call itself).
 
-The scheduling logic takes a backend with `qr(rid, key, stream)`, `solve(fkey,
-nrhs, seed, stream)`, `footprint(key)`, `release(fkey)` and `stream(i)`, so it
-can be exercised on the CPU with a stand-in backend; `GpuBackend` binds it to
-the library.  A solve whose factor was evicted before it arrived factorises the
-matrix again first (counted in `refactored`).
+The loop takes a backend with `qr_batch(keys)`, `solve(factor, nrhs, seed)`,
+`footprint(key)` and `release(factor)`, so it is exercised on the CPU with a
+stand-in backend; `GpuBackend` binds it to the library.
 """
 from __future__ import annotations
 
 import collections
 import dataclasses
-import threading
 import time
 
 import numpy as np
@@ -62,121 +65,125 @@ def poisson_requests(count: int, rate: float, n_matrices: int, seed: int, p_qr: 
 
 
 class Scheduler:
-    """Continuous-batching loop: `slots` workers, admission by footprint
-    against `budget` bytes, LRU eviction of resident factors that no pending
-    solve needs.  A factor is used by one request at a time (handles are not
-    shared between streams)."""
+    """Continuous batching from one host thread.  A step admits the arrived QR
+    requests in arrival order while their factors fit the budget next to the
+    resident ones (at most `max_batch` of them; one always, so the loop makes
+    progress), plus the arrived solves whose factor is resident, is formed in
+    this step, or was evicted (then its matrix is factorised again in this
+    step).  keep_results: leave each request's factor or solution in its
+    `result` (otherwise only the loop holds factors, so evicting frees them)."""
 
-    def __init__(self, backend, slots: int, budget: float):
-        self.b, self.slots, self.budget = backend, slots, budget
-        self.lock = threading.Condition()
+    def __init__(self, backend, budget: float, max_batch: int = 64, batching: bool = True,
+                 keep_results: bool = False):
+        self.b, self.budget, self.max_batch, self.batching = backend, budget, max_batch, batching
+        self.keep = keep_results
         self.resident = collections.OrderedDict()  # qr rid -> bytes (LRU order)
-        self.busy = set()                          # factors in use by a running solve
-        self.inflight = 0.0
-        self.pending = collections.deque()
-        self.finished = False
+        self.factors = {}                          # qr rid -> factor handle
+        self.evicted = set()                       # qr rids whose factors were released
+        self.qr_matrix = {}                        # qr rid -> matrix index
         self.evictions = 0
         self.refactored = 0
-        self.evicted = set()   # qr rids whose factors were released
-        self.qr_matrix = {}    # qr rid -> matrix index
+        self.steps = 0
+        self.max_qr_batch = 0
 
     def _resident_bytes(self):
         return sum(self.resident.values())
 
-    def _admit_qr(self, r):
-        """Called with the lock held: may QR request r start now?  Evicts least
-        recently used factors that neither a running nor a pending solve needs."""
-        need = self.b.footprint(r.key)
-        if self._resident_bytes() + self.inflight + need > self.budget:
-            wanted = {p.key for p in self.pending if p.kind == "solve"} | self.busy
-            for victim in list(self.resident):
-                if self._resident_bytes() + self.inflight + need <= self.budget:
-                    break
-                if victim in wanted:
-                    continue
-                del self.resident[victim]
-                self.b.release(victim)
-                self.evicted.add(victim)
-                self.evictions += 1
-        return self._resident_bytes() + self.inflight + need <= self.budget or self.inflight == 0.0
+    def _make_room(self, need, keep):
+        """Evict least recently used factors outside `keep` until `need` more
+        bytes fit; returns whether they do."""
+        for victim in list(self.resident):
+            if self._resident_bytes() + need <= self.budget:
+                break
+            if victim in keep:
+                continue
+            del self.resident[victim]
+            self.b.release(self.factors.pop(victim))
+            self.evicted.add(victim)
+            self.evictions += 1
+        return self._resident_bytes() + need <= self.budget
 
-    def _next(self):
-        """Called with the lock held: the first pending request that can start."""
-        for i, r in enumerate(self.pending):
-            if r.kind == "solve":
-                if r.key in self.evicted and r.key not in self.busy:
-                    ok = self._admit_qr(Request(-1, 0.0, "qr", self.qr_matrix[r.key]))
-                else:
-                    ok = r.key in self.resident and r.key not in self.busy
-            else:
-                ok = self._admit_qr(r)
-            if ok:
-                del self.pending[i]
-                return r
-        return None
-
-    def _worker(self, stream):
-        while True:
-            with self.lock:
-                r = self._next()
-                while r is None:
-                    if self.finished and not self.pending:
-                        return
-                    self.lock.wait(0.001)
-                    r = self._next()
-                refactor = r.kind == "solve" and r.key in self.evicted
-                if r.kind == "qr":
-                    self.inflight += self.b.footprint(r.key)
-                else:
-                    self.busy.add(r.key)
-                    if refactor:
-                        self.evicted.discard(r.key)
-                        self.refactored += 1
-                        self.inflight += self.b.footprint(self.qr_matrix[r.key])
-                    else:
-                        self.resident.move_to_end(r.key)
-            r.start = time.perf_counter() - self.t0
+    def _plan(self, pending):
+        """The requests of the next step: (qr requests, refactored qr rids, solves)."""
+        if not self.batching:
+            r = pending[0]
             if r.kind == "qr":
-                r.result = self.b.qr(r.rid, r.key, stream)
-            else:
-                if refactor:
-                    self.b.qr(r.key, self.qr_matrix[r.key], stream)
-                r.result = self.b.solve(r.key, r.nrhs, r.seed, stream)
-            r.done = time.perf_counter() - self.t0
-            with self.lock:
-                if r.kind == "qr":
-                    self.inflight -= self.b.footprint(r.key)
-                    self.resident[r.rid] = self.b.footprint(r.key)
-                else:
-                    if refactor:
-                        fp = self.b.footprint(self.qr_matrix[r.key])
-                        self.inflight -= fp
-                        self.resident[r.key] = fp
-                    self.busy.discard(r.key)
-                self.lock.notify_all()
+                return [r], [], []
+            if r.key in self.factors:
+                return [], [], [r]
+            if r.key in self.evicted:
+                return [], [r.key], [r]
+            return [], [], []  # its factorisation has not run yet (cannot happen in FIFO order)
+        wanted = {p.key for p in pending if p.kind == "solve"}
+        qrs, refs, need = [], [], 0.0
+        for r in pending:
+            if r.kind != "qr" or len(qrs) + len(refs) >= self.max_batch:
+                continue
+            fp = self.b.footprint(r.key)
+            if self._make_room(need + fp, wanted) or not (qrs or refs):
+                qrs.append(r)
+                need += fp
+        batch_qr = {r.rid for r in qrs}
+        solves = []
+        for r in pending:
+            if r.kind != "solve":
+                continue
+            if r.key in self.factors or r.key in batch_qr or r.key in refs:
+                solves.append(r)
+            elif r.key in self.evicted and len(qrs) + len(refs) < self.max_batch:
+                fp = self.b.footprint(self.qr_matrix[r.key])
+                if self._make_room(need + fp, wanted) or not (qrs or refs):
+                    refs.append(r.key)
+                    need += fp
+                    solves.append(r)
+        return qrs, refs, solves
 
     def run(self, requests, time_scale: float = 1.0):
-        """Release the requests at their arrival times (times time_scale) and
-        serve them; returns them with start/done times filled in (seconds)."""
-        self.t0 = time.perf_counter()
-        workers = [threading.Thread(target=self._worker, args=(self.b.stream(i),)) for i in range(self.slots)]
-        for w in workers:
-            w.start()
-        for r in requests:
-            r.arrival *= time_scale
-            delay = r.arrival - (time.perf_counter() - self.t0)
-            if delay > 0:
-                time.sleep(delay)
-            with self.lock:
+        """Serve the requests at their arrival times (times time_scale); returns
+        them with start/done times (seconds) and results filled in."""
+        order = sorted(requests, key=lambda r: r.arrival)
+        t0 = time.perf_counter()
+        clock = lambda: time.perf_counter() - t0
+        pending = []
+        i = 0
+        while i < len(order) or pending:
+            while i < len(order) and order[i].arrival * time_scale <= clock():
+                r = order[i]
                 if r.kind == "qr":
                     self.qr_matrix[r.rid] = r.key
-                self.pending.append(r)
-                self.lock.notify_all()
-        with self.lock:
-            self.finished = True
-            self.lock.notify_all()
-        for w in workers:
-            w.join()
+                pending.append(r)
+                i += 1
+            if not pending:
+                time.sleep(max(0.0, order[i].arrival * time_scale - clock()))
+                continue
+            qrs, refs, solves = self._plan(pending)
+            if not (qrs or refs or solves):  # a solve waiting for its factor's step
+                time.sleep(max(0.0, order[i].arrival * time_scale - clock()) if i < len(order) else 0.0)
+                continue
+            self.steps += 1
+            start = clock()
+            keys = [r.key for r in qrs] + [self.qr_matrix[f] for f in refs]
+            if keys:
+                self.max_qr_batch = max(self.max_qr_batch, len(keys))
+                made = self.b.qr_batch(keys)
+                done = clock()
+                for rid, key, F in zip([r.rid for r in qrs] + refs, keys, made):
+                    self.factors[rid] = F
+                    self.resident[rid] = self.b.footprint(key)
+                    self.evicted.discard(rid)
+                self.refactored += len(refs)
+                for r, F in zip(qrs, made):
+                    r.start, r.done = start, done
+                    r.result = F if self.keep else None
+                del made
+            for r in solves:
+                self.resident.move_to_end(r.key)
+                r.start = start
+                x = self.b.solve(self.factors[r.key], r.nrhs, r.seed)
+                r.done = clock()
+                r.result = x if self.keep else None
+            served = {id(r) for r in qrs} | {id(r) for r in solves}
+            pending = [r for r in pending if id(r) not in served]
         return requests
 
 
@@ -189,16 +196,13 @@ def summarize(requests) -> dict:
 
 
 class GpuBackend:
-    """The library behind the scheduler: inputs resident on the device, one HIP
-    stream per worker slot, factors kept per QR request."""
+    """The library behind the loop: inputs resident on the device, calls on the
+    current stream, each returning when its work is done."""
 
-    def __init__(self, H, matrices, eps: float, slots: int):
+    def __init__(self, H, matrices, eps: float):
         import torch
         self.H, self.torch, self.eps = H, torch, eps
         self.A = matrices
-        self.streams = [torch.cuda.Stream() for _ in range(slots)]
-        self.factors = {}
-        self.flock = threading.Lock()
         self._fp = [self._estimate(A) for A in matrices]
 
     @staticmethod
@@ -207,30 +211,22 @@ class GpuBackend:
         # times, n x cap temporaries) plus the schedule's workspace, as a bound
         return 64.0 * A.n * (A.rank_cap * (A.levels + 16) + 512)
 
-    def stream(self, i):
-        return self.streams[i]
-
     def footprint(self, key):
         return self._fp[key]
 
-    def qr(self, rid, key, stream):
-        F = self.H.hodlr_qr(self.A[key], self.eps, stream=stream)
-        with self.flock:
-            self.factors[rid] = F
-        return F
+    def qr_batch(self, keys):
+        Fs = self.H.hodlr_qr_batched([self.A[k] for k in keys], self.eps)
+        self.torch.cuda.synchronize()
+        return Fs
 
-    def solve(self, fkey, nrhs, seed, stream):
+    def solve(self, F, nrhs, seed):
         torch = self.torch
-        with self.flock:
-            F = self.factors[fkey]
         g = torch.Generator(device="cuda")
         g.manual_seed(seed)
-        with torch.cuda.stream(stream):
-            B = torch.randn((nrhs, F.n), generator=g, dtype=torch.float64, device="cuda").t()
-            X = self.H.hodlr_solve(F, B, stream=stream)
-        stream.synchronize()
+        B = torch.randn((nrhs, F.n), generator=g, dtype=torch.float64, device="cuda").t()
+        X = self.H.hodlr_solve(F, B)
+        torch.cuda.synchronize()
         return X
 
-    def release(self, fkey):
-        with self.flock:
-            self.factors.pop(fkey, None)
+    def release(self, F):
+        del F
