@@ -142,6 +142,51 @@ def bench_served(H, G, np, requests=200, rate=200.0, pool=16, seed=4):
     return out
 
 
+def accuracy_case(H, inp, eps, rank_cap=64):
+    """e_orth = |Q^T Q - I|_2 and e_acc = |QR - A|_2 (eq. accuracy) of hQR on the
+    device for the HODLR matrix `inp`, and the same for dense Householder QR
+    (numpy) of its dense form; dense products and 2-norms on the host."""
+    import numpy as np
+    import torch
+    from paper_1809_10585_amd import _lib
+    n = inp.n
+    Ad = inp.to_dense()
+    Qd, Rd = np.linalg.qr(Ad)
+    I = np.eye(n)
+    out = {"kappa2": float(np.linalg.cond(Ad)),
+           "dense_e_orth": float(np.linalg.norm(Qd.T @ Qd - I, 2)),
+           "dense_e_acc": float(np.linalg.norm(Qd @ Rd - Ad, 2)),
+           "max_rank_A": max(U.shape[1] for U, V in inp.blocks.values())}
+    try:
+        A = H.hodlr_build(inp, rank_cap=rank_cap)
+        F = H.hodlr_qr(A, eps)
+    except _lib.HodlrError as e:
+        out["hqr"] = str(e)
+        return out
+    Q = H.hodlr_apply_q(F, H.colmajor(I)).cpu().numpy()
+    R = H.hodlr_qr_matmul(F, "R", H.colmajor(I)).cpu().numpy()
+    info = H.hodlr_qr_info(F)
+    torch.cuda.synchronize()
+    out.update(e_orth=float(np.linalg.norm(Q.T @ Q - I, 2)), e_acc=float(np.linalg.norm(Q @ R - Ad, 2)),
+               max_rank_y_t_r=[info["max_rank_y"], info["max_rank_t"], info["max_rank_r"]])
+    return out
+
+
+def bench_accuracy(H, G):
+    """The paper's accuracy examples on the device path: Cauchy matrices A_1..A_3
+    (n = 2000, leaf 250) at eps = 1e-10, and A_3 for eps = 1e-2 .. 1e-20 (the
+    HODLR approximation and hQR at the same eps)."""
+    out = {"cauchy_eps_1e-10": {}, "a3_eps_sweep": {}}
+    for i in (1, 2, 3):
+        out["cauchy_eps_1e-10"][f"A{i}"] = accuracy_case(H, G.cauchy_example(i, eps=1e-10), 1e-10)
+        log(f"A{i}: {out['cauchy_eps_1e-10'][f'A{i}']}")
+    for e in range(2, 21, 2):
+        eps = 10.0 ** -e
+        out["a3_eps_sweep"][f"{eps:g}"] = accuracy_case(H, G.cauchy_example(3, eps=eps), eps)
+        log(f"A3 eps {eps:g}: {out['a3_eps_sweep'][f'{eps:g}']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +200,8 @@ def main():
     ap.add_argument("--served", action="store_true",
                     help="also run the served measurement (Poisson request stream, about a minute "
                          "of GPU time: the plain loop it is compared with cannot keep up)")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="only the accuracy study of the paper's Cauchy examples (e_orth, e_acc)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy kernel (the reference "
                          "dispatch for scaling FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -171,6 +218,9 @@ def main():
     import paper_1809_10585_amd as H
 
     torch.cuda.set_device(0)
+    if args.accuracy:
+        print(json.dumps({"accuracy": bench_accuracy(H, G)}), flush=True)
+        return
     if args.copy_calibration:
         src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

@@ -279,6 +279,42 @@ def cauchy_hodlr(n: int, n_min: int = 256, seed=1, eps: float = 1e-10,
     return H
 
 
+# Intervals of Sec. 5, Example "Accuracy for Cauchy matrices": x from I_x,
+# y from I_y(i) for the matrices A_1, A_2, A_3 (closer intervals: worse conditioned).
+CAUCHY_EXAMPLE_IX = (-1.25, 998.25)
+CAUCHY_EXAMPLE_IY = {1: (-0.7, 998.9), 2: (-0.45, 999.15), 3: (-0.15, 999.45)}
+
+
+def cauchy_example(which: int, n: int = 2000, n_min: int = 250, eps: float = 1e-10,
+                   seed: int = 11) -> HodlrInput:
+    """The Cauchy matrices A_1..A_3 of the paper's accuracy example (Sec. 5):
+    A_ij = 1/(x_i - y_j) with x, y n equally spaced points of I_x, I_y(which),
+    each moved by +-2e-2 (sign drawn uniformly, x's signs first, then y's),
+    compressed to HODLR (leaf n_min) by the truncated SVD of every off-diagonal
+    block, keeping singular values > eps |A|_2 (U = U_k, V = V_k Sigma_k).  n is
+    small enough for dense SVDs; `dense` holds the uncompressed matrix."""
+    rng = np.random.default_rng(seed)
+    x = np.linspace(*CAUCHY_EXAMPLE_IX, n) + 2e-2 * rng.choice([-1.0, 1.0], n)
+    y = np.linspace(*CAUCHY_EXAMPLE_IY[which], n) + 2e-2 * rng.choice([-1.0, 1.0], n)
+    A = _cauchy_block(x, y)
+    anorm = float(np.linalg.norm(A, 2))
+    thr = eps * anorm
+    levels, off = partition(n, n_min)
+    leaves = [A[int(off[j]):int(off[j + 1]), int(off[j]):int(off[j + 1])].copy() for j in range(len(off) - 1)]
+    H = HodlrInput(n=n, levels=levels, leaf_off=off, leaves=leaves,
+                   name=f"cauchy_example(A{which},n={n},leaf={n_min},eps={eps:g})")
+    for v in H.internal_nodes():
+        lo, hi = H.node_range(v)
+        mid = H.node_range(2 * v)[1]
+        for kind, ri, cj in (("up", (lo, mid), (mid, hi)), ("lo", (mid, hi), (lo, mid))):
+            Ub, sv, Vt = np.linalg.svd(A[ri[0]:ri[1], cj[0]:cj[1]], full_matrices=False)
+            k = int(np.sum(sv > thr))
+            H.blocks[(v, kind)] = (np.ascontiguousarray(Ub[:, :k]), np.ascontiguousarray(Vt[:k].T * sv[:k]))
+    H.anorm_generator = anorm
+    H.dense = A
+    return H
+
+
 def batched_set(count: int = 256, seed: int = 3, dmin: int = 2, dmax: int = 6, kmin: int = 1,
                 kmax: int = 4, n_min: int = 256) -> list:
     """The batch of independent matrices of the batched workload: for each of
