@@ -289,6 +289,35 @@ __device__ __forceinline__ int tr_root_slot(int p0, int G) {
   return s;
 }
 
+// Rotation of one-sided Jacobi for a column pair with a = |x_i|^2, b = |x_j|^2,
+// g = x_i . x_j: false when |g| <= tol sqrt(a b) (tested squared); otherwise
+// the (cs, sn) that makes the rotated pair orthogonal, the smaller angle with
+// tan(2 theta) = 2g / (b - a) (the rotation of jacobi()).  Short dependency
+// chain: with d = b - a and g2 = 2g scaled by a power of two (squares neither
+// overflow nor underflow), r = |(d, g2)|, s = r + |d| and q = 1/sqrt(2 r s),
+// cs = s q and sn = sign(d) g2 q (cs^2 + sn^2 = (s^2 + g2^2) / (2 r s) = 1).
+__device__ __forceinline__ bool jac_rot_fast(double al, double be, double ga, double tol2, double& cs,
+                                             double& sn) {
+  if (!(ga != 0.0 && ga * ga > tol2 * (al * be))) return false;
+  double d = be - al, g = 2.0 * ga;
+  const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(d), fabs(g)));
+  d = __builtin_ldexp(d, -e);
+  g = __builtin_ldexp(g, -e);
+  const double h2 = fma(d, d, g * g);  // in [1/4, 2]
+  double y = __builtin_amdgcn_rsq(h2);
+  y = y * fma(-0.5 * h2 * y, y, 1.5);
+  y = y * fma(-0.5 * h2 * y, y, 1.5);
+  const double r = h2 * y;
+  const double s = r + fabs(d);
+  const double u = 2.0 * r * s;
+  double q = __builtin_amdgcn_rsq(u);
+  q = q * fma(-0.5 * u * q, q, 1.5);
+  q = q * fma(-0.5 * u * q, q, 1.5);
+  cs = s * q;
+  sn = (d >= 0.0 ? g : -g) * q;
+  return true;
+}
+
 // One-sided Jacobi on the columns of X (w x w, ld lx), accumulating the
 // rotations in V (ld lv).  Round-robin pairing; one pair per group of TPP
 // lanes; a sweep ends when no pair needed a rotation.
@@ -334,14 +363,8 @@ __device__ __forceinline__ void jacobi(double* X, int lx, double* V, int lv, int
         al = gsum(al, TPP);
         be = gsum(be, TPP);
         ga = gsum(ga, TPP);
-        if (valid && ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          double t;
-          if (fabs(zeta) > 1e150)
-            t = 0.5 / zeta;
-          else
-            t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        double cs, sn;
+        if (valid && jac_rot_fast(al, be, ga, tol * tol, cs, sn)) {
           for (int row = sub; row < w; row += TPP) {
             const double xi = X[row + i * lx], xj = X[row + j * lx];
             X[row + i * lx] = cs * xi - sn * xj;
@@ -359,35 +382,6 @@ __device__ __forceinline__ void jacobi(double* X, int lx, double* V, int lv, int
     __syncthreads();
     if (f == 0) break;
   }
-}
-
-// Rotation of one-sided Jacobi for a column pair with a = |x_i|^2, b = |x_j|^2,
-// g = x_i . x_j: false when |g| <= tol sqrt(a b) (tested squared); otherwise
-// the (cs, sn) that makes the rotated pair orthogonal, the smaller angle with
-// tan(2 theta) = 2g / (b - a) (the rotation of jacobi()).  Short dependency
-// chain: with d = b - a and g2 = 2g scaled by a power of two (squares neither
-// overflow nor underflow), r = |(d, g2)|, s = r + |d| and q = 1/sqrt(2 r s),
-// cs = s q and sn = sign(d) g2 q (cs^2 + sn^2 = (s^2 + g2^2) / (2 r s) = 1).
-__device__ __forceinline__ bool jac_rot_fast(double al, double be, double ga, double tol2, double& cs,
-                                             double& sn) {
-  if (!(ga != 0.0 && ga * ga > tol2 * (al * be))) return false;
-  double d = be - al, g = 2.0 * ga;
-  const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(d), fabs(g)));
-  d = __builtin_ldexp(d, -e);
-  g = __builtin_ldexp(g, -e);
-  const double h2 = fma(d, d, g * g);  // in [1/4, 2]
-  double y = __builtin_amdgcn_rsq(h2);
-  y = y * fma(-0.5 * h2 * y, y, 1.5);
-  y = y * fma(-0.5 * h2 * y, y, 1.5);
-  const double r = h2 * y;
-  const double s = r + fabs(d);
-  const double u = 2.0 * r * s;
-  double q = __builtin_amdgcn_rsq(u);
-  q = q * fma(-0.5 * u * q, q, 1.5);
-  q = q * fma(-0.5 * u * q, q, 1.5);
-  cs = s * q;
-  sn = (d >= 0.0 ? g : -g) * q;
-  return true;
 }
 
 // The same one-sided Jacobi for w <= WS (WS = 8 or 16) inside one wavefront.
@@ -762,13 +756,14 @@ __global__ void __launch_bounds__(NT_TR) k_tr_qr(const TrJob* __restrict__ jobs,
 
 constexpr size_t TR_FORM_LDS = sizeof(double) * (size_t)WMAX * WMAX;
 
-// out[r, p] = sum_c A(r, c) B[c + p*ldb] for r < rows, p < k; thread = row,
-// 16 output columns at a time in registers.  A(r, c) = a[r + c*lda].
+// out[r, p] = sum_c A(r, c) B[c + p*ldb] for r < rows, p < k; thread = row
+// (NT threads), 16 output columns at a time in registers.  A(r, c) = a[r + c*lda].
+template <int NT = NT_MM>
 __device__ __forceinline__ void rows_times_small(const double* a, int64_t lda, int rows, int w,
                                                  const double* B, int ldb, int k, double* out,
                                                  int64_t ldo) {
   const int tid = threadIdx.x;
-  for (int r = tid; r < rows; r += NT_MM) {
+  for (int r = tid; r < rows; r += NT) {
     for (int p0 = 0; p0 < k; p0 += 16) {
       double acc[16];
 #pragma unroll
@@ -1280,16 +1275,41 @@ __device__ __forceinline__ void tr_small_form(const TrJob& J, const double* ws, 
     const double* Zuse = Z;
     if (S.p0 > 1) {
       const double* Qn = ws + S.node0 + (int64_t)S.p0 * TR_NODE + WMAX * WMAX + c * w;
-      rows_times_small(Qn, CH, w, w, Z, w, k, Zc, w);
+      rows_times_small<NT_TR>(Qn, CH, w, w, Z, w, k, Zc, w);
       __syncthreads();
       Zuse = Zc;
     }
     const double* Qc = ws + S.node0 + (int64_t)c * TR_NODE + WMAX * WMAX;
-    rows_times_small(Qc, CH, h, w, Zuse, w, k, J.out[0] + row0, J.ldout[0]);
+    rows_times_small<NT_TR>(Qc, CH, h, w, Zuse, w, k, J.out[0] + row0, J.ldout[0]);
     __syncthreads();
   }
+  // R' = R P.  R' may overwrite R in place (row r of R' over row r of R), so a
+  // thread computes all k outputs of its row before it writes them: with
+  // k <= 16 it reads its row straight from the segments (coalesced over the
+  // threads), otherwise 64-row pieces of R are staged in LDS first.
   const int n0 = (int)hdr[3];
   const Seg s0 = J.seg[1][0], s1 = J.seg[1][1];
+  if (k <= 16) {
+    double* Ps = sm;  // w x k, ld w
+    for (int e = tid; e < w * k; e += NT_TR) Ps[e] = P[(e % w) + (e / w) * WMAX];
+    __syncthreads();
+    for (int r = tid; r < J.side[1].m; r += NT_TR) {
+      double acc[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+      for (int c = 0; c < w; ++c) {
+        const double x = (c < n0) ? s0.scale * s0.p[r + (int64_t)c * s0.ld]
+                                  : s1.scale * s1.p[r + (int64_t)(c - n0) * s1.ld];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (q < k) acc[q] += x * Ps[c + q * w];
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (q < k) J.out[1][r + (int64_t)q * J.ldout[1]] = acc[q];
+    }
+    return;
+  }
   double* In = sm;           // rows x w, ld 64
   double* Ps = sm + 64 * w;  // w x k, ld w
   const bool fits = 64 * w + w * k <= WMAX * WMAX;
@@ -1305,9 +1325,9 @@ __device__ __forceinline__ void tr_small_form(const TrJob& J, const double* ws, 
     }
     __syncthreads();
     if (fits)
-      rows_times_small(In, 64, rows, w, Ps, w, k, J.out[1] + r0, J.ldout[1]);
+      rows_times_small<NT_TR>(In, 64, rows, w, Ps, w, k, J.out[1] + r0, J.ldout[1]);
     else
-      rows_times_small(In, 64, rows, w, P, WMAX, k, J.out[1] + r0, J.ldout[1]);
+      rows_times_small<NT_TR>(In, 64, rows, w, P, WMAX, k, J.out[1] + r0, J.ldout[1]);
     __syncthreads();
   }
 }
