@@ -1477,11 +1477,13 @@ __global__ void __launch_bounds__(NT_MM) k_mm_red(const MmJob* __restrict__ jobs
 // A block takes RT rows of one leaf; thread (r, g) = (tid % RT, tid / RT).
 // Group g adds the leaf columns of its share and the low-rank parts of the
 // ancestor levels g, g + G, ...; the groups' partial rows are then summed in a
-// fixed order.  X of the leaf rows is staged in LDS, 16 columns at a time.
+// fixed order.  X of the leaf rows is staged in LDS, CW columns at a time
+// (CW = 4 for blocks of at most 4 columns, else 16).
 //  RT = 16: the group's leaf columns kk = g, g + 16, ... are loaded into
 //           registers up front (short launches: one round trip of loads);
 //  RT = 64: the group streams a contiguous quarter of the columns, so a wave
-//           reads whole 512-byte column pieces (long launches: bandwidth).
+//           reads whole 512-byte column pieces (long launches: bandwidth); the
+//           loop is unrolled 64/CW times, which keeps two wavefronts per SIMD.
 // Dynamic LDS: max(m_leaf, 256) * 17 doubles.
 constexpr int MA_LD = 17;
 
@@ -1497,19 +1499,15 @@ __device__ __forceinline__ double leaf_elem(const HLeaf& lf, int kind, int trans
   return (ii <= jj) ? lf.D[ii + (int64_t)jj * lf.ld] : 0.0;
 }
 
-template <int RT>
-__global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jobs,
-                                                     const MmApply* __restrict__ items, int first,
-                                                     const double* __restrict__ ws) {
+// The rows of one item in column slabs of CW columns (CW = 4 when s <= 4:
+// a quarter of the LDS reads and FMAs of the 16-wide slab).
+template <int RT, int CW>
+__device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it, const double* ws,
+                                              double* shm, int s) {
   constexpr int G = NT_MM / RT;
   constexpr int DMAX = RT == 16 ? MAXLEAF / G : 1;
-  extern __shared__ double shm[];
   const int tid = threadIdx.x;
   const int r = tid % RT, g = tid / RT;
-  const MmApply it = items[first + blockIdx.x];
-  const MmJob& J = jobs[it.job];
-  const int s = mm_s(J);
-  if (s == 0) return;
   const HLeaf lf = J.M.leaf[it.leaf];
   const int kind = J.M.leaf_kind;
   const int trans = J.trans;
@@ -1529,16 +1527,16 @@ __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jo
   const int hleaf = (1 << J.M.levels) + it.leaf;
   const double* xl = J.X + (lf.r0 - J.row0);
   double* Xs = shm;
-  for (int c0 = 0; c0 < s; c0 += 16) {
-    const int cn = min(16, s - c0);
-    for (int e = tid; e < m * 16; e += NT_MM) {
+  for (int c0 = 0; c0 < s; c0 += CW) {
+    const int cn = min(CW, s - c0);
+    for (int e = tid; e < m * CW; e += NT_MM) {
       const int kk = e % m, c = e / m;
       Xs[kk * MA_LD + c] = (c < cn) ? xl[kk + (int64_t)(c0 + c) * J.ldX] : 0.0;
     }
     __syncthreads();
-    double acc[16];
+    double acc[CW];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+    for (int c = 0; c < CW; ++c) acc[c] = 0.0;
     if constexpr (RT == 16) {
 #pragma unroll
       for (int i = 0; i < DMAX; ++i) {
@@ -1546,16 +1544,16 @@ __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jo
         if (kk < m) {
           const double d = dv[i];
 #pragma unroll
-          for (int c = 0; c < 16; ++c) acc[c] += d * Xs[kk * MA_LD + c];
+          for (int c = 0; c < CW; ++c) acc[c] += d * Xs[kk * MA_LD + c];
         }
       }
     } else {
       if (live) {
-#pragma unroll 8
+#pragma unroll(64 / CW)
         for (int kk = kb0; kk < kb1; ++kk) {
           const double d = leaf_elem<RT>(lf, kind, trans, R, kk);
 #pragma unroll
-          for (int c = 0; c < 16; ++c) acc[c] += d * Xs[kk * MA_LD + c];
+          for (int c = 0; c < CW; ++c) acc[c] += d * Xs[kk * MA_LD + c];
         }
       }
     }
@@ -1577,7 +1575,7 @@ __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jo
           for (int j = 0; j < kb; ++j) {
             const double fv = live ? F[frow + (int64_t)j * ldF] : 0.0;
 #pragma unroll
-            for (int c = 0; c < 16; ++c)
+            for (int c = 0; c < CW; ++c)
               if (c < cn) acc[c] += fv * red[j + c * KCAP];
           }
         }
@@ -1588,9 +1586,9 @@ __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jo
     }
     __syncthreads();  // Xs is reused for the partial rows
 #pragma unroll
-    for (int c = 0; c < 16; ++c) shm[(g * RT + r) * MA_LD + c] = acc[c];
+    for (int c = 0; c < CW; ++c) shm[(g * RT + r) * MA_LD + c] = acc[c];
     __syncthreads();
-    for (int e = tid; e < RT * 16; e += NT_MM) {
+    for (int e = tid; e < RT * CW; e += NT_MM) {
       const int rr = e % RT, c = e / RT;
       if (rr < it.rows && c < cn) {
         double sacc = 0.0;
@@ -1603,8 +1601,26 @@ __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jo
     }
     __syncthreads();
   }
-  if (tid == 0) {
-    double flops = 2.0 * it.rows * m * s * (J.tri ? 0.5 : 1.0);
+}
+
+template <int RT>
+__global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jobs,
+                                                     const MmApply* __restrict__ items, int first,
+                                                     const double* __restrict__ ws) {
+  extern __shared__ double shm[];
+  const MmApply it = items[first + blockIdx.x];
+  const MmJob& J = jobs[it.job];
+  const int s = mm_s(J);
+  if (s == 0) return;
+  if (s <= 4)
+    mm_apply_rows<RT, 4>(J, it, ws, shm, s);
+  else
+    mm_apply_rows<RT, 16>(J, it, ws, shm, s);
+  if (threadIdx.x == 0) {
+    const HLeaf lf = J.M.leaf[it.leaf];
+    const int trans = J.trans;
+    const int hleaf = (1 << J.M.levels) + it.leaf;
+    double flops = 2.0 * it.rows * lf.m * s * (J.tri ? 0.5 : 1.0);
     int child2 = hleaf, u2 = hleaf >> 1;
     while (child2 != J.v && u2 >= 1) {
       const bool left = (child2 == 2 * u2);
