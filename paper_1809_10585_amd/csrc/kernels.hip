@@ -1684,10 +1684,12 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_tall(const GemmJob* __restrict__
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int cc = cg + 4 * q;
-      double sacc = acc[q];
+      if (cc < nc) {  // uniform in the wavefront (cg is its index): skips empty columns
+        double sacc = acc[q];
 #pragma unroll 8
-      for (int kk = 0; kk < 32; ++kk) sacc += At[r][kk] * Bt[kk][cc];
-      acc[q] = sacc;
+        for (int kk = 0; kk < 32; ++kk) sacc += At[r][kk] * Bt[kk][cc];
+        acc[q] = sacc;
+      }
     }
     __syncthreads();
   }
