@@ -1723,6 +1723,26 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_red(const GemmJob* __restrict__ 
   double acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  if (nout <= 16 && it.kn <= NT_MM) {
+    // small C: thread t takes K index k0 + t, all nout products of it; sums over
+    // the wavefront (DPP) and then over the four wavefronts (LDS); thread e <
+    // nout ends with output e in acc[0], as the staged loop below leaves it
+    __shared__ double wsum[NT_MM / 64][16];
+    const int kk = it.k0 + tid;
+    const bool on = tid < it.kn;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      double x = 0.0;
+      if (on && e < nout) x = gA(J, e % M, kk) * gB(J, kk, e / M);
+      x = gsumt<64>(x);
+      if ((tid & 63) == 0) wsum[tid >> 6][e] = x;
+    }
+    __syncthreads();
+    double tot = 0.0;
+    if (tid < nout)
+      for (int w = 0; w < NT_MM / 64; ++w) tot += wsum[w][tid];
+    acc[0] = tot;
+  } else {
   for (int k0 = it.k0; k0 < it.k0 + it.kn; k0 += 32) {
     const int kn = min(32, it.k0 + it.kn - k0);
     for (int e = tid; e < 32 * KCAP; e += NT_MM) {
@@ -1743,6 +1763,7 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_red(const GemmJob* __restrict__ 
       }
     }
     __syncthreads();
+  }
   }
   if (it.nchunk == 1) {
 #pragma unroll
