@@ -1432,6 +1432,7 @@ __global__ void __launch_bounds__(NT_MM) k_mm_proj(const MmJob* __restrict__ job
       const int j = e % k, c = e / k;
       const double* f = F + c0 + (int64_t)j * ldF;
       const double* x = X + c0 + (int64_t)c * ldX;
+#pragma unroll 8
       for (int r = q; r < cn; r += Q) acc += f[r] * x[r];
     }
     part_s[tid] = acc;
@@ -2256,8 +2257,20 @@ __global__ void __launch_bounds__(1024) k_normalize(const VecJob* __restrict__ i
   const VecJob it = items[first + blockIdx.x];
   const double* z = it.z;
   const int64_t n = it.n;
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) s += z[i] * z[i];
+  // eight loads in flight per thread (a plain loop waits for every load)
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t i = threadIdx.x;
+  for (; i + 7 * 1024 < n; i += 8 * 1024) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = z[i + u * 1024];
+    s0 += v[0] * v[0] + v[4] * v[4];
+    s1 += v[1] * v[1] + v[5] * v[5];
+    s2 += v[2] * v[2] + v[6] * v[6];
+    s3 += v[3] * v[3] + v[7] * v[7];
+  }
+  for (; i < n; i += 1024) s0 += z[i] * z[i];
+  double s = (s0 + s1) + (s2 + s3);
   s = gsum(s, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -2266,7 +2279,15 @@ __global__ void __launch_bounds__(1024) k_normalize(const VecJob* __restrict__ i
   const double nrm = sqrt(t);
   if (it.x != nullptr) {
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) it.x[i] = z[i] * inv;
+    int64_t j = threadIdx.x;
+    for (; j + 7 * 1024 < n; j += 8 * 1024) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = z[j + u * 1024];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) it.x[j + u * 1024] = v[u] * inv;
+    }
+    for (; j < n; j += 1024) it.x[j] = z[j] * inv;
   }
   if (threadIdx.x == 0 && it.out != nullptr) it.out[0] = nrm;
 }
