@@ -1895,9 +1895,9 @@ __device__ __forceinline__ void leaf_reduce_tile(d4_t acc, double* part, double*
 // Unblocked Householder QR of panel columns [c0, c0+pw) over rows [c0, M):
 // wavefront w owns column c0 + w, lane l owns rows c0 + l + 64 t.  Step j: the
 // owner forms reflector j and broadcasts it through LDS, the wavefronts of the
-// later columns apply it.  Afterwards the Gram matrix G = Y^T Y of the panel
-// (FP64 MFMA) gives T by eq. recqrcombined row by row: lane i of wavefront 0
-// runs T[i, j] = -tau_j sum_{i <= k < j} T[i, k] G[k, j] over j, T[i, i] = tau_i.
+// later columns apply it, and the wavefronts of the finished columns i < j
+// form the Gram entries G[i, j] = v_i^T v_j meanwhile.  T then follows from G
+// by eq. recqrcombined (below).
 template <int RPT>
 __device__ __forceinline__ void leaf_panel_rows(LeafWs W, int c0, int pw, int M, double* sm) {
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -1955,6 +1955,18 @@ __device__ __forceinline__ void leaf_panel_rows(LeafWs W, int c0, int pw, int M,
 #pragma unroll
         for (int t = 0; t < RPT; ++t) a[t] -= f * v[t];
       }
+    } else if (w < j) {
+      // a finished column: G[w, j] = v_w^T v_j (the Gram matrix for T) while
+      // the later columns take reflector j
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int r = lane + 64 * t;
+        const double y = r > w ? a[t] : (r == w ? 1.0 : 0.0);
+        if (t & 1) d1 += vb[r] * y; else d0 += vb[r] * y;
+      }
+      const double d = gsumt<64>(d0 + d1);
+      if (lane == 0) gram[w + NB * j] = d;
     }
   }
 #pragma unroll
@@ -1962,26 +1974,7 @@ __device__ __forceinline__ void leaf_panel_rows(LeafWs W, int c0, int pw, int M,
     const int r = lane + 64 * t;
     if (w < pw && r < h) col[r] = a[t];
   }
-  // G = Y^T Y over the panel rows, LF_CH rows at a time through LDS
-  double* Ys = sm + LF_A;
-  d4_t acc = {0.0, 0.0, 0.0, 0.0};
-  for (int r0 = 0; r0 < h; r0 += LF_CH) {
-    const int rn = min(LF_CH, h - r0);
-#pragma unroll
-    for (int t = 0; t < RPT; ++t) {
-      const int r = lane + 64 * t;
-      if (r >= r0 && r < r0 + LF_CH) {
-        double y = 0.0;
-        if (w < pw && r < h) y = r > w ? a[t] : (r == w ? 1.0 : 0.0);
-        Ys[(r - r0) + w * LF_LD] = y;
-      }
-    }
-    if (tid < 4 * NB) Ys[LF_CH + (tid & 3) + (tid >> 2) * LF_LD] = 0.0;  // pad rows of the last k-step
-    __syncthreads();
-    acc = leaf_ytb_acc(Ys, Ys, rn, acc);
-    __syncthreads();
-  }
-  leaf_reduce_tile(acc, sm + LF_PART, gram);
+  __syncthreads();  // the last column's Gram entries
   // T by eq. recqrcombined, doubling the block size: on blocks B1 = [2ab, 2ab+b)
   // and B2 = [2ab+b, 2ab+2b), T[B1, B2] = -T[B1, B1] (Y_B1^T Y_B2) T[B2, B2].
   // Wavefront 0 alone (at most 64 entries per step), ordered by wavefront fences.
