@@ -2017,8 +2017,14 @@ __device__ __forceinline__ void leaf_panel_rows(LeafWs W, int c0, int pw, int M,
 }
 
 __device__ __forceinline__ void leaf_panel(LeafWs W, int c0, int pw, int M, double* sm) {
-  const int h = M - c0;
-  if (h <= 320)
+  const int h = M - c0;  // rows per lane: as few as the panel's height allows
+  if (h <= 128)
+    leaf_panel_rows<2>(W, c0, pw, M, sm);
+  else if (h <= 192)
+    leaf_panel_rows<3>(W, c0, pw, M, sm);
+  else if (h <= 256)
+    leaf_panel_rows<4>(W, c0, pw, M, sm);
+  else if (h <= 320)
     leaf_panel_rows<5>(W, c0, pw, M, sm);
   else if (h <= 576)
     leaf_panel_rows<9>(W, c0, pw, M, sm);
