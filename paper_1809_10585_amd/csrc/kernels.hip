@@ -22,6 +22,22 @@
 namespace hq {
 
 // ------------------------------------------------------------------ helpers
+// Device memory reached through pointers held in job structs.  A generic
+// pointer compiles to flat instructions, which also count against the LDS
+// counter, so the compiler waits for outstanding loads and stores before
+// later memory operations; a pointer in the global address space compiles to
+// global instructions that do not.
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ gdouble* gmem(double* p) { return (gdouble*)p; }
+
+// Wait until this thread's vector memory loads have returned (s_waitcnt with
+// vmcnt 0, the other counters at their maxima).  Used after loads whose values
+// are later stored under divergent control flow: the compiler cannot see that
+// every path has consumed them, so it would otherwise put a vmcnt(0) wait in
+// front of each conditional store, and each such wait also waits for the
+// stores before it.
+__device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Cross-lane moves of a double through DPP (VALU, a few cycles) instead of
 // ds_bpermute round trips.  CTRL is a gfx9 DPP control word.
 template <int CTRL>
@@ -1904,13 +1920,14 @@ __device__ __forceinline__ void leaf_panel_rows(LeafWs W, int c0, int pw, int M,
   const int h = M - c0;
   double* taus = sm + LF_TAU;
   double* gram = sm + LF_GRAM;
-  double* col = W.H + (int64_t)(c0 + w) * MAXSTACK + c0;
+  gdouble* col = gmem(W.H) + (int64_t)(c0 + w) * MAXSTACK + c0;
   double a[RPT];
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
     const int r = lane + 64 * t;
     a[t] = (w < pw && r < h) ? col[r] : 0.0;
   }
+  wait_loads();
   for (int j = 0; j < pw; ++j) {
     double* vb = sm + LF_VBUF + (j & 1) * MAXSTACK;
     if (w == j) {
@@ -2011,7 +2028,7 @@ __device__ __forceinline__ void leaf_panel_rows(LeafWs W, int c0, int pw, int M,
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int idx = tid + 64 * e, i = idx % NB, j = idx / NB;
-      if (i < pw && j < pw) W.T[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] = Tp[idx];
+      if (i < pw && j < pw) gmem(W.T)[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] = Tp[idx];
     }
   }
 }
@@ -2045,6 +2062,7 @@ __device__ __forceinline__ double leaf_y(const LeafWs& W, int c0, int r, int j) 
 __device__ __forceinline__ void leaf_stage(const LeafWs& W, int c0, int pw, int r0, int rn, int cb,
                                            int bw, double* Ys, double* Bs) {
   constexpr int PER = (LF_CH * NB + NT_LEAF - 1) / NT_LEAF;
+  const gdouble* H = gmem(W.H);
   double y[PER], bv[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -2053,8 +2071,8 @@ __device__ __forceinline__ void leaf_stage(const LeafWs& W, int c0, int pw, int 
     const bool row_ok = rr < rn && jj < NB;
     const int r = row_ok ? r0 + rr : r0;
     const int rel = r - c0;
-    const double yv = W.H[(int64_t)r + (int64_t)(c0 + (jj < pw ? jj : 0)) * MAXSTACK];
-    const double bb = W.H[(int64_t)r + (int64_t)(cb + (jj < bw ? jj : 0)) * MAXSTACK];
+    const double yv = H[(int64_t)r + (int64_t)(c0 + (jj < pw ? jj : 0)) * MAXSTACK];
+    const double bb = H[(int64_t)r + (int64_t)(cb + (jj < bw ? jj : 0)) * MAXSTACK];
     y[q] = (row_ok && jj < pw) ? (rel < jj ? 0.0 : (rel == jj ? 1.0 : yv)) : 0.0;
     bv[q] = (row_ok && jj < bw) ? bb : 0.0;
   }
@@ -2100,7 +2118,7 @@ __device__ __forceinline__ void leaf_strip(const LeafWs& W, int c0, int pw, int 
   double tval = 0.0;  // T_pp tile, loaded together with the first staging
   if (tid < 256) {
     const int i = tid & 15, j = tid >> 4;
-    tval = (i <= j && i < pw && j < pw) ? W.T[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] : 0.0;
+    tval = (i <= j && i < pw && j < pw) ? gmem(W.T)[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] : 0.0;
   }
   d4_t acc = {0.0, 0.0, 0.0, 0.0};
   const bool one_chunk = (M - c0) <= LF_CH;
@@ -2136,7 +2154,7 @@ __device__ __forceinline__ void leaf_strip(const LeafWs& W, int c0, int pw, int 
       for (int e = 0; e < 4; ++e) {
         const int row = 16 * t + 4 * e + (l >> 4), col = l & 15;
         if (row < rn && col < sw)
-          W.H[(int64_t)(r0 + row) + (int64_t)(cs + col) * MAXSTACK] = Bs[row + col * LF_LD] - d[e];
+          gmem(W.H)[(int64_t)(r0 + row) + (int64_t)(cs + col) * MAXSTACK] = Bs[row + col * LF_LD] - d[e];
       }
     }
     if (!one_chunk) __syncthreads();
@@ -2190,7 +2208,7 @@ __global__ void __launch_bounds__(NT_LEAF) k_leaf_step(const LeafJob* __restrict
     // leaf_ytb computed Y_p^T Y_b; store its transpose
     if (tid < 256) {
       const int i = tid & 15, j = tid >> 4;  // (Y_p^T Y_b)[i][j] = G[b*16 + j][c0 + i]
-      if (i < pw) W.G[(int64_t)(b * NB + j) + (int64_t)(c0 + i) * MAXLEAF] = sm[LF_W + i + j * NB];
+      if (i < pw) gmem(W.G)[(int64_t)(b * NB + j) + (int64_t)(c0 + i) * MAXLEAF] = sm[LF_W + i + j * NB];
     }
     return;
   }
@@ -2204,15 +2222,15 @@ __global__ void __launch_bounds__(NT_LEAF) k_leaf_step(const LeafJob* __restrict
   double* Tq = X + NB * NB;
   if (tid < 256) {
     const int i = tid & 15, j = tid >> 4;
-    Tq[tid] = (i <= j && i < qw && j < qw) ? W.T[(int64_t)(cq + i) + (int64_t)(cq + j) * MAXLEAF] : 0.0;
+    Tq[tid] = (i <= j && i < qw && j < qw) ? gmem(W.T)[(int64_t)(cq + i) + (int64_t)(cq + j) * MAXLEAF] : 0.0;
   }
   // X = T[i0:i0+16, i0:cq] G[i0:cq, cq:cq+16]  (T upper: zero left of its diagonal)
   d4_t acc = {0.0, 0.0, 0.0, 0.0};
   const int nk = (cq - i0) >> 2;
   for (int ks = w; ks < nk; ks += 16) {
     const int row = i0 + (l & 15), colT = i0 + 4 * ks + (l >> 4);
-    const double a = (colT >= row) ? W.T[(int64_t)row + (int64_t)colT * MAXLEAF] : 0.0;
-    const double g = W.G[(int64_t)(i0 + 4 * ks + (l >> 4)) + (int64_t)(cq + (l & 15)) * MAXLEAF];
+    const double a = (colT >= row) ? gmem(W.T)[(int64_t)row + (int64_t)colT * MAXLEAF] : 0.0;
+    const double g = gmem(W.G)[(int64_t)(i0 + 4 * ks + (l >> 4)) + (int64_t)(cq + (l & 15)) * MAXLEAF];
     acc = mfma16(a, g, acc);
   }
   leaf_reduce_tile(acc, sm + LF_PART, X);
@@ -2221,7 +2239,7 @@ __global__ void __launch_bounds__(NT_LEAF) k_leaf_step(const LeafJob* __restrict
     double sacc = 0.0;
 #pragma unroll
     for (int q2 = 0; q2 < NB; ++q2) sacc += X[i + NB * q2] * Tq[q2 + NB * j];
-    if (j < qw) W.T[(int64_t)(i0 + i) + (int64_t)(cq + j) * MAXLEAF] = -sacc;
+    if (j < qw) gmem(W.T)[(int64_t)(i0 + i) + (int64_t)(cq + j) * MAXLEAF] = -sacc;
   }
 }
 
