@@ -75,6 +75,15 @@ def test_invalid_arguments_are_rejected_on_host(lib):
     q["leaf_off"] = p["leaf_off"].copy()
     q["leaf_off"][1] = 0
     assert _build(lib, q) == -1
+    # empty matrix (n = 0, all leaves empty)
+    q = dict(p)
+    q["n"] = 0
+    q["leaf_off"] = np.zeros_like(p["leaf_off"])
+    assert _build(lib, q) == -1
+    # a leaf above the 512-row maximum
+    big = G.gaussian_hodlr(1040, 520, 2, seed=2).pack()
+    assert _build(lib, big, levels=1) == -1
+    assert b"512" in lib.hodlr_last_error()
     # non-finite entry
     q = dict(p)
     q["leaves"] = p["leaves"].copy()
