@@ -1501,8 +1501,13 @@ __global__ void __launch_bounds__(NT_MM) k_mm_red(const MmJob* __restrict__ jobs
 //  RT = 64: the group streams a contiguous quarter of the columns, so a wave
 //           reads whole 512-byte column pieces (long launches: bandwidth); the
 //           loop is unrolled 64/CW times, which keeps two wavefronts per SIMD.
+//           For op(D) = D^T the rows of the output are columns of D: the
+//           block reads 64 x 64 tiles of D along its columns (coalesced),
+//           stores them transposed in LDS (next tile's loads in flight
+//           meanwhile), and group g takes rows 16g .. 16g + 15 of each tile.
 // Dynamic LDS: max(m_leaf, 256) * 17 doubles.
 constexpr int MA_LD = 17;
+constexpr int DT_LD = 65;  // transposed leaf tile, padded row
 
 __host__ __device__ constexpr size_t mm_apply_lds(int mleaf) {
   return sizeof(double) * (size_t)MA_LD * (size_t)(mleaf > 256 ? mleaf : 256);
@@ -1518,9 +1523,29 @@ __device__ __forceinline__ double leaf_elem(const HLeaf& lf, int kind, int trans
 
 // The rows of one item in column slabs of CW columns (CW = 4 when s <= 4:
 // a quarter of the LDS reads and FMAs of the 16-wide slab).
+// Tile [k0, k0 + 64) x [row0, row0 + 64) of the leaf, element (kk, R) of D
+// for the transposed product, zero outside the leaf and the item's rows.
+// Thread tid takes elements e = tid + 256 q: kk = k0 + e % 64, R = row0 + e / 64.
+__device__ __forceinline__ void mm_tile_load(double (&tv)[16], const HLeaf& lf, int kind,
+                                             const MmApply& it, int m, int k0) {
+  const gdouble* D = gmem(lf.D);  // 32-bit offsets: a leaf has at most 512^2 entries
+  int ld = lf.ld;
+  asm volatile("" : "+v"(ld));  // recompute the 16 addresses per tile instead of holding them
+  const int kk = k0 + (threadIdx.x & 63);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int rr = (threadIdx.x >> 6) + 4 * q, R = it.row0 + rr;
+    const bool in = kk < m && rr < it.rows;
+    // element (kk, R) of the leaf's stored part (as leaf_elem with trans)
+    const bool keep = kind == LEAF_FULL || (kind == LEAF_UNIT_LOWER ? kk > R : kk <= R);
+    const double x = (in && keep) ? D[kk + R * ld] : 0.0;
+    tv[q] = (in && kind == LEAF_UNIT_LOWER && kk == R) ? 1.0 : x;
+  }
+}
+
 template <int RT, int CW>
 __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it, const double* ws,
-                                              double* shm, int s) {
+                                              double* shm, double* Dt, int s) {
   constexpr int G = NT_MM / RT;
   constexpr int DMAX = RT == 16 ? MAXLEAF / G : 1;
   const int tid = threadIdx.x;
@@ -1563,6 +1588,25 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
 #pragma unroll
           for (int c = 0; c < CW; ++c) acc[c] += d * Xs[kk * MA_LD + c];
         }
+      }
+    } else if (CW == 4 && trans) {
+      double tv[16];
+      mm_tile_load(tv, lf, kind, it, m, 0);
+      for (int k0 = 0; k0 < m; k0 += 64) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) Dt[(tid & 63) * DT_LD + (tid >> 6) + 4 * q] = tv[q];
+        __syncthreads();
+        if (k0 + 64 < m) mm_tile_load(tv, lf, kind, it, m, k0 + 64);
+#pragma unroll 4
+        for (int i = 0; i < 16; ++i) {
+          const int kl = 16 * g + i;  // g is the wavefront's index: uniform branch
+          if (k0 + kl < m) {
+            const double d = Dt[kl * DT_LD + r];
+#pragma unroll
+            for (int c = 0; c < CW; ++c) acc[c] += d * Xs[(k0 + kl) * MA_LD + c];
+          }
+        }
+        __syncthreads();  // the tile is overwritten next
       }
     } else {
       if (live) {
@@ -1625,14 +1669,19 @@ __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jo
                                                      const MmApply* __restrict__ items, int first,
                                                      const double* __restrict__ ws) {
   extern __shared__ double shm[];
+  double* Dt = nullptr;  // transposed leaf tile (RT = 64 only)
+  if constexpr (RT == 64) {
+    __shared__ double dtile[64 * DT_LD];
+    Dt = dtile;
+  }
   const MmApply it = items[first + blockIdx.x];
   const MmJob& J = jobs[it.job];
   const int s = mm_s(J);
   if (s == 0) return;
   if (s <= 4)
-    mm_apply_rows<RT, 4>(J, it, ws, shm, s);
+    mm_apply_rows<RT, 4>(J, it, ws, shm, Dt, s);
   else
-    mm_apply_rows<RT, 16>(J, it, ws, shm, s);
+    mm_apply_rows<RT, 16>(J, it, ws, shm, Dt, s);
   if (threadIdx.x == 0) {
     const HLeaf lf = J.M.leaf[it.leaf];
     const int trans = J.trans;

@@ -63,6 +63,23 @@ def test_matmul_against_dense(H, n, leaf, k):
     np.testing.assert_allclose(H.hodlr_matmul(A, H.colmajor(X)).cpu().numpy(), Ad @ X, atol=1e-12 * n)
 
 
+def test_matmul_long_launch_against_oracle(H):
+    """Products over at least 32768 rows take the 64-row tiles (and, for A^T X
+    with at most 4 columns, the transposed leaf tiles staged in LDS); checked
+    against the oracle's HODLR products on a ragged partition."""
+    from oracle import hodlr as OH
+    inp = G.gaussian_hodlr(33001, 256, 3, seed=31)
+    A = H.hodlr_build(inp, rank_cap=8)
+    M = OH.from_input(inp)
+    for s_cols in (1, 3, 9):
+        X = np.random.default_rng(s_cols).standard_normal((inp.n, s_cols))
+        print(f"n=33001 s={s_cols}", flush=True)
+        for trans, ref in ((False, OH.hmat(M, X)), (True, OH.hmatT(M, X))):
+            Z = H.hodlr_matmul(A, H.colmajor(X), trans=trans).cpu().numpy()
+            err = np.abs(Z - ref).max() / np.abs(ref).max()
+            assert err <= 1e-13, (s_cols, trans, err)
+
+
 def test_norm2_est_matches_oracle(H):
     inp = G.config(0)
     A = H.hodlr_build(inp, rank_cap=8)
