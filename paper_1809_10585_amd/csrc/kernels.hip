@@ -1567,6 +1567,38 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
   const int q = (m + G - 1) / G;  // RT = 64: columns [g q, g q + q) of this group
   const int kb0 = min(m, g * q), kb1 = min(m, g * q + q);
   const int hleaf = (1 << J.M.levels) + it.leaf;
+  // RT = 16: this group's ancestor levels li = g, g + 16 (at most two): the
+  // block's rank, factor row and reduced projection, read before the leaf
+  // part so that these dependent loads overlap it (same order of terms as the
+  // loop below)
+  constexpr int NA = RT == 16 ? (MAXGROUPS + G - 1) / G : 1;
+  int akb[NA], ald[NA];
+  const double* aF[NA];
+  const double* aR[NA];
+  if constexpr (RT == 16) {
+    const int dv = (31 - __clz(hleaf)) - (31 - __clz(J.v));  // levels from the leaf up to v
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const int li = g + G * a;
+      akb[a] = 0;
+      ald[a] = 0;
+      aF[a] = nullptr;
+      aR[a] = nullptr;
+      if (li < dv) {
+        const int child = hleaf >> li, u = child >> 1;
+        const bool left = (child & 1) == 0;
+        const int bk = trans ? (left ? 1 : 0) : (left ? 0 : 1);
+        const HBlk* arr = bk == 0 ? J.M.up : J.M.lo;
+        if (arr != nullptr) {
+          const HBlk& b = arr[u];
+          akb[a] = *b.rank;
+          ald[a] = trans ? b.ldV : b.ldU;
+          aF[a] = (trans ? b.V : b.U) + (lf.r0 + R - (trans ? b.c0 : b.r0));
+          aR[a] = ws + J.red0 + (int64_t)(2 * rel_node(u, J.v) + bk) * (KCAP * SMAX);
+        }
+      }
+    }
+  }
   const double* xl = J.X + (lf.r0 - J.row0);
   double* Xs = shm;
   for (int c0 = 0; c0 < s; c0 += CW) {
@@ -1619,8 +1651,20 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
       }
     }
     // low-rank parts
+    if constexpr (RT == 16) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        const double* red = aR[a] + (int64_t)c0 * KCAP;
+        for (int j = 0; j < akb[a]; ++j) {
+          const double fv = live ? aF[a][(int64_t)j * ald[a]] : 0.0;
+#pragma unroll
+          for (int c = 0; c < CW; ++c)
+            if (c < cn) acc[c] += fv * red[j + c * KCAP];
+        }
+      }
+    }
     int child = hleaf, u = hleaf >> 1, li = 0;
-    while (child != J.v && u >= 1) {
+    while (RT != 16 && child != J.v && u >= 1) {
       if (li % G == g) {
         const bool left = (child == 2 * u);
         const int bk = trans ? (left ? 1 : 0) : (left ? 0 : 1);
@@ -2323,17 +2367,20 @@ __global__ void __launch_bounds__(1024) k_normalize(const VecJob* __restrict__ i
   const VecJob it = items[first + blockIdx.x];
   const double* z = it.z;
   const int64_t n = it.n;
-  // eight loads in flight per thread (a plain loop waits for every load)
+  // sixteen loads in flight per thread (a plain loop waits for every load)
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int64_t i = threadIdx.x;
-  for (; i + 7 * 1024 < n; i += 8 * 1024) {
-    double v[8];
+  for (; i + 15 * 1024 < n; i += 16 * 1024) {
+    double v[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = z[i + u * 1024];
-    s0 += v[0] * v[0] + v[4] * v[4];
-    s1 += v[1] * v[1] + v[5] * v[5];
-    s2 += v[2] * v[2] + v[6] * v[6];
-    s3 += v[3] * v[3] + v[7] * v[7];
+    for (int u = 0; u < 16; ++u) v[u] = z[i + u * 1024];
+#pragma unroll
+    for (int u = 0; u < 16; u += 4) {
+      s0 += v[u] * v[u];
+      s1 += v[u + 1] * v[u + 1];
+      s2 += v[u + 2] * v[u + 2];
+      s3 += v[u + 3] * v[u + 3];
+    }
   }
   for (; i < n; i += 1024) s0 += z[i] * z[i];
   double s = (s0 + s1) + (s2 + s3);
@@ -2346,12 +2393,12 @@ __global__ void __launch_bounds__(1024) k_normalize(const VecJob* __restrict__ i
   if (it.x != nullptr) {
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
     int64_t j = threadIdx.x;
-    for (; j + 7 * 1024 < n; j += 8 * 1024) {
-      double v[8];
+    for (; j + 15 * 1024 < n; j += 16 * 1024) {
+      double v[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = z[j + u * 1024];
+      for (int u = 0; u < 16; ++u) v[u] = z[j + u * 1024];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) it.x[j + u * 1024] = v[u] * inv;
+      for (int u = 0; u < 16; ++u) it.x[j + u * 1024] = v[u] * inv;
     }
     for (; j < n; j += 1024) it.x[j] = z[j] * inv;
   }
