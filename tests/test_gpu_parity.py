@@ -80,6 +80,26 @@ def test_matmul_long_launch_against_oracle(H):
             assert err <= 1e-13, (s_cols, trans, err)
 
 
+def test_factor_products_long_launch_adjoint(H):
+    """Y, T and R (unit lower, upper, upper leaves) over 33001 rows: the
+    transposed products (64-row tiles staged through LDS) are the adjoints of
+    the direct ones, <M X1, X2> = <X1, M^T X2>."""
+    inp = G.gaussian_hodlr(33001, 256, 2, seed=32)  # oracle ranks of Y, T, R: 16, 16, 31
+    A = H.hodlr_build(inp, rank_cap=48)
+    F = H.hodlr_qr(A, EPS)
+    rng = np.random.default_rng(5)
+    for s_cols in (1, 4, 9):
+        X1 = rng.standard_normal((inp.n, s_cols))
+        X2 = rng.standard_normal((inp.n, s_cols))
+        for which in "YTR":
+            print(f"n=33001 {which} s={s_cols}", flush=True)
+            MX1 = H.hodlr_qr_matmul(F, which, H.colmajor(X1)).cpu().numpy()
+            MtX2 = H.hodlr_qr_matmul(F, which, H.colmajor(X2), trans=True).cpu().numpy()
+            a, b = np.sum(MX1 * X2), np.sum(X1 * MtX2)
+            scale = np.linalg.norm(MX1) * np.linalg.norm(X2) + np.linalg.norm(MtX2) * np.linalg.norm(X1)
+            assert abs(a - b) <= 1e-13 * scale, (which, s_cols, a, b)
+
+
 def test_norm2_est_matches_oracle(H):
     inp = G.config(0)
     A = H.hodlr_build(inp, rank_cap=8)
