@@ -1,6 +1,13 @@
-"""Compile the HIP library libhodlr.so for gfx950 (in-tree, next to this file)."""
+"""Compile the HIP library libhodlr.so for gfx950 (in-tree, next to this file).
+
+The kernels are split by family into translation units that compile in
+parallel (csrc/k_*.hip), plus the host scheduler and C ABI (csrc/hodlr.cpp);
+the objects are linked into one shared library.
+"""
 from __future__ import annotations
 
+import concurrent.futures as cf
+import hashlib
 import os
 import shutil
 import subprocess
@@ -8,15 +15,17 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "hodlr.cpp")
+CSRC = os.path.join(HERE, "csrc")
+UNITS = ["hodlr.cpp", "k_tr.hip", "k_mm.hip", "k_leaf.hip", "k_vec.hip"]
 OUT = os.path.join(HERE, "libhodlr.so")
+OBJ = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("HODLR_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc"),
+    "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
 
 
@@ -27,13 +36,46 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = OUT + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-x", "hip", SRC, "-o", tmp]
+def _key(unit: str) -> str:
+    """Content hash of a unit, every header of csrc/ and include/, and the flags."""
+    h = hashlib.sha256(" ".join(FLAGS).encode())
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for f in sorted(os.listdir(d)):
+            if f.endswith(".h") or f == unit:
+                h.update(f.encode())
+                h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _compile(unit: str, reuse: bool) -> str:
+    obj = os.path.join(OBJ, f"{unit}.{_key(unit)}.o")
+    if reuse and os.path.exists(obj):
+        return obj
+    tmp = obj + ".tmp"
+    cmd = [hipcc()] + FLAGS + ["-c", "-x", "hip", os.path.join(CSRC, unit), "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed for libhodlr.so")
+        raise RuntimeError(f"hipcc failed for {unit}")
+    os.replace(tmp, obj)
+    return obj
+
+
+def build(verbose: bool = False, reuse: bool | None = None) -> str:
+    """Compile every unit (in parallel) and link libhodlr.so.  With reuse (or
+    HODLR_BUILD_REUSE=1) an object whose sources and flags are unchanged is
+    taken from _build/ instead of being compiled again."""
+    if reuse is None:
+        reuse = os.environ.get("HODLR_BUILD_REUSE") == "1"
+    os.makedirs(OBJ, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=len(UNITS)) as ex:
+        objs = list(ex.map(lambda u: _compile(u, reuse), UNITS))
+    tmp = OUT + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("linking libhodlr.so failed")
     if verbose:
         sys.stderr.write(r.stderr)
     os.replace(tmp, OUT)
@@ -41,4 +83,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, reuse="--reuse" in sys.argv or None))

@@ -12,7 +12,7 @@
 //                    overwritten by Y~_B^T slice by slice as the leaves below
 //                    node v's left child are factorised (Y_B = B_L Y~_B).
 //  * T block v     : T12 = -T1 T~12 T2 in factored form.
-#include "kernels.hip"
+#include "kernels.h"
 
 #include <hip/hip_ext.h>
 

@@ -1,0 +1,1131 @@
+// Recompression T_tau of Sec. 2.1.1 (k_tr_qr, k_tr_form, k_tr_small).
+#include "kernels_common.h"
+#include "kernels.h"
+
+namespace hq {
+
+// ------------------------------------------------------------------ recompression
+// LDS layout of k_tr_qr (doubles)
+
+__device__ __forceinline__ int tr_root_slot(int p0, int G) {
+  int s = 0, cnt = p0;
+  while (cnt > 1) {
+    s += cnt;
+    cnt = (cnt + G - 1) / G;
+  }
+  return s;
+}
+
+// Rotation of one-sided Jacobi for a column pair with a = |x_i|^2, b = |x_j|^2,
+// g = x_i . x_j: false when |g| <= tol sqrt(a b) (tested squared); otherwise
+// the (cs, sn) that makes the rotated pair orthogonal, the smaller angle with
+// tan(2 theta) = 2g / (b - a) (the rotation of jacobi()).  Short dependency
+// chain: with d = b - a and g2 = 2g scaled by a power of two (squares neither
+// overflow nor underflow), r = |(d, g2)|, s = r + |d| and q = 1/sqrt(2 r s),
+// cs = s q and sn = sign(d) g2 q (cs^2 + sn^2 = (s^2 + g2^2) / (2 r s) = 1).
+__device__ __forceinline__ bool jac_rot_fast(double al, double be, double ga, double tol2, double& cs,
+                                             double& sn) {
+  if (!(ga != 0.0 && ga * ga > tol2 * (al * be))) return false;
+  double d = be - al, g = 2.0 * ga;
+  const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(d), fabs(g)));
+  d = __builtin_ldexp(d, -e);
+  g = __builtin_ldexp(g, -e);
+  const double h2 = fma(d, d, g * g);  // in [1/4, 2]
+  double y = __builtin_amdgcn_rsq(h2);
+  y = y * fma(-0.5 * h2 * y, y, 1.5);
+  y = y * fma(-0.5 * h2 * y, y, 1.5);
+  const double r = h2 * y;
+  const double s = r + fabs(d);
+  const double u = 2.0 * r * s;
+  double q = __builtin_amdgcn_rsq(u);
+  q = q * fma(-0.5 * u * q, q, 1.5);
+  q = q * fma(-0.5 * u * q, q, 1.5);
+  cs = s * q;
+  sn = (d >= 0.0 ? g : -g) * q;
+  return true;
+}
+
+// One-sided Jacobi on the columns of X (w x w, ld lx), accumulating the
+// rotations in V (ld lv).  Round-robin pairing; one pair per group of TPP
+// lanes; a sweep ends when no pair needed a rotation.
+__device__ __forceinline__ void jacobi(double* X, int lx, double* V, int lv, int w, int* sflag) {
+  const int tid = threadIdx.x;
+  const int n = w + (w & 1);
+  if (n < 2) return;
+  const int P = n / 2;
+  int Pp = 1;
+  while (Pp < P) Pp <<= 1;
+  int TPP = NT_TR / Pp;
+  if (TPP > 64) TPP = 64;
+  const int p = tid / TPP, sub = tid % TPP;
+  const double tol = (double)w * DBL_EPSILON;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) *sflag = 0;
+    __syncthreads();
+    for (int r = 0; r < n - 1; ++r) {
+      if (p < P) {
+        int i, j;
+        if (p == 0) {
+          i = r;
+          j = n - 1;
+        } else {
+          i = (r + p) % (n - 1);
+          j = (r - p + n - 1) % (n - 1);
+        }
+        if (i > j) {
+          const int t = i;
+          i = j;
+          j = t;
+        }
+        const bool valid = j < w;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (valid) {
+          for (int row = sub; row < w; row += TPP) {
+            const double xi = X[row + i * lx], xj = X[row + j * lx];
+            al += xi * xi;
+            be += xj * xj;
+            ga += xi * xj;
+          }
+        }
+        al = gsum(al, TPP);
+        be = gsum(be, TPP);
+        ga = gsum(ga, TPP);
+        double cs, sn;
+        if (valid && jac_rot_fast(al, be, ga, tol * tol, cs, sn)) {
+          for (int row = sub; row < w; row += TPP) {
+            const double xi = X[row + i * lx], xj = X[row + j * lx];
+            X[row + i * lx] = cs * xi - sn * xj;
+            X[row + j * lx] = sn * xi + cs * xj;
+            const double vi = V[row + i * lv], vj = V[row + j * lv];
+            V[row + i * lv] = cs * vi - sn * vj;
+            V[row + j * lv] = sn * vi + cs * vj;
+          }
+          if (sub == 0) *sflag = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int f = *sflag;
+    __syncthreads();
+    if (f == 0) break;
+  }
+}
+
+// The same one-sided Jacobi for w <= WS (WS = 8 or 16) inside one wavefront.
+// X (and V = X + WS*WS) are WS x WS in LDS with leading dimension WS, rows and
+// columns beyond w zero (rotations keep them zero), so a lane loads, rotates and
+// stores whole padded columns without branches.  Lane p rotates pair p of the
+// round-robin schedule; a round costs no block barrier and no cross-lane
+// reduction; the sweep test is a wavefront vote.  Same rotation and threshold as
+// jacobi() (|g| > tol sqrt(a b) is tested squared).  All threads of the block
+// call it; it ends with a block barrier.
+template <int WS>
+__device__ __forceinline__ void jacobi_small(double* X, int w) {
+  double* V = X + WS * WS;
+  const int tid = threadIdx.x;
+  const int n = w + (w & 1);
+  if (n >= 2 && tid < 64) {
+    const int P = n / 2;
+    const double tol = (double)w * DBL_EPSILON;
+    const double tol2 = tol * tol;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+      int rot = 0;
+      for (int r = 0; r < n - 1; ++r) {
+        int i = 0, j = 0;
+        if (tid == 0) {
+          i = r;
+          j = n - 1;
+        } else {
+          i = (r + tid) % (n - 1);
+          j = (r - tid + n - 1) % (n - 1);
+        }
+        if (i > j) {
+          const int t = i;
+          i = j;
+          j = t;
+        }
+        if (tid < P && j < w) {
+          double* xi = X + i * WS;
+          double* xj = X + j * WS;
+          double* vi = V + i * WS;
+          double* vj = V + j * WS;
+          double a[WS], b[WS], c[WS], d[WS];
+#pragma unroll
+          for (int row = 0; row < WS; ++row) {
+            a[row] = xi[row];
+            b[row] = xj[row];
+            c[row] = vi[row];
+            d[row] = vj[row];
+          }
+          double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+          for (int row = 0; row < WS; ++row) {
+            al = fma(a[row], a[row], al);
+            be = fma(b[row], b[row], be);
+            ga = fma(a[row], b[row], ga);
+          }
+          double cs, sn;
+          if (jac_rot_fast(al, be, ga, tol2, cs, sn)) {
+#pragma unroll
+            for (int row = 0; row < WS; ++row) {
+              xi[row] = cs * a[row] - sn * b[row];
+              xj[row] = sn * a[row] + cs * b[row];
+              vi[row] = cs * c[row] - sn * d[row];
+              vj[row] = sn * c[row] + cs * d[row];
+            }
+            rot = 1;
+          }
+        }
+        // the next round reads columns other lanes of this wavefront wrote
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (__ballot(rot) == 0) break;
+    }
+  }
+  __syncthreads();
+}
+
+// Flops of one recompression (the oracle's counting: Householder QR of both
+// factors, the product of the R factors, the SVD as 21 p^3, forming the factors).
+__device__ __forceinline__ double qr_flops(double m, double n) {
+  const double pp = fmin(m, n);
+  return m >= n ? 2.0 * m * n * pp - 2.0 / 3.0 * pp * pp * pp : 2.0 * n * m * m - 2.0 / 3.0 * m * m * m;
+}
+
+__device__ __forceinline__ double tr_flops_full(int m0, int m1, int w, int k) {
+  const double p1 = min(m0, w), p2 = min(m1, w);
+  const double mp = fmax(p1, p2);
+  return qr_flops(m0, w) + qr_flops(m1, w) + 2.0 * p1 * p2 * w + 21.0 * mp * mp * mp +
+         4.0 * (double)m0 * p1 * k + 2.0 * (double)m1 * w * k;
+}
+
+__device__ __forceinline__ double tr_flops_orth(int m0, int m1, int w) {
+  const double pq = (double)min(m0, w);
+  return 2.0 * (2.0 * (double)m0 * w * pq - 2.0 / 3.0 * pq * pq * pq) + 2.0 * (double)w * w * m1;
+}
+
+// Last block of a job: SVD of R1 R2^T and the small factors U_k, P = R1^T U_k.
+template <int W>
+__device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0a, int n0b, double* smem, int* err,
+                       double* fc) {
+  const int tid = threadIdx.x;
+  constexpr int G = CH / W;
+  double* hdr = ws + J.hdr;
+  double* Uk = hdr + 8;
+  double* P = Uk + WMAX * WMAX;
+  const double* R1 = ws + J.side[0].node0 + (int64_t)tr_root_slot(J.side[0].p0, G) * TR_NODE;
+  int* sflag = (int*)(smem + TRS_FLAG);
+  const int m0 = J.side[0].m, m1 = J.side[1].m;
+  const double tau = *J.tau;
+  const int capk = J.cap, fcat = J.fc;
+  int k;
+  if (J.flags & TR_ORTH) {
+    k = min(m0, w);
+    for (int e = tid; e < w * k; e += NT_TR) {
+      const int r = e % w, p = e / w;
+      Uk[r + p * WMAX] = (r == p) ? 1.0 : 0.0;
+      P[r + p * WMAX] = R1[p + r * WMAX];
+    }
+    if (tid == 0) add_flops(fc, fcat, tr_flops_orth(m0, m1, w));
+  } else {
+    const double* R2 = ws + J.side[1].node0 + (int64_t)tr_root_slot(J.side[1].p0, G) * TR_NODE;
+    // w <= 16: X and V padded to WS x WS (zeros beyond w) for jacobi_small
+    const int WSs = w <= 8 ? 8 : (w <= 16 ? 16 : 0);
+    const int LX = WSs ? WSs : w;
+    double* X = smem + TRS_X;
+    double* V;
+    int LV;
+    if (WSs) {
+      V = X + LX * LX;
+      LV = LX;
+    } else if (2 * w * w <= WMAX * WMAX) {  // X and V both in LDS
+      V = X + w * w;
+      LV = w;
+    } else {
+      V = hdr + 8 + 2 * WMAX * WMAX;
+      LV = WMAX;
+    }
+    double* sig = smem + TRS_X + WMAX * WMAX;
+    int* perm = (int*)(sig + WMAX);
+    // stage R1 and R2 in LDS when they fit next to X and V
+    const double* R1s = R1;
+    const double* R2s = R2;
+    int lr = WMAX;
+    if (4 * LX * LX <= WMAX * WMAX) {
+      double* r1 = X + 2 * LX * LX;
+      double* r2 = r1 + w * w;
+      for (int e = tid; e < w * w; e += NT_TR) {
+        const int i = e % w, j = e / w;
+        r1[e] = R1[i + j * WMAX];
+        r2[e] = R2[i + j * WMAX];
+      }
+      R1s = r1;
+      R2s = r2;
+      lr = w;
+      __syncthreads();
+    }
+    // X = R2 R1^T  (both upper triangular, w x w; zero padding up to LX)
+    const int wx = WSs ? LX : w;
+    for (int e = tid; e < wx * wx; e += NT_TR) {
+      const int i = e % wx, j = e / wx;
+      double sacc = 0.0;
+      if (i < w && j < w)
+        for (int l = max(i, j); l < w; ++l) sacc += R2s[i + l * lr] * R1s[j + l * lr];
+      X[i + j * LX] = sacc;
+      V[i + j * LV] = (i == j && i < w) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (WSs == 8)
+      jacobi_small<8>(X, w);
+    else if (WSs == 16)
+      jacobi_small<16>(X, w);
+    else
+      jacobi(X, LX, V, LV, w, sflag);
+    for (int cc = tid; cc < w; cc += NT_TR) {
+      double sacc = 0.0;
+      for (int r = 0; r < w; ++r) sacc += X[r + cc * LX] * X[r + cc * LX];
+      sig[cc] = sqrt(sacc);
+    }
+    __syncthreads();
+    for (int cc = tid; cc < w; cc += NT_TR) {
+      int pos = 0;
+      const double sc = sig[cc];
+      for (int j = 0; j < w; ++j) {
+        const double sj = sig[j];
+        pos += (sj > sc || (sj == sc && j < cc)) ? 1 : 0;
+      }
+      perm[pos] = cc;
+    }
+    __syncthreads();
+    k = 0;
+    for (int j = 0; j < w; ++j) k += (sig[j] > tau) ? 1 : 0;
+    if (k > capk) {
+      if (tid == 0) atomicOr(err, ERR_CAPACITY);
+      k = capk;
+    }
+    for (int e = tid; e < w * k; e += NT_TR) {
+      const int r = e % w, p = e / w;
+      const int pc = perm[p];
+      Uk[r + p * WMAX] = V[r + pc * LV];
+      double sacc = 0.0;
+      for (int l = 0; l <= r; ++l) sacc += R1s[l + r * lr] * V[l + pc * LV];
+      P[r + p * WMAX] = sacc;
+    }
+    if (tid == 0) add_flops(fc, fcat, tr_flops_full(m0, m1, w, k));
+  }
+  if (tid == 0) {
+    hdr[0] = (double)w;
+    hdr[1] = (double)k;
+    hdr[2] = (double)n0a;
+    hdr[3] = (double)n0b;
+  }
+}
+
+template <int W>
+// Returns true in the block that ran the SVD (the job's last block).
+__device__ __forceinline__ bool tr_chunk(const TrJob& J, int side, int chunk, double* ws, int* counters, int* err,
+                         double* fc, double* smem, int w, int n0a, int n0b) {
+  constexpr int TPC = NT_TR / W;
+  constexpr int RPT = CH / TPC;
+  constexpr int G = CH / W;
+  const int tid = threadIdx.x, c = tid / TPC, sub = tid % TPC;
+  double* vbuf = smem + TRS_VBUF;
+  double* taus = smem + TRS_TAU;
+  int* sflag = (int*)(smem + TRS_FLAG);
+  const TrSide S = J.side[side];
+  const int n0 = side == 0 ? n0a : n0b;
+  const Seg s0 = J.seg[side][0], s1 = J.seg[side][1];
+
+  double a[RPT];
+  int idx = chunk, count = S.p0;
+  int64_t base = 0;  // first slot of the current level
+  int row0 = (int)((int64_t)idx * S.m / S.p0);
+  int h = (int)((int64_t)(idx + 1) * S.m / S.p0) - row0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = sub + TPC * i;
+    double x = 0.0;
+    if (r < h && c < w) {
+      const int64_t gr = row0 + r;
+      x = (c < n0) ? s0.scale * s0.p[gr + (int64_t)c * s0.ld]
+                   : s1.scale * s1.p[gr + (int64_t)(c - n0) * s1.ld];
+    }
+    a[i] = x;
+  }
+  int64_t slot = idx;
+  while (true) {
+    reg_qr<TPC, RPT>(a, c, sub, h, w, vbuf, taus, nullptr, 0);
+    double* node = ws + S.node0 + slot * TR_NODE;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = sub + TPC * i;
+      if (c < w && r < w) node[r + c * WMAX] = (r <= c && r < h) ? a[i] : 0.0;
+    }
+    if (side == 0) {
+      double q[RPT];
+      double* Qa = node + WMAX * WMAX;
+      if constexpr (W <= 32) {
+        __syncthreads();
+        reg_formq<TPC, RPT>(a, q, c, sub, h, w, vbuf, taus);
+      } else {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const int r = sub + TPC * i;
+          if (r < h && c < w) Qa[r + c * CH] = a[i];
+        }
+        __threadfence_block();
+        __syncthreads();
+        reg_formq_g<TPC, RPT>(Qa, q, c, sub, h, w, vbuf, taus);
+      }
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = sub + TPC * i;
+        if (r < h && c < w) Qa[r + c * CH] = q[i];
+      }
+    }
+    if (count == 1) break;
+    const int pidx = idx / G;
+    const int pcount = (count + G - 1) / G;
+    const int nchild = min(G, count - pidx * G);
+    const int64_t pbase = base + count;
+    const int64_t pslot = pbase + pidx;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      int* cnt = counters + S.cnt0 + (int)(pslot - S.p0);
+      const int old = atomicAdd(cnt, 1);
+      const int last = (old == nchild - 1) ? 1 : 0;
+      if (last) atomicExch(cnt, 0);
+      sflag[0] = last;
+    }
+    __syncthreads();
+    const int last = sflag[0];
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    // become the parent: stack the children's R factors
+    const int64_t cbase = base;
+    const int cfirst = pidx * G;
+    base = pbase;
+    idx = pidx;
+    count = pcount;
+    slot = pslot;
+    h = nchild * w;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = sub + TPC * i;
+      double x = 0.0;
+      if (r < h && c < w) {
+        const int ch = r / w, rr = r % w;
+        x = ws[S.node0 + (cbase + cfirst + ch) * TR_NODE + rr + c * WMAX];
+      }
+      a[i] = x;
+    }
+  }
+  // this side is reduced; join the two sides
+  if (!(J.flags & TR_ORTH)) {
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      int* cnt = counters + J.jcounter;
+      const int old = atomicAdd(cnt, 1);
+      const int last = (old == 1) ? 1 : 0;
+      if (last) atomicExch(cnt, 0);
+      sflag[0] = last;
+    }
+    __syncthreads();
+    const int last = sflag[0];
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+  }
+  tr_svd<W>(J, ws, w, n0a, n0b, smem, err, fc);
+  return true;
+}
+
+// WTOP: widest tier compiled into this instantiation (the host picks it from
+// the rank capacity: a recompression is at most twice as wide as a block).
+template <int WTOP>
+__global__ void __launch_bounds__(NT_TR) k_tr_qr(const TrJob* __restrict__ jobs,
+                                                  const TrChunk* __restrict__ items, int first,
+                                                  double* ws, int* counters) {
+  extern __shared__ double smem[];
+  const TrChunk it = items[first + blockIdx.x];
+  const TrJob& J = jobs[it.job];
+  int* err = J.err;
+  double* fc = J.flops;
+  const int n0a = seg_n(J.seg[0][0]);
+  const int w = n0a + seg_n(J.seg[0][1]);
+  const int n0b = seg_n(J.seg[1][0]);
+  if (w == 0 || w > WTOP) {
+    if (it.side == 0 && it.chunk == 0 && threadIdx.x == 0) {
+      double* hdr = ws + J.hdr;
+      hdr[0] = 0.0;
+      hdr[1] = 0.0;
+      if (w > WTOP) atomicOr(err, ERR_WIDTH);
+    }
+    return;
+  }
+  const int t = tier_of(w);
+  if (t == 8) {
+    tr_chunk<8>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b);
+  } else if (t == 16) {
+    if constexpr (WTOP >= 16) tr_chunk<16>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b);
+  } else if (t == 32) {
+    if constexpr (WTOP >= 32) tr_chunk<32>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b);
+  } else if (t == 64) {
+    if constexpr (WTOP >= 64) tr_chunk<64>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b);
+  } else {
+    if constexpr (WTOP >= 128) tr_chunk<128>(J, it.side, it.chunk, ws, counters, err, fc, smem, w, n0a, n0b);
+  }
+}
+
+
+// out[r, p] = sum_c A(r, c) B[c + p*ldb] for r < rows, p < k; thread = row
+// (NT threads), 16 output columns at a time in registers.  A(r, c) = a[r + c*lda].
+template <int NT = NT_MM>
+__device__ __forceinline__ void rows_times_small(const double* a, int64_t lda, int rows, int w,
+                                                 const double* B, int ldb, int k, double* out,
+                                                 int64_t ldo) {
+  const int tid = threadIdx.x;
+  for (int r = tid; r < rows; r += NT) {
+    for (int p0 = 0; p0 < k; p0 += 16) {
+      double acc[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+#pragma unroll 4
+      for (int c = 0; c < w; ++c) {
+        const double x = a[r + (int64_t)c * lda];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (p0 + q < k) acc[q] += x * B[c + (p0 + q) * ldb];
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (p0 + q < k) out[r + (int64_t)(p0 + q) * ldo] = acc[q];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ jobs,
+                                                    const TrForm* __restrict__ items, int first,
+                                                    const double* __restrict__ ws) {
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x;
+  const TrForm it = items[first + blockIdx.x];
+  const TrJob& J = jobs[it.job];
+  const double* hdr = ws + J.hdr;
+  const int w = (int)hdr[0], k = (int)hdr[1];
+  // the header is written by k_tr_qr for every job; refuse anything else
+  if (w < 0 || w > WMAX || k < 0 || k > w || k > J.cap) return;
+  if (it.leader && tid == 0) *J.out_rank = k;
+  if (w == 0 || k == 0) return;
+  const double* Uk = hdr + 8;
+  const double* P = Uk + WMAX * WMAX;
+  const int G = CH / tier_of(w);
+  if (it.side == 0) {
+    const TrSide S = J.side[0];
+    double* out = J.out[0];
+    const int ldo = J.ldout[0];
+    // path of tree indices from the chunk to the root
+    int idxs[16], bases[16];
+    int lvl = 0, idx = it.chunk, count = S.p0, base = 0;
+    idxs[0] = idx;
+    bases[0] = 0;
+    while (count > 1) {
+      base += count;
+      idx /= G;
+      count = (count + G - 1) / G;
+      ++lvl;
+      idxs[lvl] = idx;
+      bases[lvl] = base;
+    }
+    // Z = U_k (w x k, ld w), then Z <- Q_node[slot rows] Z down the path
+    double* Z = smem;
+    double* Zn = smem + w * k;
+    const bool fits = 2 * w * k <= WMAX * WMAX;
+    for (int e = tid; e < w * k; e += NT_MM) Z[e] = Uk[(e % w) + (e / w) * WMAX];
+    __syncthreads();
+    for (int l = lvl; l >= 1; --l) {
+      const int cslot = idxs[l - 1] - idxs[l] * G;
+      const double* Qn = ws + S.node0 + (int64_t)(bases[l] + idxs[l]) * TR_NODE + WMAX * WMAX + cslot * w;
+      if (fits) {
+        rows_times_small(Qn, CH, w, w, Z, w, k, Zn, w);
+        __syncthreads();
+        for (int e = tid; e < w * k; e += NT_MM) Z[e] = Zn[e];
+        __syncthreads();
+      } else {
+        // wide case: one column of Z at a time through registers
+        for (int p = 0; p < k; ++p) {
+          double zr = 0.0;
+          if (tid < w)
+            for (int c = 0; c < w; ++c) zr += Qn[tid + (int64_t)c * CH] * Z[c + p * w];
+          __syncthreads();
+          if (tid < w) Z[tid + p * w] = zr;
+          __syncthreads();
+        }
+      }
+    }
+    const int row0 = (int)((int64_t)it.chunk * S.m / S.p0);
+    const int h = (int)((int64_t)(it.chunk + 1) * S.m / S.p0) - row0;
+    const double* Qc = ws + S.node0 + (int64_t)it.chunk * TR_NODE + WMAX * WMAX;
+    rows_times_small(Qc, CH, h, w, Z, w, k, out + row0, ldo);
+  } else {
+    const int n0 = (int)hdr[3];
+    const Seg s0 = J.seg[1][0], s1 = J.seg[1][1];
+    double* out = J.out[1];
+    const int ldo = J.ldout[1];
+    double* In = smem;                 // rows x w, ld 64
+    double* Ps = smem + 64 * w;        // w x k, ld w
+    const bool fits = 64 * w + w * k <= WMAX * WMAX;
+    const int rows = it.rows;
+    for (int e = tid; e < rows * w; e += NT_MM) {
+      const int r = e % rows, cc = e / rows;
+      const int64_t gr = it.row0 + r;
+      In[r + cc * 64] = (cc < n0) ? s0.scale * s0.p[gr + (int64_t)cc * s0.ld]
+                                  : s1.scale * s1.p[gr + (int64_t)(cc - n0) * s1.ld];
+    }
+    if (fits)
+      for (int e = tid; e < w * k; e += NT_MM) Ps[e] = P[(e % w) + (e / w) * WMAX];
+    __syncthreads();
+    if (fits)
+      rows_times_small(In, 64, rows, w, Ps, w, k, out + it.row0, ldo);
+    else
+      rows_times_small(In, 64, rows, w, P, WMAX, k, out + it.row0, ldo);
+  }
+}
+
+// ------------------------------------------------------------------ one-block recompression
+// A recompression whose two factors have at most TRS_MAXCH chunks each (rows
+// split evenly, at most CH per chunk) in one launch, without the tree in
+// global memory or the forming kernel.  Width w <= 8: a TSQR inside one block.
+// Wavefront c < 4 factorises chunk c of L and wavefront 4 + c chunk c of R in
+// registers (wave_qr); wavefronts 4 and 5 factorise the stacked chunk R
+// factors; wavefront 4 runs the SVD of R2 R1^T (jacobi_wave) and applies the
+// stacked Q factor of L to [U_k; 0]; then wavefront c applies its chunk's Q to
+// its rows of that product (L' = Q1 U_k) and wavefront 4 + c forms its rows of
+// R (R1^T U_k).  Wider jobs run the chunk code of k_tr_qr in one block per
+// chunk and the block that ran the SVD forms both factors.
+
+// Load rows [r0, r0 + h) of the factor [seg0 | seg1] (n0 columns in seg0)
+// into a wavefront's tile: lane l holds rows r0 + l + 64 i, columns < WT (zero
+// beyond w and h).
+template <int WT>
+__device__ __forceinline__ void wave_load(double (&a)[4][WT], const Seg& s0, const Seg& s1, int n0, int r0,
+                                          int h, int w) {
+  const int lane = threadIdx.x & 63;
+  if (h <= 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < WT; ++c) a[i][c] = 0.0;
+    return;
+  }
+  // every load is issued (elements outside the tile read the factor's first
+  // element, which exists for w >= 1 and h >= 1) before any is used
+  const double* base = (n0 > 0) ? s0.p : s1.p;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t r = lane + 64 * i;
+    const int64_t gr = r0 + r;
+#pragma unroll
+    for (int c = 0; c < WT; ++c) {
+      const bool ok = r < h && c < w;
+      const double* src = (c < n0) ? s0.p + gr + (int64_t)c * s0.ld : s1.p + gr + (int64_t)(c - n0) * s1.ld;
+      a[i][c] = *(ok ? src : base);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = lane + 64 * i;
+#pragma unroll
+    for (int c = 0; c < WT; ++c) a[i][c] = (r < h && c < w) ? ((c < n0) ? s0.scale : s1.scale) * a[i][c] : 0.0;
+  }
+}
+
+// Householder QR of the h x w tile of one wavefront (w <= WT, h <= 256), the
+// reflector convention of reg_qr.  On exit R is on and above the diagonal, v
+// below it, tau[j] in registers (0 past min(h, w)).  The products with the
+// later columns are independent and run interleaved (columns past w are zero
+// and stay zero).
+template <int WT>
+__device__ __forceinline__ void wave_qr(double (&a)[4][WT], int h, int w, double (&tau)[WT]) {
+  const int lane = threadIdx.x & 63;
+  const int jmax = min(h, w);
+#pragma unroll
+  for (int j = 0; j < WT; ++j) {
+    tau[j] = 0.0;
+    if (j < jmax) {
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double x = (lane + 64 * i > j) ? a[i][j] : 0.0;
+        if (i & 1) s1 += x * x; else s0 += x * x;
+      }
+      const double ss = gsumt<64>(s0 + s1);
+      const double al = lane_read(a[0][j], j);
+      double tj, beta, scal;
+      house_scalars(al, ss, beta, tj, scal);
+      const double sc = (ss != 0.0) ? scal : 1.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = lane + 64 * i;
+        a[i][j] = (r > j) ? a[i][j] * sc : (r == j ? beta : a[i][j]);
+      }
+      tau[j] = tj;
+      if (tj != 0.0) {
+        double f[WT];
+#pragma unroll
+        for (int c = j + 1; c < WT; ++c) {
+          double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double v = (lane + 64 * i > j) ? a[i][j] : 0.0;
+            if (i & 1) d1 += v * a[i][c]; else d0 += v * a[i][c];
+          }
+          f[c] = tj * (gsumt<64>(d0 + d1) + lane_read(a[0][c], j));
+        }
+#pragma unroll
+        for (int c = j + 1; c < WT; ++c) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = lane + 64 * i;
+            const double v = (r > j) ? a[i][j] : (r == j ? 1.0 : 0.0);
+            a[i][c] -= f[c] * v;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Z <- H_0 H_1 ... H_{jmax-1} Z for the reflectors of wave_qr (columns of a)
+// on the wavefront's tile Z (columns < WT).
+template <int WT>
+__device__ __forceinline__ void wave_apply_q(const double (&a)[4][WT], const double (&tau)[WT], int jmax,
+                                             double (&z)[4][WT]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = WT - 1; j >= 0; --j) {
+    if (j < jmax && tau[j] != 0.0) {
+      double f[WT];
+#pragma unroll
+      for (int c = 0; c < WT; ++c) {
+        double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = lane + 64 * i;
+          const double v = (r > j) ? a[i][j] : (r == j ? 1.0 : 0.0);
+          if (i & 1) d1 += v * z[i][c]; else d0 += v * z[i][c];
+        }
+        f[c] = tau[j] * gsumt<64>(d0 + d1);
+      }
+#pragma unroll
+      for (int c = 0; c < WT; ++c) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = lane + 64 * i;
+          const double v = (r > j) ? a[i][j] : (r == j ? 1.0 : 0.0);
+          z[i][c] -= f[c] * v;
+        }
+      }
+    }
+  }
+}
+
+// One-sided Jacobi (rotation and threshold of jacobi_small) on the w <= WT
+// columns of X (WT x WT, ld WT, zero beyond w), rotations accumulated in V, by
+// one wavefront: lane (p, r) = (lane / WT, lane % WT) holds row r of column
+// pair p of the round-robin schedule and the pair's sums are WT-lane reductions.
+template <int WT>
+__device__ __forceinline__ void jacobi_wave(double* X, double* V, int w) {
+  const int lane = threadIdx.x & 63;
+  const int n = w + (w & 1);
+  if (n < 2) return;
+  const int P = n / 2;
+  const int p = lane / WT, r = lane % WT;
+  const double tol = (double)w * DBL_EPSILON;
+  const double tol2 = tol * tol;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    int rot = 0;
+    for (int rd = 0; rd < n - 1; ++rd) {
+      int i = 0, j = 0;
+      if (p == 0) {
+        i = rd;
+        j = n - 1;
+      } else {  // (rd + p) mod (n - 1) and (rd - p) mod (n - 1), p < n/2
+        i = rd + p;
+        if (i >= n - 1) i -= n - 1;
+        j = rd - p;
+        if (j < 0) j += n - 1;
+      }
+      if (i > j) {
+        const int t = i;
+        i = j;
+        j = t;
+      }
+      const bool live = p < P;
+      double xi = 0.0, xj = 0.0, vi = 0.0, vj = 0.0;
+      if (live) {
+        xi = X[r + i * WT];
+        xj = X[r + j * WT];
+        vi = V[r + i * WT];
+        vj = V[r + j * WT];
+      }
+      const double al = gsumt<WT>(xi * xi), be = gsumt<WT>(xj * xj), ga = gsumt<WT>(xi * xj);
+      double cs, sn;
+      if (live && j < w && jac_rot_fast(al, be, ga, tol2, cs, sn)) {
+        X[r + i * WT] = cs * xi - sn * xj;
+        X[r + j * WT] = sn * xi + cs * xj;
+        V[r + i * WT] = cs * vi - sn * vj;
+        V[r + j * WT] = sn * vi + cs * vj;
+        rot = 1;
+      }
+      // the next round reads columns that other lanes wrote
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (__ballot(rot) == 0) break;
+  }
+}
+
+// LDS layout of the narrow path (doubles): the stacked chunk R factors of
+// both sides (TRS_MAXCH*WT x WT, ld 32), the stacked product Q_top [U_k; 0]
+// (ld 32), R1, R2, X, V, U_k, P (WT x WT, ld WT), then ints.
+constexpr int TSM_S0 = 0, TSM_S1 = 256, TSM_Z = 512, TSM_R1 = 768, TSM_R2 = 832, TSM_X = 896, TSM_V = 960,
+              TSM_U = 1024, TSM_P = 1088, TSM_INT = 1152;
+constexpr int TSM_LD = 32;
+
+// chunk c of nc over m rows: [row0, row0 + h)
+__device__ __forceinline__ void tr_chunk_rows(int m, int nc, int c, int& row0, int& h) {
+  row0 = (int)((int64_t)c * m / nc);
+  h = (int)((int64_t)(c + 1) * m / nc) - row0;
+}
+
+template <int WT>
+__device__ __forceinline__ void tr_small_narrow(const TrJob& J, int w, int n0a, int n0b, double* sm) {
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const bool orth = (J.flags & TR_ORTH) != 0;
+  const int m0 = J.side[0].m, m1 = J.side[1].m;
+  const int nc0 = max(1, (m0 + CH - 1) / CH), nc1 = max(1, (m1 + CH - 1) / CH);
+  double* S0 = sm + TSM_S0;
+  double* S1 = sm + TSM_S1;
+  double* Zt = sm + TSM_Z;
+  double* R1 = sm + TSM_R1;
+  double* R2 = sm + TSM_R2;
+  double* X = sm + TSM_X;
+  double* V = sm + TSM_V;
+  double* Uk = sm + TSM_U;
+  double* P = sm + TSM_P;
+  int* perm = (int*)(sm + TSM_INT);
+  const int side = wv >> 2, c = wv & 3;  // this wavefront's chunk
+  int row0 = 0, h = 0;
+  if (side == 0 && c < nc0) tr_chunk_rows(m0, nc0, c, row0, h);
+  if (side == 1 && c < nc1) tr_chunk_rows(m1, nc1, c, row0, h);
+  double a[4][WT];  // the chunk's tile; wavefronts 4, 5 then the stacked R factors
+  double tau[WT];
+#pragma unroll
+  for (int j = 0; j < WT; ++j) tau[j] = 0.0;
+  // chunk QRs; their R factors stacked in LDS
+  if (side == 0 ? c < nc0 : (!orth && c < nc1)) {
+    if (side == 0)
+      wave_load<WT>(a, J.seg[0][0], J.seg[0][1], n0a, row0, h, w);
+    else
+      wave_load<WT>(a, J.seg[1][0], J.seg[1][1], n0b, row0, h, w);
+    wave_qr<WT>(a, h, w, tau);
+    double* S = side == 0 ? S0 : S1;
+    if (lane < WT) {
+#pragma unroll
+      for (int q = 0; q < WT; ++q) S[c * WT + lane + q * TSM_LD] = (lane <= q) ? a[0][q] : 0.0;
+    }
+  }
+  __syncthreads();
+  // R1 (wavefront 4) and R2 (wavefront 5): QR of the stacked chunk factors
+  // (their own chunk's reflectors are no longer needed)
+  const int ncs = (wv == 4) ? nc0 : nc1;
+  if (wv == 4 || (wv == 5 && !orth)) {
+    const double* S = (wv == 4) ? S0 : S1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < WT; ++q) a[i][q] = (i == 0 && lane < ncs * WT) ? S[lane + q * TSM_LD] : 0.0;
+#pragma unroll
+    for (int j = 0; j < WT; ++j) tau[j] = 0.0;
+    if (ncs > 1) wave_qr<WT>(a, ncs * WT, w, tau);
+    double* R = (wv == 4) ? R1 : R2;
+    if (lane < WT) {
+#pragma unroll
+      for (int q = 0; q < WT; ++q) R[lane + q * WT] = (lane <= q) ? a[0][q] : 0.0;
+    }
+  }
+  __syncthreads();
+  int k = 0;
+  if (wv == 4) {
+    const double thr = *J.tau;
+    if (orth) {
+      k = min(m0, w);
+      if (lane < WT * WT) {
+        const int rr = lane % WT, pp = lane / WT;
+        Uk[lane] = (rr == pp && pp < k) ? 1.0 : 0.0;
+        P[lane] = (pp < k) ? R1[pp + rr * WT] : 0.0;  // P = R1^T [I_k; 0]
+      }
+    } else {
+      // X = R2 R1^T (upper triangular factors, zero beyond w), V = I
+      if (lane < WT * WT) {
+        const int ii = lane % WT, jj = lane / WT;
+        double s = 0.0;
+        for (int l = max(ii, jj); l < w; ++l) s += R2[ii + l * WT] * R1[jj + l * WT];
+        X[lane] = s;
+        V[lane] = (ii == jj && ii < w) ? 1.0 : 0.0;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      jacobi_wave<WT>(X, V, w);
+      // singular values (column norms), their descending order, and k (sig > tau)
+      double sg = -1.0;
+      if (lane < w) {
+        double s = 0.0;
+        for (int rr = 0; rr < WT; ++rr) s += X[rr + lane * WT] * X[rr + lane * WT];
+        sg = sqrt(s);
+      }
+      int pos = 0;
+#pragma unroll
+      for (int jj = 0; jj < WT; ++jj) {
+        const double sj = lane_read(sg, jj);
+        pos += (jj < w && (sj > sg || (sj == sg && jj < lane))) ? 1 : 0;
+      }
+      if (lane < w) perm[pos] = lane;
+      k = __popcll(__ballot(lane < w && sg > thr));
+      if (k > J.cap) {
+        if (lane == 0) atomicOr(J.err, ERR_CAPACITY);
+        k = J.cap;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // U_k = V[:, perm[:k]], P = R1^T U_k
+      if (lane < WT * WT) {
+        const int rr = lane % WT, pp = lane / WT;
+        Uk[lane] = (pp < k && rr < w) ? V[rr + perm[pp] * WT] : 0.0;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (lane < WT * WT) {
+        const int rr = lane % WT, pp = lane / WT;
+        double s = 0.0;
+        for (int l = 0; l <= rr; ++l) s += R1[l + rr * WT] * Uk[l + pp * WT];
+        P[lane] = (pp < k && rr < w) ? s : 0.0;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // Zt = Q_top [U_k; 0] (stacked rows; Q_top = I for one chunk)
+    double z[4][WT];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < WT; ++q) z[i][q] = (i == 0 && lane < WT) ? Uk[lane + q * WT] : 0.0;
+    if (nc0 > 1) wave_apply_q<WT>(a, tau, w, z);
+    if (lane < nc0 * WT) {
+#pragma unroll
+      for (int q = 0; q < WT; ++q) Zt[lane + q * TSM_LD] = z[0][q];
+    }
+    if (lane == 0) {
+      *J.out_rank = k;
+      perm[WT] = k;  // for the other wavefronts
+      add_flops(J.flops, J.fc, orth ? tr_flops_orth(m0, m1, w) : tr_flops_full(m0, m1, w, k));
+    }
+  }
+  __syncthreads();
+  k = perm[WT];
+  if (side == 0 && c < nc0) {
+    // rows of L' = Q_c [Zt rows of chunk c; 0] (rows past min(h, w) are zero)
+    double z[4][WT];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = lane + 64 * i;
+#pragma unroll
+      for (int q = 0; q < WT; ++q) z[i][q] = (i == 0 && r < WT && r < h) ? Zt[c * WT + r + q * TSM_LD] : 0.0;
+    }
+    wave_apply_q<WT>(a, tau, min(h, w), z);
+    double* out = J.out[0];
+    const int ld = J.ldout[0];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = lane + 64 * i;
+#pragma unroll
+      for (int q = 0; q < WT; ++q)
+        if (r < h && q < k) out[row0 + r + (int64_t)q * ld] = z[i][q];
+    }
+  } else if (side == 1 && c < nc1) {
+    // rows of R' = R P (R read again: it is cached)
+    double b[4][WT];
+    wave_load<WT>(b, J.seg[1][0], J.seg[1][1], n0b, row0, h, w);
+    double* out = J.out[1];
+    const int ld = J.ldout[1];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = lane + 64 * i;
+#pragma unroll
+      for (int q = 0; q < WT; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < WT; ++l) s += b[i][l] * P[l + q * WT];
+        if (r < h && q < k) out[row0 + r + (int64_t)q * ld] = s;
+      }
+    }
+  }
+}
+
+// Forming step inside the block that ran the SVD (k_tr_form for a tree of
+// at most one combine level): L' = Q_chunk (Q_root rows of the chunk) U_k for
+// each chunk of side 0, and R' = R P, from the header tr_svd wrote.
+__device__ __forceinline__ void tr_small_form(const TrJob& J, const double* ws, double* sm) {
+  const int tid = threadIdx.x;
+  const double* hdr = ws + J.hdr;
+  const int w = (int)hdr[0], k = (int)hdr[1];
+  if (w < 0 || w > WMAX || k < 0 || k > w || k > J.cap) return;
+  if (tid == 0) *J.out_rank = k;
+  if (w == 0 || k == 0) return;
+  const double* Uk = hdr + 8;
+  const double* P = Uk + WMAX * WMAX;
+  const TrSide S = J.side[0];
+  double* Z = sm;           // U_k (w x k, ld w)
+  double* Zc = sm + w * k;  // Q_root rows of a chunk times U_k
+  for (int e = tid; e < w * k; e += NT_TR) Z[e] = Uk[(e % w) + (e / w) * WMAX];
+  __syncthreads();
+  for (int c = 0; c < S.p0; ++c) {
+    int row0, h;
+    tr_chunk_rows(S.m, S.p0, c, row0, h);
+    const double* Zuse = Z;
+    if (S.p0 > 1) {
+      const double* Qn = ws + S.node0 + (int64_t)S.p0 * TR_NODE + WMAX * WMAX + c * w;
+      rows_times_small<NT_TR>(Qn, CH, w, w, Z, w, k, Zc, w);
+      __syncthreads();
+      Zuse = Zc;
+    }
+    const double* Qc = ws + S.node0 + (int64_t)c * TR_NODE + WMAX * WMAX;
+    rows_times_small<NT_TR>(Qc, CH, h, w, Zuse, w, k, J.out[0] + row0, J.ldout[0]);
+    __syncthreads();
+  }
+  // R' = R P.  R' may overwrite R in place (row r of R' over row r of R), so a
+  // thread computes all k outputs of its row before it writes them: with
+  // k <= 16 it reads its row straight from the segments (coalesced over the
+  // threads), otherwise 64-row pieces of R are staged in LDS first.
+  const int n0 = (int)hdr[3];
+  const Seg s0 = J.seg[1][0], s1 = J.seg[1][1];
+  if (k <= 16) {
+    double* Ps = sm;  // w x k, ld w
+    for (int e = tid; e < w * k; e += NT_TR) Ps[e] = P[(e % w) + (e / w) * WMAX];
+    __syncthreads();
+    for (int r = tid; r < J.side[1].m; r += NT_TR) {
+      double acc[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+      for (int c = 0; c < w; ++c) {
+        const double x = (c < n0) ? s0.scale * s0.p[r + (int64_t)c * s0.ld]
+                                  : s1.scale * s1.p[r + (int64_t)(c - n0) * s1.ld];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (q < k) acc[q] += x * Ps[c + q * w];
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (q < k) J.out[1][r + (int64_t)q * J.ldout[1]] = acc[q];
+    }
+    return;
+  }
+  double* In = sm;           // rows x w, ld 64
+  double* Ps = sm + 64 * w;  // w x k, ld w
+  const bool fits = 64 * w + w * k <= WMAX * WMAX;
+  if (fits)
+    for (int e = tid; e < w * k; e += NT_TR) Ps[e] = P[(e % w) + (e / w) * WMAX];
+  for (int r0 = 0; r0 < J.side[1].m; r0 += 64) {
+    const int rows = min(64, J.side[1].m - r0);
+    for (int e = tid; e < rows * w; e += NT_TR) {
+      const int r = e % rows, cc = e / rows;
+      const int64_t gr = r0 + r;
+      In[r + cc * 64] = (cc < n0) ? s0.scale * s0.p[gr + (int64_t)cc * s0.ld]
+                                  : s1.scale * s1.p[gr + (int64_t)(cc - n0) * s1.ld];
+    }
+    __syncthreads();
+    if (fits)
+      rows_times_small<NT_TR>(In, 64, rows, w, Ps, w, k, J.out[1] + r0, J.ldout[1]);
+    else
+      rows_times_small<NT_TR>(In, 64, rows, w, P, WMAX, k, J.out[1] + r0, J.ldout[1]);
+    __syncthreads();
+  }
+}
+
+// Wider jobs: the chunk code of k_tr_qr, one block per chunk (the chunks
+// and sides join through the job's counters); the block that ran the SVD
+// then forms both factors.
+template <int WTOP>
+__device__ __forceinline__ void tr_small_wide(const TrJob& J, int side, int chunk, int w, int n0a, int n0b,
+                                              double* ws, int* counters, double* smem) {
+  const int t = tier_of(w);
+  bool last = false;
+  if (t == 16) {
+    if constexpr (WTOP >= 16) last = tr_chunk<16>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+  } else if (t == 32) {
+    if constexpr (WTOP >= 32) last = tr_chunk<32>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+  } else if (t == 64) {
+    if constexpr (WTOP >= 64) last = tr_chunk<64>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+  } else {
+    if constexpr (WTOP >= 128)
+      last = tr_chunk<128>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+  }
+  if (!last) return;
+  __threadfence_block();
+  __syncthreads();
+  tr_small_form(J, ws, smem);
+}
+
+// One block per chunk of each side (the items of k_tr_qr).  Width <= 8: the
+// block of side 0, chunk 0 does the whole job and the others return.  The
+// host sends a job here only when each side has at most TRS_MAXCH chunks and
+// at most CH / WTOP of them (so that a wide job's tree has one combine level).
+template <int WTOP>
+__global__ void __launch_bounds__(NT_TR) k_tr_small(const TrJob* __restrict__ jobs,
+                                                     const TrChunk* __restrict__ items, int first,
+                                                     double* ws, int* counters) {
+  extern __shared__ double smem[];
+  const TrChunk it = items[first + blockIdx.x];
+  const TrJob& J = jobs[it.job];
+  const int n0a = seg_n(J.seg[0][0]);
+  const int w = n0a + seg_n(J.seg[0][1]);
+  const int n0b = seg_n(J.seg[1][0]);
+  const bool lead = it.side == 0 && it.chunk == 0;
+  if (w == 0 || w > WTOP) {
+    if (lead && threadIdx.x == 0) {
+      *J.out_rank = 0;
+      if (w > WTOP) atomicOr(J.err, ERR_WIDTH);
+    }
+    return;
+  }
+  if (w <= 8) {
+    if (!lead) return;
+    if (max(J.side[0].m, J.side[1].m) > TRS_MAXCH * CH) {  // not sent here by the host
+      if (threadIdx.x == 0) atomicOr(J.err, ERR_WIDTH);
+      return;
+    }
+    if (w <= 4)
+      tr_small_narrow<4>(J, w, n0a, n0b, smem);
+    else
+      tr_small_narrow<8>(J, w, n0a, n0b, smem);
+    return;
+  }
+  tr_small_wide<WTOP>(J, it.side, it.chunk, w, n0a, n0b, ws, counters, smem);
+}
+}  // namespace hq
+
+namespace hq {
+template __global__ void k_tr_qr<16>(const TrJob*, const TrChunk*, int, double*, int*);
+template __global__ void k_tr_qr<32>(const TrJob*, const TrChunk*, int, double*, int*);
+template __global__ void k_tr_qr<64>(const TrJob*, const TrChunk*, int, double*, int*);
+template __global__ void k_tr_qr<128>(const TrJob*, const TrChunk*, int, double*, int*);
+template __global__ void k_tr_small<16>(const TrJob*, const TrChunk*, int, double*, int*);
+template __global__ void k_tr_small<32>(const TrJob*, const TrChunk*, int, double*, int*);
+template __global__ void k_tr_small<64>(const TrJob*, const TrChunk*, int, double*, int*);
+template __global__ void k_tr_small<128>(const TrJob*, const TrChunk*, int, double*, int*);
+}  // namespace hq
