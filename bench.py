@@ -31,14 +31,26 @@ KERNEL = {"leaf_panel": "k_leaf_step", "leaf_update": "k_leaf_step", "tr_qr": "k
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_leaf_step_expkernel_n65536_traffic.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1809_10585_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1809_10585_amd", "csrc")
+# translation unit of each kernel family (plus the headers every unit includes)
+KERNEL_UNIT = {"k_leaf": "k_leaf.hip", "k_tr": "k_tr.hip", "k_mm": "k_mm.hip", "k_gemm": "k_mm.hip"}
+SHARED_HEADERS = ["common.h", "kernels.h", "kernels_common.h"]
+
+
+def kernel_source_sha(kernel):
+    """sha256 over the translation unit that holds `kernel` and the shared headers."""
+    import hashlib
+    unit = next((u for p, u in KERNEL_UNIT.items() if kernel.startswith(p)), "k_vec.hip")
+    h = hashlib.sha256()
+    for f in [unit] + SHARED_HEADERS:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel):
     """HBM bytes per dispatch of `kernel` from the committed rocprofv3 PMC summary
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None if there is none
     for this kernel or the kernel source changed since it was taken."""
-    import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -46,8 +58,7 @@ def measured_traffic(kernel):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if kv.get("kernel") != kernel or kv.get("kernels_sha256") != src:
+    if kv.get("kernel") != kernel or kv.get("kernels_sha256") != kernel_source_sha(kernel):
         return None
     return float(kv["bytes_per_launch"])
 

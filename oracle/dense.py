@@ -71,7 +71,7 @@ def house_qr(H: np.ndarray, cnt: Counter | None = None):
 
 
 def trunc(L: np.ndarray, R: np.ndarray, tau: float, cnt: Counter | None = None,
-          site: str = ""):
+          site: str = "", key=None):
     """Recompression T_tau of a low-rank product L @ R (Sec. 2.1.1,
     "Recompression"): economy QRs L = Q1 R1 and R^T = Q2 R2, SVD
     R1 R2^T = U S V^T, keep the k singular values with sigma_i > tau (the
@@ -79,14 +79,15 @@ def trunc(L: np.ndarray, R: np.ndarray, tau: float, cnt: Counter | None = None,
     columns) and R' = S_k V_k^T Q2^T.
 
     Paper orientation: L is m_L x w, R is w x m_R.  A width-0 input returns
-    empty factors.  `cnt` receives the flop count and a rank-log entry.
+    empty factors.  `cnt` receives the flop count and a rank-log entry (with
+    `key`, the recompression's name in the log).
     """
     mL, w = L.shape
     mR = R.shape[1]
     assert R.shape[0] == w
     if w == 0:
         if cnt is not None:
-            cnt.log_trunc(site, mL, mR, 0, 0, tau, np.zeros(0))
+            cnt.log_trunc(site, mL, mR, 0, 0, tau, np.zeros(0), key)
         return np.zeros((mL, 0)), np.zeros((0, mR))
     Q1, R1 = np.linalg.qr(L)            # LAPACK Householder QR (dgeqrf/dorgqr)
     Q2, R2 = np.linalg.qr(R.T)
@@ -96,7 +97,7 @@ def trunc(L: np.ndarray, R: np.ndarray, tau: float, cnt: Counter | None = None,
     Rk = (s[:k, None] * Vt[:k]) @ Q2.T
     if cnt is not None:
         cnt.add("trunc", trunc_flops(mL, mR, w, k))
-        cnt.log_trunc(site, mL, mR, w, k, tau, s)
+        cnt.log_trunc(site, mL, mR, w, k, tau, s, key)
     return Lk, Rk
 
 
@@ -115,16 +116,17 @@ def trunc_flops(mL: int, mR: int, w: int, k: int) -> float:
             + 4.0 * mL * p1 * k + 2.0 * mR * w * k)
 
 
-def chunked_trunc(terms, tau: float, cnt: Counter | None = None, site: str = ""):
+def chunked_trunc(terms, tau: float, cnt: Counter | None = None, site: str = "", key=()):
     """Sum of low-rank terms with rank control (Sec. 4.2, cost of lines
     compute_Stilde/compute_S): the terms are added one at a time and every
     addition is followed immediately by T_tau, so the width of each
     recompression stays at (current rank + rank of one term).  A single term
     is recompressed once.  terms: list of (L_t, R_t) with L_t @ R_t the term.
+    The i-th recompression is logged with key `key + (i,)`.
     """
     L, R = terms[0]
     if len(terms) == 1:
-        return trunc(L, R, tau, cnt, site)
-    for Lt, Rt in terms[1:]:
-        L, R = trunc(np.hstack([L, Lt]), np.vstack([R, Rt]), tau, cnt, site)
+        return trunc(L, R, tau, cnt, site, tuple(key) + (0,))
+    for i, (Lt, Rt) in enumerate(terms[1:]):
+        L, R = trunc(np.hstack([L, Lt]), np.vstack([R, Rt]), tau, cnt, site, tuple(key) + (i,))
     return L, R

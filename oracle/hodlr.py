@@ -144,11 +144,13 @@ def hmatT(M: HNode, X: np.ndarray, cnt: Counter | None = None, tri: bool = False
 
 
 def lowrank_update(M: HNode, U: np.ndarray, Vr: np.ndarray, tau: float,
-                   cnt: Counter | None = None) -> HNode:
+                   cnt: Counter | None = None, key=()) -> HNode:
     """M -_H U Vr (Table 1, matrix low-rank update, with the sign of Alg. 2
     line compute_update): every off-diagonal block b with rows I and columns J
     becomes T_tau([b_L | U(I,:)] [b_R; -Vr(:,J)]) and every leaf becomes
-    D - U(I,:) Vr(:,I).  U is m x r, Vr is r x m.  Returns a new tree."""
+    D - U(I,:) Vr(:,I).  U is m x r, Vr is r x m.  Returns a new tree.  Each
+    recompression is logged with key `key + (first row, first column)` of its
+    block."""
     r = U.shape[1]
 
     def rec(N: HNode, off: int) -> HNode:
@@ -162,9 +164,9 @@ def lowrank_update(M: HNode, U: np.ndarray, Vr: np.ndarray, tau: float,
         c1, c2 = rec(N.c1, off), rec(N.c2, off)
         A12 = N.A12
         L12, R12 = trunc(np.hstack([A12.L, U[a:mid]]), np.vstack([A12.R, -Vr[:, mid:b]]), tau,
-                         cnt, "update")
+                         cnt, "update", tuple(key) + (N.lo, N.c1.hi))
         L21, R21 = trunc(np.hstack([N.A21.L, U[mid:b]]), np.vstack([N.A21.R, -Vr[:, a:mid]]), tau,
-                         cnt, "update")
+                         cnt, "update", tuple(key) + (N.c1.hi, N.lo))
         return HNode(N.lo, N.hi, c1=c1, c2=c2, A12=LowRank(L12, R12, True),
                      A21=LowRank(L21, R21, True))
 

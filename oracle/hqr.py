@@ -112,17 +112,17 @@ def _node(At: HNode, B: LowRank | None, C: list, ctx: _Ctx) -> _Out:
              (YtB21.T, hmatT(A22, BL, cnt).T)]
     for Yg1, Cg2 in zip(Y1, G2):
         terms.append((Yg1.T, Cg2))
-    SL, SR = chunked_trunc(terms, ctx.tauA, cnt, "S")
+    SL, SR = chunked_trunc(terms, ctx.tauA, cnt, "S", ("S", At.lo, At.hi))
 
     # compute_S: S = T1^T S~  (S = SL @ SR)
     SL = hmatT(T1, SL, cnt, tri=True)
 
     # compute_update, eq. (update2ndblockH)
     L12, R12 = trunc(np.hstack([A12.L, -hmat(YA11, SL, cnt, tri=True)]),
-                     np.vstack([A12.R, SR]), ctx.tauA, cnt, "A12")
+                     np.vstack([A12.R, SR]), ctx.tauA, cnt, "A12", ("A12", At.lo, At.hi))
     W = YtB21 @ SL                                   # Y_A21 S = BL (W SR)
     cnt.add("dense", 2.0 * W.shape[0] * YtB21.shape[1] * W.shape[1])
-    A22h = lowrank_update(A22, BL, W @ SR, ctx.tauA, cnt)
+    A22h = lowrank_update(A22, BL, W @ SR, ctx.tauA, cnt, ("update", At.lo, At.hi))
     cnt.add("dense", 2.0 * W.shape[0] * W.shape[1] * SR.shape[1])
     G2h = []
     for Yg1, Cg2 in zip(Y1, G2):
@@ -139,7 +139,7 @@ def _node(At: HNode, B: LowRank | None, C: list, ctx: _Ctx) -> _Out:
     tterms = [(YtB21.T, hmatT(YA22, BL, cnt, tri=True).T)]
     for Yg1, Yg2 in zip(Y1, Y2):
         tterms.append((Yg1.T, Yg2))
-    TL, TR = chunked_trunc(tterms, ctx.tauT, cnt, "T")
+    TL, TR = chunked_trunc(tterms, ctx.tauT, cnt, "T", ("T", At.lo, At.hi))
 
     # compute_T2: T12 = -T1 T~12 T2 = (-T1 TL)(TR T2)
     T12 = LowRank(-hmat(T1, TL, cnt, tri=True), hmatT(T2, TR.T, cnt, tri=True).T)
