@@ -18,15 +18,26 @@
  *    to right), the upper block of a node before its lower block.
  *  - "device" pointers are HIP device memory on the current device, "host"
  *    pointers are ordinary host memory.  The caller owns every array it passes;
- *    the library owns the handles and all device memory behind them.
+ *    the library owns the handles and all device memory behind them.  Device
+ *    memory comes from the allocator installed with hodlr_set_allocator, else
+ *    from hipMalloc (memory held by a handle) and hipMallocAsync (temporaries
+ *    of one call).
  *  - Every call returns a hodlr_status.  Argument errors are detected on the
  *    host before any work is queued; hodlr_last_error() then describes the
  *    failure (thread-local string).  No call aborts or throws.
  *  - Work is queued on the given stream (0 = the null stream).  hodlr_build
  *    and hodlr_qr synchronise that stream before returning (they read back a
- *    few scalars); hodlr_apply_q, hodlr_solve and hodlr_matmul are
- *    asynchronous.
- *  - A handle may be used from one thread at a time.
+ *    few scalars).  hodlr_apply_q, hodlr_solve, hodlr_matmul and
+ *    hodlr_qr_matmul are stream-ordered and asynchronous: they replay launch
+ *    sequences the handle cached when it was made (a product's on its first
+ *    call), take their temporaries from the allocator on the call's stream,
+ *    and return without waiting for the device.
+ *  - Threads: a finished hodlr_t or hodlr_qr_t is not modified by the calls
+ *    that read it, so apply_q, solve and the products may run on one handle
+ *    from several threads and streams at once (each call has its own
+ *    temporaries).  A handle must outlive the work queued with it: release it
+ *    only after that work is done.  hodlr_qr_time / hodlr_qr_profile and the
+ *    batched calls create private handles.
  */
 #ifndef HODLR_H
 #define HODLR_H
@@ -52,6 +63,19 @@ typedef enum {
   HODLR_EDEVICE = -5,    /* a HIP call failed; hodlr_last_error() has its text     */
   HODLR_ENOTBUILT = -6   /* the library was loaded without device code            */
 } hodlr_status;
+
+/*
+ * hodlr_set_allocator - route the library's device memory through the caller's
+ * allocator (for example a framework's caching allocator).  alloc(bytes,
+ * stream, ctx) returns device memory usable in stream order on `stream` (NULL
+ * on failure, reported as HODLR_ENOMEM); release(ptr, stream, ctx) gives it
+ * back, called once the work using it has been queued on `stream`.  Both NULL:
+ * back to hipMalloc / hipMallocAsync.  Handles keep the allocator they were
+ * made with; calls made later use the one installed at the time of the call.
+ * Returns HODLR_EINVAL if exactly one of alloc, release is NULL.
+ */
+hodlr_status hodlr_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
+                                 void (*release)(void *ptr, void *stream, void *ctx), void *ctx);
 
 /* hodlr_qr / hodlr_qr_time flags.  By default the launches are issued directly,
  * with the T-factor steps of every node (T~12 and T12, Alg. hQR) on a second
@@ -134,8 +158,10 @@ hodlr_status hodlr_qr_batched_time(const hodlr_t *const *A, int32_t count, doubl
 
 /*
  * hodlr_apply_q - X <- Q X (trans = 0) or X <- Q^T X (trans = 1), with
- * Q = I - Y T Y^T (eq. compactwy).  X: device, n x nrhs, leading dimension
- * ldx >= n.  Asynchronous.
+ * Q = I - Y T Y^T (eq. compactwy): W = Y^T X, W <- op(T) W, X <- X - Y W, in
+ * blocks of at most 64 columns.  X: device, n x nrhs, leading dimension
+ * ldx >= n (< 2^31).  Stream-ordered and asynchronous; temporaries 2 n
+ * min(nrhs, 64) doubles plus the products' projections, from the allocator.
  */
 hodlr_status hodlr_apply_q(const hodlr_qr_t *F, int32_t trans, int64_t nrhs, double *X,
                            int64_t ldx, hodlr_stream_t stream);
@@ -143,7 +169,9 @@ hodlr_status hodlr_apply_q(const hodlr_qr_t *F, int32_t trans, int64_t nrhs, dou
 /*
  * hodlr_solve - B <- R^{-1} Q^T B, i.e. the solution of A x = b for every
  * column of B (device, n x nrhs, ldb >= n).  Back substitution with the upper
- * triangular HODLR R runs leaf by leaf from the last one.  Asynchronous.
+ * triangular HODLR R runs leaf by leaf from the last one
+ * (x2 = R22^{-1} c2, c1 <- c1 - R12 x2, x1 = R11^{-1} c1).  Stream-ordered and
+ * asynchronous.
  */
 hodlr_status hodlr_solve(const hodlr_qr_t *F, int64_t nrhs, double *B, int64_t ldb,
                          hodlr_stream_t stream);
@@ -151,7 +179,9 @@ hodlr_status hodlr_solve(const hodlr_qr_t *F, int64_t nrhs, double *B, int64_t l
 /*
  * hodlr_matmul - Z <- op(A) X for the HODLR matrix A (HODLR matrix times a
  * dense block, Table 1's matrix-vector product applied to nrhs columns).
- * trans = 0: op(A) = A, 1: A^T.  X, Z: device, n x nrhs, distinct.  Asynchronous.
+ * trans = 0: op(A) = A, 1: A^T.  X, Z: device, n x nrhs, distinct.  A may be
+ * a factor view from hodlr_qr_factor.  Stream-ordered and asynchronous (the
+ * first call per (A, trans) builds and uploads its launch sequence).
  */
 hodlr_status hodlr_matmul(const hodlr_t *A, int32_t trans, int64_t nrhs, const double *X,
                           int64_t ldx, double *Z, int64_t ldz, hodlr_stream_t stream);
@@ -179,10 +209,13 @@ typedef struct {
   int32_t max_rank_y, max_rank_t, max_rank_r; /* largest off-diagonal ranks          */
   double anorm, tau_a, tau_t;                 /* thresholds actually used             */
   double flops;        /* algorithmic FP64 flops of the factorisation (counted on the
-                          device from the realised sizes and ranks)                  */
+                          device from the realised sizes and ranks, Table 1 and the
+                          cost terms of Sec. 4.1), the |A|_2 estimate excluded       */
   int64_t n_truncations; /* recompressions performed                                 */
   int64_t n_launches;    /* kernel launches in one factorisation                     */
   int64_t device_bytes;  /* device memory held by the factors                        */
+  double norm_flops;     /* flops of the |A|_2 estimate (0 when anorm was given); not
+                            part of `flops`                                           */
 } hodlr_qr_info_t;
 
 hodlr_status hodlr_qr_info(const hodlr_qr_t *F, hodlr_qr_info_t *info);
@@ -227,7 +260,55 @@ hodlr_status hodlr_qr_profile(const hodlr_t *A, double eps, double anorm, int32_
 const char *hodlr_op_name(int32_t type);
 int32_t hodlr_op_count(void);
 
-void hodlr_free(hodlr_t *A);        /* NULL-safe */
+/*
+ * hodlr_qr_factor - borrowed view of one factor of F as a HODLR matrix:
+ * which = 'Y' (unit lower triangular leaves, lower blocks), 'T' or 'R' (upper
+ * triangular leaves, upper blocks).  The view stays valid while F lives; it
+ * can be passed to hodlr_matmul and hodlr_export; hodlr_free ignores it, and
+ * hodlr_qr / hodlr_qr_batched reject it (HODLR_EINVAL).
+ */
+hodlr_status hodlr_qr_factor(const hodlr_qr_t *F, char which, const hodlr_t **view);
+
+/*
+ * hodlr_check - wait for the work queued on `stream` and report the conditions
+ * the device flagged for F: HODLR_ECAPACITY if a rank outgrew rank_cap, a
+ * recompression outgrew 128 columns or a stacked leaf column outgrew 1024 rows;
+ * HODLR_OK otherwise.
+ */
+hodlr_status hodlr_check(const hodlr_qr_t *F, hodlr_stream_t stream);
+
+/*
+ * hodlr_qr_ranklog - the decision of every recompression T_tau (Sec. 2.1.1) of
+ * the factorisation, one record of 7 int32 each: (site, a, b, c, d, w, k) with
+ * w the input width and k the kept rank (#{sigma_i > tau}).  Sites and keys:
+ *   0 left-orthogonalisation of a lower block (a, b = its first row, column);
+ *   1 i-th recompression of the sum S~ at the node covering [a, b) (c = i);
+ *   2 the node's new upper block of R;
+ *   3 the -_H update at node [a, b) of the block whose first row, column are c, d;
+ *   4 i-th recompression of the sum T~12 at node [a, b) (c = i).
+ * recs: host, room for `cap` records, or NULL to query *count only.  Synchronous.
+ */
+hodlr_status hodlr_qr_ranklog(const hodlr_qr_t *F, int32_t *recs, int64_t cap, int64_t *count);
+
+/*
+ * hodlr_plan_check - build the factorisation schedule of `count` matrices on
+ * the partition (n, levels, leaf_off) with rank capacity rank_cap without a
+ * device (every address virtual), and test it for hazards: every pair of
+ * launches the two streams may run at the same time (lane order plus the
+ * schedule's events) and every pair of jobs inside one launch is checked for a
+ * write that overlaps the other's reads or writes (byte ranges from the jobs'
+ * descriptors, ranks at capacity).  flags: HODLR_QR_ONE_STREAM checks the serial
+ * order, HODLR_CHECK_ESTIMATE includes the |A|_2 estimate, HODLR_CHECK_PLANT
+ * plants a known hazard (self test).  stats (host, 5): launches, launches of the
+ * second stream, launch pairs checked, conflicting pairs, conflicting job pairs
+ * within launches.  msg (host, msglen bytes, may be NULL): the first conflict.
+ */
+#define HODLR_CHECK_ESTIMATE 0x100u
+#define HODLR_CHECK_PLANT 0x200u
+hodlr_status hodlr_plan_check(int64_t n, int32_t levels, const int64_t *leaf_off, int32_t rank_cap,
+                              int32_t count, uint32_t flags, int64_t *stats, char *msg, int64_t msglen);
+
+void hodlr_free(hodlr_t *A);        /* NULL-safe; ignores factor views */
 void hodlr_qr_free(hodlr_qr_t *F);  /* NULL-safe */
 const char *hodlr_last_error(void); /* thread-local; empty string if none */
 const char *hodlr_version(void);

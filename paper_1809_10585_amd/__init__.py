@@ -13,17 +13,67 @@ import ctypes as C
 
 import numpy as np
 
+import os
+
 from . import _lib
-from ._lib import HODLR_QR_GRAPH, HODLR_QR_ONE_STREAM, HodlrError, QRInfo
+from ._lib import (HODLR_CHECK_ESTIMATE, HODLR_CHECK_PLANT, HODLR_QR_GRAPH, HODLR_QR_ONE_STREAM,
+                   HodlrError, QRInfo)
 
 __all__ = [
     "hodlr_build", "hodlr_qr", "hodlr_apply_q", "hodlr_solve", "hodlr_matmul", "hodlr_qr_matmul",
-    "hodlr_norm2_est", "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time",
-    "hodlr_qr_profile", "hodlr_qr_batched", "hodlr_qr_batched_time", "HodlrMatrix", "QRFactors",
-    "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "load",
+    "hodlr_qr_factor", "hodlr_check", "hodlr_qr_ranklog", "hodlr_plan_check", "hodlr_norm2_est",
+    "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time", "hodlr_qr_profile",
+    "hodlr_qr_batched", "hodlr_qr_batched_time", "use_torch_allocator", "HodlrMatrix", "QRFactors",
+    "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "HODLR_CHECK_ESTIMATE",
+    "HODLR_CHECK_PLANT", "load",
 ]
 
-load = _lib.load
+_alloc_hook = None  # the ctypes callbacks installed in the library (kept alive here)
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route the library's device memory through PyTorch's caching allocator
+    (hodlr_set_allocator): handles and per-call temporaries are then blocks of
+    torch's pool on the stream of the call.  Installed by the first call that
+    touches the device unless HODLR_TORCH_ALLOCATOR=0; enable=False restores
+    hipMalloc / hipMallocAsync."""
+    global _alloc_hook
+    lib = _lib.load()
+    if not enable:
+        _lib.check(lib.hodlr_set_allocator(_lib.ALLOC_FN(), _lib.RELEASE_FN(), None))
+        _alloc_hook = False
+        return
+    import torch
+
+    raw_alloc = torch._C._cuda_cudaCachingAllocator_raw_alloc  # on the current device
+    raw_delete = torch._C._cuda_cudaCachingAllocator_raw_delete
+
+    def _alloc(size, stream, ctx):
+        try:
+            return int(raw_alloc(int(size), int(stream or 0)))
+        except Exception:
+            return None
+
+    def _release(ptr, stream, ctx):
+        try:
+            raw_delete(int(ptr))
+        except Exception:
+            pass
+
+    hook = (_lib.ALLOC_FN(_alloc), _lib.RELEASE_FN(_release))
+    _lib.check(lib.hodlr_set_allocator(hook[0], hook[1], None))
+    _alloc_hook = hook
+
+
+def load(path: str = _lib.LIB_PATH):
+    return _lib.load(path)
+
+
+def _device():
+    """First call that touches the device: install torch's allocator once."""
+    if _alloc_hook is None and os.environ.get("HODLR_TORCH_ALLOCATOR", "1") != "0":
+        use_torch_allocator(True)
+    return _lib.load()
 
 
 def _stream(stream):
@@ -62,17 +112,19 @@ def _ptr(a, ctype):
 
 
 class HodlrMatrix:
-    """Owning wrapper of a hodlr_t handle."""
+    """Owning wrapper of a hodlr_t handle (or a borrowed factor view, which
+    keeps its QRFactors alive and is never freed)."""
 
-    def __init__(self, handle, n, levels, rank_cap):
+    def __init__(self, handle, n, levels, rank_cap, owner=None):
         self.handle, self.n, self.levels, self.rank_cap = handle, n, levels, rank_cap
+        self.owner = owner
 
     def __del__(self):
         h = getattr(self, "handle", None)
         lib = getattr(_lib, "_lib", None) if _lib is not None else None
-        if h and lib is not None:
+        if h and lib is not None and getattr(self, "owner", None) is None:
             lib.hodlr_free(h)
-            self.handle = None
+        self.handle = None
 
 
 class QRFactors:
@@ -91,7 +143,7 @@ class QRFactors:
 
 def hodlr_build(H, rank_cap: int = 64, stream=None) -> HodlrMatrix:
     """Copy a HODLR matrix (hodlr_gen.HodlrInput or its .pack() dict) to the GPU."""
-    lib = load()
+    lib = _device()
     p = H.pack() if hasattr(H, "pack") else H
     h = C.c_void_p()
     _lib.check(lib.hodlr_build(
@@ -103,7 +155,7 @@ def hodlr_build(H, rank_cap: int = 64, stream=None) -> HodlrMatrix:
 
 
 def hodlr_qr(A: HodlrMatrix, eps: float, anorm: float = 0.0, flags: int = 0, stream=None) -> QRFactors:
-    lib = load()
+    lib = _device()
     h = C.c_void_p()
     _lib.check(lib.hodlr_qr(A.handle, float(eps), float(anorm), int(flags), _stream(stream), C.byref(h)))
     return QRFactors(h, A)
@@ -124,7 +176,7 @@ def _anorms(anorm, count):
 def hodlr_qr_batched(As, eps: float, anorm=None, flags: int = 0, stream=None) -> list:
     """hodlr_qr of every matrix of As in shared launches; anorm: None, a value
     or one value per matrix (<= 0: estimate)."""
-    lib = load()
+    lib = _device()
     hp, keep = _handles(As)
     ap, akeep = _anorms(anorm, len(As))
     out = (C.c_void_p * len(As))()
@@ -179,6 +231,46 @@ def hodlr_qr_matmul(F: QRFactors, which: str, X, trans: bool = False, stream=Non
                                       C.c_void_p(X.data_ptr()), ldx, C.c_void_p(Z.data_ptr()), F.n,
                                       _stream(stream)))
     return Z
+
+
+def hodlr_qr_factor(F: QRFactors, which: str) -> HodlrMatrix:
+    """Borrowed view of the factor 'Y', 'T' or 'R' of F as a HODLR matrix
+    (usable with hodlr_matmul and hodlr_export; keeps F alive)."""
+    v = C.c_void_p()
+    _lib.check(load().hodlr_qr_factor(F.handle, which.encode()[:1], C.byref(v)))
+    return HodlrMatrix(v, F.n, F.levels, F.rank_cap, owner=F)
+
+
+def hodlr_check(F: QRFactors, stream=None):
+    """Wait for the stream; raise HodlrError if the device flagged a capacity overflow."""
+    _lib.check(load().hodlr_check(F.handle, _stream(stream)))
+
+
+def hodlr_qr_ranklog(F: QRFactors):
+    """Every recompression's decision: int32 array (count, 7) of
+    (site, a, b, c, d, w, k); see include/hodlr.h."""
+    lib = load()
+    cnt = C.c_int64()
+    _lib.check(lib.hodlr_qr_ranklog(F.handle, None, 0, C.byref(cnt)))
+    out = np.zeros((max(cnt.value, 1), 7), dtype=np.int32)
+    _lib.check(lib.hodlr_qr_ranklog(F.handle, _ptr(out, C.c_int32), cnt.value, C.byref(cnt)))
+    return out[:cnt.value]
+
+
+def hodlr_plan_check(H, rank_cap: int, count: int = 1, flags: int = 0) -> dict:
+    """Hazard check of the factorisation schedule on H's partition (no device
+    needed); H: hodlr_gen.HodlrInput or (n, levels, leaf_off)."""
+    if hasattr(H, "leaf_off"):
+        n, levels, off = H.n, H.levels, H.leaf_off
+    else:
+        n, levels, off = H
+    off = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    stats = np.zeros(5, dtype=np.int64)
+    msg = C.create_string_buffer(512)
+    _lib.check(load().hodlr_plan_check(int(n), int(levels), _ptr(off, C.c_int64), int(rank_cap), int(count),
+                                       int(flags), _ptr(stats, C.c_int64), msg, 512))
+    return {"launches": int(stats[0]), "launches_stream1": int(stats[1]), "pairs": int(stats[2]),
+            "conflicts": int(stats[3]), "intra_conflicts": int(stats[4]), "first": msg.value.decode()}
 
 
 def hodlr_norm2_est(A: HodlrMatrix, iters: int = 50, stream=None) -> float:

@@ -18,11 +18,14 @@ HODLR_QR_ONE_STREAM = 2
 
 # every symbol include/hodlr.h declares
 EXPORTS = [
-    "hodlr_build", "hodlr_qr", "hodlr_apply_q", "hodlr_solve", "hodlr_matmul", "hodlr_qr_matmul",
+    "hodlr_set_allocator", "hodlr_build", "hodlr_qr", "hodlr_apply_q", "hodlr_solve", "hodlr_matmul",
+    "hodlr_qr_matmul", "hodlr_qr_factor", "hodlr_check", "hodlr_qr_ranklog", "hodlr_plan_check",
     "hodlr_norm2_est", "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time",
     "hodlr_qr_profile", "hodlr_op_name", "hodlr_op_count", "hodlr_qr_batched", "hodlr_qr_batched_time",
     "hodlr_free", "hodlr_qr_free", "hodlr_last_error", "hodlr_version",
 ]
+HODLR_CHECK_ESTIMATE = 0x100
+HODLR_CHECK_PLANT = 0x200
 
 
 class HodlrError(RuntimeError):
@@ -37,7 +40,7 @@ class QRInfo(C.Structure):
         ("max_rank_y", C.c_int32), ("max_rank_t", C.c_int32), ("max_rank_r", C.c_int32),
         ("anorm", C.c_double), ("tau_a", C.c_double), ("tau_t", C.c_double),
         ("flops", C.c_double), ("n_truncations", C.c_int64), ("n_launches", C.c_int64),
-        ("device_bytes", C.c_int64),
+        ("device_bytes", C.c_int64), ("norm_flops", C.c_double),
     ]
 
     def as_dict(self):
@@ -54,6 +57,8 @@ D = C.c_double
 PD = C.POINTER(C.c_double)
 PI64 = C.POINTER(C.c_int64)
 PI32 = C.POINTER(C.c_int32)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 
 
 def load(path: str = LIB_PATH):
@@ -65,6 +70,11 @@ def load(path: str = LIB_PATH):
         raise HodlrError(-6, f"{path} is missing; run paper_1809_10585_amd/build.py first")
     lib = C.CDLL(path)
     sig = {
+        "hodlr_set_allocator": (I32, [ALLOC_FN, RELEASE_FN, P]),
+        "hodlr_qr_factor": (I32, [P, C.c_char, PP]),
+        "hodlr_check": (I32, [P, P]),
+        "hodlr_qr_ranklog": (I32, [P, PI32, I64, PI64]),
+        "hodlr_plan_check": (I32, [I64, I32, PI64, I32, I32, C.c_uint32, PI64, C.c_char_p, I64]),
         "hodlr_build": (I32, [I64, I32, PI64, PD, PI64, PD, PI64, PD, PI64, PI32, I32, P, PP]),
         "hodlr_qr": (I32, [P, D, D, C.c_uint32, P, PP]),
         "hodlr_apply_q": (I32, [P, I32, I64, P, I64, P]),

@@ -16,7 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-UNITS = ["hodlr.cpp", "k_tr.hip", "k_mm.hip", "k_leaf.hip", "k_vec.hip"]
+UNITS = ["hodlr.cpp", "check.cpp", "k_tr.hip", "k_mm.hip", "k_leaf.hip", "k_vec.hip"]
 OUT = os.path.join(HERE, "libhodlr.so")
 OBJ = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("HODLR_OFFLOAD_ARCH", "gfx950")

@@ -30,12 +30,25 @@ constexpr int64_t TR_HDR = 8 + 3 * (int64_t)WMAX * WMAX;
 // device-side error bits
 enum : int { ERR_CAPACITY = 1, ERR_WIDTH = 2, ERR_STACK = 4 };
 
-// flop counter categories (same counting conventions as the CPU oracle)
+// flop counter categories (same counting conventions as the CPU oracle).  The
+// factorisation's total sums the first FC_N; FC_NORM (the |A|_2 power
+// iteration, which the oracle does not count) is kept apart.
 enum : int { FC_LEAF = 0, FC_HMAT = 1, FC_TRUNC = 2, FC_DENSE = 3, FC_UPDATE = 4, FC_ORTH = 5,
-             FC_N = 6 };
+             FC_N = 6, FC_NORM = 6 };
 // flop counters: FC_N categories x FC_STRIPE stripes (summed on the host)
 constexpr int FC_STRIPE = 64;
 constexpr int FC_SIZE = 8 * FC_STRIPE;
+
+// Operands bound per call of a cached launch sequence (apply Q, solve,
+// products): jobs that name a slot >= 0 read pointer p[slot] + their offset and
+// leading dimension ld[slot]; a job whose width is not fixed uses s columns.
+// Passed to the kernels by value, so a cached sequence is reused with new
+// operands without touching device memory.
+struct Opnd {
+  double* p[4];
+  int ld[4];
+  int s;
+};
 
 // Columns [0, ncols) of a column-major array, scaled by `scale`.  ncols is
 // *ncols_dev when that pointer is set.  p == nullptr means an empty segment.
@@ -76,6 +89,7 @@ struct TrJob {
   int64_t hdr;      // offset (doubles) of the job header in the workspace
   int* err;         // error word of the factorisation the job belongs to
   double* flops;    // flop counters of that factorisation
+  int* log;         // rank log entry (input width, kept rank) or nullptr
 };
 
 struct TrChunk {    // one block of the first recompression kernel
@@ -119,6 +133,8 @@ struct HView {
 };
 
 // Z = alpha * op(M_v) X + beta * Z  for the sub-HODLR rooted at heap node v.
+// X (Z) is operand slot xs (zs) + xoff (zoff) when xs (zs) >= 0.  Width: *s_dev
+// if set, else s if > 0, else the call's Opnd::s.
 struct MmJob {
   HView M;
   int v;
@@ -132,8 +148,12 @@ struct MmJob {
   double alpha, beta;
   int64_t row0;        // global index of row 0 of X and Z
   int64_t red0;        // reduced projection of node u, kind t at
-                       // red0 + (2*(rel(u)) + t) * KCAP*SMAX
+                       // red0 + (2*(rel(u)) + t) * rld*SMAX
+  int rld;             // leading dimension of a projection (>= every block rank)
   int tri;             // triangular operand (halves the leaf flop count)
+  int fc;              // flop category
+  int xs, zs;
+  int64_t xoff, zoff;
   double* flops;
 };
 
@@ -142,7 +162,7 @@ struct MmProj {      // phase A: one row chunk of one block projection
   int node;
   int kind;          // 0 = upper block, 1 = lower block
   int chunk, nchunk;
-  int64_t part;      // this chunk's partial (KCAP x SMAX, ld KCAP); for k_mm_red
+  int64_t part;      // this chunk's partial (rld x SMAX, ld rld); for k_mm_red
                      // items the first chunk's partial
 };
 
@@ -153,7 +173,10 @@ struct MmApply {     // phase B: rows of one leaf of the output
 };
 
 // ---------------------------------------------------------------- small GEMMs
-// C = beta*C + alpha * op(A) op(B); op(A) is M x K, op(B) is K x N.
+// C = beta*C + alpha * op(A) op(B); op(A) is M x K, op(B) is K x N.  A, B, C
+// are operand slot as_, bs_, cs_ + their offset when the slot is >= 0 (leading
+// dimension from the slot unless lda/ldb/ldc > 0).  N: *Nd if set, else N if
+// > 0, else the call's Opnd::s.
 struct GemmJob {
   int ta, tb;
   int M, N, K;
@@ -166,6 +189,8 @@ struct GemmJob {
   int ldc;
   double alpha, beta;
   int fc;
+  int as_, bs_, cs_;
+  int64_t aoff, boff, coff;
   double* flops;
 };
 

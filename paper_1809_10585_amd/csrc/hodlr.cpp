@@ -1,7 +1,8 @@
 // Host side of the HODLR QR library: device-resident HODLR storage, the
 // depth-first schedule of Algorithm hQR (Kressner & Susnjara, Sec. 4)
 // compiled into a flat list of batched kernel launches, its execution
-// (directly or as a captured HIP graph), and the C ABI of include/hodlr.h.
+// (directly or as a captured HIP graph), the cached launch sequences of
+// apply-Q, solve and the products, and the C ABI of include/hodlr.h.
 //
 // Storage of the factors (all on A's partition):
 //  * leaf j        : R (upper triangle) and Y (strictly lower, unit diagonal
@@ -12,25 +13,25 @@
 //                    overwritten by Y~_B^T slice by slice as the leaves below
 //                    node v's left child are factorised (Y_B = B_L Y~_B).
 //  * T block v     : T12 = -T1 T~12 T2 in factored form.
-#include "kernels.h"
+#include "plan.h"
 
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <utility>
 #include <vector>
 
-#include "hodlr.h"
-
-using namespace hq;
-
-namespace {
+namespace hqh {
 
 thread_local std::string g_err;
 
@@ -39,116 +40,136 @@ hodlr_status fail(hodlr_status s, const std::string& m) {
   return s;
 }
 
-#define HIPCHK(x)                                                                       \
-  do {                                                                                  \
-    hipError_t e_ = (x);                                                                \
-    if (e_ != hipSuccess) {                                                             \
-      g_err = std::string(#x) + ": " + hipGetErrorString(e_);                           \
-      return e_ == hipErrorOutOfMemory ? HODLR_ENOMEM : HODLR_EDEVICE;                  \
-    }                                                                                   \
-  } while (0)
+const char* const OP_NAMES[OP_NTYPES] = {
+  "tr_qr", "tr_form", "mm_proj", "mm_apply", "gemm_tall", "gemm_red", "leaf_gather", "leaf_panel",
+  "leaf_update", "leaf_scatter", "fill", "normalize", "leaf_trsm", "set_scal", "mm_red", "tr_small",
+  "signal", "wait"};
 
-// ------------------------------------------------------------------ device memory
-struct DMem {
-  std::vector<void*> ptrs;
-  size_t bytes = 0;
-  // when set, every allocation is zero-filled on `zero_stream` (capacity padding
-  // of factors and temporaries then holds zeros, never recycled garbage)
-  bool zero = false;
-  hipStream_t zero_stream = nullptr;
-  ~DMem() {
-    for (void* p : ptrs) (void)hipFree(p);
+// ------------------------------------------------------------------ memory
+namespace {
+std::mutex g_hook_mu;
+AllocHook g_hook;
+// hipMallocAsync: -1 not tried yet, 1 works, 0 not supported (hipMalloc then)
+std::atomic<int> g_async_ok{-1};
+}  // namespace
+
+AllocHook current_hook() {
+  std::lock_guard<std::mutex> lk(g_hook_mu);
+  return g_hook;
+}
+
+thread_local bool g_virtual = false;
+
+void* virtual_alloc(size_t bytes) {
+  static std::atomic<uint64_t> next{(uint64_t)1 << 44};
+  bytes = (bytes + 255) & ~(size_t)255;
+  return (void*)(uintptr_t)next.fetch_add(bytes + 256);  // a gap after every block
+}
+
+DMem::~DMem() {
+  if (virt) return;
+  for (const Blk& b : ptrs) {
+    if (hook.release != nullptr)
+      hook.release(b.p, stream, hook.ctx);
+    else
+      (void)hipFree(b.p);
   }
-  template <class T>
-  hodlr_status alloc(T** out, size_t count) {
-    *out = nullptr;
-    if (count == 0) count = 1;
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(HODLR_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-    }
-    ptrs.push_back(p);
-    bytes += count * sizeof(T);
-    *out = static_cast<T*>(p);
-    if (zero && hipMemsetAsync(p, 0, count * sizeof(T), zero_stream) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(HODLR_EDEVICE, "hipMemsetAsync of a new allocation failed");
-    }
+}
+
+hodlr_status DMem::raw(void** out, size_t nbytes) {
+  *out = nullptr;
+  if (g_virtual) {
+    virt = true;
+    void* p = virtual_alloc(nbytes);
+    ptrs.push_back({p, nbytes});
+    bytes += nbytes;
+    *out = p;
     return HODLR_OK;
   }
-};
-
-#define TRY(x)                       \
-  do {                               \
-    hodlr_status s_ = (x);           \
-    if (s_ != HODLR_OK) return s_;   \
-  } while (0)
-
-template <class T>
-hodlr_status upload(DMem& mem, T** d, const std::vector<T>& h, hipStream_t st) {
-  TRY(mem.alloc(d, h.size()));
-  if (!h.empty()) HIPCHK(hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  if (!hooked) {
+    hook = current_hook();
+    hooked = true;
+  }
+  void* p = nullptr;
+  if (hook.alloc != nullptr) {
+    p = hook.alloc(nbytes, stream, hook.ctx);
+    if (p == nullptr)
+      return fail(HODLR_ENOMEM, "the installed allocator returned NULL for " + std::to_string(nbytes) + " bytes");
+  } else {
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(HODLR_ENOMEM, "hipMalloc of " + std::to_string(nbytes) + " bytes failed");
+    }
+  }
+  ptrs.push_back({p, nbytes});
+  bytes += nbytes;
+  *out = p;
+  if (zero) TRY(dzero(p, nbytes, stream));
   return HODLR_OK;
 }
 
-// ------------------------------------------------------------------ tree
-struct Tree {
-  int L = 0;
-  int64_t n = 0;
-  std::vector<int64_t> lo, hi;  // heap numbering 1 .. 2^(L+1)-1
-  int nleaf() const { return 1 << L; }
-  bool is_leaf(int v) const { return v >= (1 << L); }
-  int64_t m(int v) const { return hi[v] - lo[v]; }
-  void init(int levels, const int64_t* off) {
-    L = levels;
-    n = off[1 << L];
-    lo.assign(2 << L, 0);
-    hi.assign(2 << L, 0);
-    for (int j = 0; j < (1 << L); ++j) {
-      lo[(1 << L) + j] = off[j];
-      hi[(1 << L) + j] = off[j + 1];
-    }
-    for (int v = (1 << L) - 1; v >= 1; --v) {
-      lo[v] = lo[2 * v];
-      hi[v] = hi[2 * v + 1];
+CallMem::CallMem(hipStream_t st) : hook(current_hook()), stream(st) {}
+
+CallMem::~CallMem() {
+  for (const Blk& b : ptrs) {
+    if (hook.release != nullptr) {
+      hook.release(b.p, stream, hook.ctx);
+    } else if (b.async) {
+      (void)hipFreeAsync(b.p, stream);
+    } else {
+      (void)hipStreamSynchronize(stream);
+      (void)hipFree(b.p);
     }
   }
-  void subtree_internal(int v, std::vector<int>& out) const {
-    if (is_leaf(v)) return;
-    out.push_back(v);
-    subtree_internal(2 * v, out);
-    subtree_internal(2 * v + 1, out);
+}
+
+hodlr_status CallMem::raw(void** out, size_t nbytes) {
+  *out = nullptr;
+  void* p = nullptr;
+  if (hook.alloc != nullptr) {
+    p = hook.alloc(nbytes, stream, hook.ctx);
+    if (p == nullptr)
+      return fail(HODLR_ENOMEM, "the installed allocator returned NULL for " + std::to_string(nbytes) + " bytes");
+    ptrs.push_back({p, false});
+    *out = p;
+    return HODLR_OK;
   }
-  void subtree_leaves(int v, std::vector<int>& out) const {
-    if (is_leaf(v)) {
-      out.push_back(v - (1 << L));
-      return;
+  if (g_async_ok.load() != 0) {
+    hipError_t e = hipMallocAsync(&p, nbytes, stream);
+    if (e == hipSuccess) {
+      g_async_ok.store(1);
+      ptrs.push_back({p, true});
+      *out = p;
+      return HODLR_OK;
     }
-    subtree_leaves(2 * v, out);
-    subtree_leaves(2 * v + 1, out);
+    (void)hipGetLastError();
+    if (e == hipErrorOutOfMemory) return fail(HODLR_ENOMEM, "hipMallocAsync failed");
+    g_async_ok.store(0);
   }
-  int subtree_size(int v) const {  // nodes in the subtree (heap-relative numbering bound)
-    int d = 31 - __builtin_clz(v);
-    return (2 << (L - d)) - 1;
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HODLR_ENOMEM, "hipMalloc of " + std::to_string(nbytes) + " bytes failed");
   }
-};
+  ptrs.push_back({p, false});
+  *out = p;
+  return HODLR_OK;
+}
 
-// One family of off-diagonal blocks (upper, lower or T's upper) with rank
-// capacity `cap` per block.
-struct BlockSet {
-  double* U = nullptr;
-  double* V = nullptr;
-  std::vector<int64_t> uoff, voff;
-  int64_t usz = 0, vsz = 0;
-  int* rank = nullptr;  // device, indexed by node
-  HBlk* dview = nullptr;
-  std::vector<HBlk> hview;
-};
+hodlr_status h2d(void* dst, const void* src, size_t nbytes, hipStream_t st) {
+  if (g_virtual || nbytes == 0) return HODLR_OK;
+  HIPCHK(hipMemcpyAsync(dst, src, nbytes, hipMemcpyHostToDevice, st));
+  return HODLR_OK;
+}
 
-enum BKind { BK_UP = 0, BK_LO = 1 };
+hodlr_status dzero(void* dst, size_t nbytes, hipStream_t st) {
+  if (g_virtual || nbytes == 0) return HODLR_OK;
+  HIPCHK(hipMemsetAsync(dst, 0, nbytes, st));
+  return HODLR_OK;
+}
 
+// ------------------------------------------------------------------ storage
 hodlr_status make_blocks(DMem& mem, const Tree& t, int cap, BKind kind, int* rank, BlockSet& B) {
   const int nn = 1 << t.L;
   B.uoff.assign(nn, 0);
@@ -182,14 +203,6 @@ hodlr_status make_blocks(DMem& mem, const Tree& t, int cap, BKind kind, int* ran
   return HODLR_OK;
 }
 
-struct LeafSet {
-  double* D = nullptr;
-  std::vector<int64_t> off;
-  int64_t size = 0;
-  HLeaf* dview = nullptr;
-  std::vector<HLeaf> hview;
-};
-
 hodlr_status make_leaves(DMem& mem, const Tree& t, LeafSet& S) {
   const int nl = t.nleaf();
   S.off.assign(nl, 0);
@@ -208,368 +221,251 @@ hodlr_status make_leaves(DMem& mem, const Tree& t, LeafSet& S) {
   return HODLR_OK;
 }
 
-// ------------------------------------------------------------------ schedule
-enum OpType {
-  OP_TRQR, OP_TRFORM, OP_MMPROJ, OP_MMAPPLY, OP_GTALL, OP_GRED, OP_LGATHER, OP_LPANEL,
-  OP_LUPDATE, OP_LSCATTER, OP_FILL, OP_NORMALIZE, OP_TRSM, OP_SETSCAL,
-  OP_MMRED, OP_TRSMALL,
-  OP_SIGNAL,  // record event a0 on the op's lane (no kernel)
-  OP_WAIT,    // the op's lane waits for event a0 (no kernel)
-  OP_NTYPES
-};
-const char* const OP_NAMES[OP_NTYPES] = {
-  "tr_qr", "tr_form", "mm_proj", "mm_apply", "gemm_tall", "gemm_red", "leaf_gather", "leaf_panel",
-  "leaf_update", "leaf_scatter", "fill", "normalize", "leaf_trsm", "set_scal", "mm_red", "tr_small",
-  "signal", "wait"};
-
-struct Op {
-  int type;
-  int first, count;  // item range (grid = count blocks)
-  int a0;            // leaf job / panel / misc
-  int a1;
-  const double* p0;
-  double* p1;
-  double d0;
-  int64_t n;
-  double* pout;
-  double d1;
-  int lane = 0;  // 0: main chain, 1: the T-factor chain (runs beside it)
-};
-
-struct TrSpec {
-  Seg seg[2][2];
-  int m[2];
-  const double* tau;
-  int flags;
-  double* out[2];
-  int ldout[2];
-  int cap;
-  int* out_rank;
-  int fc;
-  int* err;
-  double* flops;
-};
-
-struct MmSpec {
-  HView M;
-  bool has_up, has_lo;
-  int v, trans;
-  const double* X;
-  int ldX;
-  int s;
-  const int* s_dev;
-  double* Z;
-  int ldZ;
-  double alpha, beta;
-  int tri;
-  double* flops = nullptr;
-};
-
-struct GSpec {  // gemm job with host-side capacities for tiling
-  GemmJob J;
-  int Mcap, Ncap, Kstat;
-};
-
-Seg mkseg(const double* p, int ld, const int* ncols_dev, double scale = 1.0, int ncols = 0) {
-  Seg s;
-  s.p = p;
-  s.ld = ld;
-  s.ncols = ncols;
-  s.ncols_dev = ncols_dev;
-  s.scale = scale;
-  return s;
+// ------------------------------------------------------------------ plan building
+bool Plan::uses_counters() const {
+  for (const Op& o : ops)
+    if (o.type == OP_TRQR || o.type == OP_TRSMALL || o.type == OP_GRED) return true;
+  return false;
 }
 
-Seg noseg() { return mkseg(nullptr, 1, nullptr); }
-
-struct Plan {
-  std::vector<TrJob> trj;
-  std::vector<TrChunk> trc;
-  std::vector<TrForm> trf;
-  std::vector<MmJob> mmj;
-  std::vector<MmProj> mmp;
-  std::vector<MmApply> mma;
-  std::vector<GemmJob> gj;
-  std::vector<GemmTile> gt;
-  std::vector<GemmRed> gr;
-  std::vector<LeafJob> lj;
-  std::vector<VecJob> vj;
-  std::vector<Op> ops;
-  // Workspace and counters are reused by consecutive ops of one lane; the two
-  // lanes get disjoint regions because their ops may run at the same time.
-  int64_t ws_lane[2] = {0, 0};
-  int cnt_lane[2] = {1, 1};
-  int lane = 0;  // lane of the ops being added
-  int n_events = 0;
-  int64_t ws_need() const { return ws_lane[0] + ws_lane[1]; }
-  int cnt_need() const { return cnt_lane[0] + cnt_lane[1]; }
-  int64_t ws_off(int l) const { return l == 0 ? 0 : ws_lane[0]; }
-  int cnt_off(int l) const { return l == 0 ? 0 : cnt_lane[0]; }
-  void push(Op o) {
-    o.lane = lane;
-    ops.push_back(o);
-  }
-  int signal() {
-    Op o{OP_SIGNAL};
-    o.a0 = n_events++;
-    push(o);
-    return o.a0;
-  }
-  void wait(int ev) {
-    Op o{OP_WAIT};
-    o.a0 = ev;
-    push(o);
-  }
-  // one launch over vector items (fill / normalise / thresholds)
-  void vec(int type, const std::vector<VecJob>& items) {
-    const int first = (int)vj.size();
-    vj.insert(vj.end(), items.begin(), items.end());
-    push(Op{type, first, (int)items.size()});
-  }
-  int64_t n_trunc = 0;
-  int wtop = WMAX;  // widest recompression this plan can produce
-  int mleaf = 0;    // largest leaf any product of this plan touches
-  // device copies
-  TrJob* d_trj = nullptr;
-  TrChunk* d_trc = nullptr;
-  TrForm* d_trf = nullptr;
-  MmJob* d_mmj = nullptr;
-  MmProj* d_mmp = nullptr;
-  MmApply* d_mma = nullptr;
-  GemmJob* d_gj = nullptr;
-  GemmTile* d_gt = nullptr;
-  GemmRed* d_gr = nullptr;
-  LeafJob* d_lj = nullptr;
-  VecJob* d_vj = nullptr;
-
-  void trunc(const std::vector<TrSpec>& specs) {
-    if (specs.empty()) return;
-    int64_t off = 0;
-    int cnt = 0;
-    const int c_first = (int)trc.size(), f_first = (int)trf.size();
-    std::vector<TrChunk> small;
-    for (const TrSpec& sp : specs) {
-      TrJob J{};
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) J.seg[a][b] = sp.seg[a][b];
-      J.tau = sp.tau;
-      J.flags = sp.flags;
-      J.out[0] = sp.out[0];
-      J.out[1] = sp.out[1];
-      J.ldout[0] = sp.ldout[0];
-      J.ldout[1] = sp.ldout[1];
-      J.cap = sp.cap;
-      J.out_rank = sp.out_rank;
-      J.fc = sp.fc;
-      J.err = sp.err;
-      J.flops = sp.flops;
-      J.hdr = off;
-      off += TR_HDR;
-      for (int side = 0; side < 2; ++side) {
-        TrSide& S = J.side[side];
-        S.m = sp.m[side];
-        if (side == 1 && (sp.flags & TR_ORTH)) {
-          S.p0 = 0;
-          S.node0 = 0;
-          S.cnt0 = 0;
-          continue;
-        }
-        S.p0 = std::max(1, (S.m + CH - 1) / CH);
-        S.node0 = off;
-        off += 2 * (int64_t)S.p0 * TR_NODE;
-        S.cnt0 = cnt;
-        cnt += S.p0;
-      }
-      J.jcounter = cnt++;
-      const int jid = (int)trj.size();
-      trj.push_back(J);
-      ++n_trunc;
-      // factors of a few chunks: k_tr_small (for wide jobs its forming step
-      // needs a tree of one combine level and w k doubles of LDS twice)
-      const int mx = std::max(J.side[0].m, J.side[1].m);
-      if (mx <= CH || (wtop <= 64 && mx <= TRS_MAXCH * CH)) {
-        for (int side = 0; side < 2; ++side)
-          for (int c = 0; c < J.side[side].p0; ++c) small.push_back(TrChunk{jid, side, c});
+void Plan::trunc(const std::vector<TrSpec>& specs) {
+  if (specs.empty()) return;
+  int64_t off = 0;
+  int cnt = 0;
+  const int c_first = (int)trc.size(), f_first = (int)trf.size();
+  std::vector<TrChunk> small;
+  for (const TrSpec& sp : specs) {
+    TrJob J{};
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) J.seg[a][b] = sp.seg[a][b];
+    J.tau = sp.tau;
+    J.flags = sp.flags;
+    J.out[0] = sp.out[0];
+    J.out[1] = sp.out[1];
+    J.ldout[0] = sp.ldout[0];
+    J.ldout[1] = sp.ldout[1];
+    J.cap = sp.cap;
+    J.out_rank = sp.out_rank;
+    J.fc = sp.fc;
+    J.err = sp.err;
+    J.flops = sp.flops;
+    J.log = sp.log;
+    J.hdr = off;
+    off += TR_HDR;
+    for (int side = 0; side < 2; ++side) {
+      TrSide& S = J.side[side];
+      S.m = sp.m[side];
+      if (side == 1 && (sp.flags & TR_ORTH)) {
+        S.p0 = 0;
+        S.node0 = 0;
+        S.cnt0 = 0;
         continue;
       }
+      S.p0 = std::max(1, (S.m + CH - 1) / CH);
+      S.node0 = off;
+      off += 2 * (int64_t)S.p0 * TR_NODE;
+      S.cnt0 = cnt;
+      cnt += S.p0;
+    }
+    J.jcounter = cnt++;
+    const int jid = (int)trj.size();
+    trj.push_back(J);
+    ++n_trunc;
+    // factors of a few chunks: k_tr_small (for wide jobs its forming step
+    // needs a tree of one combine level and w k doubles of LDS twice)
+    const int mx = std::max(J.side[0].m, J.side[1].m);
+    if (mx <= CH || (wtop <= 64 && mx <= TRS_MAXCH * CH)) {
       for (int side = 0; side < 2; ++side)
-        for (int c = 0; c < J.side[side].p0; ++c) trc.push_back(TrChunk{jid, side, c});
-      bool leader = true;
-      for (int c = 0; c < J.side[0].p0; ++c) {
-        trf.push_back(TrForm{jid, 0, c, 0, 0, leader ? 1 : 0});
-        leader = false;
-      }
-      for (int r0 = 0; r0 < J.side[1].m; r0 += 64)
-        trf.push_back(TrForm{jid, 1, 0, r0, std::min(64, J.side[1].m - r0), 0});
+        for (int c = 0; c < J.side[side].p0; ++c) small.push_back(TrChunk{jid, side, c});
+      continue;
     }
-    if (!small.empty()) {
-      const int s_first = (int)trc.size();
-      trc.insert(trc.end(), small.begin(), small.end());
-      push(Op{OP_TRSMALL, s_first, (int)small.size()});
+    for (int side = 0; side < 2; ++side)
+      for (int c = 0; c < J.side[side].p0; ++c) trc.push_back(TrChunk{jid, side, c});
+    bool leader = true;
+    for (int c = 0; c < J.side[0].p0; ++c) {
+      trf.push_back(TrForm{jid, 0, c, 0, 0, leader ? 1 : 0});
+      leader = false;
     }
-    if ((int)trc.size() > c_first + (int)small.size()) {
-      push(Op{OP_TRQR, c_first, (int)trc.size() - c_first - (int)small.size()});
-      push(Op{OP_TRFORM, f_first, (int)trf.size() - f_first});
-    }
-    ws_lane[lane] = std::max(ws_lane[lane], off);
-    cnt_lane[lane] = std::max(cnt_lane[lane], cnt);
+    for (int r0 = 0; r0 < J.side[1].m; r0 += 64)
+      trf.push_back(TrForm{jid, 1, 0, r0, std::min(64, J.side[1].m - r0), 0});
   }
-
-  static int rel_node_h(int u, int v) {
-    int du = 0, dv = 0;
-    while ((u >> du) > 1) ++du;
-    while ((v >> dv) > 1) ++dv;
-    const int d = du - dv;
-    return (1 << d) - 1 + (u - (v << d));
+  if (!small.empty()) {
+    const int s_first = (int)trc.size();
+    trc.insert(trc.end(), small.begin(), small.end());
+    push(Op{OP_TRSMALL, s_first, (int)small.size()});
   }
-
-  // Z = alpha op(M_v) X + beta Z for every spec: projections of all blocks in one
-  // launch (plus a summing launch if some block spans several chunks), then the
-  // leaf rows in one launch.
-  void mm(const Tree& t, const std::vector<MmSpec>& specs) {
-    int64_t off = 0;
-    const int p_first = (int)mmp.size();
-    std::vector<MmProj> reds;
-    int64_t rows_total = 0;
-    for (const MmSpec& sp : specs) rows_total += t.m(sp.v);
-    const int RT = rows_total >= 32768 ? 64 : 16;
-    std::vector<MmApply> apply;
-    for (const MmSpec& sp : specs) {
-      MmJob J{};
-      J.M = sp.M;
-      J.v = sp.v;
-      J.trans = sp.trans;
-      J.X = sp.X;
-      J.ldX = sp.ldX;
-      J.s = sp.s;
-      J.s_dev = sp.s_dev;
-      J.Z = sp.Z;
-      J.ldZ = sp.ldZ;
-      J.alpha = sp.alpha;
-      J.beta = sp.beta;
-      J.row0 = t.lo[sp.v];
-      J.tri = sp.tri;
-      J.flops = sp.flops;
-      J.red0 = off;
-      off += 2 * (int64_t)t.subtree_size(sp.v) * KCAP * SMAX;
-      const int jid = (int)mmj.size();
-      std::vector<int> nodes;
-      t.subtree_internal(sp.v, nodes);
-      for (int u : nodes) {
-        for (int kind = 0; kind < 2; ++kind) {
-          if ((kind == 0 && !sp.has_up) || (kind == 1 && !sp.has_lo)) continue;
-          const int64_t rows = kind == 0 ? t.m(2 * u) : t.m(2 * u + 1);
-          const int64_t cols = kind == 0 ? t.m(2 * u + 1) : t.m(2 * u);
-          const int64_t len = sp.trans ? rows : cols;
-          const int nch = (int)((len + MM_CH - 1) / MM_CH);
-          if (nch == 1) {
-            const int64_t red = J.red0 + (int64_t)(2 * rel_node_h(u, sp.v) + kind) * KCAP * SMAX;
-            mmp.push_back(MmProj{jid, u, kind, 0, 1, red});
-          } else {
-            for (int c = 0; c < nch; ++c) mmp.push_back(MmProj{jid, u, kind, c, nch, off + (int64_t)c * KCAP * SMAX});
-            reds.push_back(MmProj{jid, u, kind, 0, nch, off});
-            off += (int64_t)nch * KCAP * SMAX;
-          }
-        }
-      }
-      mmj.push_back(J);
-      std::vector<int> leaves;
-      t.subtree_leaves(sp.v, leaves);
-      for (int j : leaves) {
-        const int m = (int)t.m(t.nleaf() + j);
-        mleaf = std::max(mleaf, m);
-        for (int r0 = 0; r0 < m; r0 += RT) apply.push_back(MmApply{jid, j, r0, std::min(RT, m - r0)});
-      }
-    }
-    if ((int)mmp.size() > p_first) push(Op{OP_MMPROJ, p_first, (int)mmp.size() - p_first});
-    if (!reds.empty()) {
-      const int r_first = (int)mmp.size();
-      mmp.insert(mmp.end(), reds.begin(), reds.end());
-      push(Op{OP_MMRED, r_first, (int)reds.size()});
-    }
-    const int a_first = (int)mma.size();
-    mma.insert(mma.end(), apply.begin(), apply.end());
-    push(Op{OP_MMAPPLY, a_first, (int)apply.size(), 0, RT});
-    ws_lane[lane] = std::max(ws_lane[lane], off);
+  if ((int)trc.size() > c_first + (int)small.size()) {
+    push(Op{OP_TRQR, c_first, (int)trc.size() - c_first - (int)small.size()});
+    push(Op{OP_TRFORM, f_first, (int)trf.size() - f_first});
   }
-
-  void gemm_tall(const std::vector<GSpec>& specs) {
-    if (specs.empty()) return;
-    const int t_first = (int)gt.size();
-    for (const GSpec& g : specs) {
-      const int jid = (int)gj.size();
-      gj.push_back(g.J);
-      for (int r0 = 0; r0 < g.Mcap; r0 += 64)
-        for (int c0 = 0; c0 < g.Ncap; c0 += 64) gt.push_back(GemmTile{jid, r0, c0});
-    }
-    if ((int)gt.size() > t_first) push(Op{OP_GTALL, t_first, (int)gt.size() - t_first});
-  }
-
-  void gemm_red(const std::vector<GSpec>& specs) {
-    if (specs.empty()) return;
-    int64_t off = 0;
-    int cnt = 0;
-    const int r_first = (int)gr.size();
-    for (const GSpec& g : specs) {
-      const int jid = (int)gj.size();
-      gj.push_back(g.J);
-      const int K = g.Kstat;
-      const int nch = std::max(1, (K + CH - 1) / CH);
-      const int counter = cnt++;
-      for (int c = 0; c < nch; ++c)
-        gr.push_back(GemmRed{jid, c * CH, std::min(CH, K - c * CH), nch, c, off + (int64_t)c * KCAP * KCAP,
-                             counter});
-      if (nch > 1) off += (int64_t)nch * KCAP * KCAP;
-    }
-    push(Op{OP_GRED, r_first, (int)gr.size() - r_first});
-    ws_lane[lane] = std::max(ws_lane[lane], off);
-    cnt_lane[lane] = std::max(cnt_lane[lane], cnt);
-  }
-
-  hodlr_status upload_all(DMem& mem, hipStream_t st) {
-    TRY(upload(mem, &d_trj, trj, st));
-    TRY(upload(mem, &d_trc, trc, st));
-    TRY(upload(mem, &d_trf, trf, st));
-    TRY(upload(mem, &d_mmj, mmj, st));
-    TRY(upload(mem, &d_mmp, mmp, st));
-    TRY(upload(mem, &d_mma, mma, st));
-    TRY(upload(mem, &d_gj, gj, st));
-    TRY(upload(mem, &d_gt, gt, st));
-    TRY(upload(mem, &d_gr, gr, st));
-    TRY(upload(mem, &d_lj, lj, st));
-    TRY(upload(mem, &d_vj, vj, st));
-    return HODLR_OK;
-  }
-};
-
-// Workspace + counters + error word + flop counters shared by a handle's plans.
-struct Work {
-  double* ws = nullptr;
-  int64_t ws_size = 0;
-  int* counters = nullptr;
-  int cnt_size = 0;
-  int* err = nullptr;
-  double* fc = nullptr;
-  LeafWs leaf{};
-};
-
-// sum of the striped device flop counters (synchronous); -1 on failure
-double flop_total(const double* fc) {
-  std::vector<double> h(FC_SIZE);
-  if (hipMemcpy(h.data(), fc, FC_SIZE * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return -1.0;
-  double tot = 0.0;
-  for (int c = 0; c < FC_N; ++c)
-    for (int k = 0; k < FC_STRIPE; ++k) tot += h[c * FC_STRIPE + k];
-  return tot;
+  ws_lane[lane] = std::max(ws_lane[lane], off);
+  cnt_lane[lane] = std::max(cnt_lane[lane], cnt);
 }
 
-hodlr_status ensure_work(DMem& mem, Work& W, int64_t ws_need, int cnt_need, bool leafws,
-                         hipStream_t st) {
+namespace {
+int rel_node_h(int u, int v) {
+  int du = 0, dv = 0;
+  while ((u >> du) > 1) ++du;
+  while ((v >> dv) > 1) ++dv;
+  const int d = du - dv;
+  return (1 << d) - 1 + (u - (v << d));
+}
+}  // namespace
+
+// Z = alpha op(M_v) X + beta Z for every spec: projections of all blocks in one
+// launch (plus a summing launch if some block spans several chunks), then the
+// leaf rows in one launch.
+void Plan::mm(const Tree& t, const std::vector<MmSpec>& specs) {
+  int64_t off = 0;
+  const int p_first = (int)mmp.size();
+  std::vector<MmProj> reds;
+  int64_t rows_total = 0;
+  for (const MmSpec& sp : specs) rows_total += t.m(sp.v);
+  const int RT = rows_total >= 32768 ? 64 : 16;
+  std::vector<MmApply> apply;
+  for (const MmSpec& sp : specs) {
+    MmJob J{};
+    J.M = sp.M;
+    J.v = sp.v;
+    J.trans = sp.trans;
+    J.X = sp.X;
+    J.ldX = sp.ldX;
+    J.s = sp.s;
+    J.s_dev = sp.s_dev;
+    J.Z = sp.Z;
+    J.ldZ = sp.ldZ;
+    J.alpha = sp.alpha;
+    J.beta = sp.beta;
+    J.row0 = t.lo[sp.v];
+    J.tri = sp.tri;
+    J.fc = sp.fc;
+    J.xs = sp.xs;
+    J.zs = sp.zs;
+    J.xoff = sp.xoff;
+    J.zoff = sp.zoff;
+    J.flops = sp.flops;
+    J.rld = sp.rld;
+    const int64_t stride = (int64_t)sp.rld * SMAX;
+    J.red0 = off;
+    off += 2 * (int64_t)t.subtree_size(sp.v) * stride;
+    const int jid = (int)mmj.size();
+    std::vector<int> nodes;
+    t.subtree_internal(sp.v, nodes);
+    for (int u : nodes) {
+      for (int kind = 0; kind < 2; ++kind) {
+        if ((kind == 0 && !sp.has_up) || (kind == 1 && !sp.has_lo)) continue;
+        const int64_t rows = kind == 0 ? t.m(2 * u) : t.m(2 * u + 1);
+        const int64_t cols = kind == 0 ? t.m(2 * u + 1) : t.m(2 * u);
+        const int64_t len = sp.trans ? rows : cols;
+        const int nch = (int)((len + MM_CH - 1) / MM_CH);
+        if (nch == 1) {
+          const int64_t red = J.red0 + (int64_t)(2 * rel_node_h(u, sp.v) + kind) * stride;
+          mmp.push_back(MmProj{jid, u, kind, 0, 1, red});
+        } else {
+          for (int c = 0; c < nch; ++c) mmp.push_back(MmProj{jid, u, kind, c, nch, off + (int64_t)c * stride});
+          reds.push_back(MmProj{jid, u, kind, 0, nch, off});
+          off += (int64_t)nch * stride;
+        }
+      }
+    }
+    mmj.push_back(J);
+    std::vector<int> leaves;
+    t.subtree_leaves(sp.v, leaves);
+    for (int j : leaves) {
+      const int m = (int)t.m(t.nleaf() + j);
+      mleaf = std::max(mleaf, m);
+      for (int r0 = 0; r0 < m; r0 += RT) apply.push_back(MmApply{jid, j, r0, std::min(RT, m - r0)});
+    }
+  }
+  if ((int)mmp.size() > p_first) push(Op{OP_MMPROJ, p_first, (int)mmp.size() - p_first});
+  if (!reds.empty()) {
+    const int r_first = (int)mmp.size();
+    mmp.insert(mmp.end(), reds.begin(), reds.end());
+    push(Op{OP_MMRED, r_first, (int)reds.size()});
+  }
+  const int a_first = (int)mma.size();
+  mma.insert(mma.end(), apply.begin(), apply.end());
+  push(Op{OP_MMAPPLY, a_first, (int)apply.size(), 0, RT});
+  ws_lane[lane] = std::max(ws_lane[lane], off);
+}
+
+void Plan::gemm_tall(const std::vector<GSpec>& specs) {
+  if (specs.empty()) return;
+  const int t_first = (int)gt.size();
+  for (const GSpec& g : specs) {
+    const int jid = (int)gj.size();
+    gj.push_back(g.J);
+    for (int r0 = 0; r0 < g.Mcap; r0 += 64)
+      for (int c0 = 0; c0 < g.Ncap; c0 += 64) gt.push_back(GemmTile{jid, r0, c0});
+  }
+  if ((int)gt.size() > t_first) push(Op{OP_GTALL, t_first, (int)gt.size() - t_first});
+}
+
+void Plan::gemm_red(const std::vector<GSpec>& specs) {
+  if (specs.empty()) return;
+  int64_t off = 0;
+  int cnt = 0;
+  const int r_first = (int)gr.size();
+  for (const GSpec& g : specs) {
+    const int jid = (int)gj.size();
+    gj.push_back(g.J);
+    const int K = g.Kstat;
+    const int nch = std::max(1, (K + CH - 1) / CH);
+    const int counter = cnt++;
+    for (int c = 0; c < nch; ++c)
+      gr.push_back(GemmRed{jid, c * CH, std::min(CH, K - c * CH), nch, c, off + (int64_t)c * KCAP * KCAP,
+                           counter});
+    if (nch > 1) off += (int64_t)nch * KCAP * KCAP;
+  }
+  push(Op{OP_GRED, r_first, (int)gr.size() - r_first});
+  ws_lane[lane] = std::max(ws_lane[lane], off);
+  cnt_lane[lane] = std::max(cnt_lane[lane], cnt);
+}
+
+namespace {
+// one device buffer for all descriptor arrays of a plan (one allocation, one copy)
+struct Packer {
+  std::vector<char>& buf;
+  std::vector<std::pair<size_t, void**>> fix;
+  template <class T>
+  void add(const std::vector<T>& v, T** dptr) {
+    size_t off = (buf.size() + 255) & ~(size_t)255;
+    buf.resize(off + std::max<size_t>(1, v.size()) * sizeof(T));
+    if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(T));
+    fix.push_back({off, (void**)dptr});
+  }
+};
+}  // namespace
+
+hodlr_status Plan::upload_all(DMem& mem, hipStream_t st) {
+  staged.clear();
+  Packer pk{staged, {}};
+  pk.add(trj, &d_trj);
+  pk.add(trc, &d_trc);
+  pk.add(trf, &d_trf);
+  pk.add(mmj, &d_mmj);
+  pk.add(mmp, &d_mmp);
+  pk.add(mma, &d_mma);
+  pk.add(gj, &d_gj);
+  pk.add(gt, &d_gt);
+  pk.add(gr, &d_gr);
+  pk.add(lj, &d_lj);
+  pk.add(vj, &d_vj);
+  char* base = nullptr;
+  TRY(mem.alloc(&base, staged.size()));
+  for (auto& f : pk.fix) *f.second = base + f.first;
+  return h2d(base, staged.data(), staged.size(), st);
+}
+
+// ------------------------------------------------------------------ execution
+namespace {
+
+hodlr_status ensure_work(DMem& mem, Work& W, int64_t ws_need, int cnt_need, bool leafws, hipStream_t st) {
   if (W.err == nullptr) {
     TRY(mem.alloc(&W.err, 4));
     TRY(mem.alloc(&W.fc, FC_SIZE));
-    HIPCHK(hipMemsetAsync(W.err, 0, 4 * sizeof(int), st));
-    HIPCHK(hipMemsetAsync(W.fc, 0, FC_SIZE * sizeof(double), st));
+    TRY(dzero(W.err, 4 * sizeof(int), st));
+    TRY(dzero(W.fc, FC_SIZE * sizeof(double), st));
   }
   if (ws_need > W.ws_size) {
     TRY(mem.alloc(&W.ws, (size_t)ws_need));
@@ -577,7 +473,7 @@ hodlr_status ensure_work(DMem& mem, Work& W, int64_t ws_need, int cnt_need, bool
   }
   if (cnt_need > W.cnt_size) {
     TRY(mem.alloc(&W.counters, (size_t)cnt_need));
-    HIPCHK(hipMemsetAsync(W.counters, 0, (size_t)cnt_need * sizeof(int), st));
+    TRY(dzero(W.counters, (size_t)cnt_need * sizeof(int), st));
     W.cnt_size = cnt_need;
   }
   if (leafws && W.leaf.H == nullptr) {
@@ -588,21 +484,39 @@ hodlr_status ensure_work(DMem& mem, Work& W, int64_t ws_need, int cnt_need, bool
   return HODLR_OK;
 }
 
-bool g_attr_done = false;
+// sum of the striped device flop counters of categories [c0, c1) (synchronous); -1 on failure
+double flop_sum(const double* fc, int c0, int c1) {
+  std::vector<double> h(FC_SIZE);
+  if (hipMemcpy(h.data(), fc, FC_SIZE * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return -1.0;
+  double tot = 0.0;
+  for (int c = c0; c < c1; ++c)
+    for (int k = 0; k < FC_STRIPE; ++k) tot += h[c * FC_STRIPE + k];
+  return tot;
+}
+double flop_total(const double* fc) { return flop_sum(fc, 0, FC_N); }
+
+std::once_flag g_attr_once;
+hodlr_status g_attr_status = HODLR_OK;
+std::string g_attr_msg;
 
 hodlr_status set_attrs() {
-  if (g_attr_done) return HODLR_OK;
-  for (const void* f : {(const void*)k_tr_qr<16>, (const void*)k_tr_qr<32>, (const void*)k_tr_qr<64>,
-                        (const void*)k_tr_qr<128>, (const void*)k_tr_small<16>, (const void*)k_tr_small<32>,
-                        (const void*)k_tr_small<64>, (const void*)k_tr_small<128>})
-    HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TR_QR_LDS));
-  HIPCHK(hipFuncSetAttribute((const void*)k_tr_form, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)TR_FORM_LDS));
-  for (const void* f : {(const void*)k_mm_apply<16>, (const void*)k_mm_apply<64>})
-    HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mm_apply_lds(MAXLEAF)));
-  HIPCHK(hipFuncSetAttribute((const void*)k_leaf_step, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)LEAF_LDS));
-  g_attr_done = true;
+  std::call_once(g_attr_once, [] {
+    auto set = [](const void* f, size_t bytes) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      if (e != hipSuccess && g_attr_status == HODLR_OK) {
+        g_attr_status = HODLR_EDEVICE;
+        g_attr_msg = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e);
+      }
+    };
+    for (const void* f : {(const void*)k_tr_qr<16>, (const void*)k_tr_qr<32>, (const void*)k_tr_qr<64>,
+                          (const void*)k_tr_qr<128>, (const void*)k_tr_small<16>, (const void*)k_tr_small<32>,
+                          (const void*)k_tr_small<64>, (const void*)k_tr_small<128>})
+      set(f, TR_QR_LDS);
+    set((const void*)k_tr_form, TR_FORM_LDS);
+    for (const void* f : {(const void*)k_mm_apply<16>, (const void*)k_mm_apply<64>}) set(f, mm_apply_lds(MAXLEAF));
+    set((const void*)k_leaf_step, LEAF_LDS);
+  });
+  if (g_attr_status != HODLR_OK) return fail(g_attr_status, g_attr_msg);
   return HODLR_OK;
 }
 
@@ -627,12 +541,10 @@ void launch(const Launch& L, void (*kern)(P...), dim3 g, dim3 b, size_t sh, hipS
   (void)hipExtLaunchKernel((const void*)kern, g, b, args, sh, st, L.e0, L.e1, 0);
 }
 
-bool op_launches(const Op& o) { return o.count > 0 && o.type != OP_SIGNAL && o.type != OP_WAIT; }
-
-void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st, const Launch& L = Launch()) {
+void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st, const Launch& L, const Opnd& op) {
   if (!op_launches(o)) return;
-  double* ws = W.ws + P.ws_off(o.lane);
-  int* cnt = W.counters + P.cnt_off(o.lane);
+  double* ws = W.ws ? W.ws + P.ws_off(o.lane) : nullptr;
+  int* cnt = W.counters ? W.counters + P.cnt_off(o.lane) : nullptr;
   switch (o.type) {
     case OP_TRQR: {
       const int wt = P.wtop;
@@ -647,23 +559,23 @@ void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st, const Lau
       break;
     }
     case OP_TRFORM:
-      launch(L, k_tr_form, o.count, NT_MM, TR_FORM_LDS, st, P.d_trj, P.d_trf, o.first, ws);
+      launch(L, k_tr_form, o.count, NT_MM, TR_FORM_LDS, st, P.d_trj, P.d_trf, o.first, (const double*)ws);
       break;
     case OP_MMPROJ:
-      launch(L, k_mm_proj, o.count, NT_MM, 0, st, P.d_mmj, P.d_mmp, o.first, ws);
+      launch(L, k_mm_proj, o.count, NT_MM, 0, st, P.d_mmj, P.d_mmp, o.first, ws, op);
       break;
     case OP_MMRED:
-      launch(L, k_mm_red, o.count, NT_MM, 0, st, P.d_mmj, P.d_mmp, o.first, ws);
+      launch(L, k_mm_red, o.count, NT_MM, 0, st, P.d_mmj, P.d_mmp, o.first, ws, op);
       break;
     case OP_MMAPPLY:
       launch(L, o.a1 == 64 ? k_mm_apply<64> : k_mm_apply<16>, o.count, NT_MM, mm_apply_lds(P.mleaf), st,
-             P.d_mmj, P.d_mma, o.first, (const double*)ws);
+             P.d_mmj, P.d_mma, o.first, (const double*)ws, op);
       break;
     case OP_GTALL:
-      launch(L, k_gemm_tall, o.count, NT_MM, 0, st, P.d_gj, P.d_gt, o.first);
+      launch(L, k_gemm_tall, o.count, NT_MM, 0, st, P.d_gj, P.d_gt, o.first, op);
       break;
     case OP_GRED:
-      launch(L, k_gemm_red, o.count, NT_MM, 0, st, P.d_gj, P.d_gr, o.first, ws, cnt);
+      launch(L, k_gemm_red, o.count, NT_MM, 0, st, P.d_gj, P.d_gr, o.first, ws, cnt, op);
       break;
     case OP_LGATHER:
       launch(L, k_leaf_gather, o.count, NT_MM, 0, st, P.d_lj, o.first, (int)o.n);
@@ -685,7 +597,12 @@ void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st, const Lau
       launch(L, k_set_scal, (o.count + 63) / 64, 64, 0, st, P.d_vj, o.first, o.count);
       break;
     case OP_TRSM:
-      launch(L, k_leaf_trsm, o.count, NT_MM, 0, st, o.p0, o.a0, o.a0, o.p1, (int)o.n, o.count);
+      if (o.xs >= 0) {
+        if (op.s > 0)
+          launch(L, k_leaf_trsm, op.s, NT_MM, 0, st, o.p0, o.a0, o.a0, op.p[o.xs] + o.xoff, op.ld[o.xs], op.s);
+      } else {
+        launch(L, k_leaf_trsm, o.count, NT_MM, 0, st, o.p0, o.a0, o.a0, o.p1, (int)o.n, o.count);
+      }
       break;
   }
 }
@@ -695,7 +612,7 @@ void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st, const Lau
 // become event records and waits.  Without it every op runs on `st` in list
 // order, which is a valid serial order of the same work.
 hodlr_status run_ops(const Plan& P, const Work& W, hipStream_t st, hipStream_t aux = nullptr,
-                     const hipEvent_t* ev = nullptr) {
+                     const hipEvent_t* ev = nullptr, const Opnd& op = Opnd{}) {
   TRY(set_attrs());
   if (aux != nullptr) {
     HIPCHK(hipEventRecord(ev[P.n_events], st));
@@ -708,7 +625,7 @@ hodlr_status run_ops(const Plan& P, const Work& W, hipStream_t st, hipStream_t a
     } else if (o.type == OP_WAIT) {
       if (aux != nullptr) HIPCHK(hipStreamWaitEvent(s, ev[o.a0], 0));
     } else {
-      run_op(P, W, o, s);
+      run_op(P, W, o, s, Launch(), op);
     }
   }
   if (aux != nullptr) {
@@ -719,13 +636,29 @@ hodlr_status run_ops(const Plan& P, const Work& W, hipStream_t st, hipStream_t a
   return HODLR_OK;
 }
 
-// power-iteration estimate of |M|_2 (50 steps on M^T M from x0 = 1/sqrt(n));
-// writes the result to *out (device).  x, y, z: device vectors of length n.
-void plan_norm2(Plan& P, const Tree& t, HView V, int iters, double* x, double* y, double* z, double* out);
+// a launch sequence kept by a handle and replayed with new operands
+struct CachedPlan {
+  Plan P;
+  DMem mem;  // the descriptors
+};
+
+// zero-filled per-call counters (a kernel, so that a caller may capture the call)
+hodlr_status zero_counters(int* cnt, int n, hipStream_t st) {
+  if (n <= 0) return HODLR_OK;
+  k_zero_i32<<<(n + 255) / 256, 256, 0, st>>>(cnt, n);
+  HIPCHK(hipGetLastError());
+  return HODLR_OK;
+}
 
 }  // namespace
+}  // namespace hqh
+
+using namespace hqh;
 
 // ------------------------------------------------------------------ handles
+// A HODLR matrix on the device, or a borrowed view of one factor of a QR
+// (hodlr_qr_factor): then the leaves are unit lower (Y) or upper (T, R)
+// triangular and only one family of off-diagonal blocks is present.
 struct hodlr_s {
   Tree t;
   int cap = 0;
@@ -733,9 +666,20 @@ struct hodlr_s {
   LeafSet leaves;
   BlockSet up, lo;
   int* ranks = nullptr;  // [0,2^L) up, [2^L, 2^(L+1)) lo
-  std::vector<int32_t> h_ranks_in;
-  Work work;  // for products / norm estimates
+  int* rank_up_dev = nullptr;
+  int* rank_lo_dev = nullptr;
+  int leaf_kind = LEAF_FULL;
+  bool has_up = true, has_lo = true;
+  bool borrowed = false;
+  std::mutex mu;                          // guards the cached product sequences
+  std::unique_ptr<CachedPlan> mmplan[2];  // Z = A X, Z = A^T X
+  HView view() const {
+    return HView{t.L, has_up ? up.dview : nullptr, has_lo ? lo.dview : nullptr, leaves.dview, leaf_kind};
+  }
 };
+
+namespace hqh {
+namespace {
 
 // The launch schedule of one batch of factorisations that share a tree: one
 // plan whose every launch carries the jobs of all of them, the workspace of
@@ -756,6 +700,13 @@ struct Batch {
   }
 };
 
+// rank-log sites (the first field of a key)
+enum : int { RL_ORTH = 0, RL_S = 1, RL_A12 = 2, RL_UPDATE = 3, RL_T = 4 };
+using LogKey = std::array<int, 5>;
+
+}  // namespace
+}  // namespace hqh
+
 struct hodlr_qr_s {
   Tree t;
   int cap = 0;
@@ -766,13 +717,21 @@ struct hodlr_qr_s {
   double anorm = 0, eps = 0, tauA = 0, tauT = 0;
   double anorm_in = 0;     // |A|_2 given by the caller (<= 0: estimated)
   double* scal = nullptr;  // device: |A|_2, eps*|A|_2, eps
-  Work work;               // error word, flop counters, leaf workspace; ws of apply/solve
+  Work work;               // error word, flop counters, leaf workspace
   // temporaries of the node steps (n x cap each)
   double *SL = nullptr, *SR = nullptr, *SLt = nullptr, *Z1 = nullptr, *Z2 = nullptr, *Z4 = nullptr,
          *SRW = nullptr, *TL = nullptr, *TR = nullptr, *Z5 = nullptr, *Wm = nullptr, *Mg = nullptr;
-  double *X1 = nullptr, *X2 = nullptr;  // n x SMAX scratch of apply_q / solve / the norm estimate
+  double *X1 = nullptr, *X2 = nullptr;   // n x 2 vectors of the norm estimate
   std::shared_ptr<Batch> batch;          // the schedule (dropped once the factors are final)
   int64_t n_launch = 0, n_trunc = 0;     // counts of that schedule per factorisation
+  // rank log: (input width, kept rank) per recompression, keys on the host
+  int* rlog = nullptr;
+  int64_t nlog_cap = 0;
+  std::vector<LogKey> logkeys;
+  // cached launch sequences of apply Q (Q X, Q^T X) and of the back substitution
+  std::unique_ptr<CachedPlan> applyp[2], solvep;
+  // borrowed views of the factors (hodlr_qr_factor)
+  std::unique_ptr<hodlr_s> vY, vT, vR;
   HView view_gen() const { return HView{t.L, up.dview, lo.dview, leaves.dview, LEAF_FULL}; }
   HView view_y() const { return HView{t.L, nullptr, lo.dview, leaves.dview, LEAF_UNIT_LOWER}; }
   HView view_t() const { return HView{t.L, tup.dview, nullptr, tleaves.dview, LEAF_UPPER}; }
@@ -783,6 +742,7 @@ struct hodlr_qr_s {
   int* rank_s() { return ranks + 3 * (1 << t.L); }
 };
 
+namespace hqh {
 namespace {
 
 MmSpec mmspec(HView M, bool up, bool lo, int v, int trans, const double* X, int ldX, const int* s_dev,
@@ -809,7 +769,7 @@ MmSpec mmspec(HView M, bool up, bool lo, int v, int trans, const double* X, int 
 GemmJob gjob(int ta, int tb, int M, const int* Md, int N, const int* Nd, int K, const int* Kd,
              const double* A, int lda, const double* B, int ldb, double* C, int ldc, double alpha,
              double beta, int fc, double* flops = nullptr) {
-  GemmJob J;
+  GemmJob J{};
   J.ta = ta;
   J.tb = tb;
   J.M = M;
@@ -827,8 +787,30 @@ GemmJob gjob(int ta, int tb, int M, const int* Md, int N, const int* Nd, int K, 
   J.alpha = alpha;
   J.beta = beta;
   J.fc = fc;
+  J.as_ = J.bs_ = J.cs_ = -1;
   J.flops = flops;
   return J;
+}
+
+// number of recompressions of one factorisation (the rank log's length):
+// one per lower block (orthogonalisation), and at each internal node the S~
+// chain (1 + q), R's upper block, two per internal node of the right subtree
+// (-_H) and the T~12 chain (max(1, q)), q = the node's row groups
+int64_t count_truncs(const Tree& t) {
+  int64_t c = t.nleaf() - 1;
+  struct R {
+    const Tree& t;
+    int64_t& c;
+    void go(int v, int q) {
+      if (t.is_leaf(v)) return;
+      const int Rc = 2 * v + 1;
+      c += (1 + q) + 1 + 2 * (int64_t)((t.subtree_size(Rc) - 1) / 2) + std::max(1, q);
+      go(2 * v, q + 1);
+      go(Rc, q);
+    }
+  } r{t, c};
+  r.go(1, 0);
+  return c;
 }
 
 // Builds the launch list of a batch of factorisations with the same tree
@@ -839,6 +821,7 @@ struct QRBuilder {
   Plan& P;
   const Tree& t;
   int cap;
+  int plant = 0;  // hazard-checker self test: see hodlr_plan_check
   QRBuilder(const std::vector<hodlr_qr_s*>& fs, Plan& plan)
       : Fs(fs), P(plan), t(fs[0]->t), cap(fs[0]->cap) {}
 
@@ -883,7 +866,7 @@ struct QRBuilder {
   }
 
   TrSpec trspec(hodlr_qr_s& F, Seg l0, Seg l1, Seg r0, Seg r1, int mL, int mR, const double* tau,
-                double* oL, double* oR, int ldL, int ldR, int* orank, int fc, int flags = 0) {
+                double* oL, double* oR, int ldL, int ldR, int* orank, int fc, const LogKey& key, int flags = 0) {
     TrSpec s;
     s.seg[0][0] = l0;
     s.seg[0][1] = l1;
@@ -902,6 +885,9 @@ struct QRBuilder {
     s.fc = fc;
     s.err = F.work.err;
     s.flops = F.work.fc;
+    const int64_t slot = (int64_t)F.logkeys.size();
+    s.log = slot < F.nlog_cap ? F.rlog + 2 * slot : nullptr;
+    F.logkeys.push_back(key);
     return s;
   }
 
@@ -917,6 +903,7 @@ struct QRBuilder {
     }
     const int Lc = 2 * v, Rc = 2 * v + 1;
     const int mL = (int)t.m(Lc), mR = (int)t.m(Rc);
+    const int klo = (int)t.lo[v], khi = (int)t.hi[v];
     // first block column: hQR(A11, A21, [B_R1; C1])
     std::vector<int> gl;
     gl.push_back(v);
@@ -929,10 +916,13 @@ struct QRBuilder {
       hodlr_qr_s& F = *Fp;
       const HBlk& A12 = F.up.hview[v];
       const HBlk& A21 = F.lo.hview[v];
-      mms.push_back(mmspec(F.view_y(), false, true, Lc, 1, A12.U, mL, F.rank_up(v), F.Z1, mL, 1.0, 0.0, 1, 0,
-                           F.work.fc));
-      mms.push_back(mmspec(F.view_gen(), true, true, Rc, 1, A21.U, mR, F.rank_lo(v), F.Z2, mR, 1.0, 0.0, 0,
-                           0, F.work.fc));
+      MmSpec a = mmspec(F.view_y(), false, true, Lc, 1, A12.U, mL, F.rank_up(v), F.Z1, mL, 1.0, 0.0, 1, 0,
+                        F.work.fc);
+      MmSpec b = mmspec(F.view_gen(), true, true, Rc, 1, A21.U, mR, F.rank_lo(v), F.Z2, mR, 1.0, 0.0, 0, 0,
+                        F.work.fc);
+      a.rld = b.rld = cap;
+      mms.push_back(a);
+      mms.push_back(b);
     }
     P.mm(t, mms);
     // S~ = T(Y_A11^T A12 + Y_A21^T A22 + sum over groups), term by term
@@ -943,17 +933,20 @@ struct QRBuilder {
       int* k12 = F.rank_up(v);
       int* k21 = F.rank_lo(v);
       trs.push_back(trspec(F, mkseg(F.Z1, mL, k12), mkseg(A21.V, mL, k21), mkseg(A12.V, mR, k12),
-                           mkseg(F.Z2, mR, k21), mL, mR, F.scal + 1, F.SL, F.SR, mL, mR, F.rank_s(), FC_TRUNC));
+                           mkseg(F.Z2, mR, k21), mL, mR, F.scal + 1, F.SL, F.SR, mL, mR, F.rank_s(), FC_TRUNC,
+                           LogKey{RL_S, klo, khi, 0, 0}));
     }
     P.trunc(trs);
-    for (int g : groups) {
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const int g = groups[gi];
       trs.clear();
       for (hodlr_qr_s* Fp : Fs) {
         hodlr_qr_s& F = *Fp;
         int* rS = F.rank_s();
         trs.push_back(trspec(F, mkseg(F.SL, mL, rS), mkseg(gslice(F, g, Lc), gld(g), F.rank_lo(g)),
                              mkseg(F.SR, mR, rS), mkseg(gslice(F, g, Rc), gld(g), F.rank_lo(g)), mL, mR,
-                             F.scal + 1, F.SL, F.SR, mL, mR, rS, FC_TRUNC));
+                             F.scal + 1, F.SL, F.SR, mL, mR, rS, FC_TRUNC,
+                             LogKey{RL_S, klo, khi, 1 + (int)gi, 0}));
       }
       P.trunc(trs);
     }
@@ -962,16 +955,20 @@ struct QRBuilder {
     mms.clear();
     for (hodlr_qr_s* Fp : Fs) {
       hodlr_qr_s& F = *Fp;
-      mms.push_back(mmspec(F.view_t(), true, false, Lc, 1, F.SL, mL, F.rank_s(), F.SLt, mL, 1.0, 0.0, 1, 0,
-                           F.work.fc));
+      MmSpec a = mmspec(F.view_t(), true, false, Lc, 1, F.SL, mL, F.rank_s(), F.SLt, mL, 1.0, 0.0, 1, 0,
+                        F.work.fc);
+      a.rld = cap;
+      mms.push_back(a);
     }
     P.mm(t, mms);
     // Y_A11 S_L for the new upper block
     mms.clear();
     for (hodlr_qr_s* Fp : Fs) {
       hodlr_qr_s& F = *Fp;
-      mms.push_back(mmspec(F.view_y(), false, true, Lc, 0, F.SLt, mL, F.rank_s(), F.Z4, mL, 1.0, 0.0, 1, 0,
-                           F.work.fc));
+      MmSpec a = mmspec(F.view_y(), false, true, Lc, 0, F.SLt, mL, F.rank_s(), F.Z4, mL, 1.0, 0.0, 1, 0,
+                        F.work.fc);
+      a.rld = cap;
+      mms.push_back(a);
     }
     P.mm(t, mms);
     // W = Y~_B21 S_L (k21 x s) and M_g = S_L^T Y_C1g^T (s x k_g)
@@ -1029,7 +1026,8 @@ struct QRBuilder {
         int* k21 = F.rank_lo(v);
         int* rS = F.rank_s();
         sp.push_back(trspec(F, mkseg(A12.U, mL, k12), mkseg(F.Z4, mL, rS, -1.0), mkseg(A12.V, mR, k12),
-                            mkseg(F.SR, mR, rS), mL, mR, F.scal + 1, A12.U, A12.V, mL, mR, k12, FC_TRUNC));
+                            mkseg(F.SR, mR, rS), mL, mR, F.scal + 1, A12.U, A12.V, mL, mR, k12, FC_TRUNC,
+                            LogKey{RL_A12, klo, khi, 0, 0}));
         for (int u : sub) {
           for (int kind = 0; kind < 2; ++kind) {
             const HBlk& b = kind == 0 ? F.up.hview[u] : F.lo.hview[u];
@@ -1037,7 +1035,7 @@ struct QRBuilder {
             const int64_t ri = b.r0 - t.lo[Rc], cj = b.c0 - t.lo[Rc];
             sp.push_back(trspec(F, mkseg(b.U, b.ldU, kb), mkseg(A21.U + ri, mR, k21), mkseg(b.V, b.ldV, kb),
                                 mkseg(F.SRW + cj, mR, k21, -1.0), b.rows, b.cols, F.scal + 1, b.U, b.V,
-                                b.ldU, b.ldV, kb, FC_TRUNC));
+                                b.ldU, b.ldV, kb, FC_TRUNC, LogKey{RL_UPDATE, klo, khi, (int)b.r0, (int)b.c0}));
           }
         }
         // leaves of the trailing part: D -= U21(I) (S_R W^T)(I)^T
@@ -1062,8 +1060,10 @@ struct QRBuilder {
     mms.clear();
     for (hodlr_qr_s* Fp : Fs) {
       hodlr_qr_s& F = *Fp;
-      mms.push_back(mmspec(F.view_y(), false, true, Rc, 1, F.lo.hview[v].U, mR, F.rank_lo(v), F.Z5, mR, 1.0,
-                           0.0, 1, 0, F.work.fc));
+      MmSpec a = mmspec(F.view_y(), false, true, Rc, 1, F.lo.hview[v].U, mR, F.rank_lo(v), F.Z5, mR, 1.0, 0.0,
+                        1, 0, F.work.fc);
+      a.rld = cap;
+      mms.push_back(a);
     }
     P.mm(t, mms);
     const size_t nterm = groups.empty() ? 1 : groups.size();
@@ -1074,16 +1074,20 @@ struct QRBuilder {
         const HBlk& A21 = F.lo.hview[v];
         int* k21 = F.rank_lo(v);
         int* rt = F.rank_t(v);
+        // self test of the hazard checker: node 2's first T~12 recompression
+        // writes into S~'s buffer, which the root's main chain uses meanwhile
+        double* outL = (plant && v == 2 && i == 0) ? F.SL : F.TL;
         const Seg l0 = i == 0 ? mkseg(A21.V, mL, k21) : mkseg(F.TL, mL, rt);
         const Seg r0 = i == 0 ? mkseg(F.Z5, mR, k21) : mkseg(F.TR, mR, rt);
+        const LogKey key{RL_T, klo, khi, (int)i, 0};
         if (groups.empty()) {
-          trs.push_back(trspec(F, l0, noseg(), r0, noseg(), mL, mR, F.scal + 2, F.TL, F.TR, mL, mR, rt,
-                               FC_TRUNC));
+          trs.push_back(trspec(F, l0, noseg(), r0, noseg(), mL, mR, F.scal + 2, outL, F.TR, mL, mR, rt,
+                               FC_TRUNC, key));
         } else {
           const int g = groups[i];
           trs.push_back(trspec(F, l0, mkseg(gslice(F, g, Lc), gld(g), F.rank_lo(g)), r0,
-                               mkseg(gslice(F, g, Rc), gld(g), F.rank_lo(g)), mL, mR, F.scal + 2, F.TL, F.TR,
-                               mL, mR, rt, FC_TRUNC));
+                               mkseg(gslice(F, g, Rc), gld(g), F.rank_lo(g)), mL, mR, F.scal + 2, outL, F.TR,
+                               mL, mR, rt, FC_TRUNC, key));
         }
       }
       P.trunc(trs);
@@ -1094,8 +1098,11 @@ struct QRBuilder {
       hodlr_qr_s& F = *Fp;
       const HBlk& T12 = F.tup.hview[v];
       int* rt = F.rank_t(v);
-      mms.push_back(mmspec(F.view_t(), true, false, Lc, 0, F.TL, mL, rt, T12.U, mL, -1.0, 0.0, 1, 0, F.work.fc));
-      mms.push_back(mmspec(F.view_t(), true, false, Rc, 1, F.TR, mR, rt, T12.V, mR, 1.0, 0.0, 1, 0, F.work.fc));
+      MmSpec a = mmspec(F.view_t(), true, false, Lc, 0, F.TL, mL, rt, T12.U, mL, -1.0, 0.0, 1, 0, F.work.fc);
+      MmSpec b = mmspec(F.view_t(), true, false, Rc, 1, F.TR, mR, rt, T12.V, mR, 1.0, 0.0, 1, 0, F.work.fc);
+      a.rld = b.rld = cap;
+      mms.push_back(a);
+      mms.push_back(b);
     }
     P.mm(t, mms);
     const int evT = P.signal();
@@ -1112,7 +1119,7 @@ struct QRBuilder {
         const HBlk& b = F.lo.hview[v];
         orth.push_back(trspec(F, mkseg(b.U, b.ldU, F.rank_lo(v)), noseg(), mkseg(b.V, b.ldV, F.rank_lo(v)),
                               noseg(), b.rows, b.cols, F.scal + 2, b.U, b.V, b.ldU, b.ldV, F.rank_lo(v),
-                              FC_ORTH, TR_ORTH));
+                              FC_ORTH, LogKey{RL_ORTH, (int)b.r0, (int)b.c0, 0, 0}, TR_ORTH));
       }
     }
     P.trunc(orth);
@@ -1120,11 +1127,12 @@ struct QRBuilder {
   }
 };
 
-// One power-iteration estimate of |M|_2 per item (50 steps on M^T M from
+// One power-iteration estimate of |M|_2 per item (iters steps on M^T M from
 // x0 = 1/sqrt(n)), all items in the same launches; writes each result to
 // its out (device).  x, y, z: device vectors of length n per item.
 struct NormItem {
   HView V;
+  int rld;
   double *x, *y, *z, *out;
   double* flops;
 };
@@ -1140,8 +1148,12 @@ void plan_norm2(Plan& P, const Tree& t, const std::vector<NormItem>& items, int 
   P.vec(OP_FILL, fill);
   std::vector<MmSpec> a, b;
   for (const NormItem& it : items) {
-    a.push_back(mmspec(it.V, true, true, 1, 0, it.x, (int)n, nullptr, it.y, (int)n, 1.0, 0.0, 0, 1, it.flops));
-    b.push_back(mmspec(it.V, true, true, 1, 1, it.y, (int)n, nullptr, it.z, (int)n, 1.0, 0.0, 0, 1, it.flops));
+    MmSpec sa = mmspec(it.V, true, true, 1, 0, it.x, (int)n, nullptr, it.y, (int)n, 1.0, 0.0, 0, 1, it.flops);
+    MmSpec sb = mmspec(it.V, true, true, 1, 1, it.y, (int)n, nullptr, it.z, (int)n, 1.0, 0.0, 0, 1, it.flops);
+    sa.fc = sb.fc = FC_NORM;
+    sa.rld = sb.rld = it.rld;
+    a.push_back(sa);
+    b.push_back(sb);
   }
   for (int i = 0; i < iters; ++i) {
     P.mm(t, a);
@@ -1170,12 +1182,35 @@ hodlr_status reset_factor(hodlr_qr_s& F, const hodlr_s& A, hipStream_t st) {
   return HODLR_OK;
 }
 
+// the borrowed views of F's factors (hodlr_qr_factor)
+void make_views(hodlr_qr_s& F) {
+  const int nn = 1 << F.t.L;
+  auto mk = [&](const LeafSet& L, const BlockSet* up, const BlockSet* lo, int* rup, int* rlo, int kind) {
+    auto V = std::make_unique<hodlr_s>();
+    V->t = F.t;
+    V->cap = F.cap;
+    V->leaves = L;
+    if (up) V->up = *up;
+    if (lo) V->lo = *lo;
+    V->has_up = up != nullptr;
+    V->has_lo = lo != nullptr;
+    V->rank_up_dev = rup;
+    V->rank_lo_dev = rlo;
+    V->leaf_kind = kind;
+    V->borrowed = true;
+    return V;
+  };
+  F.vY = mk(F.leaves, nullptr, &F.lo, nullptr, F.ranks + nn, LEAF_UNIT_LOWER);
+  F.vT = mk(F.tleaves, &F.tup, nullptr, F.ranks + 2 * nn, nullptr, LEAF_UPPER);
+  F.vR = mk(F.leaves, &F.up, nullptr, F.ranks, nullptr, LEAF_UPPER);
+}
+
 // device storage of the factors of A (no schedule yet)
 hodlr_status make_storage(const hodlr_s& A, double eps, double anorm, hipStream_t st,
                           std::unique_ptr<hodlr_qr_s>& out) {
   auto F = std::make_unique<hodlr_qr_s>();
   F->mem.zero = true;
-  F->mem.zero_stream = st;
+  F->mem.stream = st;
   F->t = A.t;
   F->cap = A.cap;
   F->anorm = anorm;
@@ -1187,9 +1222,7 @@ hodlr_status make_storage(const hodlr_s& A, double eps, double anorm, hipStream_
   if (t.L > MAXGROUPS) return fail(HODLR_EINVAL, "too many levels");
   const int nn = 1 << t.L;
   TRY(F->mem.alloc(&F->scal, 8));
-  HIPCHK(hipMemsetAsync(F->scal, 0, 8 * sizeof(double), st));
   TRY(F->mem.alloc(&F->ranks, 3 * (size_t)nn + 8));
-  HIPCHK(hipMemsetAsync(F->ranks, 0, (3 * (size_t)nn + 8) * sizeof(int), st));
   TRY(make_leaves(F->mem, t, F->leaves));
   TRY(make_leaves(F->mem, t, F->tleaves));
   TRY(make_blocks(F->mem, t, F->cap, BK_UP, F->ranks, F->up));
@@ -1205,18 +1238,22 @@ hodlr_status make_storage(const hodlr_s& A, double eps, double anorm, hipStream_
     TRY(F->mem.alloc(p, nc));
   TRY(F->mem.alloc(&F->Wm, (size_t)KCAP * KCAP));
   TRY(F->mem.alloc(&F->Mg, (size_t)KCAP * KCAP * (t.L + 1)));
-  TRY(F->mem.alloc(&F->X1, (size_t)t.n * SMAX));
-  TRY(F->mem.alloc(&F->X2, (size_t)t.n * SMAX));
+  TRY(F->mem.alloc(&F->X1, (size_t)t.n * 2));
+  TRY(F->mem.alloc(&F->X2, (size_t)t.n));
+  F->nlog_cap = count_truncs(t);
+  TRY(F->mem.alloc(&F->rlog, 2 * (size_t)F->nlog_cap));
   TRY(ensure_work(F->mem, F->work, 0, 1, true, st));  // error word, flop counters, leaf workspace
-  // later allocations (plans of apply_q / solve) are filled on their own streams
   F->mem.zero = false;
+  make_views(*F);
   out = std::move(F);
   return HODLR_OK;
 }
 
 // the schedule of a batch of factors that share a tree and a capacity
-hodlr_status make_batch(const std::vector<hodlr_qr_s*>& Fs, hipStream_t st, std::shared_ptr<Batch>& out) {
+hodlr_status make_batch(const std::vector<hodlr_qr_s*>& Fs, hipStream_t st, std::shared_ptr<Batch>& out,
+                        int plant = 0) {
   auto B = std::make_shared<Batch>();
+  B->mem.stream = st;
   Plan& P = B->plan;
   const Tree& t = Fs[0]->t;
   P.wtop = 2 * Fs[0]->cap;
@@ -1225,13 +1262,15 @@ hodlr_status make_batch(const std::vector<hodlr_qr_s*>& Fs, hipStream_t st, std:
   std::vector<NormItem> est;
   std::vector<VecJob> sc;
   for (hodlr_qr_s* F : Fs) {
+    F->logkeys.clear();
     if (!(F->anorm_in > 0.0))
-      est.push_back(NormItem{F->view_gen(), F->X1, F->X1 + t.n, F->X2, F->scal, F->work.fc});
+      est.push_back(NormItem{F->view_gen(), F->cap, F->X1, F->X1 + t.n, F->X2, F->scal, F->work.fc});
     sc.push_back(VecJob{nullptr, F->scal, 3, nullptr, F->eps, F->anorm_in > 0.0 ? F->anorm_in : -1.0});
   }
   if (!est.empty()) plan_norm2(P, t, est, 50);
   P.vec(OP_SETSCAL, sc);
   QRBuilder qb(Fs, P);
+  qb.plant = plant;
   qb.build();
   TRY(P.upload_all(B->mem, st));
   TRY(ensure_work(B->mem, B->work, P.ws_need(), P.cnt_need(), false, st));
@@ -1268,11 +1307,11 @@ hodlr_status lane_streams(Batch& B) {
 // every edge of it was present, so the graph keeps the serial order.
 hodlr_status run_batch(Batch& B, const std::vector<hodlr_qr_s*>& Fs, const std::vector<const hodlr_s*>& As,
                        uint32_t flags, hipStream_t st) {
-  TRY(lane_streams(B));
   if (!(flags & HODLR_QR_GRAPH)) {
     for (size_t i = 0; i < Fs.size(); ++i) TRY(reset_factor(*Fs[i], *As[i], st));
-    hipStream_t aux = (flags & HODLR_QR_ONE_STREAM) ? nullptr : B.aux;
-    return run_ops(B.plan, B.work, st, aux, B.events.data());
+    if (flags & HODLR_QR_ONE_STREAM) return run_ops(B.plan, B.work, st);
+    TRY(lane_streams(B));
+    return run_ops(B.plan, B.work, st, B.aux, B.events.data());
   }
   if (B.graph == nullptr) {
     // capture on a private stream so that the caller's stream state is untouched
@@ -1306,13 +1345,91 @@ hodlr_status run_factor(hodlr_qr_s& F, const hodlr_s& A, uint32_t flags, hipStre
   return run_batch(*F.batch, {&F}, {&A}, flags, st);
 }
 
-// keep the schedule's counts, release its plan and workspace (the factors no
-// longer need them; apply_q / solve build their own small plans)
-void drop_schedule(hodlr_qr_s& F) {
-  if (!F.batch) return;
-  F.n_launch = F.batch->n_launch;
-  F.n_trunc = F.batch->plan.n_trunc / std::max(1, F.batch->size);
-  F.batch.reset();
+// ---- cached launch sequences of the finished factors
+// apply Q (trans 0) or Q^T (trans 1): slot 0 = X (n x s, the caller's), slots
+// 1 and 2 = n x s temporaries:  W1 = Y^T X; W2 = op(T) W1; X -= Y W2
+// (Q = I - Y T Y^T, eq. compactwy)
+hodlr_status build_apply_plan(hodlr_qr_s& F, int trans, hipStream_t st, std::unique_ptr<CachedPlan>& out) {
+  auto C = std::make_unique<CachedPlan>();
+  C->mem.stream = st;
+  Plan& P = C->P;
+  MmSpec a = mmspec(F.view_y(), false, true, 1, 1, nullptr, 0, nullptr, nullptr, 0, 1.0, 0.0, 1);
+  MmSpec b = mmspec(F.view_t(), true, false, 1, trans, nullptr, 0, nullptr, nullptr, 0, 1.0, 0.0, 1);
+  MmSpec c = mmspec(F.view_y(), false, true, 1, 0, nullptr, 0, nullptr, nullptr, 0, -1.0, 1.0, 1);
+  a.xs = 0, a.zs = 1;
+  b.xs = 1, b.zs = 2;
+  c.xs = 2, c.zs = 0;
+  a.rld = b.rld = c.rld = F.cap;
+  P.mm(F.t, {a});
+  P.mm(F.t, {b});
+  P.mm(F.t, {c});
+  TRY(P.upload_all(C->mem, st));
+  out = std::move(C);
+  return HODLR_OK;
+}
+
+// back substitution with the upper triangular HODLR R, last leaf first:
+// x2 = R22^{-1} c2; c1 -= R12 x2; x1 = R11^{-1} c1.  Slot 0 = the right-hand
+// sides (n x s), slot 1 = a KCAP x s temporary (V12^T x2).
+hodlr_status build_solve_plan(hodlr_qr_s& F, hipStream_t st, std::unique_ptr<CachedPlan>& out) {
+  auto C = std::make_unique<CachedPlan>();
+  C->mem.stream = st;
+  Plan& P = C->P;
+  const Tree& t = F.t;
+  struct Rec {
+    hodlr_qr_s& f;
+    Plan& P;
+    const Tree& t;
+    void go(int v) {
+      if (t.is_leaf(v)) {
+        const int j = v - t.nleaf();
+        Op o{OP_TRSM};
+        o.a0 = (int)t.m(v);
+        o.p0 = f.leaves.hview[j].D;
+        o.xs = 0;
+        o.xoff = t.lo[v];
+        P.push(o);
+        return;
+      }
+      go(2 * v + 1);
+      const HBlk& b = f.up.hview[v];
+      const int mL = (int)t.m(2 * v), mR = (int)t.m(2 * v + 1);
+      // Wt = V12^T x2 (k x s), c1 -= U12 Wt
+      GemmJob r = gjob(1, 0, 0, f.rank_up(v), 0, nullptr, mR, nullptr, b.V, mR, nullptr, 0, nullptr, KCAP, 1.0,
+                       0.0, FC_DENSE);
+      r.bs_ = 0;
+      r.boff = t.lo[2 * v + 1];
+      r.cs_ = 1;
+      P.gemm_red({GSpec{r, KCAP, KCAP, mR}});
+      GemmJob u = gjob(0, 0, mL, nullptr, 0, nullptr, 0, f.rank_up(v), b.U, mL, nullptr, KCAP, nullptr, 0, -1.0,
+                       1.0, FC_DENSE);
+      u.bs_ = 1;
+      u.cs_ = 0;
+      u.coff = t.lo[2 * v];
+      P.gemm_tall({GSpec{u, mL, SMAX, 0}});
+      go(2 * v);
+    }
+  } rec{F, P, t};
+  rec.go(1);
+  TRY(P.upload_all(C->mem, st));
+  out = std::move(C);
+  return HODLR_OK;
+}
+
+// Z = op(M) X for a HODLR matrix or a factor view: slot 0 = X, slot 1 = Z
+hodlr_status build_mm_plan(const hodlr_s& A, int trans, hipStream_t st, std::unique_ptr<CachedPlan>& out) {
+  auto C = std::make_unique<CachedPlan>();
+  C->mem.stream = st;
+  Plan& P = C->P;
+  MmSpec a = mmspec(A.view(), A.has_up, A.has_lo, 1, trans, nullptr, 0, nullptr, nullptr, 0, 1.0, 0.0,
+                    A.leaf_kind != LEAF_FULL ? 1 : 0);
+  a.xs = 0;
+  a.zs = 1;
+  a.rld = A.cap;
+  P.mm(A.t, {a});
+  TRY(P.upload_all(C->mem, st));
+  out = std::move(C);
+  return HODLR_OK;
 }
 
 hodlr_status finish_factor(hodlr_qr_s& F, hipStream_t st) {
@@ -1330,34 +1447,88 @@ hodlr_status finish_factor(hodlr_qr_s& F, hipStream_t st) {
   return HODLR_OK;
 }
 
+// keep the schedule's counts, release its plan and workspace, and cache the
+// launch sequences of apply Q and solve (the factors are final)
+hodlr_status finalize_factor(hodlr_qr_s& F, hipStream_t st) {
+  if (F.batch) {
+    F.n_launch = F.batch->n_launch;
+    F.n_trunc = F.batch->plan.n_trunc / std::max(1, F.batch->size);
+    F.batch.reset();
+  }
+  F.mem.stream = st;
+  TRY(build_apply_plan(F, 0, st, F.applyp[0]));
+  TRY(build_apply_plan(F, 1, st, F.applyp[1]));
+  TRY(build_solve_plan(F, st, F.solvep));
+  return HODLR_OK;
+}
+
+// run a cached plan over the columns of the caller's operands in chunks of at
+// most SMAX: slots[c] = (pointer, leading dimension) of slot c at column 0;
+// slots flagged in `percol` advance by ld * c0 per chunk, the others are
+// temporaries reused by every chunk
+hodlr_status run_cached(const CachedPlan& C, hipStream_t st, int nslots, double* const* base, const int* ld,
+                        const bool* percol, int64_t nrhs, int smax, double* ws, int* cnt) {
+  Work W;
+  W.ws = ws;
+  W.counters = cnt;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += smax) {
+    Opnd op{};
+    for (int i = 0; i < nslots; ++i) {
+      op.p[i] = base[i] + (percol[i] ? c0 * (int64_t)ld[i] : 0);
+      op.ld[i] = ld[i];
+    }
+    op.s = (int)std::min<int64_t>(smax, nrhs - c0);
+    if (cnt != nullptr && C.P.uses_counters()) TRY(zero_counters(cnt, C.P.cnt_need(), st));
+    TRY(run_ops(C.P, W, st, nullptr, nullptr, op));
+  }
+  return HODLR_OK;
+}
+
 // power iteration on A^T A with HODLR products
-hodlr_status norm2_est_impl(hodlr_s& A, int iters, hipStream_t st, double* out) {
+hodlr_status norm2_est_impl(const hodlr_s& A, int iters, hipStream_t st, double* out) {
   const Tree& t = A.t;
   const int64_t n = t.n;
+  CallMem tmp(st);
   double *x, *y, *z, *res;
-  DMem tmp;
   TRY(tmp.alloc(&x, n));
   TRY(tmp.alloc(&y, n));
   TRY(tmp.alloc(&z, n));
   TRY(tmp.alloc(&res, 1));
-  HView V{t.L, A.up.dview, A.lo.dview, A.leaves.dview, LEAF_FULL};
   Plan P;
-  plan_norm2(P, t, {NormItem{V, x, y, z, res, nullptr}}, iters);
-  TRY(P.upload_all(tmp, st));
-  TRY(ensure_work(A.mem, A.work, P.ws_need(), P.cnt_need(), false, st));
-  TRY(run_ops(P, A.work, st));
+  plan_norm2(P, t, {NormItem{A.view(), A.cap, x, y, z, res, nullptr}}, iters);
+  DMem pm;
+  pm.stream = st;
+  TRY(P.upload_all(pm, st));
+  double* ws = nullptr;
+  TRY(tmp.alloc(&ws, (size_t)std::max<int64_t>(1, P.ws_need())));
+  Work W;
+  W.ws = ws;
+  TRY(run_ops(P, W, st));
   HIPCHK(hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   return HODLR_OK;
 }
 
 }  // namespace
+}  // namespace hqh
 
 // ================================================================== C ABI
 extern "C" {
 
 const char* hodlr_last_error(void) { return g_err.c_str(); }
-const char* hodlr_version(void) { return "hodlr-qr-gfx950 0.1"; }
+const char* hodlr_version(void) { return "hodlr-qr-gfx950 0.2"; }
+
+hodlr_status hodlr_set_allocator(void* (*alloc)(size_t, hodlr_stream_t, void*),
+                                 void (*release)(void*, hodlr_stream_t, void*), void* ctx) {
+  g_err.clear();
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(HODLR_EINVAL, "alloc and release must both be set or both be NULL");
+  std::lock_guard<std::mutex> lk(g_hook_mu);
+  g_hook.alloc = alloc;
+  g_hook.release = release;
+  g_hook.ctx = ctx;
+  return HODLR_OK;
+}
 
 hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t* leaf_off, const double* leaves,
                          const int64_t* leaf_data_off, const double* U, const int64_t* u_off,
@@ -1382,6 +1553,7 @@ hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t* leaf_off, con
   }
   hipStream_t st = (hipStream_t)stream;
   auto A = std::make_unique<hodlr_s>();
+  A->mem.stream = st;
   A->t.init(levels, leaf_off);
   A->cap = rank_cap;
   const Tree& t = A->t;
@@ -1403,6 +1575,8 @@ hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t* leaf_off, con
     TRY(check_finite(leaves + leaf_data_off[j], (size_t)(m * m), "leaves"));
   }
   TRY(A->mem.alloc(&A->ranks, 2 * (size_t)nl + 8));
+  A->rank_up_dev = A->ranks;
+  A->rank_lo_dev = A->ranks + nl;
   TRY(make_leaves(A->mem, t, A->leaves));
   TRY(make_blocks(A->mem, t, rank_cap, BK_UP, A->ranks, A->up));
   TRY(make_blocks(A->mem, t, rank_cap, BK_LO, A->ranks + nl, A->lo));
@@ -1432,7 +1606,6 @@ hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t* leaf_off, con
         std::memcpy(bv.data() + B.voff[v], V + v_off[bi], (size_t)(cols * k) * sizeof(double));
         hr[(kind == 0 ? 0 : nl) + v] = k;
       }
-  A->h_ranks_in = hr;
   HIPCHK(hipMemcpyAsync(A->leaves.D, hl.data(), hl.size() * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(A->up.U, uu.data(), uu.size() * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(A->up.V, uv.data(), uv.size() * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1444,13 +1617,15 @@ hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t* leaf_off, con
   return HODLR_OK;
 }
 
-void hodlr_free(hodlr_t* A) { delete A; }
+void hodlr_free(hodlr_t* A) {
+  if (A != nullptr && !A->borrowed) delete A;
+}
 void hodlr_qr_free(hodlr_qr_t* F) { delete F; }
 
 hodlr_status hodlr_norm2_est(const hodlr_t* A, int32_t iters, hodlr_stream_t stream, double* out) {
   g_err.clear();
   if (A == nullptr || out == nullptr || iters < 0) return fail(HODLR_EINVAL, "bad argument");
-  return norm2_est_impl(*const_cast<hodlr_t*>(A), iters, (hipStream_t)stream, out);
+  return norm2_est_impl(*A, iters, (hipStream_t)stream, out);
 }
 
 hodlr_status hodlr_qr(const hodlr_t* A, double eps, double anorm, uint32_t flags, hodlr_stream_t stream,
@@ -1458,19 +1633,21 @@ hodlr_status hodlr_qr(const hodlr_t* A, double eps, double anorm, uint32_t flags
   g_err.clear();
   if (A == nullptr || out == nullptr) return fail(HODLR_EINVAL, "NULL argument");
   *out = nullptr;
+  if (A->borrowed || A->leaf_kind != LEAF_FULL) return fail(HODLR_EINVAL, "A is a factor view, not a matrix");
   if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(HODLR_EINVAL, "eps must be finite and >= 0");
   hipStream_t st = (hipStream_t)stream;
   std::unique_ptr<hodlr_qr_s> F;
   TRY(make_factor(*A, eps, anorm, st, F));
   TRY(run_factor(*F, *A, flags, st));
   TRY(finish_factor(*F, st));
-  drop_schedule(*F);
+  TRY(finalize_factor(*F, st));
   *out = F.release();
   return HODLR_OK;
 }
 
 }  // extern "C"
 
+namespace hqh {
 namespace {
 
 // Factors of a set of matrices with one schedule per group of matrices that share
@@ -1522,13 +1699,80 @@ hodlr_status run_batch_set(BatchSet& S, const hodlr_t* const* A, uint32_t flags,
 
 hodlr_status check_batch_args(const hodlr_t* const* A, int count, double eps) {
   if (A == nullptr || count < 1) return fail(HODLR_EINVAL, "need at least one matrix");
-  for (int i = 0; i < count; ++i)
+  for (int i = 0; i < count; ++i) {
     if (A[i] == nullptr) return fail(HODLR_EINVAL, "NULL matrix in the batch");
+    if (A[i]->borrowed || A[i]->leaf_kind != LEAF_FULL)
+      return fail(HODLR_EINVAL, "a factor view in the batch");
+  }
   if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(HODLR_EINVAL, "eps must be finite and >= 0");
   return HODLR_OK;
 }
 
+// the view of one factor of F, or nullptr
+const hodlr_s* factor_view(const hodlr_qr_s* F, char which) {
+  switch (which) {
+    case 'Y': return F->vY.get();
+    case 'T': return F->vT.get();
+    case 'R': return F->vR.get();
+    default: return nullptr;
+  }
+}
+
+hodlr_status matmul_impl(const hodlr_s& A, int32_t trans, int64_t nrhs, const double* X, int64_t ldx,
+                         double* Z, int64_t ldz, hipStream_t st) {
+  if (X == nullptr || Z == nullptr || nrhs < 0 || ldx < A.t.n || ldz < A.t.n)
+    return fail(HODLR_EINVAL, "bad operand");
+  if (nrhs == 0) return HODLR_OK;
+  if (ldx > INT32_MAX || ldz > INT32_MAX) return fail(HODLR_EINVAL, "leading dimension too large");
+  const int tr = trans ? 1 : 0;
+  hodlr_s& a = const_cast<hodlr_s&>(A);
+  const CachedPlan* C;
+  {
+    std::lock_guard<std::mutex> lk(a.mu);
+    if (!a.mmplan[tr]) TRY(build_mm_plan(A, tr, st, a.mmplan[tr]));
+    C = a.mmplan[tr].get();
+  }
+  CallMem tmp(st);
+  double* ws = nullptr;
+  TRY(tmp.alloc(&ws, (size_t)std::max<int64_t>(1, C->P.ws_need())));
+  double* base[2] = {const_cast<double*>(X), Z};
+  const int ld[2] = {(int)ldx, (int)ldz};
+  const bool percol[2] = {true, true};
+  return run_cached(*C, st, 2, base, ld, percol, nrhs, SMAX, ws, nullptr);
+}
+
+// X <- Q X or Q^T X with temporaries from `scratch` (doubles) when given, else
+// from the caller's allocator
+hodlr_status apply_q_impl(const hodlr_qr_s& F, int32_t trans, int64_t nrhs, double* X, int64_t ldx,
+                          hipStream_t st, double* scratch, int64_t scratch_doubles) {
+  if (X == nullptr || nrhs < 0 || ldx < F.t.n) return fail(HODLR_EINVAL, "bad argument");
+  if (ldx > INT32_MAX) return fail(HODLR_EINVAL, "leading dimension too large");
+  if (nrhs == 0) return HODLR_OK;
+  const CachedPlan& C = *F.applyp[trans ? 1 : 0];
+  const int64_t n = F.t.n;
+  const int64_t wsn = std::max<int64_t>(1, C.P.ws_need());
+  int smax = (int)std::min<int64_t>(SMAX, nrhs);
+  double* buf = nullptr;
+  std::unique_ptr<CallMem> tmp;
+  if (scratch != nullptr) {
+    const int64_t fit = (scratch_doubles - wsn) / (2 * n);
+    if (fit < 1)
+      return fail(HODLR_EINVAL, "the static scratch holds " + std::to_string(scratch_doubles) +
+                                    " doubles; this factor needs at least " + std::to_string(wsn + 2 * n));
+    smax = (int)std::min<int64_t>(smax, fit);
+    buf = scratch;
+  } else {
+    tmp = std::make_unique<CallMem>(st);
+    TRY(tmp->alloc(&buf, (size_t)(2 * n * smax + wsn)));
+  }
+  double* base[3] = {X, buf, buf + n * smax};
+  const int ld[3] = {(int)ldx, (int)n, (int)n};
+  const bool percol[3] = {true, false, false};
+  return run_cached(C, st, 3, base, ld, percol, nrhs, smax, buf + 2 * n * smax, nullptr);
+}
+
 }  // namespace
+}  // namespace hqh
 
 extern "C" {
 
@@ -1552,10 +1796,8 @@ hodlr_status hodlr_qr_batched(const hodlr_t* const* A, int32_t count, double eps
     }
   }
   if (first_err != HODLR_OK) return fail(first_err, msg);
-  for (int i = 0; i < count; ++i) {
-    drop_schedule(*S.F[i]);
-    out[i] = S.F[i].release();
-  }
+  for (int i = 0; i < count; ++i) TRY(finalize_factor(*S.F[i], st));
+  for (int i = 0; i < count; ++i) out[i] = S.F[i].release();
   return HODLR_OK;
 }
 
@@ -1592,6 +1834,7 @@ hodlr_status hodlr_qr_time(const hodlr_t* A, double eps, double anorm, uint32_t 
                            int32_t reps, hodlr_stream_t stream, double* ms) {
   g_err.clear();
   if (A == nullptr || ms == nullptr || reps < 1 || warmup < 0) return fail(HODLR_EINVAL, "bad argument");
+  if (A->borrowed || A->leaf_kind != LEAF_FULL) return fail(HODLR_EINVAL, "A is a factor view, not a matrix");
   hipStream_t st = (hipStream_t)stream;
   std::unique_ptr<hodlr_qr_s> F;
   TRY(make_factor(*A, eps, anorm, st, F));
@@ -1614,127 +1857,68 @@ hodlr_status hodlr_qr_time(const hodlr_t* A, double eps, double anorm, uint32_t 
   return finish_factor(*F, st);
 }
 
-static hodlr_status matmul_view(const Tree& t, HView V, bool up, bool lo, int tri, Work& W, DMem& mem,
-                                int32_t trans, int64_t nrhs, const double* X, int64_t ldx, double* Z,
-                                int64_t ldz, double alpha, double beta, hipStream_t st) {
-  if (X == nullptr || Z == nullptr || nrhs < 0 || ldx < t.n || ldz < t.n)
-    return fail(HODLR_EINVAL, "bad operand");
-  if (nrhs == 0) return HODLR_OK;
-  Plan P;
-  for (int64_t c0 = 0; c0 < nrhs; c0 += SMAX) {
-    const int s = (int)std::min<int64_t>(SMAX, nrhs - c0);
-    P.mm(t, {mmspec(V, up, lo, 1, trans ? 1 : 0, X + c0 * ldx, (int)ldx, nullptr, Z + c0 * ldz, (int)ldz,
-                    alpha, beta, tri, s)});
-  }
-  DMem tmp;
-  TRY(P.upload_all(tmp, st));
-  TRY(ensure_work(mem, W, P.ws_need(), P.cnt_need(), false, st));
-  TRY(run_ops(P, W, st));
-  HIPCHK(hipStreamSynchronize(st));  // the plan's descriptor memory is released on return
-  return HODLR_OK;
-}
-
 hodlr_status hodlr_matmul(const hodlr_t* A, int32_t trans, int64_t nrhs, const double* X, int64_t ldx,
                           double* Z, int64_t ldz, hodlr_stream_t stream) {
   g_err.clear();
   if (A == nullptr) return fail(HODLR_EINVAL, "NULL matrix");
-  hodlr_t* a = const_cast<hodlr_t*>(A);
-  HView V{a->t.L, a->up.dview, a->lo.dview, a->leaves.dview, LEAF_FULL};
-  return matmul_view(a->t, V, true, true, 0, a->work, a->mem, trans, nrhs, X, ldx, Z, ldz, 1.0, 0.0,
-                     (hipStream_t)stream);
+  return matmul_impl(*A, trans, nrhs, X, ldx, Z, ldz, (hipStream_t)stream);
+}
+
+hodlr_status hodlr_qr_factor(const hodlr_qr_t* F, char which, const hodlr_t** view) {
+  g_err.clear();
+  if (F == nullptr || view == nullptr) return fail(HODLR_EINVAL, "NULL argument");
+  const hodlr_s* v = factor_view(F, which);
+  if (v == nullptr) return fail(HODLR_EINVAL, "which must be 'Y', 'T' or 'R'");
+  *view = v;
+  return HODLR_OK;
 }
 
 hodlr_status hodlr_qr_matmul(const hodlr_qr_t* F, char which, int32_t trans, int64_t nrhs, const double* X,
                              int64_t ldx, double* Z, int64_t ldz, hodlr_stream_t stream) {
   g_err.clear();
   if (F == nullptr) return fail(HODLR_EINVAL, "NULL factors");
-  hodlr_qr_t* f = const_cast<hodlr_qr_t*>(F);
-  HView V;
-  bool up, lo;
-  switch (which) {
-    case 'Y': V = f->view_y(); up = false; lo = true; break;
-    case 'T': V = f->view_t(); up = true; lo = false; break;
-    case 'R': V = f->view_r(); up = true; lo = false; break;
-    default: return fail(HODLR_EINVAL, "which must be 'Y', 'T' or 'R'");
-  }
-  return matmul_view(f->t, V, up, lo, 1, f->work, f->mem, trans, nrhs, X, ldx, Z, ldz, 1.0, 0.0,
-                     (hipStream_t)stream);
+  const hodlr_s* v = factor_view(F, which);
+  if (v == nullptr) return fail(HODLR_EINVAL, "which must be 'Y', 'T' or 'R'");
+  return matmul_impl(*v, trans, nrhs, X, ldx, Z, ldz, (hipStream_t)stream);
 }
 
 hodlr_status hodlr_apply_q(const hodlr_qr_t* F, int32_t trans, int64_t nrhs, double* X, int64_t ldx,
                            hodlr_stream_t stream) {
   g_err.clear();
-  if (F == nullptr || X == nullptr || nrhs < 0 || ldx < F->t.n) return fail(HODLR_EINVAL, "bad argument");
-  hodlr_qr_t* f = const_cast<hodlr_qr_t*>(F);
-  const Tree& t = f->t;
-  hipStream_t st = (hipStream_t)stream;
-  const int n = (int)t.n;
-  Plan P;
-  for (int64_t c0 = 0; c0 < nrhs; c0 += SMAX) {
-    const int s = (int)std::min<int64_t>(SMAX, nrhs - c0);
-    double* Xc = X + c0 * ldx;
-    // W1 = Y^T X ; W2 = op(T) W1 ; X -= Y W2   (Q = I - Y T Y^T, Q^T = I - Y T^T Y^T)
-    P.mm(t, {mmspec(f->view_y(), false, true, 1, 1, Xc, (int)ldx, nullptr, f->X1, n, 1.0, 0.0, 1, s)});
-    P.mm(t, {mmspec(f->view_t(), true, false, 1, trans ? 1 : 0, f->X1, n, nullptr, f->X2, n, 1.0, 0.0, 1, s)});
-    P.mm(t, {mmspec(f->view_y(), false, true, 1, 0, f->X2, n, nullptr, Xc, (int)ldx, -1.0, 1.0, 1, s)});
-  }
-  DMem tmp;
-  TRY(P.upload_all(tmp, st));
-  TRY(ensure_work(f->mem, f->work, P.ws_need(), P.cnt_need(), false, st));
-  TRY(run_ops(P, f->work, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return HODLR_OK;
+  if (F == nullptr) return fail(HODLR_EINVAL, "NULL factors");
+  return apply_q_impl(*F, trans, nrhs, X, ldx, (hipStream_t)stream, nullptr, 0);
 }
 
 hodlr_status hodlr_solve(const hodlr_qr_t* F, int64_t nrhs, double* B, int64_t ldb, hodlr_stream_t stream) {
-  TRY(hodlr_apply_q(F, 1, nrhs, B, ldb, stream));
-  hodlr_qr_t* f = const_cast<hodlr_qr_t*>(F);
-  const Tree& t = f->t;
+  g_err.clear();
+  if (F == nullptr || B == nullptr || nrhs < 0 || ldb < F->t.n) return fail(HODLR_EINVAL, "bad argument");
+  if (ldb > INT32_MAX) return fail(HODLR_EINVAL, "leading dimension too large");
+  if (nrhs == 0) return HODLR_OK;
   hipStream_t st = (hipStream_t)stream;
-  for (int64_t c0 = 0; c0 < nrhs; c0 += SMAX) {
-    const int s = (int)std::min<int64_t>(SMAX, nrhs - c0);
-    double* Bc = B + c0 * ldb;
-    Plan P;
-    // back substitution, last leaf first: x2 = R22^{-1} c2; c1 -= R12 x2; x1 = R11^{-1} c1
-    struct Rec {
-      hodlr_qr_s& f;
-      Plan& P;
-      const Tree& t;
-      double* Bc;
-      int64_t ldb;
-      int s;
-      void go(int v) {
-        if (t.is_leaf(v)) {
-          const int j = v - t.nleaf();
-          Op o{OP_TRSM};
-          o.count = s;
-          o.a0 = (int)t.m(v);
-          o.p0 = f.leaves.hview[j].D;
-          o.p1 = Bc + t.lo[v];
-          o.n = ldb;
-          P.push(o);
-          return;
-        }
-        go(2 * v + 1);
-        const HBlk& b = f.up.hview[v];
-        const int mL = (int)t.m(2 * v), mR = (int)t.m(2 * v + 1);
-        // Wt = V12^T x2 (k x s), c1 -= U12 Wt
-        P.gemm_red({GSpec{gjob(1, 0, 0, f.rank_up(v), s, nullptr, mR, nullptr, b.V, mR, Bc + t.lo[2 * v + 1],
-                               (int)ldb, f.Wm, KCAP, 1.0, 0.0, FC_DENSE),
-                          KCAP, KCAP, mR}});
-        P.gemm_tall({GSpec{gjob(0, 0, mL, nullptr, s, nullptr, 0, f.rank_up(v), b.U, mL, f.Wm, KCAP,
-                                Bc + t.lo[2 * v], (int)ldb, -1.0, 1.0, FC_DENSE),
-                           mL, s, 0}});
-        go(2 * v);
-      }
-    } rec{*f, P, t, Bc, ldb, s};
-    rec.go(1);
-    DMem tmp;
-    TRY(P.upload_all(tmp, st));
-    TRY(ensure_work(f->mem, f->work, P.ws_need(), P.cnt_need(), false, st));
-    TRY(run_ops(P, f->work, st));
-    HIPCHK(hipStreamSynchronize(st));
-  }
+  TRY(apply_q_impl(*F, 1, nrhs, B, ldb, st, nullptr, 0));
+  const CachedPlan& C = *F->solvep;
+  CallMem tmp(st);
+  double *wm = nullptr, *ws = nullptr;
+  int* cnt = nullptr;
+  TRY(tmp.alloc(&wm, (size_t)KCAP * SMAX));
+  TRY(tmp.alloc(&ws, (size_t)std::max<int64_t>(1, C.P.ws_need())));
+  TRY(tmp.alloc(&cnt, (size_t)C.P.cnt_need()));
+  double* base[2] = {B, wm};
+  const int ld[2] = {(int)ldb, KCAP};
+  const bool percol[2] = {true, false};
+  return run_cached(C, st, 2, base, ld, percol, nrhs, SMAX, ws, cnt);
+}
+
+hodlr_status hodlr_check(const hodlr_qr_t* F, hodlr_stream_t stream) {
+  g_err.clear();
+  if (F == nullptr) return fail(HODLR_EINVAL, "NULL factors");
+  hipStream_t st = (hipStream_t)stream;
+  int err = 0;
+  HIPCHK(hipMemcpyAsync(&err, F->work.err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (err & ERR_STACK) return fail(HODLR_ECAPACITY, "stacked leaf column exceeds 1024 rows");
+  if (err & ERR_WIDTH) return fail(HODLR_ECAPACITY, "a recompression width exceeded 128 columns");
+  if (err & ERR_CAPACITY) return fail(HODLR_ECAPACITY, "an off-diagonal rank exceeded rank_cap");
   return HODLR_OK;
 }
 
@@ -1763,12 +1947,12 @@ hodlr_status hodlr_qr_profile(const hodlr_t* A, double eps, double anorm, int32_
     Launch L;
     L.e0 = e0;
     L.e1 = e1;
-    run_op(B.plan, B.work, o, st, L);
+    run_op(B.plan, B.work, o, st, L, Opnd{});
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventSynchronize(e1));
     float t = 0.0f;
     HIPCHK(hipEventElapsedTime(&t, e0, e1));
-    const double tot = flop_total(F->work.fc);
+    const double tot = flop_sum(F->work.fc, 0, FC_N + 1);  // the norm estimate's products included
     if (tot < 0.0) return fail(HODLR_EDEVICE, "reading the flop counters failed");
     if (o.type < ntypes) {
       ms[o.type] += t;
@@ -1790,9 +1974,7 @@ hodlr_status hodlr_qr_info(const hodlr_qr_t* F, hodlr_qr_info_t* info) {
   if (F == nullptr || info == nullptr) return fail(HODLR_EINVAL, "NULL argument");
   const int nn = 1 << F->t.L;
   std::vector<int> r(3 * (size_t)nn + 8);
-
   HIPCHK(hipMemcpy(r.data(), F->ranks, r.size() * sizeof(int), hipMemcpyDeviceToHost));
-
   std::memset(info, 0, sizeof(*info));
   info->n = F->t.n;
   info->levels = F->t.L;
@@ -1806,16 +1988,38 @@ hodlr_status hodlr_qr_info(const hodlr_qr_t* F, hodlr_qr_info_t* info) {
   info->tau_a = F->tauA;
   info->tau_t = F->tauT;
   info->flops = flop_total(F->work.fc);
+  info->norm_flops = flop_sum(F->work.fc, FC_NORM, FC_NORM + 1);
   info->n_truncations = F->batch ? F->batch->plan.n_trunc / F->batch->size : F->n_trunc;
   info->n_launches = F->batch ? F->batch->n_launch : F->n_launch;
   info->device_bytes = (int64_t)F->mem.bytes;
   return HODLR_OK;
 }
 
-static hodlr_status export_impl(const Tree& t, int cap, const LeafSet& L, const BlockSet* up,
-                                const BlockSet* lo, const int* d_ranks_up, const int* d_ranks_lo,
-                                int leafmode, double* leaves, double* U, int64_t* u_off, double* V,
-                                int64_t* v_off, int32_t* ranks) {
+hodlr_status hodlr_qr_ranklog(const hodlr_qr_t* F, int32_t* recs, int64_t cap, int64_t* count) {
+  g_err.clear();
+  if (F == nullptr || count == nullptr) return fail(HODLR_EINVAL, "NULL argument");
+  const int64_t n = std::min<int64_t>((int64_t)F->logkeys.size(), F->nlog_cap);
+  *count = n;
+  if (recs == nullptr) return HODLR_OK;
+  if (cap < n) return fail(HODLR_EINVAL, "the record array holds fewer than count records");
+  std::vector<int> h(2 * (size_t)std::max<int64_t>(1, n));
+  if (n > 0) HIPCHK(hipMemcpy(h.data(), F->rlog, 2 * (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < n; ++i) {
+    for (int q = 0; q < 5; ++q) recs[7 * i + q] = F->logkeys[i][q];
+    recs[7 * i + 5] = h[2 * i];
+    recs[7 * i + 6] = h[2 * i + 1];
+  }
+  return HODLR_OK;
+}
+
+}  // extern "C"
+
+namespace hqh {
+namespace {
+
+hodlr_status export_impl(const Tree& t, const LeafSet& L, const BlockSet* up, const BlockSet* lo,
+                         const int* d_ranks_up, const int* d_ranks_lo, int leafmode, double* leaves, double* U,
+                         int64_t* u_off, double* V, int64_t* v_off, int32_t* ranks) {
   if (leaves == nullptr || ranks == nullptr || u_off == nullptr || v_off == nullptr)
     return fail(HODLR_EINVAL, "NULL output");
   const int nl = t.nleaf();
@@ -1827,8 +2031,8 @@ static hodlr_status export_impl(const Tree& t, int cap, const LeafSet& L, const 
     for (int64_t c = 0; c < m; ++c)
       for (int64_t r = 0; r < m; ++r) {
         double x = hl[L.off[j] + r + c * m];
-        if (leafmode == 1) x = r > c ? x : (r == c ? 1.0 : 0.0);
-        if (leafmode == 2) x = r <= c ? x : 0.0;
+        if (leafmode == LEAF_UNIT_LOWER) x = r > c ? x : (r == c ? 1.0 : 0.0);
+        if (leafmode == LEAF_UPPER) x = r <= c ? x : 0.0;
         leaves[pos + r + c * m] = x;
       }
     pos += m * m;
@@ -1856,37 +2060,90 @@ static hodlr_status export_impl(const Tree& t, int cap, const LeafSet& L, const 
         up_ += rows * k;
         vp_ += cols * k;
       }
-  (void)cap;
   return HODLR_OK;
 }
+
+hodlr_status export_view(const hodlr_s& A, double* leaves, double* U, int64_t* u_off, double* V, int64_t* v_off,
+                         int32_t* ranks) {
+  return export_impl(A.t, A.leaves, A.has_up ? &A.up : nullptr, A.has_lo ? &A.lo : nullptr,
+                     A.has_up ? A.rank_up_dev : nullptr, A.has_lo ? A.rank_lo_dev : nullptr, A.leaf_kind, leaves, U,
+                     u_off, V, v_off, ranks);
+}
+
+}  // namespace
+}  // namespace hqh
+
+extern "C" {
 
 hodlr_status hodlr_export(const hodlr_t* A, double* leaves, double* U, int64_t* u_off, double* V,
                           int64_t* v_off, int32_t* ranks) {
   g_err.clear();
   if (A == nullptr) return fail(HODLR_EINVAL, "NULL matrix");
-  const int nl = A->t.nleaf();
-  return export_impl(A->t, A->cap, A->leaves, &A->up, &A->lo, A->ranks, A->ranks + nl, 0, leaves, U, u_off,
-                     V, v_off, ranks);
+  return export_view(*A, leaves, U, u_off, V, v_off, ranks);
 }
 
 hodlr_status hodlr_qr_export(const hodlr_qr_t* F, char which, double* leaves, double* U, int64_t* u_off,
                              double* V, int64_t* v_off, int32_t* ranks) {
   g_err.clear();
   if (F == nullptr) return fail(HODLR_EINVAL, "NULL factors");
-  const int nl = F->t.nleaf();
-  switch (which) {
-    case 'Y':
-      return export_impl(F->t, F->cap, F->leaves, nullptr, &F->lo, nullptr, F->ranks + nl, 1, leaves, U, u_off,
-                         V, v_off, ranks);
-    case 'T':
-      return export_impl(F->t, F->cap, F->tleaves, &F->tup, nullptr, F->ranks + 2 * nl, nullptr, 2, leaves, U,
-                         u_off, V, v_off, ranks);
-    case 'R':
-      return export_impl(F->t, F->cap, F->leaves, &F->up, nullptr, F->ranks, nullptr, 2, leaves, U, u_off, V,
-                         v_off, ranks);
-    default:
-      return fail(HODLR_EINVAL, "which must be 'Y', 'T' or 'R'");
+  const hodlr_s* v = factor_view(F, which);
+  if (v == nullptr) return fail(HODLR_EINVAL, "which must be 'Y', 'T' or 'R'");
+  return export_view(*v, leaves, U, u_off, V, v_off, ranks);
+}
+
+// Build the factorisation schedule of a partition without a device (every
+// address virtual) and test it for hazards between the two streams and
+// between the jobs of each launch.
+hodlr_status hodlr_plan_check(int64_t n, int32_t levels, const int64_t* leaf_off, int32_t rank_cap, int32_t count,
+                              uint32_t flags, int64_t* stats, char* msg, int64_t msglen) {
+  g_err.clear();
+  if (leaf_off == nullptr || stats == nullptr || levels < 0 || levels > MAXGROUPS || count < 1 ||
+      rank_cap < 1 || rank_cap > KCAP)
+    return fail(HODLR_EINVAL, "bad argument");
+  const int nl = 1 << levels;
+  if (leaf_off[0] != 0 || leaf_off[nl] != n) return fail(HODLR_EINVAL, "leaf_off must run from 0 to n");
+  for (int j = 0; j < nl; ++j)
+    if (leaf_off[j + 1] - leaf_off[j] < 1 || leaf_off[j + 1] - leaf_off[j] > MAXLEAF)
+      return fail(HODLR_EINVAL, "bad leaf size");
+  struct Virt {
+    Virt() { g_virtual = true; }
+    ~Virt() { g_virtual = false; }
+  } virt;
+  hodlr_s A;
+  A.t.init(levels, leaf_off);
+  A.cap = rank_cap;
+  std::vector<std::unique_ptr<hodlr_qr_s>> Fs(count);
+  std::vector<hodlr_qr_s*> fp;
+  for (int i = 0; i < count; ++i) {
+    TRY(make_storage(A, 1e-10, (flags & HODLR_CHECK_ESTIMATE) ? 0.0 : 1.0, nullptr, Fs[i]));
+    fp.push_back(Fs[i].get());
   }
+  std::shared_ptr<Batch> B;
+  TRY(make_batch(fp, nullptr, B, (flags & HODLR_CHECK_PLANT) ? 1 : 0));
+  Plan& P = B->plan;
+  if (flags & HODLR_QR_ONE_STREAM)
+    for (Op& o : P.ops) o.lane = 0;
+  CheckCtx C;
+  C.cap = rank_cap;
+  C.work = &B->work;
+  for (hodlr_qr_s* F : fp) {
+    C.blocks[F->up.dview] = &F->up.hview;
+    C.blocks[F->lo.dview] = &F->lo.hview;
+    C.blocks[F->tup.dview] = &F->tup.hview;
+    C.leaves[F->leaves.dview] = &F->leaves.hview;
+    C.leaves[F->tleaves.dview] = &F->tleaves.hview;
+  }
+  const CheckResult R = check_plan(P, C);
+  stats[0] = R.ops;
+  stats[1] = R.lane1_ops;
+  stats[2] = R.pairs;
+  stats[3] = R.conflicts;
+  stats[4] = R.intra_conflicts;
+  if (msg != nullptr && msglen > 0) {
+    std::strncpy(msg, R.first.c_str(), (size_t)msglen - 1);
+    msg[msglen - 1] = '\0';
+  }
+  return HODLR_OK;
 }
 
 }  // extern "C"

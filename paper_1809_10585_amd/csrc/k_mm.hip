@@ -6,7 +6,26 @@
 namespace hq {
 
 // ------------------------------------------------------------------ HODLR x tall-skinny
-__device__ __forceinline__ int mm_s(const MmJob& J) { return J.s_dev ? *J.s_dev : J.s; }
+__device__ __forceinline__ int mm_s(const MmJob& J, const Opnd& o) {
+  return J.s_dev ? *J.s_dev : (J.s > 0 ? J.s : o.s);
+}
+// X and Z of a job with their leading dimensions (a slot >= 0 binds the call's operand)
+__device__ __forceinline__ const double* mm_x(const MmJob& J, const Opnd& o, int& ld) {
+  if (J.xs < 0) {
+    ld = J.ldX;
+    return J.X;
+  }
+  ld = o.ld[J.xs];
+  return o.p[J.xs] + J.xoff;
+}
+__device__ __forceinline__ double* mm_z(const MmJob& J, const Opnd& o, int& ld) {
+  if (J.zs < 0) {
+    ld = J.ldZ;
+    return J.Z;
+  }
+  ld = o.ld[J.zs];
+  return o.p[J.zs] + J.zoff;
+}
 
 // Phase A: projections P_b = F_b^T X (F = V for op N, U for op T) of every
 // block of the sub-HODLR, MM_CH rows per block of threads.  Thread t takes
@@ -17,12 +36,13 @@ __device__ __forceinline__ int mm_s(const MmJob& J) { return J.s_dev ? *J.s_dev 
 // k_mm_red sums (a separate launch: no cross-block fences).
 __global__ void __launch_bounds__(NT_MM) k_mm_proj(const MmJob* __restrict__ jobs,
                                                     const MmProj* __restrict__ items, int first,
-                                                    double* ws) {
+                                                    double* ws, Opnd op) {
   __shared__ double part_s[NT_MM];
   const int tid = threadIdx.x;
   const MmProj it = items[first + blockIdx.x];
   const MmJob& J = jobs[it.job];
-  const int s = mm_s(J);
+  const int s = mm_s(J, op);
+  const int rld = J.rld;
   const HBlk b = (it.kind == 0 ? J.M.up : J.M.lo)[it.node];
   const int k = *b.rank;
   if (k == 0 || s == 0) return;
@@ -30,8 +50,8 @@ __global__ void __launch_bounds__(NT_MM) k_mm_proj(const MmJob* __restrict__ job
   const int len = trans ? b.rows : b.cols;
   const double* F = trans ? b.U : b.V;
   const int ldF = trans ? b.ldU : b.ldV;
-  const double* X = J.X + ((trans ? b.r0 : b.c0) - J.row0);
-  const int ldX = J.ldX;
+  int ldX;
+  const double* X = mm_x(J, op, ldX) + ((trans ? b.r0 : b.c0) - J.row0);
   const int c0 = it.chunk * MM_CH;
   const int cn = min(MM_CH, len - c0);
   const int nout = k * s;
@@ -52,7 +72,7 @@ __global__ void __launch_bounds__(NT_MM) k_mm_proj(const MmJob* __restrict__ job
     if (tid < nout) {
       double sacc = 0.0;
       for (int q2 = 0; q2 < Q; ++q2) sacc += part_s[tid + q2 * nout];
-      dst[(tid % k) + (tid / k) * KCAP] = sacc;
+      dst[(tid % k) + (tid / k) * rld] = sacc;
     }
   } else {
     for (int e = tid; e < nout; e += NT_MM) {
@@ -61,27 +81,28 @@ __global__ void __launch_bounds__(NT_MM) k_mm_proj(const MmJob* __restrict__ job
       const double* x = X + c0 + (int64_t)c * ldX;
       double acc = 0.0;
       for (int r = 0; r < cn; ++r) acc += f[r] * x[r];
-      dst[j + c * KCAP] = acc;
+      dst[j + c * rld] = acc;
     }
   }
-  if (tid == 0) add_flops(J.flops, FC_HMAT, 2.0 * k * cn * s);
+  if (tid == 0) add_flops(J.flops, J.fc, 2.0 * k * cn * s);
 }
 
 // Sum the per-chunk partials of one block projection (chunk order fixed).
 __global__ void __launch_bounds__(NT_MM) k_mm_red(const MmJob* __restrict__ jobs,
                                                    const MmProj* __restrict__ items, int first,
-                                                   double* ws) {
+                                                   double* ws, Opnd op) {
   const MmProj it = items[first + blockIdx.x];
   const MmJob& J = jobs[it.job];
-  const int s = mm_s(J);
+  const int s = mm_s(J, op);
+  const int rld = J.rld;
   const HBlk b = (it.kind == 0 ? J.M.up : J.M.lo)[it.node];
   const int k = *b.rank;
   const double* part0 = ws + it.part;
-  double* red = ws + J.red0 + (int64_t)(2 * rel_node(it.node, J.v) + it.kind) * (KCAP * SMAX);
+  double* red = ws + J.red0 + (int64_t)(2 * rel_node(it.node, J.v) + it.kind) * (rld * SMAX);
   for (int e = threadIdx.x; e < k * s; e += NT_MM) {
-    const int off = (e % k) + (e / k) * KCAP;
+    const int off = (e % k) + (e / k) * rld;
     double acc = 0.0;
-    for (int ch = 0; ch < it.nchunk; ++ch) acc += part0[(int64_t)ch * (KCAP * SMAX) + off];
+    for (int ch = 0; ch < it.nchunk; ++ch) acc += part0[(int64_t)ch * (rld * SMAX) + off];
     red[off] = acc;
   }
 }
@@ -136,7 +157,9 @@ __device__ __forceinline__ void mm_tile_load(double (&tv)[16], const HLeaf& lf, 
 
 template <int RT, int CW>
 __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it, const double* ws,
-                                              double* shm, double* Dt, int s) {
+                                              double* shm, double* Dt, int s, const double* JX, int ldX,
+                                              double* JZ, int ldZ) {
+  const int rld = J.rld;
   constexpr int G = NT_MM / RT;
   constexpr int DMAX = RT == 16 ? MAXLEAF / G : 1;
   const int tid = threadIdx.x;
@@ -185,18 +208,18 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
           akb[a] = *b.rank;
           ald[a] = trans ? b.ldV : b.ldU;
           aF[a] = (trans ? b.V : b.U) + (lf.r0 + R - (trans ? b.c0 : b.r0));
-          aR[a] = ws + J.red0 + (int64_t)(2 * rel_node(u, J.v) + bk) * (KCAP * SMAX);
+          aR[a] = ws + J.red0 + (int64_t)(2 * rel_node(u, J.v) + bk) * (rld * SMAX);
         }
       }
     }
   }
-  const double* xl = J.X + (lf.r0 - J.row0);
+  const double* xl = JX + (lf.r0 - J.row0);
   double* Xs = shm;
   for (int c0 = 0; c0 < s; c0 += CW) {
     const int cn = min(CW, s - c0);
     for (int e = tid; e < m * CW; e += NT_MM) {
       const int kk = e % m, c = e / m;
-      Xs[kk * MA_LD + c] = (c < cn) ? xl[kk + (int64_t)(c0 + c) * J.ldX] : 0.0;
+      Xs[kk * MA_LD + c] = (c < cn) ? xl[kk + (int64_t)(c0 + c) * ldX] : 0.0;
     }
     __syncthreads();
     double acc[CW];
@@ -245,12 +268,12 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
     if constexpr (RT == 16) {
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
-        const double* red = aR[a] + (int64_t)c0 * KCAP;
+        const double* red = aR[a] + (int64_t)c0 * rld;
         for (int j = 0; j < akb[a]; ++j) {
           const double fv = live ? aF[a][(int64_t)j * ald[a]] : 0.0;
 #pragma unroll
           for (int c = 0; c < CW; ++c)
-            if (c < cn) acc[c] += fv * red[j + c * KCAP];
+            if (c < cn) acc[c] += fv * red[j + c * rld];
         }
       }
     }
@@ -263,8 +286,8 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
         if (arr != nullptr) {
           const HBlk& b = arr[u];
           const int kb = *b.rank;
-          const double* red = ws + J.red0 + (int64_t)(2 * rel_node(u, J.v) + bk) * (KCAP * SMAX) +
-                              (int64_t)c0 * KCAP;
+          const double* red = ws + J.red0 + (int64_t)(2 * rel_node(u, J.v) + bk) * (rld * SMAX) +
+                              (int64_t)c0 * rld;
           const double* F = trans ? b.V : b.U;
           const int ldF = trans ? b.ldV : b.ldU;
           const int64_t frow = lf.r0 + R - (trans ? b.c0 : b.r0);
@@ -272,7 +295,7 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
             const double fv = live ? F[frow + (int64_t)j * ldF] : 0.0;
 #pragma unroll
             for (int c = 0; c < CW; ++c)
-              if (c < cn) acc[c] += fv * red[j + c * KCAP];
+              if (c < cn) acc[c] += fv * red[j + c * rld];
           }
         }
       }
@@ -290,7 +313,7 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
         double sacc = 0.0;
 #pragma unroll
         for (int g2 = 0; g2 < G; ++g2) sacc += shm[(g2 * RT + rr) * MA_LD + c];
-        double* zp = J.Z + (lf.r0 - J.row0 + it.row0 + rr) + (int64_t)(c0 + c) * J.ldZ;
+        double* zp = JZ + (lf.r0 - J.row0 + it.row0 + rr) + (int64_t)(c0 + c) * ldZ;
         const double v = J.alpha * sacc;
         *zp = (J.beta == 0.0) ? v : v + J.beta * (*zp);
       }
@@ -302,7 +325,7 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
 template <int RT>
 __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jobs,
                                                      const MmApply* __restrict__ items, int first,
-                                                     const double* __restrict__ ws) {
+                                                     const double* __restrict__ ws, Opnd op) {
   extern __shared__ double shm[];
   double* Dt = nullptr;  // transposed leaf tile (RT = 64 only)
   if constexpr (RT == 64) {
@@ -311,12 +334,15 @@ __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jo
   }
   const MmApply it = items[first + blockIdx.x];
   const MmJob& J = jobs[it.job];
-  const int s = mm_s(J);
+  const int s = mm_s(J, op);
   if (s == 0) return;
+  int ldX, ldZ;
+  const double* JX = mm_x(J, op, ldX);
+  double* JZ = mm_z(J, op, ldZ);
   if (s <= 4)
-    mm_apply_rows<RT, 4>(J, it, ws, shm, Dt, s);
+    mm_apply_rows<RT, 4>(J, it, ws, shm, Dt, s, JX, ldX, JZ, ldZ);
   else
-    mm_apply_rows<RT, 16>(J, it, ws, shm, Dt, s);
+    mm_apply_rows<RT, 16>(J, it, ws, shm, Dt, s, JX, ldX, JZ, ldZ);
   if (threadIdx.x == 0) {
     const HLeaf lf = J.M.leaf[it.leaf];
     const int trans = J.trans;
@@ -331,11 +357,30 @@ __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jo
       child2 = u2;
       u2 >>= 1;
     }
-    add_flops(J.flops, FC_HMAT, flops);
+    add_flops(J.flops, J.fc, flops);
   }
 }
 
 // ------------------------------------------------------------------ small GEMMs
+// A, B, C and N of a job with the call's operands bound
+__device__ __forceinline__ GemmJob gemm_bind(const GemmJob& J0, const Opnd& o) {
+  GemmJob J = J0;
+  if (J.as_ >= 0) {
+    J.A = o.p[J.as_] + J.aoff;
+    if (J.lda <= 0) J.lda = o.ld[J.as_];
+  }
+  if (J.bs_ >= 0) {
+    J.B = o.p[J.bs_] + J.boff;
+    if (J.ldb <= 0) J.ldb = o.ld[J.bs_];
+  }
+  if (J.cs_ >= 0) {
+    J.C = o.p[J.cs_] + J.coff;
+    if (J.ldc <= 0) J.ldc = o.ld[J.cs_];
+  }
+  if (J.Nd == nullptr && J.N <= 0) J.N = o.s;
+  return J;
+}
+
 __device__ __forceinline__ double gA(const GemmJob& J, int r, int kk) {
   return J.ta ? J.A[kk + (int64_t)r * J.lda] : J.A[r + (int64_t)kk * J.lda];
 }
@@ -344,12 +389,13 @@ __device__ __forceinline__ double gB(const GemmJob& J, int kk, int c) {
 }
 
 __global__ void __launch_bounds__(NT_MM) k_gemm_tall(const GemmJob* __restrict__ jobs,
-                                                      const GemmTile* __restrict__ items, int first) {
+                                                      const GemmTile* __restrict__ items, int first,
+                                                      Opnd op) {
   __shared__ double At[64][33];
   __shared__ double Bt[32][65];
   const int tid = threadIdx.x;
   const GemmTile it = items[first + blockIdx.x];
-  const GemmJob J = jobs[it.job];
+  const GemmJob J = gemm_bind(jobs[it.job], op);
   const int M = J.Md ? *J.Md : J.M, N = J.Nd ? *J.Nd : J.N, K = J.Kd ? *J.Kd : J.K;
   if (it.row0 >= M || it.col0 >= N) return;
   const int mr = min(64, M - it.row0), nc = min(64, N - it.col0);
@@ -411,13 +457,13 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_tall(const GemmJob* __restrict__
 // C (M x N, both <= KCAP) from a long K, split into chunks; the last chunk sums.
 __global__ void __launch_bounds__(NT_MM) k_gemm_red(const GemmJob* __restrict__ jobs,
                                                      const GemmRed* __restrict__ items, int first,
-                                                     double* ws, int* counters) {
+                                                     double* ws, int* counters, Opnd op) {
   __shared__ double At[32][KCAP + 1];
   __shared__ double Bt[32][KCAP + 1];
   __shared__ int lastf;
   const int tid = threadIdx.x;
   const GemmRed it = items[first + blockIdx.x];
-  const GemmJob J = jobs[it.job];
+  const GemmJob J = gemm_bind(jobs[it.job], op);
   const int M = J.Md ? *J.Md : J.M, N = J.Nd ? *J.Nd : J.N;
   if (M == 0 || N == 0) return;
   const int nout = M * N;
@@ -510,6 +556,6 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_red(const GemmJob* __restrict__ 
 }  // namespace hq
 
 namespace hq {
-template __global__ void k_mm_apply<16>(const MmJob*, const MmApply*, int, const double*);
-template __global__ void k_mm_apply<64>(const MmJob*, const MmApply*, int, const double*);
+template __global__ void k_mm_apply<16>(const MmJob*, const MmApply*, int, const double*, Opnd);
+template __global__ void k_mm_apply<64>(const MmJob*, const MmApply*, int, const double*, Opnd);
 }  // namespace hq

@@ -5,7 +5,15 @@
 namespace hq {
 
 // ------------------------------------------------------------------ recompression
-// LDS layout of k_tr_qr (doubles)
+// The kept rank k of a job (and, when the job carries a log entry, its input
+// width w next to k).
+__device__ __forceinline__ void tr_set_rank(const TrJob& J, int w, int k) {
+  *J.out_rank = k;
+  if (J.log != nullptr) {
+    J.log[0] = w;
+    J.log[1] = k;
+  }
+}
 
 __device__ __forceinline__ int tr_root_slot(int p0, int G) {
   int s = 0, cnt = p0;
@@ -519,7 +527,7 @@ __global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ job
   const int w = (int)hdr[0], k = (int)hdr[1];
   // the header is written by k_tr_qr for every job; refuse anything else
   if (w < 0 || w > WMAX || k < 0 || k > w || k > J.cap) return;
-  if (it.leader && tid == 0) *J.out_rank = k;
+  if (it.leader && tid == 0) tr_set_rank(J, w, k);
   if (w == 0 || k == 0) return;
   const double* Uk = hdr + 8;
   const double* P = Uk + WMAX * WMAX;
@@ -931,7 +939,7 @@ __device__ __forceinline__ void tr_small_narrow(const TrJob& J, int w, int n0a, 
       for (int q = 0; q < WT; ++q) Zt[lane + q * TSM_LD] = z[0][q];
     }
     if (lane == 0) {
-      *J.out_rank = k;
+      tr_set_rank(J, w, k);
       perm[WT] = k;  // for the other wavefronts
       add_flops(J.flops, J.fc, orth ? tr_flops_orth(m0, m1, w) : tr_flops_full(m0, m1, w, k));
     }
@@ -985,7 +993,7 @@ __device__ __forceinline__ void tr_small_form(const TrJob& J, const double* ws, 
   const double* hdr = ws + J.hdr;
   const int w = (int)hdr[0], k = (int)hdr[1];
   if (w < 0 || w > WMAX || k < 0 || k > w || k > J.cap) return;
-  if (tid == 0) *J.out_rank = k;
+  if (tid == 0) tr_set_rank(J, w, k);
   if (w == 0 || k == 0) return;
   const double* Uk = hdr + 8;
   const double* P = Uk + WMAX * WMAX;
@@ -1098,7 +1106,7 @@ __global__ void __launch_bounds__(NT_TR) k_tr_small(const TrJob* __restrict__ jo
   const bool lead = it.side == 0 && it.chunk == 0;
   if (w == 0 || w > WTOP) {
     if (lead && threadIdx.x == 0) {
-      *J.out_rank = 0;
+      tr_set_rank(J, w, 0);
       if (w > WTOP) atomicOr(J.err, ERR_WIDTH);
     }
     return;

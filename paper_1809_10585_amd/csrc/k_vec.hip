@@ -71,6 +71,11 @@ __global__ void k_fill(double* x, int64_t n, double v) {
   if (i < n) x[i] = v;
 }
 
+__global__ void k_zero_i32(int* x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0;
+}
+
 // Back substitution with one upper triangular leaf: X <- R^{-1} X (m x nrhs).
 __global__ void __launch_bounds__(NT_MM) k_leaf_trsm(const double* __restrict__ D, int m, int ld,
                                                       double* X, int ldx, int nrhs) {

@@ -37,15 +37,16 @@ __host__ __device__ constexpr size_t mm_apply_lds(int mleaf) {
 }
 
 __global__ void k_mm_proj(const MmJob* __restrict__ jobs, const MmProj* __restrict__ items, int first,
-                          double* ws);
+                          double* ws, Opnd op);
 __global__ void k_mm_red(const MmJob* __restrict__ jobs, const MmProj* __restrict__ items, int first,
-                         double* ws);
+                         double* ws, Opnd op);
 template <int RT>
 __global__ void k_mm_apply(const MmJob* __restrict__ jobs, const MmApply* __restrict__ items, int first,
-                           const double* __restrict__ ws);
-__global__ void k_gemm_tall(const GemmJob* __restrict__ jobs, const GemmTile* __restrict__ items, int first);
+                           const double* __restrict__ ws, Opnd op);
+__global__ void k_gemm_tall(const GemmJob* __restrict__ jobs, const GemmTile* __restrict__ items, int first,
+                            Opnd op);
 __global__ void k_gemm_red(const GemmJob* __restrict__ jobs, const GemmRed* __restrict__ items, int first,
-                           double* ws, int* counters);
+                           double* ws, int* counters, Opnd op);
 
 // ---------------------------------------------------------------- leaf QR (k_leaf.hip)
 // LDS layout of the leaf kernels (doubles)
@@ -70,6 +71,7 @@ __global__ void k_normalize(const VecJob* __restrict__ items, int first);
 __global__ void k_set_scal(const VecJob* __restrict__ items, int first, int count);
 __global__ void k_fill_items(const VecJob* __restrict__ items, int first);
 __global__ void k_fill(double* x, int64_t n, double v);
+__global__ void k_zero_i32(int* x, int n);
 __global__ void k_leaf_trsm(const double* __restrict__ D, int m, int ld, double* X, int ldx, int nrhs);
 
 }  // namespace hq

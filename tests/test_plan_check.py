@@ -1,0 +1,68 @@
+"""The factorisation schedule is free of hazards (CPU only, no device).
+
+The library issues the T-factor steps of every node (T~12, T12 of Alg. hQR)
+on a second stream beside the main chain, ordered only by the schedule's
+events, and every launch carries many independent jobs.  hodlr_plan_check
+builds the schedule with virtual addresses and tests every pair of launches
+the two streams may run together, and every pair of jobs inside one launch,
+for a write overlapping the other's reads or writes (byte ranges from the job
+descriptors, ranks at their capacity).  A planted hazard must be found, so the
+check is not vacuous.
+"""
+import numpy as np
+import pytest
+
+import hodlr_gen as G
+
+
+@pytest.fixture(scope="module")
+def H():
+    import paper_1809_10585_amd as H
+    try:
+        H.load()
+    except H.HodlrError:
+        from paper_1809_10585_amd import build
+        build.build()
+    return H
+
+
+CASES = [
+    (G.partition(512, 64), 64, 1),       # Gaussian configuration, depth 3
+    (G.partition(4096, 256), 16, 1),     # exponential kernel, depth 4
+    (G.partition(16384, 256), 16, 1),    # depth 6
+    (G.partition(65536, 256), 16, 1),    # the benchmark size, depth 8
+    (G.partition(1500, 200), 32, 1),     # ragged partition (uneven chunks)
+    (G.partition(257, 33), 64, 1),       # ragged, small leaves
+    (G.partition(2048, 256), 32, 5),     # a batch of five matrices in lockstep
+]
+
+
+@pytest.mark.parametrize("part,cap,count", CASES)
+def test_two_stream_schedule_has_no_hazard(H, part, cap, count):
+    levels, off = part
+    n = int(off[-1])
+    for flags in (0, H.HODLR_CHECK_ESTIMATE):
+        r = H.hodlr_plan_check((n, levels, off), cap, count=count, flags=flags)
+        assert r["conflicts"] == 0 and r["intra_conflicts"] == 0, r["first"]
+        if levels >= 2:
+            assert r["launches_stream1"] > 0 and r["pairs"] > 0
+
+
+@pytest.mark.parametrize("part", [G.partition(512, 64), G.partition(4096, 256)])
+def test_planted_hazard_is_found(H, part):
+    """Node 2's first T~12 recompression made to write S~'s buffer, which the
+    root's main chain fills at the same time: the check must report it."""
+    levels, off = part
+    r = H.hodlr_plan_check((int(off[-1]), levels, off), 16, flags=H.HODLR_CHECK_PLANT)
+    assert r["conflicts"] >= 1 and "stream 1" in r["first"]
+
+
+def test_serial_order_has_no_concurrent_pairs(H):
+    levels, off = G.partition(4096, 256)
+    r = H.hodlr_plan_check((4096, levels, off), 16, flags=H.HODLR_QR_ONE_STREAM)
+    assert r["launches_stream1"] == 0 and r["pairs"] == 0 and r["conflicts"] == 0
+
+
+def test_plan_check_rejects_bad_partition(H):
+    with pytest.raises(H.HodlrError):
+        H.hodlr_plan_check((100, 1, np.array([0, 0, 100])), 8)
