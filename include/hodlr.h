@@ -167,6 +167,24 @@ hodlr_status hodlr_apply_q(const hodlr_qr_t *F, int32_t trans, int64_t nrhs, dou
                            int64_t ldx, hodlr_stream_t stream);
 
 /*
+ * hodlr_apply_q_noalloc - hodlr_apply_q for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same launch sequence and kernels, with its temporaries in a
+ * static device array of 32 MiB that the library holds on every device it runs
+ * on until the process ends.  It calls no hipMalloc, hipFree or allocating
+ * routine.  The array holds the product projections of the factor (2 x the
+ * tree's nodes x rank_cap x 64 doubles) plus two n x s blocks; s, the columns
+ * processed per pass, is chosen as large as fits (at most 64).  A factor whose
+ * projections and two n-row columns do not fit is refused with HODLR_EINVAL
+ * (n = 65536 with rank_cap 16 fits with s = 16).  All calls on one device share
+ * the array: calls that overlap on one device (other streams, other threads)
+ * race and must be serialised by the caller; a call leaves the array's
+ * contents behind and the next call overwrites them.
+ */
+hodlr_status hodlr_apply_q_noalloc(const hodlr_qr_t *F, int32_t trans, int64_t nrhs, double *X,
+                                   int64_t ldx, hodlr_stream_t stream);
+
+/*
  * hodlr_solve - B <- R^{-1} Q^T B, i.e. the solution of A x = b for every
  * column of B (device, n x nrhs, ldb >= n).  Back substitution with the upper
  * triangular HODLR R runs leaf by leaf from the last one

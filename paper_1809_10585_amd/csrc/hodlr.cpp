@@ -1741,6 +1741,37 @@ hodlr_status matmul_impl(const hodlr_s& A, int32_t trans, int64_t nrhs, const do
   return run_cached(*C, st, 2, base, ld, percol, nrhs, SMAX, ws, nullptr);
 }
 
+// ---- the allocation-free entry point's scratch
+// File-scope device array (each device the library runs on holds one copy
+// until the process ends).  Host code never passes the array's name to a
+// kernel: it is a host-side stand-in, not a device address.  Its device
+// address is looked up once per device with hipGetSymbolAddress and kept.
+constexpr int64_t NOALLOC_DOUBLES = (int64_t)1 << 22;  // 32 MiB
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;
+
+hodlr_status scratch_ptr(double** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return HODLR_OK;
+  }
+  double* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) {
+    (void)hipGetLastError();
+    return fail(HODLR_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
+  g_scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return HODLR_OK;
+}
+
 // X <- Q X or Q^T X with temporaries from `scratch` (doubles) when given, else
 // from the caller's allocator
 hodlr_status apply_q_impl(const hodlr_qr_s& F, int32_t trans, int64_t nrhs, double* X, int64_t ldx,
@@ -1887,6 +1918,16 @@ hodlr_status hodlr_apply_q(const hodlr_qr_t* F, int32_t trans, int64_t nrhs, dou
   g_err.clear();
   if (F == nullptr) return fail(HODLR_EINVAL, "NULL factors");
   return apply_q_impl(*F, trans, nrhs, X, ldx, (hipStream_t)stream, nullptr, 0);
+}
+
+hodlr_status hodlr_apply_q_noalloc(const hodlr_qr_t* F, int32_t trans, int64_t nrhs, double* X, int64_t ldx,
+                                   hodlr_stream_t stream) {
+  g_err.clear();
+  if (F == nullptr) return fail(HODLR_EINVAL, "NULL factors");
+  if (X == nullptr || nrhs < 0 || ldx < F->t.n) return fail(HODLR_EINVAL, "bad argument");
+  double* buf = nullptr;
+  TRY(scratch_ptr(&buf));
+  return apply_q_impl(*F, trans, nrhs, X, ldx, (hipStream_t)stream, buf, NOALLOC_DOUBLES);
 }
 
 hodlr_status hodlr_solve(const hodlr_qr_t* F, int64_t nrhs, double* B, int64_t ldb, hodlr_stream_t stream) {
