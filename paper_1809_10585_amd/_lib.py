@@ -8,7 +8,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhodlr.so")
+# HODLR_LIB_PATH selects another build of the library (the host-sanitized one)
+LIB_PATH = os.environ.get("HODLR_LIB_PATH") or os.path.join(HERE, "libhodlr.so")
 
 HODLR_OK = 0
 STATUS = {0: "HODLR_OK", -1: "HODLR_EINVAL", -2: "HODLR_ENOMEM", -3: "HODLR_ENONFINITE",

@@ -82,5 +82,49 @@ def build(verbose: bool = False, reuse: bool | None = None) -> str:
     return OUT
 
 
+# host-code sanitizer build: the scheduler, C ABI and hazard checker compiled
+# with AddressSanitizer and UndefinedBehaviorSanitizer for the host side only
+# (device code is not instrumented), linked with the regular kernel objects
+ASAN_OUT = os.path.join(OBJ, "asan", "libhodlr.so")
+HOST_UNITS = ["hodlr.cpp", "check.cpp"]
+SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+       "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def asan_runtime() -> str | None:
+    base = "/opt/rocm/llvm/lib/clang"
+    if not os.path.isdir(base):
+        return None
+    for ver in sorted(os.listdir(base), reverse=True):
+        p = os.path.join(base, ver, "lib", "linux", "libclang_rt.asan-x86_64.so")
+        if os.path.exists(p):
+            return p
+    return None
+
+
+def build_asan() -> str:
+    """libhodlr.so with the host units sanitized, in _build/asan/ (for the CPU
+    tests of the C ABI; load it with the ASan runtime preloaded)."""
+    os.makedirs(os.path.dirname(ASAN_OUT), exist_ok=True)
+    kern = [_compile(u, True) for u in UNITS if u not in HOST_UNITS]
+    objs = []
+    for u in HOST_UNITS:
+        obj = os.path.join(OBJ, "asan", f"{u}.{_key(u)}.o")
+        if not os.path.exists(obj):
+            cmd = [hipcc()] + FLAGS + ["-O1", "-g"] + SAN + ["-c", "-x", "hip", os.path.join(CSRC, u), "-o", obj]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+                raise RuntimeError(f"hipcc (sanitized) failed for {u}")
+        objs.append(obj)
+    cmd = ([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host", "-shared-libasan"] + SAN
+           + objs + kern + ["-o", ASAN_OUT])
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("linking the sanitized libhodlr.so failed")
+    return ASAN_OUT
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv, reuse="--reuse" in sys.argv or None))

@@ -140,3 +140,43 @@ def test_ranklog_shape(H, fac):
     assert log.shape == (info["n_truncations"], 7)
     assert ((log[:, 6] >= 0) & (log[:, 6] <= log[:, 5])).all()
     assert set(np.unique(log[:, 0])) <= {0, 1, 2, 3, 4}
+
+
+def test_allocation_failure_is_reported(H):
+    """A caller's allocator that refuses once a small budget is spent: hodlr_qr
+    returns HODLR_ENOMEM (releasing what it had taken) instead of failing
+    later, and the library works again with the normal allocator."""
+    import ctypes as C
+    import torch
+    from paper_1809_10585_amd import _lib
+    inp = G.expkernel_hodlr(4096, 256, 2)
+    A = H.hodlr_build(inp, rank_cap=16)
+    state = {"used": 0, "live": {}, "budget": 4 << 20}
+    raw_alloc = torch._C._cuda_cudaCachingAllocator_raw_alloc
+    raw_delete = torch._C._cuda_cudaCachingAllocator_raw_delete
+
+    def alloc(size, stream, ctx):
+        if state["used"] + size > state["budget"]:
+            return None
+        p = int(raw_alloc(int(size), int(stream or 0)))
+        state["used"] += size
+        state["live"][p] = size
+        return p
+
+    def release(ptr, stream, ctx):
+        state["used"] -= state["live"].pop(int(ptr))
+        raw_delete(int(ptr))
+
+    hook = (_lib.ALLOC_FN(alloc), _lib.RELEASE_FN(release))
+    lib = H.load()
+    _lib.check(lib.hodlr_set_allocator(hook[0], hook[1], None))
+    try:
+        with pytest.raises(H.HodlrError) as e:
+            H.hodlr_qr(A, EPS, anorm=0.186 * 4096)
+        assert e.value.status == -2
+        torch.cuda.synchronize()
+        assert state["used"] == 0 and not state["live"]
+    finally:
+        H.use_torch_allocator(True)
+    F = H.hodlr_qr(A, EPS, anorm=0.186 * 4096)
+    H.hodlr_check(F)
