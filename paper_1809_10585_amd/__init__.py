@@ -24,11 +24,24 @@ __all__ = [
     "hodlr_qr_factor", "hodlr_check", "hodlr_qr_ranklog", "hodlr_plan_check", "hodlr_norm2_est",
     "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time", "hodlr_qr_profile",
     "hodlr_qr_batched", "hodlr_qr_batched_time", "use_torch_allocator", "HodlrMatrix", "QRFactors",
-    "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "HODLR_CHECK_ESTIMATE",
+    "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "HODLR_CHECK_ESTIMATE", "set_allocator",
     "HODLR_CHECK_PLANT", "load",
 ]
 
-_alloc_hook = None  # the ctypes callbacks installed in the library (kept alive here)
+_alloc_hook = None   # the allocator installed in the library: None (not yet), False (hipMalloc), a hook
+_torch_hook = None   # PyTorch's caching allocator as a pair of ctypes callbacks (made once)
+_keepalive = []      # every callback pair ever installed: handles made under an allocator call
+                     # its release function when they are freed, so none may be collected
+
+
+def set_allocator(alloc, release):
+    """Install a pair of ctypes callbacks (_lib.ALLOC_FN, _lib.RELEASE_FN) as the
+    library's allocator (hodlr_set_allocator); they are kept alive for the rest
+    of the process."""
+    global _alloc_hook
+    _keepalive.append((alloc, release))
+    _lib.check(_lib.load().hodlr_set_allocator(alloc, release, None))
+    _alloc_hook = (alloc, release)
 
 
 def use_torch_allocator(enable: bool = True):
@@ -37,11 +50,14 @@ def use_torch_allocator(enable: bool = True):
     torch's pool on the stream of the call.  Installed by the first call that
     touches the device unless HODLR_TORCH_ALLOCATOR=0; enable=False restores
     hipMalloc / hipMallocAsync."""
-    global _alloc_hook
+    global _alloc_hook, _torch_hook
     lib = _lib.load()
     if not enable:
         _lib.check(lib.hodlr_set_allocator(_lib.ALLOC_FN(), _lib.RELEASE_FN(), None))
         _alloc_hook = False
+        return
+    if _torch_hook is not None:
+        set_allocator(*_torch_hook)
         return
     import torch
 
@@ -60,9 +76,8 @@ def use_torch_allocator(enable: bool = True):
         except Exception:
             pass
 
-    hook = (_lib.ALLOC_FN(_alloc), _lib.RELEASE_FN(_release))
-    _lib.check(lib.hodlr_set_allocator(hook[0], hook[1], None))
-    _alloc_hook = hook
+    _torch_hook = (_lib.ALLOC_FN(_alloc), _lib.RELEASE_FN(_release))
+    set_allocator(*_torch_hook)
 
 
 def load(path: str = _lib.LIB_PATH):

@@ -70,6 +70,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise HodlrError(-6, f"{path} is missing; run paper_1809_10585_amd/build.py first")
+    # PyTorch ships its own HIP runtime: load it first so that the library binds
+    # to the same runtime instead of loading a second copy beside it
+    try:
+        import torch  # noqa: F401
+    except ImportError:  # pragma: no cover
+        pass
     lib = C.CDLL(path)
     sig = {
         "hodlr_set_allocator": (I32, [ALLOC_FN, RELEASE_FN, P]),

@@ -167,9 +167,7 @@ def test_allocation_failure_is_reported(H):
         state["used"] -= state["live"].pop(int(ptr))
         raw_delete(int(ptr))
 
-    hook = (_lib.ALLOC_FN(alloc), _lib.RELEASE_FN(release))
-    lib = H.load()
-    _lib.check(lib.hodlr_set_allocator(hook[0], hook[1], None))
+    H.set_allocator(_lib.ALLOC_FN(alloc), _lib.RELEASE_FN(release))
     try:
         with pytest.raises(H.HodlrError) as e:
             H.hodlr_qr(A, EPS, anorm=0.186 * 4096)
