@@ -117,12 +117,14 @@ def cpu_baseline(inp, min_seconds=10.0, max_reps=8):
 
 def bench_batched(H, G, np, count=256, seed=3, rank_cap=64, reps=3):
     """Batched workload: `count` independent Gaussian HODLR matrices, n = 256 * 2^d
-    with d ~ U{2..6}, leaf 256, exact off-diagonal rank k ~ U{1..4}, shift 4I,
-    seed 3, eps 1e-10.  Whole-batch wall time of hodlr_qr_batched (HIP events,
-    inputs resident) against the sum of one-at-a-time hodlr_qr run times of the
-    same matrices on the same GPU."""
+    with d ~ U{2..6}, leaf 256, exact off-diagonal rank k ~ U{4..32} capped at
+    32 / d (R's ranks, about 2 d k, then fit rank_cap 64), shift 4I, seed 3,
+    eps 1e-10.  Whole-batch wall time of hodlr_qr_batched (HIP events, inputs
+    resident; the shapes merged into one launch sequence, and the shape groups
+    one after another) against the sum of one-at-a-time hodlr_qr run times of
+    the same matrices on the same GPU."""
     t0 = time.perf_counter()
-    inps = G.batched_set(count=count, seed=seed)
+    inps = G.batched_set(count=count, seed=seed, kmin=4, kmax=32, rank_budget=rank_cap)
     As = [H.hodlr_build(inp, rank_cap=rank_cap) for inp in inps]
     log(f"batched workload: {count} matrices, sum n = {sum(i.n for i in inps)}, "
         f"built in {time.perf_counter() - t0:.1f} s")
@@ -133,12 +135,17 @@ def bench_batched(H, G, np, count=256, seed=3, rank_cap=64, reps=3):
     del Fs
     ms = H.hodlr_qr_batched_time(As, EPS, 0.0, 0, 1, reps)
     batch_ms = float(np.median(ms))
+    ms_shape = H.hodlr_qr_batched_time(As, EPS, 0.0, H.HODLR_QR_BY_SHAPE, 1, reps)
+    shape_ms = float(np.median(ms_shape))
     plain_ms = sum(float(H.hodlr_qr_time(A, EPS, 0.0, 0, 0, 1)[0]) for A in As)
-    log(f"batched ms {ms.round(2).tolist()}, one at a time {plain_ms:.1f} ms")
+    log(f"batched ms {ms.round(2).tolist()} (by shape {ms_shape.round(2).tolist()}), "
+        f"one at a time {plain_ms:.1f} ms")
     return {"workload": f"{count} Gaussian HODLR matrices, n = 256*2^d, d~U{{2..6}}, leaf 256, "
-                        f"rank k~U{{1..4}}, shift 4I, eps {EPS:g}, seed {seed}",
+                        f"rank k~U{{4..min(32, 32/d)}}, shift 4I, eps {EPS:g}, seed {seed}",
             "matrices": count, "sum_n": int(sum(i.n for i in inps)), "rank_cap": rank_cap,
+            "ranks": sorted({int(i.name.split("k=")[1].rstrip(")")) for i in inps}),
             "max_rank_r": max_r, "qr_per_s": count / (batch_ms / 1e3), "ms_per_batch": batch_ms,
+            "launches": infos[0]["n_launches"], "by_shape_ms_per_batch": shape_ms,
             "plain_loop_ms": plain_ms, "speedup_vs_plain": plain_ms / batch_ms,
             "fp64_tflops": flops / (batch_ms / 1e3) / 1e12, "flops_per_batch": flops}
 

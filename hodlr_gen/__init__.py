@@ -316,17 +316,20 @@ def cauchy_example(which: int, n: int = 2000, n_min: int = 250, eps: float = 1e-
 
 
 def batched_set(count: int = 256, seed: int = 3, dmin: int = 2, dmax: int = 6, kmin: int = 1,
-                kmax: int = 4, n_min: int = 256) -> list:
+                kmax: int = 4, n_min: int = 256, rank_budget: int | None = None) -> list:
     """The batch of independent matrices of the batched workload: for each of
-    `count` matrices in turn, d ~ U{dmin..dmax} and k ~ U{kmin..kmax} are drawn,
-    then a Gaussian HODLR matrix (gaussian_hodlr, shift 4I) of order
+    `count` matrices in turn, d ~ U{dmin..dmax} and k ~ U{kmin..kmax'} are
+    drawn, then a Gaussian HODLR matrix (gaussian_hodlr, shift 4I) of order
     n_min * 2^d with exact off-diagonal rank k, all from one stream seeded
-    with `seed`."""
+    with `seed`.  kmax' = kmax, or with a rank budget
+    max(kmin, min(kmax, rank_budget // (2 d))): the top block of R has rank
+    about 2 d k for these matrices, so the budget bounds R's ranks."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
         d = int(rng.integers(dmin, dmax + 1))
-        k = int(rng.integers(kmin, kmax + 1))
+        top = kmax if rank_budget is None else max(kmin, min(kmax, rank_budget // (2 * d)))
+        k = int(rng.integers(kmin, top + 1))
         out.append(gaussian_hodlr(n_min * 2 ** d, n_min, k, seed=None, rng=rng,
                                   name=f"batched(d={d},k={k})"))
     return out

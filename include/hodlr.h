@@ -85,6 +85,10 @@ hodlr_status hodlr_set_allocator(void *(*alloc)(size_t bytes, void *stream, void
                                    on one stream and replay it as a HIP graph     */
 #define HODLR_QR_ONE_STREAM 2u  /* direct launches, all on the caller's stream in
                                    the serial order                                */
+#define HODLR_QR_BY_SHAPE 4u    /* hodlr_qr_batched: run the groups of equal shape one
+                                   after another instead of one merged sequence    */
+#define HODLR_QR_KEEP 8u        /* keep the schedule (launch lists, workspace and, with
+                                   HODLR_QR_GRAPH, the graph) for hodlr_qr_refactor */
 
 /*
  * hodlr_build - copy a HODLR matrix to the device.
@@ -137,9 +141,13 @@ hodlr_status hodlr_qr(const hodlr_t *A, double eps, double anorm, uint32_t flags
  * hodlr_qr_batched - hodlr_qr of `count` independent matrices A[0..count-1] at
  * once (Algorithm hQR for each).  Matrices with the same partition and
  * rank_cap share one schedule: every launch of it carries the jobs of all of
- * them, so they advance through the recursion in lockstep; groups of different
- * shape run one after another.  Each factorisation computes exactly what
- * hodlr_qr computes for that matrix alone (bitwise: no kernel mixes jobs).
+ * them, so they advance through the recursion in lockstep.  When the matrices
+ * have several shapes (and one rank_cap) the schedules of the shapes are merged
+ * into one launch sequence: at each step the schedule with the most launches
+ * left picks the kernel, and every schedule whose next launch runs the same
+ * kernel variant joins that launch (flag HODLR_QR_BY_SHAPE: the shapes one after
+ * another instead).  Each factorisation computes exactly what hodlr_qr
+ * computes for that matrix alone (bitwise: no kernel mixes jobs).
  *  anorm  host array of count values (<= 0: estimate) or NULL (estimate all).
  *  out    host array of count handles, released with hodlr_qr_free one by one.
  * On error no handle is returned; the message names the first failing matrix.
@@ -155,6 +163,20 @@ hodlr_status hodlr_qr_batched(const hodlr_t *const *A, int32_t count, double eps
 hodlr_status hodlr_qr_batched_time(const hodlr_t *const *A, int32_t count, double eps,
                                    const double *anorm, uint32_t flags, int32_t warmup,
                                    int32_t reps, hodlr_stream_t stream, double *ms);
+
+/*
+ * hodlr_qr_refactor - factorise new matrices into factorisations made with
+ * HODLR_QR_KEEP, replaying their kept schedules (no planning, no allocation of
+ * schedule memory; with HODLR_QR_GRAPH the captured graph is launched again).
+ * A[i] must have F[i]'s partition and rank_cap; the thresholds are those of the
+ * first factorisation (its given |A|_2, or a new estimate of |A[i]|_2 when it
+ * estimated).  The factorisations of one hodlr_qr_batched call share one
+ * schedule and must all be passed together.  F[i]'s apply-Q / solve / product
+ * calls see the new factors.  Blocks the host until the device has finished
+ * (it reads the error flags); HODLR_ECAPACITY as hodlr_qr.
+ */
+hodlr_status hodlr_qr_refactor(hodlr_qr_t *const *F, const hodlr_t *const *A, int32_t count, uint32_t flags,
+                               hodlr_stream_t stream);
 
 /*
  * hodlr_apply_q - X <- Q X (trans = 0) or X <- Q^T X (trans = 1), with
@@ -325,6 +347,18 @@ hodlr_status hodlr_qr_ranklog(const hodlr_qr_t *F, int32_t *recs, int64_t cap, i
 #define HODLR_CHECK_PLANT 0x200u
 hodlr_status hodlr_plan_check(int64_t n, int32_t levels, const int64_t *leaf_off, int32_t rank_cap,
                               int32_t count, uint32_t flags, int64_t *stats, char *msg, int64_t msglen);
+
+/*
+ * hodlr_plan_check_set - hodlr_plan_check of the merged launch sequence that
+ * hodlr_qr_batched runs for `count` matrices of each of `nshapes` partitions
+ * (n[i], levels[i]); leaf_off holds the partitions' leaf offsets one after
+ * another (2^levels[i] + 1 entries each).  With nshapes == 1 it is
+ * hodlr_plan_check; with more, HODLR_CHECK_PLANT gives every shape's schedule
+ * the same workspace (a planted hazard between the jobs of merged launches).
+ */
+hodlr_status hodlr_plan_check_set(int32_t nshapes, const int64_t *n, const int32_t *levels,
+                                  const int64_t *leaf_off, int32_t rank_cap, int32_t count, uint32_t flags,
+                                  int64_t *stats, char *msg, int64_t msglen);
 
 void hodlr_free(hodlr_t *A);        /* NULL-safe; ignores factor views */
 void hodlr_qr_free(hodlr_qr_t *F);  /* NULL-safe */

@@ -16,15 +16,15 @@ import numpy as np
 import os
 
 from . import _lib
-from ._lib import (HODLR_CHECK_ESTIMATE, HODLR_CHECK_PLANT, HODLR_QR_GRAPH, HODLR_QR_ONE_STREAM,
-                   HodlrError, QRInfo)
+from ._lib import (HODLR_CHECK_ESTIMATE, HODLR_CHECK_PLANT, HODLR_QR_BY_SHAPE, HODLR_QR_GRAPH,
+                   HODLR_QR_KEEP, HODLR_QR_ONE_STREAM, HodlrError, QRInfo)
 
 __all__ = [
     "hodlr_build", "hodlr_qr", "hodlr_apply_q", "hodlr_solve", "hodlr_matmul", "hodlr_qr_matmul",
     "hodlr_qr_factor", "hodlr_check", "hodlr_qr_ranklog", "hodlr_plan_check", "hodlr_norm2_est",
     "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time", "hodlr_qr_profile",
     "hodlr_qr_batched", "hodlr_qr_batched_time", "use_torch_allocator", "HodlrMatrix", "QRFactors",
-    "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "HODLR_CHECK_ESTIMATE", "set_allocator",
+    "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "HODLR_QR_BY_SHAPE", "HODLR_QR_KEEP", "hodlr_qr_refactor", "HODLR_CHECK_ESTIMATE", "set_allocator",
     "HODLR_CHECK_PLANT", "load",
 ]
 
@@ -200,6 +200,16 @@ def hodlr_qr_batched(As, eps: float, anorm=None, flags: int = 0, stream=None) ->
     return [QRFactors(C.c_void_p(out[i]), A) for i, A in enumerate(As)]
 
 
+def hodlr_qr_refactor(Fs, As, flags: int = 0, stream=None) -> None:
+    """Factorise As into the kept factorisations Fs (made with HODLR_QR_KEEP),
+    replaying their schedules; Fs[i] then holds the factors of As[i]."""
+    Fs = list(Fs)
+    fp = (C.c_void_p * len(Fs))(*[F.handle for F in Fs])
+    hp, keep = _handles(As)
+    _lib.check(load().hodlr_qr_refactor(C.cast(fp, C.POINTER(C.c_void_p)), hp, len(Fs), int(flags),
+                                        _stream(stream)))
+
+
 def hodlr_qr_batched_time(As, eps: float, anorm=None, flags: int = 0, warmup: int = 1, reps: int = 3,
                           stream=None):
     """Per-run wall times (ms) of factorising the whole batch."""
@@ -274,16 +284,27 @@ def hodlr_qr_ranklog(F: QRFactors):
 
 def hodlr_plan_check(H, rank_cap: int, count: int = 1, flags: int = 0) -> dict:
     """Hazard check of the factorisation schedule on H's partition (no device
-    needed); H: hodlr_gen.HodlrInput or (n, levels, leaf_off)."""
-    if hasattr(H, "leaf_off"):
-        n, levels, off = H.n, H.levels, H.leaf_off
-    else:
-        n, levels, off = H
-    off = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    needed); H: hodlr_gen.HodlrInput or (n, levels, leaf_off), or a list of
+    them: the merged launch sequence of a batch with `count` matrices of each
+    partition."""
+    shapes = H if isinstance(H, (list, tuple)) and not isinstance(H[0], (int, np.integer)) else [H]
+    ns, lv, offs = [], [], []
+    for S in shapes:
+        if hasattr(S, "leaf_off"):
+            n, levels, off = S.n, S.levels, S.leaf_off
+        else:
+            n, levels, off = S
+        ns.append(int(n))
+        lv.append(int(levels))
+        offs.append(np.asarray(off, dtype=np.int64))
+    ns = np.asarray(ns, dtype=np.int64)
+    lv = np.asarray(lv, dtype=np.int32)
+    off = np.ascontiguousarray(np.concatenate(offs))
     stats = np.zeros(5, dtype=np.int64)
     msg = C.create_string_buffer(512)
-    _lib.check(load().hodlr_plan_check(int(n), int(levels), _ptr(off, C.c_int64), int(rank_cap), int(count),
-                                       int(flags), _ptr(stats, C.c_int64), msg, 512))
+    _lib.check(load().hodlr_plan_check_set(len(shapes), _ptr(ns, C.c_int64), _ptr(lv, C.c_int32),
+                                           _ptr(off, C.c_int64), int(rank_cap), int(count), int(flags),
+                                           _ptr(stats, C.c_int64), msg, 512))
     return {"launches": int(stats[0]), "launches_stream1": int(stats[1]), "pairs": int(stats[2]),
             "conflicts": int(stats[3]), "intra_conflicts": int(stats[4]), "first": msg.value.decode()}
 

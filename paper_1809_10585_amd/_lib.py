@@ -16,12 +16,14 @@ STATUS = {0: "HODLR_OK", -1: "HODLR_EINVAL", -2: "HODLR_ENOMEM", -3: "HODLR_ENON
           -4: "HODLR_ECAPACITY", -5: "HODLR_EDEVICE", -6: "HODLR_ENOTBUILT"}
 HODLR_QR_GRAPH = 1
 HODLR_QR_ONE_STREAM = 2
+HODLR_QR_BY_SHAPE = 4
+HODLR_QR_KEEP = 8
 
 # every symbol include/hodlr.h declares
 EXPORTS = [
     "hodlr_set_allocator", "hodlr_build", "hodlr_qr", "hodlr_apply_q", "hodlr_apply_q_noalloc",
     "hodlr_solve", "hodlr_matmul",
-    "hodlr_qr_matmul", "hodlr_qr_factor", "hodlr_check", "hodlr_qr_ranklog", "hodlr_plan_check",
+    "hodlr_qr_matmul", "hodlr_qr_factor", "hodlr_check", "hodlr_qr_ranklog", "hodlr_plan_check", "hodlr_plan_check_set", "hodlr_qr_refactor",
     "hodlr_norm2_est", "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time",
     "hodlr_qr_profile", "hodlr_op_name", "hodlr_op_count", "hodlr_qr_batched", "hodlr_qr_batched_time",
     "hodlr_free", "hodlr_qr_free", "hodlr_last_error", "hodlr_version",
@@ -83,6 +85,8 @@ def load(path: str = LIB_PATH):
         "hodlr_check": (I32, [P, P]),
         "hodlr_qr_ranklog": (I32, [P, PI32, I64, PI64]),
         "hodlr_plan_check": (I32, [I64, I32, PI64, I32, I32, C.c_uint32, PI64, C.c_char_p, I64]),
+        "hodlr_plan_check_set": (I32, [I32, PI64, PI32, PI64, I32, I32, C.c_uint32, PI64, C.c_char_p, I64]),
+        "hodlr_qr_refactor": (I32, [PP, PP, I32, C.c_uint32, P]),
         "hodlr_build": (I32, [I64, I32, PI64, PD, PI64, PD, PI64, PD, PI64, PI32, I32, P, PP]),
         "hodlr_qr": (I32, [P, D, D, C.c_uint32, P, PP]),
         "hodlr_apply_q": (I32, [P, I32, I64, P, I64, P]),

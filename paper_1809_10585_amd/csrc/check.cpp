@@ -241,6 +241,68 @@ void vec_job(const VecJob& J, int job, int type, Acc& a) {
   }
 }
 
+// the parts of the lane workspace and counters each job of a launch uses, from
+// its offsets (checked against the other jobs of the launch; the schedule
+// builder and the merging of schedules assign them)
+void ws_jobs(const Ctx& X, const Op& o, Acc& a) {
+  const Work* W = X.C.work;
+  if (W == nullptr || W->ws == nullptr || W->counters == nullptr) return;
+  const Plan& P = X.P;
+  const double* ws = W->ws + P.ws_off(o.lane);
+  const int* cnt = W->counters + P.cnt_off(o.lane);
+  auto rw = [&](const void* p, size_t bytes, int job) {
+    add_bytes(a.r, p, bytes, job);
+    add_bytes(a.w, p, bytes, job);
+  };
+  auto tr = [&](int j) {
+    const TrJob& J = P.trj[j];
+    rw(ws + J.hdr, TR_HDR * sizeof(double), j);
+    for (int s = 0; s < 2; ++s)
+      if (J.side[s].p0 > 0) {
+        rw(ws + J.side[s].node0, 2 * (size_t)J.side[s].p0 * TR_NODE * sizeof(double), j);
+        rw(cnt + J.side[s].cnt0, (size_t)J.side[s].p0 * sizeof(int), j);
+      }
+    rw(cnt + J.jcounter, sizeof(int), j);
+  };
+  auto mm = [&](int j) {
+    const MmJob& J = P.mmj[j];
+    const int d = 31 - __builtin_clz(J.v);
+    const int64_t nodes = (2 << (J.M.levels - d)) - 1;
+    rw(ws + J.red0, 2 * (size_t)nodes * J.rld * SMAX * sizeof(double), j);
+  };
+  switch (o.type) {
+    case OP_TRSMALL:
+    case OP_TRQR:
+      for (int i = 0; i < o.count; ++i) tr(P.trc[o.first + i].job);
+      break;
+    case OP_TRFORM:
+      for (int i = 0; i < o.count; ++i) tr(P.trf[o.first + i].job);
+      break;
+    case OP_MMPROJ:
+    case OP_MMRED:
+      for (int i = 0; i < o.count; ++i) {
+        const MmProj& pr = P.mmp[o.first + i];
+        const size_t stride = (size_t)P.mmj[pr.job].rld * SMAX;
+        const size_t n = o.type == OP_MMRED ? (size_t)pr.nchunk : 1;
+        rw(ws + pr.part, n * stride * sizeof(double), pr.job);
+        mm(pr.job);
+      }
+      break;
+    case OP_MMAPPLY:
+      for (int i = 0; i < o.count; ++i) mm(P.mma[o.first + i].job);
+      break;
+    case OP_GRED:
+      for (int i = 0; i < o.count; ++i) {
+        const GemmRed& r = P.gr[o.first + i];
+        if (r.nchunk > 1) rw(ws + r.part, (size_t)KCAP * KCAP * sizeof(double), r.job);
+        rw(cnt + r.counter, sizeof(int), r.job);
+      }
+      break;
+    default:
+      break;
+  }
+}
+
 // accesses of one launch, per job (job = index within the launch)
 Acc op_access(const Ctx& X, const Op& o) {
   Acc a;
@@ -299,6 +361,7 @@ Acc op_access(const Ctx& X, const Op& o) {
     default:
       break;
   }
+  ws_jobs(X, o, a);
   // workspace and counters of the op's lane (shared by all its jobs)
   const Work* W = X.C.work;
   const bool uses_ws = o.type == OP_TRSMALL || o.type == OP_TRQR || o.type == OP_TRFORM || o.type == OP_MMPROJ ||

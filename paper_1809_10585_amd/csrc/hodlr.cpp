@@ -693,6 +693,8 @@ struct Batch {
   std::vector<hipEvent_t> events;  // plan events + fork + join
   int64_t n_launch = 0;
   int size = 0;
+  std::vector<hodlr_qr_s*> members;  // the factorisations the plan writes, in job order
+  bool merged = false;               // several shapes in one sequence: serial order only
   ~Batch() {
     if (graph) (void)hipGraphExecDestroy(graph);
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -1179,6 +1181,7 @@ hodlr_status reset_factor(hodlr_qr_s& F, const hodlr_s& A, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(F.lo.V, A.lo.V, F.lo.vsz * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(F.ranks, A.ranks, 2 * (size_t)(1 << A.t.L) * sizeof(int), hipMemcpyDeviceToDevice, st));
   k_fill<<<(FC_SIZE + 255) / 256, 256, 0, st>>>(F.work.fc, FC_SIZE, 0.0);
+  k_zero_i32<<<1, 64, 0, st>>>(F.work.err, 4);  // a refactorisation starts without the last run's flags
   return HODLR_OK;
 }
 
@@ -1249,15 +1252,10 @@ hodlr_status make_storage(const hodlr_s& A, double eps, double anorm, hipStream_
   return HODLR_OK;
 }
 
-// the schedule of a batch of factors that share a tree and a capacity
-hodlr_status make_batch(const std::vector<hodlr_qr_s*>& Fs, hipStream_t st, std::shared_ptr<Batch>& out,
-                        int plant = 0) {
-  auto B = std::make_shared<Batch>();
-  B->mem.stream = st;
-  Plan& P = B->plan;
+// the launch list of a batch of factors that share a tree and a capacity (host only)
+void build_plan(const std::vector<hodlr_qr_s*>& Fs, Plan& P, int plant = 0) {
   const Tree& t = Fs[0]->t;
   P.wtop = 2 * Fs[0]->cap;
-  B->size = (int)Fs.size();
   // thresholds: |A|_2 from the power iteration unless given, then tau_A, tau_T
   std::vector<NormItem> est;
   std::vector<VecJob> sc;
@@ -1272,12 +1270,262 @@ hodlr_status make_batch(const std::vector<hodlr_qr_s*>& Fs, hipStream_t st, std:
   QRBuilder qb(Fs, P);
   qb.plant = plant;
   qb.build();
-  TRY(P.upload_all(B->mem, st));
-  TRY(ensure_work(B->mem, B->work, P.ws_need(), P.cnt_need(), false, st));
-  B->n_launch = 0;
-  for (const Op& o : P.ops) B->n_launch += op_launches(o) ? 1 : 0;
+}
+
+// upload a batch's plan and allocate its workspace
+hodlr_status finish_batch(Batch& B, hipStream_t st) {
+  Plan& P = B.plan;
+  TRY(P.upload_all(B.mem, st));
+  TRY(ensure_work(B.mem, B.work, P.ws_need(), P.cnt_need(), false, st));
+  B.n_launch = 0;
+  for (const Op& o : P.ops) B.n_launch += op_launches(o) ? 1 : 0;
+  return HODLR_OK;
+}
+
+// the schedule of a batch of factors that share a tree and a capacity
+hodlr_status make_batch(const std::vector<hodlr_qr_s*>& Fs, hipStream_t st, std::shared_ptr<Batch>& out,
+                        int plant = 0) {
+  auto B = std::make_shared<Batch>();
+  B->mem.stream = st;
+  B->size = (int)Fs.size();
+  B->members = Fs;
+  build_plan(Fs, B->plan, plant);
+  TRY(finish_batch(*B, st));
   out = std::move(B);
   return HODLR_OK;
+}
+
+// Merge the launch lists of several plans (independent factorisations of
+// different shapes, one rank capacity) into one list in which a launch carries
+// the jobs of every plan that runs the same kernel variant at that point.  Each
+// plan's launches keep their order (its serial order: both lanes in list
+// order); at every step the plan with the most launches left sets the kernel
+// variant, and every plan whose next launch is that variant joins it.  The
+// plans' workspaces and counters are laid out one after another.
+void merge_plans(const std::vector<const Plan*>& in, Plan& out, bool plant = false) {
+  const int G = (int)in.size();
+  std::vector<std::vector<int>> seq(G);  // launching ops of each plan
+  std::vector<int64_t> wb(G), cb(G);
+  int64_t ws = 0, cnt = 0;
+  for (int g = 0; g < G; ++g) {
+    const Plan& P = *in[g];
+    for (int i = 0; i < (int)P.ops.size(); ++i)
+      if (op_launches(P.ops[i])) seq[g].push_back(i);
+    if (!plant) {
+      wb[g] = ws;
+      cb[g] = cnt;
+      ws += P.ws_need();
+      cnt += P.cnt_need();
+    } else {  // (self test of the hazard check: every plan at offset 0)
+      wb[g] = cb[g] = 0;
+      ws = std::max(ws, P.ws_need());
+      cnt = std::max(cnt, (int64_t)P.cnt_need());
+    }
+    out.n_trunc += P.n_trunc;
+    out.mleaf = std::max(out.mleaf, P.mleaf);
+  }
+  out.wtop = in[0]->wtop;
+  out.ws_lane[0] = ws;
+  out.ws_lane[1] = 0;
+  out.cnt_lane[0] = (int)cnt;
+  out.cnt_lane[1] = 0;
+  // jobs of every plan, rebased once each (their workspace offsets depend on
+  // the lane of the op that runs them)
+  std::vector<int> trb(G), mmb(G), gjb(G);
+  for (int g = 0; g < G; ++g) {
+    trb[g] = (int)out.trj.size();
+    mmb[g] = (int)out.mmj.size();
+    gjb[g] = (int)out.gj.size();
+    out.trj.insert(out.trj.end(), in[g]->trj.begin(), in[g]->trj.end());
+    out.mmj.insert(out.mmj.end(), in[g]->mmj.begin(), in[g]->mmj.end());
+    out.gj.insert(out.gj.end(), in[g]->gj.begin(), in[g]->gj.end());
+  }
+  std::vector<char> tr_done(out.trj.size(), 0), mm_done(out.mmj.size(), 0);
+  auto rebase_tr = [&](int g, int lane, int j) {
+    const int jj = trb[g] + j;
+    if (tr_done[jj]) return jj;
+    tr_done[jj] = 1;
+    const int64_t w0 = wb[g] + in[g]->ws_off(lane);
+    const int c0 = (int)(cb[g] + in[g]->cnt_off(lane));
+    TrJob& J = out.trj[jj];
+    J.hdr += w0;
+    for (int s = 0; s < 2; ++s) {
+      if (J.side[s].p0 > 0) {
+        J.side[s].node0 += w0;
+        J.side[s].cnt0 += c0;
+      }
+    }
+    J.jcounter += c0;
+    return jj;
+  };
+  auto rebase_mm = [&](int g, int lane, int j) {
+    const int jj = mmb[g] + j;
+    if (!mm_done[jj]) {
+      mm_done[jj] = 1;
+      out.mmj[jj].red0 += wb[g] + in[g]->ws_off(lane);
+    }
+    return jj;
+  };
+  auto sig = [&](int g, int i) {
+    const Op& o = in[g]->ops[i];
+    int64_t a = 0, b = 0;
+    if (o.type == OP_MMAPPLY) a = o.a1;
+    if (o.type == OP_LGATHER || o.type == OP_LPANEL || o.type == OP_LUPDATE || o.type == OP_LSCATTER) {
+      a = o.a1;
+      b = o.n;
+    }
+    return std::make_tuple(o.type, a, b);
+  };
+  std::vector<size_t> h(G, 0);
+  std::vector<std::pair<int, int>> last_leaf;  // (plan, first job) of the previous merged leaf launch
+  int last_leaf_first = -1;
+  while (true) {
+    int lead = -1;
+    size_t best = 0;
+    for (int g = 0; g < G; ++g) {
+      const size_t left = seq[g].size() - h[g];
+      if (left > best) {
+        best = left;
+        lead = g;
+      }
+    }
+    if (lead < 0) break;
+    const auto s0 = sig(lead, seq[lead][h[lead]]);
+    std::vector<int> grp;
+    for (int g = 0; g < G; ++g)
+      if (h[g] < seq[g].size() && sig(g, seq[g][h[g]]) == s0) grp.push_back(g);
+    const Op& o0 = in[lead]->ops[seq[lead][h[lead]]];
+    Op m{o0.type};
+    m.a0 = o0.a0;
+    m.a1 = o0.a1;
+    m.n = o0.n;
+    switch (o0.type) {
+      case OP_TRSMALL:
+      case OP_TRQR: {
+        m.first = (int)out.trc.size();
+        for (int g : grp) {
+          const Op& o = in[g]->ops[seq[g][h[g]]];
+          for (int i = 0; i < o.count; ++i) {
+            TrChunk c = in[g]->trc[o.first + i];
+            c.job = rebase_tr(g, o.lane, c.job);
+            out.trc.push_back(c);
+          }
+        }
+        m.count = (int)out.trc.size() - m.first;
+        break;
+      }
+      case OP_TRFORM: {
+        m.first = (int)out.trf.size();
+        for (int g : grp) {
+          const Op& o = in[g]->ops[seq[g][h[g]]];
+          for (int i = 0; i < o.count; ++i) {
+            TrForm f = in[g]->trf[o.first + i];
+            f.job = rebase_tr(g, o.lane, f.job);
+            out.trf.push_back(f);
+          }
+        }
+        m.count = (int)out.trf.size() - m.first;
+        break;
+      }
+      case OP_MMPROJ:
+      case OP_MMRED: {
+        m.first = (int)out.mmp.size();
+        for (int g : grp) {
+          const Op& o = in[g]->ops[seq[g][h[g]]];
+          for (int i = 0; i < o.count; ++i) {
+            MmProj pr = in[g]->mmp[o.first + i];
+            pr.job = rebase_mm(g, o.lane, pr.job);
+            pr.part += wb[g] + in[g]->ws_off(o.lane);
+            out.mmp.push_back(pr);
+          }
+        }
+        m.count = (int)out.mmp.size() - m.first;
+        break;
+      }
+      case OP_MMAPPLY: {
+        m.first = (int)out.mma.size();
+        for (int g : grp) {
+          const Op& o = in[g]->ops[seq[g][h[g]]];
+          for (int i = 0; i < o.count; ++i) {
+            MmApply ap = in[g]->mma[o.first + i];
+            ap.job = rebase_mm(g, o.lane, ap.job);
+            out.mma.push_back(ap);
+          }
+        }
+        m.count = (int)out.mma.size() - m.first;
+        break;
+      }
+      case OP_GTALL: {
+        m.first = (int)out.gt.size();
+        for (int g : grp) {
+          const Op& o = in[g]->ops[seq[g][h[g]]];
+          for (int i = 0; i < o.count; ++i) {
+            GemmTile t = in[g]->gt[o.first + i];
+            t.job += gjb[g];
+            out.gt.push_back(t);
+          }
+        }
+        m.count = (int)out.gt.size() - m.first;
+        break;
+      }
+      case OP_GRED: {
+        m.first = (int)out.gr.size();
+        for (int g : grp) {
+          const Op& o = in[g]->ops[seq[g][h[g]]];
+          for (int i = 0; i < o.count; ++i) {
+            GemmRed r = in[g]->gr[o.first + i];
+            r.job += gjb[g];
+            r.part += wb[g] + in[g]->ws_off(o.lane);
+            r.counter += (int)(cb[g] + in[g]->cnt_off(o.lane));
+            out.gr.push_back(r);
+          }
+        }
+        m.count = (int)out.gr.size() - m.first;
+        break;
+      }
+      case OP_LGATHER:
+      case OP_LPANEL:
+      case OP_LUPDATE:
+      case OP_LSCATTER: {
+        // the launch's jobs are a contiguous run of leaf jobs; reuse the previous
+        // run when the same leaves continue (the ~20 launches of one leaf QR)
+        const int nper = (int)o0.n;
+        std::vector<std::pair<int, int>> key;
+        int njobs = 0;
+        for (int g : grp) {
+          const Op& o = in[g]->ops[seq[g][h[g]]];
+          key.push_back({g, o.first});
+          njobs += o.count / nper;
+        }
+        if (key != last_leaf) {
+          last_leaf_first = (int)out.lj.size();
+          for (int g : grp) {
+            const Op& o = in[g]->ops[seq[g][h[g]]];
+            for (int i = 0; i < o.count / nper; ++i) out.lj.push_back(in[g]->lj[o.first + i]);
+          }
+          last_leaf = key;
+        }
+        m.first = last_leaf_first;
+        m.count = njobs * nper;
+        break;
+      }
+      case OP_FILL:
+      case OP_NORMALIZE:
+      case OP_SETSCAL: {
+        m.first = (int)out.vj.size();
+        for (int g : grp) {
+          const Op& o = in[g]->ops[seq[g][h[g]]];
+          for (int i = 0; i < o.count; ++i) out.vj.push_back(in[g]->vj[o.first + i]);
+        }
+        m.count = (int)out.vj.size() - m.first;
+        break;
+      }
+      default:
+        break;
+    }
+    out.ops.push_back(m);
+    for (int g : grp) ++h[g];
+  }
 }
 
 hodlr_status make_factor(const hodlr_s& A, double eps, double anorm, hipStream_t st,
@@ -1307,8 +1555,11 @@ hodlr_status lane_streams(Batch& B) {
 // every edge of it was present, so the graph keeps the serial order.
 hodlr_status run_batch(Batch& B, const std::vector<hodlr_qr_s*>& Fs, const std::vector<const hodlr_s*>& As,
                        uint32_t flags, hipStream_t st) {
+  // the inputs are copied in by direct launches, so a captured graph holds the
+  // factorisation's launches only and serves any inputs of the batch's shapes
+  for (size_t i = 0; i < Fs.size(); ++i) TRY(reset_factor(*Fs[i], *As[i], st));
+  if (B.merged) flags |= HODLR_QR_ONE_STREAM;
   if (!(flags & HODLR_QR_GRAPH)) {
-    for (size_t i = 0; i < Fs.size(); ++i) TRY(reset_factor(*Fs[i], *As[i], st));
     if (flags & HODLR_QR_ONE_STREAM) return run_ops(B.plan, B.work, st);
     TRY(lane_streams(B));
     return run_ops(B.plan, B.work, st, B.aux, B.events.data());
@@ -1319,9 +1570,7 @@ hodlr_status run_batch(Batch& B, const std::vector<hodlr_qr_s*>& Fs, const std::
     HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     TRY(set_attrs());
     HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hodlr_status s1 = HODLR_OK;
-    for (size_t i = 0; i < Fs.size() && s1 == HODLR_OK; ++i) s1 = reset_factor(*Fs[i], *As[i], cs);
-    hodlr_status s2 = s1 == HODLR_OK ? run_ops(B.plan, B.work, cs) : s1;
+    hodlr_status s2 = run_ops(B.plan, B.work, cs);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
@@ -1449,12 +1698,13 @@ hodlr_status finish_factor(hodlr_qr_s& F, hipStream_t st) {
 
 // keep the schedule's counts, release its plan and workspace, and cache the
 // launch sequences of apply Q and solve (the factors are final)
-hodlr_status finalize_factor(hodlr_qr_s& F, hipStream_t st) {
+hodlr_status finalize_factor(hodlr_qr_s& F, hipStream_t st, bool keep = false) {
   if (F.batch) {
     F.n_launch = F.batch->n_launch;
-    F.n_trunc = F.batch->plan.n_trunc / std::max(1, F.batch->size);
-    F.batch.reset();
+    F.n_trunc = (int64_t)F.logkeys.size();  // one key per recompression of this factorisation
+    if (!keep) F.batch.reset();
   }
+  if (F.applyp[0]) return HODLR_OK;  // refactorisation: same storage, cached sequences still valid
   F.mem.stream = st;
   TRY(build_apply_plan(F, 0, st, F.applyp[0]));
   TRY(build_apply_plan(F, 1, st, F.applyp[1]));
@@ -1640,7 +1890,7 @@ hodlr_status hodlr_qr(const hodlr_t* A, double eps, double anorm, uint32_t flags
   TRY(make_factor(*A, eps, anorm, st, F));
   TRY(run_factor(*F, *A, flags, st));
   TRY(finish_factor(*F, st));
-  TRY(finalize_factor(*F, st));
+  TRY(finalize_factor(*F, st, (flags & HODLR_QR_KEEP) != 0));
   *out = F.release();
   return HODLR_OK;
 }
@@ -1655,10 +1905,11 @@ namespace {
 struct BatchSet {
   std::vector<std::unique_ptr<hodlr_qr_s>> F;
   std::vector<std::vector<int>> groups;  // indices into F / A
+  bool merged = false;                   // one merged launch sequence (serial order)
 };
 
 hodlr_status make_batch_set(const hodlr_t* const* A, int count, double eps, const double* anorm,
-                            hipStream_t st, BatchSet& S) {
+                            uint32_t flags, hipStream_t st, BatchSet& S) {
   S.F.resize(count);
   for (int i = 0; i < count; ++i) {
     TRY(make_storage(*A[i], eps, anorm ? anorm[i] : 0.0, st, S.F[i]));
@@ -1673,6 +1924,32 @@ hodlr_status make_batch_set(const hodlr_t* const* A, int count, double eps, cons
       }
     }
     if (!placed) S.groups.push_back({i});
+  }
+  bool one_cap = true;
+  for (int i = 1; i < count; ++i) one_cap = one_cap && A[i]->cap == A[0]->cap;
+  if (S.groups.size() > 1 && one_cap && !(flags & HODLR_QR_BY_SHAPE)) {
+    // one launch sequence across the shapes
+    std::vector<Plan> plans(S.groups.size());
+    std::vector<const Plan*> pp;
+    for (size_t gi = 0; gi < S.groups.size(); ++gi) {
+      std::vector<hodlr_qr_s*> fs;
+      for (int i : S.groups[gi]) fs.push_back(S.F[i].get());
+      build_plan(fs, plans[gi]);
+      pp.push_back(&plans[gi]);
+    }
+    auto B = std::make_shared<Batch>();
+    B->mem.stream = st;
+    B->size = count;
+    B->merged = true;
+    for (auto& F : S.F) B->members.push_back(F.get());
+    merge_plans(pp, B->plan);
+    TRY(finish_batch(*B, st));
+    for (auto& F : S.F) F->batch = B;
+    std::vector<int> all;
+    for (int i = 0; i < count; ++i) all.push_back(i);
+    S.groups = {all};
+    S.merged = true;
+    return HODLR_OK;
   }
   for (auto& g : S.groups) {
     std::vector<hodlr_qr_s*> fs;
@@ -1815,7 +2092,7 @@ hodlr_status hodlr_qr_batched(const hodlr_t* const* A, int32_t count, double eps
   for (int i = 0; i < count; ++i) out[i] = nullptr;
   hipStream_t st = (hipStream_t)stream;
   BatchSet S;
-  TRY(make_batch_set(A, count, eps, anorm, st, S));
+  TRY(make_batch_set(A, count, eps, anorm, flags, st, S));
   TRY(run_batch_set(S, A, flags, st));
   hodlr_status first_err = HODLR_OK;
   std::string msg;
@@ -1827,8 +2104,61 @@ hodlr_status hodlr_qr_batched(const hodlr_t* const* A, int32_t count, double eps
     }
   }
   if (first_err != HODLR_OK) return fail(first_err, msg);
-  for (int i = 0; i < count; ++i) TRY(finalize_factor(*S.F[i], st));
+  for (int i = 0; i < count; ++i) TRY(finalize_factor(*S.F[i], st, (flags & HODLR_QR_KEEP) != 0));
   for (int i = 0; i < count; ++i) out[i] = S.F[i].release();
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_qr_refactor(hodlr_qr_t* const* F, const hodlr_t* const* A, int32_t count, uint32_t flags,
+                               hodlr_stream_t stream) {
+  g_err.clear();
+  if (F == nullptr || A == nullptr || count < 1) return fail(HODLR_EINVAL, "bad argument");
+  for (int i = 0; i < count; ++i) {
+    if (F[i] == nullptr || A[i] == nullptr) return fail(HODLR_EINVAL, "NULL handle");
+    if (!F[i]->batch) return fail(HODLR_EINVAL, "factorisation " + std::to_string(i) + " kept no schedule");
+    const hodlr_s& a = *A[i];
+    if (a.borrowed || a.leaf_kind != LEAF_FULL) return fail(HODLR_EINVAL, "a factor view in place of a matrix");
+    if (a.t.L != F[i]->t.L || a.t.n != F[i]->t.n || a.cap != F[i]->cap || a.t.lo != F[i]->t.lo ||
+        a.t.hi != F[i]->t.hi)
+      return fail(HODLR_EINVAL, "matrix " + std::to_string(i) + " differs in partition or rank_cap");
+  }
+  // every schedule is run once, over exactly the factorisations it was built for
+  std::vector<Batch*> seen;
+  for (int i = 0; i < count; ++i) {
+    Batch* B = F[i]->batch.get();
+    if (std::find(seen.begin(), seen.end(), B) != seen.end()) continue;
+    seen.push_back(B);
+    std::vector<const hodlr_s*> as(B->members.size(), nullptr);
+    int given = 0;
+    for (int j = 0; j < count; ++j) {
+      if (F[j]->batch.get() != B) continue;
+      auto it = std::find(B->members.begin(), B->members.end(), F[j]);
+      if (it == B->members.end() || as[it - B->members.begin()] != nullptr)
+        return fail(HODLR_EINVAL, "a factorisation appears twice");
+      as[it - B->members.begin()] = A[j];
+      ++given;
+    }
+    if (given != (int)B->members.size())
+      return fail(HODLR_EINVAL, "every factorisation of a kept batch must be refactorised together");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  for (Batch* B : seen) {
+    std::vector<const hodlr_s*> as(B->members.size());
+    for (int j = 0; j < count; ++j)
+      if (F[j]->batch.get() == B)
+        as[std::find(B->members.begin(), B->members.end(), F[j]) - B->members.begin()] = A[j];
+    TRY(run_batch(*B, B->members, as, flags, st));
+  }
+  hodlr_status first_err = HODLR_OK;
+  std::string msg;
+  for (int i = 0; i < count; ++i) {
+    const hodlr_status e = finish_factor(*F[i], st);
+    if (e != HODLR_OK && first_err == HODLR_OK) {
+      first_err = e;
+      msg = "matrix " + std::to_string(i) + ": " + g_err;
+    }
+  }
+  if (first_err != HODLR_OK) return fail(first_err, msg);
   return HODLR_OK;
 }
 
@@ -1840,7 +2170,7 @@ hodlr_status hodlr_qr_batched_time(const hodlr_t* const* A, int32_t count, doubl
   TRY(check_batch_args(A, count, eps));
   hipStream_t st = (hipStream_t)stream;
   BatchSet S;
-  TRY(make_batch_set(A, count, eps, anorm, st, S));
+  TRY(make_batch_set(A, count, eps, anorm, flags, st, S));
   for (int i = 0; i < warmup; ++i) TRY(run_batch_set(S, A, flags, st));
   for (int i = 0; i < count; ++i) TRY(finish_factor(*S.F[i], st));
   hipEvent_t e0, e1;
@@ -2030,7 +2360,7 @@ hodlr_status hodlr_qr_info(const hodlr_qr_t* F, hodlr_qr_info_t* info) {
   info->tau_t = F->tauT;
   info->flops = flop_total(F->work.fc);
   info->norm_flops = flop_sum(F->work.fc, FC_NORM, FC_NORM + 1);
-  info->n_truncations = F->batch ? F->batch->plan.n_trunc / F->batch->size : F->n_trunc;
+  info->n_truncations = (int64_t)F->logkeys.size();
   info->n_launches = F->batch ? F->batch->n_launch : F->n_launch;
   info->device_bytes = (int64_t)F->mem.bytes;
   return HODLR_OK;
@@ -2137,37 +2467,61 @@ hodlr_status hodlr_qr_export(const hodlr_qr_t* F, char which, double* leaves, do
 // between the jobs of each launch.
 hodlr_status hodlr_plan_check(int64_t n, int32_t levels, const int64_t* leaf_off, int32_t rank_cap, int32_t count,
                               uint32_t flags, int64_t* stats, char* msg, int64_t msglen) {
+  return hodlr_plan_check_set(1, &n, &levels, leaf_off, rank_cap, count, flags, stats, msg, msglen);
+}
+
+hodlr_status hodlr_plan_check_set(int32_t nshapes, const int64_t* n, const int32_t* levels, const int64_t* leaf_off,
+                                  int32_t rank_cap, int32_t count, uint32_t flags, int64_t* stats, char* msg,
+                                  int64_t msglen) {
   g_err.clear();
-  if (leaf_off == nullptr || stats == nullptr || levels < 0 || levels > MAXGROUPS || count < 1 ||
+  if (n == nullptr || levels == nullptr || leaf_off == nullptr || stats == nullptr || nshapes < 1 || count < 1 ||
       rank_cap < 1 || rank_cap > KCAP)
     return fail(HODLR_EINVAL, "bad argument");
-  const int nl = 1 << levels;
-  if (leaf_off[0] != 0 || leaf_off[nl] != n) return fail(HODLR_EINVAL, "leaf_off must run from 0 to n");
-  for (int j = 0; j < nl; ++j)
-    if (leaf_off[j + 1] - leaf_off[j] < 1 || leaf_off[j + 1] - leaf_off[j] > MAXLEAF)
-      return fail(HODLR_EINVAL, "bad leaf size");
   struct Virt {
     Virt() { g_virtual = true; }
     ~Virt() { g_virtual = false; }
   } virt;
-  hodlr_s A;
-  A.t.init(levels, leaf_off);
-  A.cap = rank_cap;
-  std::vector<std::unique_ptr<hodlr_qr_s>> Fs(count);
-  std::vector<hodlr_qr_s*> fp;
-  for (int i = 0; i < count; ++i) {
-    TRY(make_storage(A, 1e-10, (flags & HODLR_CHECK_ESTIMATE) ? 0.0 : 1.0, nullptr, Fs[i]));
-    fp.push_back(Fs[i].get());
+  std::vector<hodlr_s> A(nshapes);
+  const int64_t* off = leaf_off;
+  for (int i = 0; i < nshapes; ++i) {
+    if (levels[i] < 0 || levels[i] > MAXGROUPS) return fail(HODLR_EINVAL, "bad levels");
+    const int nl = 1 << levels[i];
+    if (off[0] != 0 || off[nl] != n[i]) return fail(HODLR_EINVAL, "leaf_off must run from 0 to n");
+    for (int j = 0; j < nl; ++j)
+      if (off[j + 1] - off[j] < 1 || off[j + 1] - off[j] > MAXLEAF) return fail(HODLR_EINVAL, "bad leaf size");
+    A[i].t.init(levels[i], off);
+    A[i].cap = rank_cap;
+    off += nl + 1;
   }
+  std::vector<std::unique_ptr<hodlr_qr_s>> Fs;
+  std::vector<std::vector<hodlr_qr_s*>> groups(nshapes);
+  for (int i = 0; i < nshapes; ++i)
+    for (int c = 0; c < count; ++c) {
+      Fs.emplace_back();
+      TRY(make_storage(A[i], 1e-10, (flags & HODLR_CHECK_ESTIMATE) ? 0.0 : 1.0, nullptr, Fs.back()));
+      groups[i].push_back(Fs.back().get());
+    }
   std::shared_ptr<Batch> B;
-  TRY(make_batch(fp, nullptr, B, (flags & HODLR_CHECK_PLANT) ? 1 : 0));
+  if (nshapes == 1) {
+    TRY(make_batch(groups[0], nullptr, B, (flags & HODLR_CHECK_PLANT) ? 1 : 0));
+  } else {
+    std::vector<Plan> plans(nshapes);
+    std::vector<const Plan*> pp;
+    for (int i = 0; i < nshapes; ++i) {
+      build_plan(groups[i], plans[i]);
+      pp.push_back(&plans[i]);
+    }
+    B = std::make_shared<Batch>();
+    merge_plans(pp, B->plan, (flags & HODLR_CHECK_PLANT) != 0);
+    TRY(finish_batch(*B, nullptr));
+  }
   Plan& P = B->plan;
   if (flags & HODLR_QR_ONE_STREAM)
     for (Op& o : P.ops) o.lane = 0;
   CheckCtx C;
   C.cap = rank_cap;
   C.work = &B->work;
-  for (hodlr_qr_s* F : fp) {
+  for (auto& F : Fs) {
     C.blocks[F->up.dview] = &F->up.hview;
     C.blocks[F->lo.dview] = &F->lo.hview;
     C.blocks[F->tup.dview] = &F->tup.hview;

@@ -105,6 +105,10 @@ def test_invalid_arguments_are_rejected_on_host(lib):
     assert lib.hodlr_qr_batched(C.cast(arr, C.POINTER(C.c_void_p)), 2, 1e-10, None, 0, None, None) == -1
     ms = (C.c_double * 1)()
     assert lib.hodlr_qr_batched_time(None, 1, 1e-10, None, 0, 0, 1, None, ms) == -1
+    # refactor: no handles, NULL handle entries
+    assert lib.hodlr_qr_refactor(None, None, 1, 0, None) == -1
+    assert lib.hodlr_qr_refactor(C.cast(arr, C.POINTER(C.c_void_p)), C.cast(arr, C.POINTER(C.c_void_p)), 2, 0,
+                                 None) == -1
 
 
 def test_header_documents_every_entry_point():

@@ -505,11 +505,17 @@ def _batch_inputs():
     return [G.gaussian_hodlr(n, 256, k, seed=sd) for n, k, sd in specs]
 
 
-def test_batched_equals_one_at_a_time_bitwise(H):
-    """Each factorisation of a batch gives the bits hodlr_qr gives alone."""
+@pytest.mark.parametrize("mode", ["merged", "by_shape", "merged_graph", "by_shape_one_stream"])
+def test_batched_equals_one_at_a_time_bitwise(H, mode):
+    """Each factorisation of a batch gives the bits hodlr_qr gives alone:
+    shapes merged into one launch sequence (the default), shape groups one
+    after another (two streams, or one), and the merged sequence captured and
+    replayed as a HIP graph."""
+    flags = {"merged": 0, "by_shape": H.HODLR_QR_BY_SHAPE, "merged_graph": H.HODLR_QR_GRAPH,
+             "by_shape_one_stream": H.HODLR_QR_BY_SHAPE | H.HODLR_QR_ONE_STREAM}[mode]
     inps = _batch_inputs()
     As = [H.hodlr_build(inp, rank_cap=32) for inp in inps]
-    Fb = H.hodlr_qr_batched(As, EPS)
+    Fb = H.hodlr_qr_batched(As, EPS, flags=flags)
     for inp, A, Fi in zip(inps, As, Fb):
         X = np.random.default_rng(5).standard_normal((inp.n, 4))
         F1 = H.hodlr_qr(A, EPS)
@@ -517,7 +523,58 @@ def test_batched_equals_one_at_a_time_bitwise(H):
             a = H.hodlr_qr_matmul(Fi, which, H.colmajor(X)).cpu().numpy()
             b = H.hodlr_qr_matmul(F1, which, H.colmajor(X)).cpu().numpy()
             assert np.array_equal(a, b), which
-        assert H.hodlr_qr_info(Fi)["anorm"] == H.hodlr_qr_info(F1)["anorm"]
+        i1, ib = H.hodlr_qr_info(F1), H.hodlr_qr_info(Fi)
+        assert ib["anorm"] == i1["anorm"]
+        assert ib["n_truncations"] == i1["n_truncations"]
+        assert np.array_equal(H.hodlr_qr_ranklog(Fi), H.hodlr_qr_ranklog(F1))
+
+
+def test_batched_graph_replays(H):
+    """The merged batch schedule kept (HODLR_QR_KEEP) and captured as one HIP
+    graph, then replayed by hodlr_qr_refactor several times with eager work and
+    synchronisations between the replays, alternating between two sets of
+    inputs of the same shapes: every replay leaves exactly the factors that
+    hodlr_qr computes for those inputs alone."""
+    import torch
+    shapes = [(1024, 1), (2048, 3), (1024, 4)]
+    sets = [[G.gaussian_hodlr(n, 256, k, seed=60 + 10 * r + i) for i, (n, k) in enumerate(shapes)]
+            for r in range(2)]
+    As = [[H.hodlr_build(inp, rank_cap=32) for inp in s] for s in sets]
+    X = [np.random.default_rng(8).standard_normal((n, 3)) for n, _ in shapes]
+    ref = [[(H.hodlr_qr_matmul(F, "R", H.colmajor(x)).cpu().numpy(), H.hodlr_apply_q(F, H.colmajor(x)).cpu().numpy())
+            for F, x in zip([H.hodlr_qr(A, EPS) for A in a], X)] for a in As]
+    Fk = H.hodlr_qr_batched(As[0], EPS, flags=H.HODLR_QR_GRAPH | H.HODLR_QR_KEEP)
+    for rep in range(5):
+        r = rep % 2
+        if rep > 0:
+            H.hodlr_qr_refactor(Fk, As[r], flags=H.HODLR_QR_GRAPH)
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64).sum().item()  # eager work between
+        torch.cuda.synchronize()
+        for i, (F, x) in enumerate(zip(Fk, X)):
+            assert np.array_equal(H.hodlr_qr_matmul(F, "R", H.colmajor(x)).cpu().numpy(), ref[r][i][0]), (rep, i, junk)
+            assert np.array_equal(H.hodlr_apply_q(F, H.colmajor(x)).cpu().numpy(), ref[r][i][1]), (rep, i)
+
+
+def test_refactor_rules(H):
+    """A kept single factorisation refactorised with new values (direct
+    launches) matches hodlr_qr; a batch member alone, a factorisation that kept
+    nothing, or a matrix of another shape is refused."""
+    a, b = G.gaussian_hodlr(1024, 128, 3, seed=70), G.gaussian_hodlr(1024, 128, 3, seed=71)
+    Aa, Ab = H.hodlr_build(a, rank_cap=32), H.hodlr_build(b, rank_cap=32)
+    F = H.hodlr_qr(Aa, EPS, flags=H.HODLR_QR_KEEP)
+    H.hodlr_qr_refactor([F], [Ab])
+    X = H.colmajor(np.random.default_rng(9).standard_normal((1024, 2)))
+    assert np.array_equal(H.hodlr_qr_matmul(F, "R", X).cpu().numpy(),
+                          H.hodlr_qr_matmul(H.hodlr_qr(Ab, EPS), "R", X).cpu().numpy())
+    assert H.hodlr_qr_info(F)["anorm"] == H.hodlr_qr_info(H.hodlr_qr(Ab, EPS))["anorm"]
+    Fb = H.hodlr_qr_batched([Aa, Ab], EPS, flags=H.HODLR_QR_KEEP)
+    with pytest.raises(H.HodlrError):
+        H.hodlr_qr_refactor(Fb[:1], [Aa])
+    with pytest.raises(H.HodlrError):
+        H.hodlr_qr_refactor([H.hodlr_qr(Aa, EPS)], [Ab])
+    Ac = H.hodlr_build(G.gaussian_hodlr(2048, 128, 3, seed=72), rank_cap=32)
+    with pytest.raises(H.HodlrError):
+        H.hodlr_qr_refactor([F], [Ac])
 
 
 def test_batched_parity_with_oracle(H):

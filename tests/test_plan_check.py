@@ -66,3 +66,35 @@ def test_serial_order_has_no_concurrent_pairs(H):
 def test_plan_check_rejects_bad_partition(H):
     with pytest.raises(H.HodlrError):
         H.hodlr_plan_check((100, 1, np.array([0, 0, 100])), 8)
+
+
+# hodlr_qr_batched merges the schedules of the shapes of a batch into one
+# launch sequence (one stream): every shape's workspace and counters are laid
+# out apart, so the jobs of different shapes that share a launch never touch
+# the same bytes.
+MERGED = [
+    ([G.partition(1024, 256), G.partition(2048, 256), G.partition(4096, 256)], 32, 2),
+    ([G.partition(256 * 2 ** d, 256) for d in range(2, 7)], 64, 1),  # the batched workload's shapes
+    ([G.partition(1500, 200), G.partition(512, 64), G.partition(257, 33)], 16, 2),  # ragged, mixed leaves
+]
+
+
+@pytest.mark.parametrize("parts,cap,count", MERGED)
+def test_merged_schedule_has_no_hazard(H, parts, cap, count):
+    shapes = [(int(off[-1]), lv, off) for lv, off in parts]
+    r = H.hodlr_plan_check(shapes, cap, count=count)
+    assert r["conflicts"] == 0 and r["intra_conflicts"] == 0, r["first"]
+    assert r["launches_stream1"] == 0
+    # fewer launches than the shapes one after another
+    alone = sum(H.hodlr_plan_check(s, cap, count=count, flags=H.HODLR_QR_ONE_STREAM)["launches"]
+                for s in shapes)
+    assert r["launches"] < alone
+    print(f"merged {r['launches']} launches, by shape {alone}")
+
+
+def test_merged_planted_overlap_is_found(H):
+    """Every shape's schedule given the same workspace: jobs of two shapes in
+    one merged launch then share workspace bytes, and the check must say so."""
+    shapes = [(int(off[-1]), lv, off) for lv, off in (G.partition(1024, 256), G.partition(2048, 256))]
+    r = H.hodlr_plan_check(shapes, 16, flags=H.HODLR_CHECK_PLANT)
+    assert r["intra_conflicts"] >= 1, r
