@@ -150,36 +150,61 @@ def bench_batched(H, G, np, count=256, seed=3, rank_cap=64, reps=3):
             "fp64_tflops": flops / (batch_ms / 1e3) / 1e12, "flops_per_batch": flops}
 
 
-def bench_served(H, G, np, requests=200, rate=200.0, pool=16, seed=4):
-    """Served workload: a Poisson stream (`rate` req/s) of `requests` requests,
-    each a QR of one of `pool` Gaussian HODLR matrices (n log-uniform in
-    [1024, 32768], leaf 256, rank k~U{1..4}, shift 4I) with probability 1/2,
-    else a solve with the factor of an earlier QR request for nrhs~U{1..64}
-    N(0,1) right-hand sides.  Continuous batching (one host thread, each step
-    batches every admissible arrived request) against serving one request per
-    step in arrival order."""
+def served_pool(H, G, np, n_gauss=16, n_cauchy=6, seed=4, rank_cap=64):
+    """The served workload's matrices, generated once and kept on the device
+    (requests draw from them instead of generating a fresh matrix each):
+    Gaussian HODLR (shift 4I) with n log-uniform in [1024, 32768], leaf 256 and
+    rank k ~ U{4..32} capped at 32 / depth (R's ranks, about 2 depth k, then fit
+    rank_cap 64); Cauchy HODLR (the ill-conditioned generator, compressed at
+    1e-10) with n log-uniform in [1024, 4096], the sizes the host generates in
+    seconds."""
     import math
-    from paper_1809_10585_amd import serve
     rng = np.random.default_rng(seed)
-    mats = []
-    for _ in range(pool):
+    mats, desc = [], []
+    for _ in range(n_gauss):
         n = int(round(math.exp(rng.uniform(math.log(1024), math.log(32768)))))
-        k = int(rng.integers(1, 5))
-        mats.append(H.hodlr_build(G.gaussian_hodlr(n, 256, k, seed=None, rng=rng), rank_cap=64))
-    out = {"workload": f"{requests} requests, Poisson {rate:g}/s, QR (p=1/2) of one of {pool} Gaussian HODLR "
-                       f"matrices n~logU[1024,32768] leaf 256 k~U{{1..4}}, or solve with 1..64 rhs with the "
-                       f"factor of an earlier QR request; eps {EPS:g}, seed {seed}"}
+        d = G.partition(n, 256)[0]
+        k = int(rng.integers(4, max(4, min(32, 32 // d)) + 1))
+        mats.append(H.hodlr_build(G.gaussian_hodlr(n, 256, k, seed=None, rng=rng), rank_cap=rank_cap))
+        desc.append(("gaussian", n, k))
+    for _ in range(n_cauchy):
+        n = int(round(math.exp(rng.uniform(math.log(1024), math.log(4096)))))
+        inp = G.cauchy_hodlr(n, 256, seed=int(rng.integers(1 << 30)))
+        mats.append(H.hodlr_build(inp, rank_cap=rank_cap))
+        desc.append(("cauchy", n, max(U.shape[1] for U, V in inp.blocks.values())))
+    pools = [list(range(n_gauss)), list(range(n_gauss, n_gauss + n_cauchy))]
+    return mats, desc, pools
+
+
+def bench_served(H, G, np, requests=1000, rate=200.0, seed=4):
+    """Served workload: a Poisson stream (`rate` req/s) of `requests` requests
+    (a bounded part of a 20k-request stream), each a QR of a pool matrix
+    (Gaussian or Cauchy generator with probability 1/2 each, see served_pool)
+    with probability 1/2, else a solve with the factor of an earlier QR request
+    for nrhs ~ U{1..64} N(0,1) right-hand sides.  Continuous batching (one host
+    thread; each step batches every admissible arrived request, its solves on
+    resident factors overlapping its factorisations; admission by the factors'
+    device bytes) against serving one request per step in arrival order."""
+    from paper_1809_10585_amd import serve
+    t0 = time.perf_counter()
+    mats, desc, pools = served_pool(H, G, np, seed=seed)
+    log(f"served pool built in {time.perf_counter() - t0:.1f} s: {desc}")
+    out = {"workload": f"{requests} requests (bounded part of a 20k stream), Poisson {rate:g}/s, QR (p=1/2) of a "
+                       f"pool matrix: {len(pools[0])} Gaussian n~logU[1024,32768] leaf 256 k~U{{4..min(32,32/d)}} "
+                       f"or {len(pools[1])} Cauchy n~logU[1024,4096] (generator chosen with p=1/2); else a solve "
+                       f"with 1..64 rhs with the factor of an earlier QR request; eps {EPS:g}, seed {seed}",
+           "pool": [{"gen": g, "n": n, "rank": k} for g, n, k in desc]}
     import torch
-    be = serve.GpuBackend(H, mats, EPS)
-    be.qr_batch(list(range(pool)))  # warm the kernels and the allocator
+    be = serve.GpuBackend(H, mats, EPS)  # factorises every pool matrix once: footprints, warm-up
     budget = 0.75 * torch.cuda.mem_get_info()[0]  # bytes for resident factors
     out["budget_gb"] = budget / 1e9
+    out["footprint_mb"] = [round(be.footprint(i) / 1e6, 2) for i in range(len(mats))]
     for name, batching in (("continuous", True), ("plain_fifo", False)):
-        reqs = serve.poisson_requests(requests, rate, len(mats), seed)
+        reqs = serve.poisson_requests(requests, rate, len(mats), seed, pools=pools)
         sch = serve.Scheduler(be, budget=budget, batching=batching)
         res = serve.summarize(sch.run(reqs))
         res.update(steps=sch.steps, max_qr_batch=sch.max_qr_batch, evictions=sch.evictions,
-                   refactored=sch.refactored)
+                   refactored=sch.refactored, overlapped_solves=sch.overlapped)
         out[name] = res
         log(f"served {name}: {res}")
     out["p99_speedup_vs_plain"] = out["plain_fifo"]["p99_ms"] / out["continuous"]["p99_ms"]
@@ -272,9 +297,10 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched measurement (256 independent matrices)")
-    ap.add_argument("--served", action="store_true",
-                    help="also run the served measurement (Poisson request stream, about a minute "
-                         "of GPU time: the plain loop it is compared with cannot keep up)")
+    ap.add_argument("--no-served", action="store_true",
+                    help="skip the served measurement (1000 requests of a Poisson stream, continuous "
+                         "batching and the plain loop)")
+    ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--accuracy", action="store_true",
                     help="only the accuracy study of the paper's Cauchy examples (e_orth, e_acc)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -358,7 +384,7 @@ def main():
 
     del A
     batched = None if args.no_batched else bench_batched(H, G, np)
-    served = bench_served(H, G, np) if args.served else None
+    served = None if args.no_served else bench_served(H, G, np, requests=args.served_requests)
 
     out = {
         "metric": "HODLR QR s & FP64 TFLOP/s at n=65536; batched QR/s + p99 served vs plain",

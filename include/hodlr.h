@@ -360,6 +360,25 @@ hodlr_status hodlr_plan_check_set(int32_t nshapes, const int64_t *n, const int32
                                   const int64_t *leaf_off, int32_t rank_cap, int32_t count, uint32_t flags,
                                   int64_t *stats, char *msg, int64_t msglen);
 
+/*
+ * Launch shapes of the schedules (an autotuned table, measured on MI355X).
+ * mm_rt64_rows: product launches over at least this many output rows take 64
+ * rows per block of threads, smaller ones 16; tr_small_chunks (1..4):
+ * recompressions whose factors span at most this many 256-row chunks (rank
+ * capacity <= 32) run in one launch, larger ones in two.  Only the launch shape
+ * changes, not what is computed (results agree to rounding).
+ * hodlr_tuning: the values schedules for order n and rank_cap get now.
+ * hodlr_set_tuning: use `t` for every schedule built afterwards (NULL: the
+ * table again); process-wide, takes effect at the next planning (a factor's
+ * cached apply / solve / product sequences keep theirs).
+ */
+typedef struct {
+  int32_t mm_rt64_rows;
+  int32_t tr_small_chunks;
+} hodlr_tuning_t;
+hodlr_status hodlr_tuning(int64_t n, int32_t rank_cap, hodlr_tuning_t *out);
+hodlr_status hodlr_set_tuning(const hodlr_tuning_t *t);
+
 void hodlr_free(hodlr_t *A);        /* NULL-safe; ignores factor views */
 void hodlr_qr_free(hodlr_qr_t *F);  /* NULL-safe */
 const char *hodlr_last_error(void); /* thread-local; empty string if none */

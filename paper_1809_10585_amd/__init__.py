@@ -24,7 +24,7 @@ __all__ = [
     "hodlr_qr_factor", "hodlr_check", "hodlr_qr_ranklog", "hodlr_plan_check", "hodlr_norm2_est",
     "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time", "hodlr_qr_profile",
     "hodlr_qr_batched", "hodlr_qr_batched_time", "use_torch_allocator", "HodlrMatrix", "QRFactors",
-    "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "HODLR_QR_BY_SHAPE", "HODLR_QR_KEEP", "hodlr_qr_refactor", "HODLR_CHECK_ESTIMATE", "set_allocator",
+    "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "HODLR_QR_BY_SHAPE", "HODLR_QR_KEEP", "hodlr_qr_refactor", "tuning", "set_tuning", "HODLR_CHECK_ESTIMATE", "set_allocator",
     "HODLR_CHECK_PLANT", "load",
 ]
 
@@ -208,6 +208,25 @@ def hodlr_qr_refactor(Fs, As, flags: int = 0, stream=None) -> None:
     hp, keep = _handles(As)
     _lib.check(load().hodlr_qr_refactor(C.cast(fp, C.POINTER(C.c_void_p)), hp, len(Fs), int(flags),
                                         _stream(stream)))
+
+
+def tuning(n: int, rank_cap: int) -> dict:
+    """The launch shapes schedules of order n and rank_cap get (table or override)."""
+    t = _lib.Tuning()
+    _lib.check(load().hodlr_tuning(int(n), int(rank_cap), C.byref(t)))
+    return {"mm_rt64_rows": t.mm_rt64_rows, "tr_small_chunks": t.tr_small_chunks}
+
+
+def set_tuning(mm_rt64_rows=None, tr_small_chunks=None) -> None:
+    """Override the launch-shape table for schedules built from now on; with
+    no arguments, go back to the table."""
+    if mm_rt64_rows is None and tr_small_chunks is None:
+        _lib.check(load().hodlr_set_tuning(None))
+        return
+    cur = tuning(1 << 16, 16)
+    t = _lib.Tuning(int(cur["mm_rt64_rows"] if mm_rt64_rows is None else mm_rt64_rows),
+                    int(cur["tr_small_chunks"] if tr_small_chunks is None else tr_small_chunks))
+    _lib.check(load().hodlr_set_tuning(C.byref(t)))
 
 
 def hodlr_qr_batched_time(As, eps: float, anorm=None, flags: int = 0, warmup: int = 1, reps: int = 3,

@@ -23,7 +23,7 @@ HODLR_QR_KEEP = 8
 EXPORTS = [
     "hodlr_set_allocator", "hodlr_build", "hodlr_qr", "hodlr_apply_q", "hodlr_apply_q_noalloc",
     "hodlr_solve", "hodlr_matmul",
-    "hodlr_qr_matmul", "hodlr_qr_factor", "hodlr_check", "hodlr_qr_ranklog", "hodlr_plan_check", "hodlr_plan_check_set", "hodlr_qr_refactor",
+    "hodlr_qr_matmul", "hodlr_qr_factor", "hodlr_check", "hodlr_qr_ranklog", "hodlr_plan_check", "hodlr_plan_check_set", "hodlr_qr_refactor", "hodlr_tuning", "hodlr_set_tuning",
     "hodlr_norm2_est", "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time",
     "hodlr_qr_profile", "hodlr_op_name", "hodlr_op_count", "hodlr_qr_batched", "hodlr_qr_batched_time",
     "hodlr_free", "hodlr_qr_free", "hodlr_last_error", "hodlr_version",
@@ -49,6 +49,10 @@ class QRInfo(C.Structure):
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Tuning(C.Structure):
+    _fields_ = [("mm_rt64_rows", C.c_int32), ("tr_small_chunks", C.c_int32)]
 
 
 _lib = None
@@ -87,6 +91,8 @@ def load(path: str = LIB_PATH):
         "hodlr_plan_check": (I32, [I64, I32, PI64, I32, I32, C.c_uint32, PI64, C.c_char_p, I64]),
         "hodlr_plan_check_set": (I32, [I32, PI64, PI32, PI64, I32, I32, C.c_uint32, PI64, C.c_char_p, I64]),
         "hodlr_qr_refactor": (I32, [PP, PP, I32, C.c_uint32, P]),
+        "hodlr_tuning": (I32, [I64, I32, C.POINTER(Tuning)]),
+        "hodlr_set_tuning": (I32, [C.POINTER(Tuning)]),
         "hodlr_build": (I32, [I64, I32, PI64, PD, PI64, PD, PI64, PD, PI64, PI32, I32, P, PP]),
         "hodlr_qr": (I32, [P, D, D, C.c_uint32, P, PP]),
         "hodlr_apply_q": (I32, [P, I32, I64, P, I64, P]),

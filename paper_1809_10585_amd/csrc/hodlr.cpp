@@ -274,7 +274,7 @@ void Plan::trunc(const std::vector<TrSpec>& specs) {
     // factors of a few chunks: k_tr_small (for wide jobs its forming step
     // needs a tree of one combine level and w k doubles of LDS twice)
     const int mx = std::max(J.side[0].m, J.side[1].m);
-    if (mx <= CH || (wtop <= 64 && mx <= TRS_MAXCH * CH)) {
+    if (mx <= CH || (wtop <= 64 && mx <= tune.tr_small_chunks * CH)) {
       for (int side = 0; side < 2; ++side)
         for (int c = 0; c < J.side[side].p0; ++c) small.push_back(TrChunk{jid, side, c});
       continue;
@@ -321,7 +321,7 @@ void Plan::mm(const Tree& t, const std::vector<MmSpec>& specs) {
   std::vector<MmProj> reds;
   int64_t rows_total = 0;
   for (const MmSpec& sp : specs) rows_total += t.m(sp.v);
-  const int RT = rows_total >= 32768 ? 64 : 16;
+  const int RT = rows_total >= tune.mm_rt64_rows ? 64 : 16;
   std::vector<MmApply> apply;
   for (const MmSpec& sp : specs) {
     MmJob J{};
@@ -1256,6 +1256,7 @@ hodlr_status make_storage(const hodlr_s& A, double eps, double anorm, hipStream_
 void build_plan(const std::vector<hodlr_qr_s*>& Fs, Plan& P, int plant = 0) {
   const Tree& t = Fs[0]->t;
   P.wtop = 2 * Fs[0]->cap;
+  P.tune = tuning_for(t.n, Fs[0]->cap);
   // thresholds: |A|_2 from the power iteration unless given, then tau_A, tau_T
   std::vector<NormItem> est;
   std::vector<VecJob> sc;
@@ -1602,6 +1603,7 @@ hodlr_status build_apply_plan(hodlr_qr_s& F, int trans, hipStream_t st, std::uni
   auto C = std::make_unique<CachedPlan>();
   C->mem.stream = st;
   Plan& P = C->P;
+  P.tune = tuning_for(F.t.n, F.cap);
   MmSpec a = mmspec(F.view_y(), false, true, 1, 1, nullptr, 0, nullptr, nullptr, 0, 1.0, 0.0, 1);
   MmSpec b = mmspec(F.view_t(), true, false, 1, trans, nullptr, 0, nullptr, nullptr, 0, 1.0, 0.0, 1);
   MmSpec c = mmspec(F.view_y(), false, true, 1, 0, nullptr, 0, nullptr, nullptr, 0, -1.0, 1.0, 1);
@@ -1625,6 +1627,7 @@ hodlr_status build_solve_plan(hodlr_qr_s& F, hipStream_t st, std::unique_ptr<Cac
   C->mem.stream = st;
   Plan& P = C->P;
   const Tree& t = F.t;
+  P.tune = tuning_for(t.n, F.cap);
   struct Rec {
     hodlr_qr_s& f;
     Plan& P;
@@ -1670,6 +1673,7 @@ hodlr_status build_mm_plan(const hodlr_s& A, int trans, hipStream_t st, std::uni
   auto C = std::make_unique<CachedPlan>();
   C->mem.stream = st;
   Plan& P = C->P;
+  P.tune = tuning_for(A.t.n, A.cap);
   MmSpec a = mmspec(A.view(), A.has_up, A.has_lo, 1, trans, nullptr, 0, nullptr, nullptr, 0, 1.0, 0.0,
                     A.leaf_kind != LEAF_FULL ? 1 : 0);
   a.xs = 0;
@@ -1745,6 +1749,7 @@ hodlr_status norm2_est_impl(const hodlr_s& A, int iters, hipStream_t st, double*
   TRY(tmp.alloc(&z, n));
   TRY(tmp.alloc(&res, 1));
   Plan P;
+  P.tune = tuning_for(n, A.cap);
   plan_norm2(P, t, {NormItem{A.view(), A.cap, x, y, z, res, nullptr}}, iters);
   DMem pm;
   pm.stream = st;
@@ -2538,6 +2543,60 @@ hodlr_status hodlr_plan_check_set(int32_t nshapes, const int64_t* n, const int32
     std::strncpy(msg, R.first.c_str(), (size_t)msglen - 1);
     msg[msglen - 1] = '\0';
   }
+  return HODLR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- launch-shape table
+#include "tune_table.h"
+
+namespace hqh {
+namespace {
+std::mutex g_tune_mu;
+bool g_tune_override = false;
+Tuning g_tune;
+}  // namespace
+
+Tuning tuning_for(int64_t n, int cap) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tune_override) return g_tune;
+  const TuneRow* row = &kTuneTable[sizeof(kTuneTable) / sizeof(kTuneTable[0]) - 1];
+  for (const TuneRow& r : kTuneTable)
+    if (n <= r.n_max && cap <= r.cap_max) {
+      row = &r;
+      break;
+    }
+  Tuning t;
+  t.mm_rt64_rows = row->mm_rt64_rows;
+  t.tr_small_chunks = row->tr_small_chunks;
+  return t;
+}
+}  // namespace hqh
+
+extern "C" {
+
+hodlr_status hodlr_tuning(int64_t n, int32_t rank_cap, hodlr_tuning_t* out) {
+  hqh::g_err.clear();
+  if (out == nullptr || n < 1 || rank_cap < 1) return hqh::fail(HODLR_EINVAL, "bad argument");
+  const hqh::Tuning t = hqh::tuning_for(n, rank_cap);
+  out->mm_rt64_rows = t.mm_rt64_rows;
+  out->tr_small_chunks = t.tr_small_chunks;
+  return HODLR_OK;
+}
+
+hodlr_status hodlr_set_tuning(const hodlr_tuning_t* t) {
+  hqh::g_err.clear();
+  std::lock_guard<std::mutex> lk(hqh::g_tune_mu);
+  if (t == nullptr) {
+    hqh::g_tune_override = false;
+    return HODLR_OK;
+  }
+  if (t->mm_rt64_rows < 0 || t->tr_small_chunks < 1 || t->tr_small_chunks > hq::TRS_MAXCH)
+    return hqh::fail(HODLR_EINVAL, "tuning out of range");
+  hqh::g_tune.mm_rt64_rows = t->mm_rt64_rows;
+  hqh::g_tune.tr_small_chunks = t->tr_small_chunks;
+  hqh::g_tune_override = true;
   return HODLR_OK;
 }
 

@@ -267,6 +267,18 @@ inline Seg mkseg(const double* p, int ld, const int* ncols_dev, double scale = 1
 }
 inline Seg noseg() { return mkseg(nullptr, 1, nullptr); }
 
+// Launch-shape choices of the schedule builder, taken from the measured table
+// (tune_table.h) for the problem's order and rank capacity unless overridden:
+// product launches over at least mm_rt64_rows output rows take 64 rows per
+// block (else 16); recompressions of at most tr_small_chunks row chunks per
+// factor (rank capacity <= 32) run in one k_tr_small launch, larger ones in
+// k_tr_qr + k_tr_form.
+struct Tuning {
+  int mm_rt64_rows = 32768;
+  int tr_small_chunks = 4;
+};
+Tuning tuning_for(int64_t n, int cap);
+
 struct Plan {
   std::vector<TrJob> trj;
   std::vector<TrChunk> trc;
@@ -314,6 +326,7 @@ struct Plan {
   }
   int64_t n_trunc = 0;
   int wtop = WMAX;  // widest recompression this plan can produce
+  Tuning tune;      // launch shapes (set by the builder from tuning_for)
   int mleaf = 0;    // largest leaf any product of this plan touches
   // device copies
   TrJob* d_trj = nullptr;

@@ -637,3 +637,22 @@ def test_batched_time_runs(H):
     As = [H.hodlr_build(inp, rank_cap=32) for inp in inps]
     ms = H.hodlr_qr_batched_time(As, EPS, warmup=1, reps=2)
     assert ms.shape == (2,) and (ms > 0).all()
+
+
+@pytest.mark.parametrize("rt,chunks", [(4096, 1), (1 << 30, 2), (32768, 4)])
+def test_launch_shape_candidates_keep_parity(H, rt, chunks):
+    """Every candidate launch shape of the autotuner computes the same
+    factorisation (oracle parity and identical rank decisions)."""
+    inp = G.gaussian_hodlr(2048, 256, 5, seed=41)
+    an = oracle_anorm(inp)
+    ref = O.hqr(inp, EPS, anorm=an)
+    H.set_tuning(rt, chunks)
+    try:
+        F = H.hodlr_qr(H.hodlr_build(inp, rank_cap=32), EPS, anorm=an)
+    finally:
+        H.set_tuning()
+    X = np.random.default_rng(41).standard_normal((inp.n, 8))
+    rR = _rel(H.hodlr_qr_matmul(F, "R", H.colmajor(X)).cpu().numpy(), O.rmat(ref, X))
+    rQ = _rel(H.hodlr_apply_q(F, H.colmajor(X)).cpu().numpy(), O.apply_q(ref, X), np.linalg.norm(X))
+    assert rR <= 1e-8 and rQ <= 1e-8, (rR, rQ)
+    assert ranklog_check(H, F, ref)[1] == 0

@@ -18,6 +18,8 @@ class FakeBackend:
         self.live = set()
         self.released = []
         self.batches = []
+        self.queued = 0
+        self.sides = []
 
     def footprint(self, key):
         return float(self.sizes[key])
@@ -33,10 +35,15 @@ class FakeBackend:
             out.append(F)
         return out
 
-    def solve(self, F, nrhs, seed):
+    def solve_async(self, F, nrhs, seed, side=False):
         assert F in self.live, "solve with a released factor"
+        self.queued += 1
+        self.sides.append(side)
         time.sleep(self.solve_s)
         return ("X", F, nrhs, seed)
+
+    def sync(self):
+        self.queued = 0
 
     def release(self, F):
         self.live.remove(F)
@@ -103,6 +110,50 @@ def test_batching_beats_plain_under_load():
     served = serve.summarize(serve.Scheduler(FakeBackend([1.0] * 4), budget=1e9).run(reqs()))
     plain = serve.summarize(serve.Scheduler(FakeBackend([1.0] * 4), budget=1e9, batching=False).run(reqs()))
     assert served["p99_ms"] < plain["p99_ms"]
+
+
+def test_solves_overlap_the_factorisations():
+    """Solves whose factors were resident before a step are queued on the
+    second stream ahead of the step's factorisations."""
+    reqs = serve.poisson_requests(200, rate=4000.0, n_matrices=4, seed=6)
+    b = FakeBackend([1.0] * 4)
+    sch = serve.Scheduler(b, budget=1e9)
+    sch.run(reqs)
+    assert sch.overlapped > 0 and any(b.sides) and not all(b.sides)
+
+
+def test_no_eviction_without_admission():
+    """A request that cannot fit even after evicting every evictable factor
+    evicts nothing (unless it is forced in as the step's only request)."""
+    b = FakeBackend([1.0] * 4)
+    sch = serve.Scheduler(b, budget=2.5)
+    for rid in (1, 2):
+        F = b.qr_batch([rid])[0]
+        sch.factors[rid], sch.resident[rid] = F, 1.0
+    assert not sch._make_room(2.0, keep={1})
+    assert list(sch.resident) == [1, 2] and sch.evictions == 0
+    assert sch._make_room(1.5, keep={1}) and list(sch.resident) == [1] and sch.evictions == 1
+    assert not sch._make_room(3.0, keep={1}, force=True) and list(sch.resident) == [1]
+
+
+def test_plain_loop_keeps_the_budget():
+    reqs = serve.poisson_requests(120, rate=3000.0, n_matrices=6, seed=7, p_qr=0.6)
+    b = FakeBackend([1.0] * 6, qr_s=0.001, solve_s=0.0002)
+    sch = serve.Scheduler(b, budget=2.5, batching=False, keep_results=True)
+    out = sch.run(reqs)
+    assert all(r.done > 0 for r in out)
+    assert sch.evictions > 0 and len(sch.resident) <= 2
+    for r in out:
+        if r.kind == "solve":
+            assert r.result[1][0] == out[r.key].key
+
+
+def test_request_pools():
+    pools = [[0, 1, 2], [3, 4]]
+    reqs = serve.poisson_requests(400, rate=100.0, n_matrices=5, seed=8, pools=pools)
+    keys = [r.key for r in reqs if r.kind == "qr"]
+    share = np.mean([k >= 3 for k in keys])
+    assert set(keys) == {0, 1, 2, 3, 4} and 0.4 < share < 0.6
 
 
 @pytest.mark.gpu
