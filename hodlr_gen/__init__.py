@@ -29,7 +29,7 @@ import numpy as np
 
 __all__ = [
     "HodlrInput", "partition", "gaussian_hodlr", "cauchy_hodlr", "expkernel_hodlr",
-    "config", "perturb", "CONFIG_EPS",
+    "config", "perturb", "CONFIG_EPS", "RectHodlrInput", "rect_partition", "rect_gaussian_hodlr",
 ]
 
 # truncation tolerance of every workload (the paper's default eps, Sec. 5)
@@ -364,3 +364,100 @@ def perturb(H: HodlrInput, seed: int, rel: float = 2.0 ** -53) -> HodlrInput:
         G.blocks[key] = (U * (1.0 + rel * rng.standard_normal(U.shape)),
                          V * (1.0 + rel * rng.standard_normal(V.shape)))
     return G
+
+
+# ---------------------------------------------------------------- rectangular
+def rect_partition(m: int, n: int, n_min: int) -> tuple[int, np.ndarray, np.ndarray]:
+    """(levels, row offsets, column offsets) of an m x n rectangular HODLR
+    matrix (Sec. 6, two integer partitions with m_j >= n_j): the columns are
+    split as partition(n, n_min) and row boundary j is floor(m c_j / n) for
+    column boundary c_j, so m_j >= n_j for every leaf when m >= n."""
+    if m < n:
+        raise ValueError("a rectangular HODLR matrix here has m >= n")
+    levels, col_off = partition(n, n_min)
+    row_off = (np.int64(m) * col_off) // np.int64(n)
+    return levels, row_off.astype(np.int64), col_off
+
+
+@dataclass
+class RectHodlrInput:
+    """A rectangular HODLR matrix (Sec. 6): leaf j is the dense m_j x n_j
+    diagonal block (rows row_off[j]:row_off[j+1], columns col_off[j]:...);
+    blocks[(v, 'up')] = (U, V) is the block rows(2v) x cols(2v+1) = U V^T and
+    blocks[(v, 'lo')] the block rows(2v+1) x cols(2v)."""
+    m: int
+    n: int
+    levels: int
+    row_off: np.ndarray
+    col_off: np.ndarray
+    leaves: list
+    blocks: dict = field(default_factory=dict)
+    name: str = ""
+
+    def _range(self, off, v):
+        depth = v.bit_length() - 1
+        span = 1 << (self.levels - depth)
+        first = (v - (1 << depth)) * span
+        return int(off[first]), int(off[first + span])
+
+    def node_rows(self, v: int) -> tuple[int, int]:
+        return self._range(self.row_off, v)
+
+    def node_cols(self, v: int) -> tuple[int, int]:
+        return self._range(self.col_off, v)
+
+    def internal_nodes(self):
+        for d in range(self.levels):
+            for v in range(1 << d, 1 << (d + 1)):
+                yield v
+
+    def pivot_rows(self) -> np.ndarray:
+        """Row index that column c is reduced onto: the first n_j rows of each
+        leaf's row block, in column order (structure only)."""
+        out = []
+        for j in range(len(self.col_off) - 1):
+            nj = int(self.col_off[j + 1] - self.col_off[j])
+            out += list(range(int(self.row_off[j]), int(self.row_off[j]) + nj))
+        return np.asarray(out, dtype=np.int64)
+
+    def to_dense(self) -> np.ndarray:
+        A = np.zeros((self.m, self.n))
+        for j, D in enumerate(self.leaves):
+            A[self.row_off[j]:self.row_off[j + 1], self.col_off[j]:self.col_off[j + 1]] = D
+        for v in self.internal_nodes():
+            r1, c1, r2, c2 = self.node_rows(2 * v), self.node_cols(2 * v), self.node_rows(2 * v + 1), \
+                self.node_cols(2 * v + 1)
+            U, V = self.blocks[(v, "up")]
+            A[r1[0]:r1[1], c2[0]:c2[1]] = U @ V.T
+            U, V = self.blocks[(v, "lo")]
+            A[r2[0]:r2[1], c1[0]:c1[1]] = U @ V.T
+        return A
+
+
+def rect_gaussian_hodlr(m: int, n: int, n_min: int, rank: int, seed=0, shift: float = 4.0,
+                        row_off=None, rng=None, name: str | None = None) -> RectHodlrInput:
+    """Rectangular Gaussian HODLR matrix: leaves i.i.d. N(0,1) with shift*I added
+    to their top n_j x n_j part, off-diagonal blocks U V^T of exact rank `rank`
+    with U, V i.i.d. N(0,1)/sqrt(rows), N(0,1)/sqrt(cols).  row_off overrides
+    the row partition (it must keep m_j >= n_j)."""
+    levels, roff, coff = rect_partition(m, n, n_min)
+    if row_off is not None:
+        roff = np.asarray(row_off, dtype=np.int64)
+        if roff[0] != 0 or roff[-1] != m or len(roff) != len(coff) or np.any(np.diff(roff) < np.diff(coff)):
+            raise ValueError("row partition must run from 0 to m with m_j >= n_j")
+    rng = rng if rng is not None else np.random.default_rng(seed)
+    leaves = []
+    for j in range(len(coff) - 1):
+        mj, nj = int(roff[j + 1] - roff[j]), int(coff[j + 1] - coff[j])
+        D = rng.standard_normal((mj, nj))
+        D[:nj, :nj] += shift * np.eye(nj)
+        leaves.append(D)
+    H = RectHodlrInput(m=m, n=n, levels=levels, row_off=roff, col_off=coff, leaves=leaves,
+                       name=name or f"rect_gaussian(m={m},n={n},leaf={n_min},k={rank})")
+    for v in H.internal_nodes():
+        for kind, rv, cv in (("up", 2 * v, 2 * v + 1), ("lo", 2 * v + 1, 2 * v)):
+            r, c = H.node_rows(rv), H.node_cols(cv)
+            mr, nc = r[1] - r[0], c[1] - c[0]
+            H.blocks[(v, kind)] = (rng.standard_normal((mr, rank)) / math.sqrt(mr),
+                                   rng.standard_normal((nc, rank)) / math.sqrt(nc))
+    return H
