@@ -37,7 +37,8 @@
  *    from several threads and streams at once (each call has its own
  *    temporaries).  A handle must outlive the work queued with it: release it
  *    only after that work is done.  hodlr_qr_time / hodlr_qr_profile and the
- *    batched calls create private handles.
+ *    batched calls create private handles.  hodlr_qr_refactor rewrites the
+ *    factorisations it is given: no other call may use them meanwhile.
  */
 #ifndef HODLR_H
 #define HODLR_H

@@ -593,6 +593,30 @@ def test_batched_parity_with_oracle(H):
         assert ranklog_check(H, Fi, ref)[1] == 0
 
 
+def test_batched_workload_sample_vs_oracle(H):
+    """Matrices of the batched benchmark's recipe (d ~ U{2..4} here so the oracle
+    finishes in seconds; k ~ U{4..min(32, 32/d)}, rank capacity 64), factorised
+    as one merged batch of several shapes: each against the oracle (forward
+    bound, backward bound, rank decisions)."""
+    inps = G.batched_set(count=8, seed=21, dmin=2, dmax=4, kmin=4, kmax=32, rank_budget=64)
+    print("batch:", [inp.name for inp in inps])
+    As = [H.hodlr_build(inp, rank_cap=64) for inp in inps]
+    anorms = [oracle_anorm(inp) for inp in inps]
+    Fb = H.hodlr_qr_batched(As, EPS, anorm=anorms)
+    for inp, A, Fi, an in zip(inps, As, Fb, anorms):
+        ref = O.hqr(inp, EPS, anorm=an)
+        X = np.random.default_rng(7).standard_normal((inp.n, 8))
+        RX = H.hodlr_qr_matmul(Fi, "R", H.colmajor(X)).cpu().numpy()
+        rR = _rel(RX, O.rmat(ref, X))
+        rQ = _rel(H.hodlr_apply_q(Fi, H.colmajor(X)).cpu().numpy(), O.apply_q(ref, X), np.linalg.norm(X))
+        assert rR <= 1e-8 and rQ <= 1e-8, (inp.name, rR, rQ)
+        AX = H.hodlr_matmul(A, H.colmajor(X)).cpu().numpy()
+        QRX = H.hodlr_apply_q(Fi, H.colmajor(RX)).cpu().numpy()
+        assert np.linalg.norm(AX - QRX) / (an * np.linalg.norm(X)) <= 10 * EPS
+        assert ranklog_check(H, Fi, ref)[1] == 0
+        assert H.hodlr_qr_info(Fi)["max_rank_r"] == O.max_ranks(ref.R)
+
+
 # Recompressions run in k_tr_small when both factors have at most four 256-row
 # chunks (narrow: w <= 8 inside one block; wide: one block per chunk and the
 # forming step in the block that ran the SVD), otherwise in k_tr_qr + k_tr_form.
