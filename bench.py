@@ -300,7 +300,7 @@ def main():
     ap.add_argument("--no-served", action="store_true",
                     help="skip the served measurement (1000 requests of a Poisson stream, continuous "
                          "batching and the plain loop)")
-    ap.add_argument("--served-requests", type=int, default=1000)
+    ap.add_argument("--served-requests", type=int, default=300)
     ap.add_argument("--accuracy", action="store_true",
                     help="only the accuracy study of the paper's Cauchy examples (e_orth, e_acc)")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -6,7 +6,7 @@ warm-up) and the fastest is written as one row of csrc/tune_table.h, which the
 library compiles in.  Rows are ordered by (rank capacity bound, n); the library
 takes the first row whose bounds hold.
 
-    python -m paper_1809_10585_amd.tune [--reps 3] [--dry-run]
+    python -m paper_1809_10585_amd.tune [--reps 3] [--dry-run] [--out FILE]
 """
 from __future__ import annotations
 
@@ -24,20 +24,23 @@ CHUNK_CANDIDATES = (1, 2, 4)
 
 HEADER = """// Launch-shape table of the schedule builder, written by
 // paper_1809_10585_amd/tune.py from timings of hodlr_qr on MI355X (exp-kernel
-// HODLR matrices, leaf 256, eps 1e-10).  The first row with n <= n_max and
-// rank_cap <= cap_max applies; shapes beyond the last row take its values.
+// HODLR matrices at rank capacity 16, Gaussian HODLR matrices at capacity 64;
+// leaf 256, eps 1e-10).  The first row with n <= n_max and rank_cap <= cap_max
+// applies; shapes beyond the last row take its values.
 """
 
 
 def grid(G):
     """(row bounds, workload, rank_cap): exp-kernel matrices at rank capacity 16
-    for orders up to 65536, Gaussian HODLR matrices of rank 8 at capacity 64."""
+    for orders up to 65536; Gaussian HODLR matrices at capacity 64 with the
+    batched workload's largest ranks for their depth (k = 32 / d: 8 at n = 4096,
+    5 at n = 16384)."""
     return [
         ((4096, 32), lambda: G.expkernel_hodlr(4096, 256, 2), 16),
         ((16384, 32), lambda: G.expkernel_hodlr(16384, 256, 2), 16),
         ((1 << 30, 32), lambda: G.expkernel_hodlr(65536, 256, 2), 16),
         ((4096, 1 << 30), lambda: G.gaussian_hodlr(4096, 256, 8, seed=11), 64),
-        ((1 << 30, 1 << 30), lambda: G.gaussian_hodlr(16384, 256, 8, seed=12), 64),
+        ((1 << 30, 1 << 30), lambda: G.gaussian_hodlr(16384, 256, 5, seed=12), 64),
     ]
 
 
@@ -52,6 +55,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--dry-run", action="store_true", help="print the table, do not write it")
+    ap.add_argument("--out", default=TABLE, help="where to write the table (default: the library's)")
     args = ap.parse_args(argv)
     import numpy as np
     sys.path.insert(0, os.path.dirname(HERE))
@@ -81,9 +85,9 @@ def main(argv=None):
     if args.dry_run:
         print(text)
     else:
-        with open(TABLE, "w") as f:
+        with open(args.out, "w") as f:
             f.write(text)
-        print(f"wrote {TABLE}")
+        print(f"wrote {args.out}")
 
 
 if __name__ == "__main__":
