@@ -54,9 +54,12 @@ __device__ __forceinline__ bool jac_rot_fast(double al, double be, double ga, do
 }
 
 // One-sided Jacobi on the columns of X (w x w, ld lx), accumulating the
-// rotations in V (ld lv).  Round-robin pairing; one pair per group of TPP
-// lanes; a sweep ends when no pair needed a rotation.
-__device__ __forceinline__ void jacobi(double* X, int lx, double* V, int lv, int w, int* sflag) {
+// rotations in V (ld lv) unless V is null.  Round-robin pairing; one pair per
+// group of TPP lanes; a sweep ends when no pair needed a rotation.  Pairs of two
+// columns whose squared norms are both <= eta2 are left alone (columns at the
+// roundoff level of the matrix, which the caller discards).
+__device__ __forceinline__ void jacobi(double* X, int lx, double* V, int lv, int w, int* sflag,
+                                       double eta2 = 0.0) {
   const int tid = threadIdx.x;
   const int n = w + (w & 1);
   if (n < 2) return;
@@ -99,14 +102,18 @@ __device__ __forceinline__ void jacobi(double* X, int lx, double* V, int lv, int
         be = gsum(be, TPP);
         ga = gsum(ga, TPP);
         double cs, sn;
-        if (valid && jac_rot_fast(al, be, ga, tol * tol, cs, sn)) {
+        if (valid && (al > eta2 || be > eta2) && jac_rot_fast(al, be, ga, tol * tol, cs, sn)) {
           for (int row = sub; row < w; row += TPP) {
             const double xi = X[row + i * lx], xj = X[row + j * lx];
             X[row + i * lx] = cs * xi - sn * xj;
             X[row + j * lx] = sn * xi + cs * xj;
-            const double vi = V[row + i * lv], vj = V[row + j * lv];
-            V[row + i * lv] = cs * vi - sn * vj;
-            V[row + j * lv] = sn * vi + cs * vj;
+          }
+          if (V != nullptr) {
+            for (int row = sub; row < w; row += TPP) {
+              const double vi = V[row + i * lv], vj = V[row + j * lv];
+              V[row + i * lv] = cs * vi - sn * vj;
+              V[row + j * lv] = sn * vi + cs * vj;
+            }
           }
           if (sub == 0) *sflag = 1;
         }
@@ -238,87 +245,177 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
     if (tid == 0) add_flops(fc, fcat, tr_flops_orth(m0, m1, w));
   } else {
     const double* R2 = ws + J.side[1].node0 + (int64_t)tr_root_slot(J.side[1].p0, G) * TR_NODE;
-    // w <= 16: X and V padded to WS x WS (zeros beyond w) for jacobi_small
-    const int WSs = w <= 8 ? 8 : (w <= 16 ? 16 : 0);
-    const int LX = WSs ? WSs : w;
-    double* X = smem + TRS_X;
-    double* V;
-    int LV;
-    if (WSs) {
-      V = X + LX * LX;
-      LV = LX;
-    } else if (2 * w * w <= WMAX * WMAX) {  // X and V both in LDS
-      V = X + w * w;
-      LV = w;
-    } else {
-      V = hdr + 8 + 2 * WMAX * WMAX;
-      LV = WMAX;
-    }
     double* sig = smem + TRS_X + WMAX * WMAX;
     int* perm = (int*)(sig + WMAX);
-    // stage R1 and R2 in LDS when they fit next to X and V
+    double* X = smem + TRS_X;
     const double* R1s = R1;
-    const double* R2s = R2;
     int lr = WMAX;
-    if (4 * LX * LX <= WMAX * WMAX) {
-      double* r1 = X + 2 * LX * LX;
-      double* r2 = r1 + w * w;
+    if (w <= 16) {
+      // X = R2 R1^T and V padded to WS x WS (zeros beyond w) for jacobi_small;
+      // the right singular vectors of X (accumulated in V) are U of R1 R2^T
+      const int LX = w <= 8 ? 8 : 16;
+      double* V = X + LX * LX;
+      const double* R2s = R2;
+      if (4 * LX * LX <= WMAX * WMAX) {
+        double* r1 = X + 2 * LX * LX;
+        double* r2 = r1 + w * w;
+        for (int e = tid; e < w * w; e += NT_TR) {
+          const int i = e % w, j = e / w;
+          r1[e] = R1[i + j * WMAX];
+          r2[e] = R2[i + j * WMAX];
+        }
+        R1s = r1;
+        R2s = r2;
+        lr = w;
+        __syncthreads();
+      }
+      for (int e = tid; e < LX * LX; e += NT_TR) {
+        const int i = e % LX, j = e / LX;
+        double sacc = 0.0;
+        if (i < w && j < w)
+          for (int l = max(i, j); l < w; ++l) sacc += R2s[i + l * lr] * R1s[j + l * lr];
+        X[i + j * LX] = sacc;
+        V[i + j * LX] = (i == j && i < w) ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      if (LX == 8)
+        jacobi_small<8>(X, w);
+      else
+        jacobi_small<16>(X, w);
+      for (int cc = tid; cc < w; cc += NT_TR) {
+        double sacc = 0.0;
+        for (int r = 0; r < w; ++r) sacc += X[r + cc * LX] * X[r + cc * LX];
+        sig[cc] = sqrt(sacc);
+      }
+      __syncthreads();
+      for (int cc = tid; cc < w; cc += NT_TR) {
+        int pos = 0;
+        const double sc = sig[cc];
+        for (int j = 0; j < w; ++j) {
+          const double sj = sig[j];
+          pos += (sj > sc || (sj == sc && j < cc)) ? 1 : 0;
+        }
+        perm[pos] = cc;
+      }
+      __syncthreads();
+      k = 0;
+      for (int j = 0; j < w; ++j) k += (sig[j] > tau) ? 1 : 0;
+      if (k > capk) {
+        if (tid == 0) atomicOr(err, ERR_CAPACITY);
+        k = capk;
+      }
+      for (int e = tid; e < w * k; e += NT_TR) {
+        const int r = e % w, p = e / w;
+        const int pc = perm[p];
+        Uk[r + p * WMAX] = V[r + pc * LX];
+        double sacc = 0.0;
+        for (int l = 0; l <= r; ++l) sacc += R1s[l + r * lr] * V[l + pc * LX];
+        P[r + p * WMAX] = sacc;
+      }
+    } else {
+      // M = R1 R2^T (w x w) in X.  When every column that can be kept lies far
+      // above the roundoff level of M (tau^2 > 1e6 eta^2), one-sided Jacobi on
+      // the columns of M: M W = U S with orthogonal W, so once every pair of
+      // kept columns is orthogonal to the relative tolerance, their norms are
+      // the singular values and the columns over their norms are U; no
+      // rotations are accumulated, and pairs of columns at the roundoff level
+      // are left alone.  Otherwise (tau at or near roundoff, e.g. tau = 0) the
+      // Jacobi runs on M^T and accumulates the rotations V, whose columns are U
+      // and stay orthonormal however far the roundoff columns converge.
+      const double* R2s = R2;
+      if (3 * w * w <= WMAX * WMAX) {
+        double* r1 = X + w * w;
+        double* r2 = r1 + w * w;
+        for (int e = tid; e < w * w; e += NT_TR) {
+          const int i = e % w, j = e / w;
+          r1[e] = R1[i + j * WMAX];
+          r2[e] = R2[i + j * WMAX];
+        }
+        R1s = r1;
+        R2s = r2;
+        lr = w;
+        __syncthreads();
+      }
       for (int e = tid; e < w * w; e += NT_TR) {
         const int i = e % w, j = e / w;
-        r1[e] = R1[i + j * WMAX];
-        r2[e] = R2[i + j * WMAX];
+        double sacc = 0.0;
+        for (int l = max(i, j); l < w; ++l) sacc += R1s[i + l * lr] * R2s[j + l * lr];
+        X[e] = sacc;
       }
-      R1s = r1;
-      R2s = r2;
-      lr = w;
       __syncthreads();
-    }
-    // X = R2 R1^T  (both upper triangular, w x w; zero padding up to LX)
-    const int wx = WSs ? LX : w;
-    for (int e = tid; e < wx * wx; e += NT_TR) {
-      const int i = e % wx, j = e / wx;
-      double sacc = 0.0;
-      if (i < w && j < w)
-        for (int l = max(i, j); l < w; ++l) sacc += R2s[i + l * lr] * R1s[j + l * lr];
-      X[i + j * LX] = sacc;
-      V[i + j * LV] = (i == j && i < w) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    if (WSs == 8)
-      jacobi_small<8>(X, w);
-    else if (WSs == 16)
-      jacobi_small<16>(X, w);
-    else
-      jacobi(X, LX, V, LV, w, sflag);
-    for (int cc = tid; cc < w; cc += NT_TR) {
-      double sacc = 0.0;
-      for (int r = 0; r < w; ++r) sacc += X[r + cc * LX] * X[r + cc * LX];
-      sig[cc] = sqrt(sacc);
-    }
-    __syncthreads();
-    for (int cc = tid; cc < w; cc += NT_TR) {
-      int pos = 0;
-      const double sc = sig[cc];
-      for (int j = 0; j < w; ++j) {
-        const double sj = sig[j];
-        pos += (sj > sc || (sj == sc && j < cc)) ? 1 : 0;
+      for (int cc = tid; cc < w; cc += NT_TR) {
+        double sacc = 0.0;
+        for (int r = 0; r < w; ++r) sacc += X[r + cc * w] * X[r + cc * w];
+        sig[cc] = sacc;
       }
-      perm[pos] = cc;
-    }
-    __syncthreads();
-    k = 0;
-    for (int j = 0; j < w; ++j) k += (sig[j] > tau) ? 1 : 0;
-    if (k > capk) {
-      if (tid == 0) atomicOr(err, ERR_CAPACITY);
-      k = capk;
-    }
-    for (int e = tid; e < w * k; e += NT_TR) {
-      const int r = e % w, p = e / w;
-      const int pc = perm[p];
-      Uk[r + p * WMAX] = V[r + pc * LV];
-      double sacc = 0.0;
-      for (int l = 0; l <= r; ++l) sacc += R1s[l + r * lr] * V[l + pc * LV];
-      P[r + p * WMAX] = sacc;
+      __syncthreads();
+      double fro2 = 0.0;
+      for (int cc = 0; cc < w; ++cc) fro2 += sig[cc];
+      const double eta2 = (double)w * DBL_EPSILON * DBL_EPSILON * fro2;
+      const bool fast = 1e6 * eta2 < tau * tau;
+      __syncthreads();
+      double* V = nullptr;
+      int LV = 0;
+      if (fast) {
+        jacobi(X, w, nullptr, 0, w, sflag, eta2);
+      } else {
+        for (int e = tid; e < w * w; e += NT_TR) {  // X <- M^T in place
+          const int i = e % w, j = e / w;
+          if (i < j) {
+            const double t = X[i + j * w];
+            X[i + j * w] = X[j + i * w];
+            X[j + i * w] = t;
+          }
+        }
+        R1s = R1;  // V takes the staging space
+        lr = WMAX;
+        if (2 * w * w <= WMAX * WMAX) {
+          V = X + w * w;
+          LV = w;
+        } else {
+          V = hdr + 8 + 2 * WMAX * WMAX;
+          LV = WMAX;
+        }
+        __syncthreads();
+        for (int e = tid; e < w * w; e += NT_TR) {
+          const int i = e % w, j = e / w;
+          V[i + j * LV] = (i == j) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        jacobi(X, w, V, LV, w, sflag);
+      }
+      for (int cc = tid; cc < w; cc += NT_TR) {
+        double sacc = 0.0;
+        for (int r = 0; r < w; ++r) sacc += X[r + cc * w] * X[r + cc * w];
+        sig[cc] = sqrt(sacc);
+      }
+      __syncthreads();
+      for (int cc = tid; cc < w; cc += NT_TR) {
+        int pos = 0;
+        const double sc = sig[cc];
+        for (int j = 0; j < w; ++j) {
+          const double sj = sig[j];
+          pos += (sj > sc || (sj == sc && j < cc)) ? 1 : 0;
+        }
+        perm[pos] = cc;
+      }
+      __syncthreads();
+      k = 0;
+      for (int j = 0; j < w; ++j) k += (sig[j] > tau) ? 1 : 0;
+      if (k > capk) {
+        if (tid == 0) atomicOr(err, ERR_CAPACITY);
+        k = capk;
+      }
+      for (int e = tid; e < w * k; e += NT_TR) {
+        const int r = e % w, p = e / w;
+        const int pc = perm[p];
+        const double* u = fast ? X + (int64_t)pc * w : V + (int64_t)pc * LV;
+        const double inv = fast ? 1.0 / sig[pc] : 1.0;
+        Uk[r + p * WMAX] = u[r] * inv;
+        double sacc = 0.0;
+        for (int l = 0; l <= r; ++l) sacc += R1s[l + r * lr] * u[l];
+        P[r + p * WMAX] = sacc * inv;
+      }
     }
     if (tid == 0) add_flops(fc, fcat, tr_flops_full(m0, m1, w, k));
   }
