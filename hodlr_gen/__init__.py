@@ -420,6 +420,36 @@ class RectHodlrInput:
             out += list(range(int(self.row_off[j]), int(self.row_off[j]) + nj))
         return np.asarray(out, dtype=np.int64)
 
+    def pack(self) -> dict:
+        """Flatten into the C-ABI layout of hodlr_build_rect (column-major; leaf j
+        m_j x n_j; blocks in level order, 'up' then 'lo' for each node)."""
+        leaf_data_off = [0]
+        for D in self.leaves:
+            leaf_data_off.append(leaf_data_off[-1] + D.size)
+        leaves = np.concatenate([np.asarray(D, dtype=np.float64).ravel(order="F") for D in self.leaves])
+        Us, Vs, ranks, u_off, v_off = [], [], [], [0], [0]
+        for v in self.internal_nodes():
+            for kind in ("up", "lo"):
+                U, V = self.blocks[(v, kind)]
+                Us.append(np.asarray(U, dtype=np.float64).ravel(order="F"))
+                Vs.append(np.asarray(V, dtype=np.float64).ravel(order="F"))
+                ranks.append(U.shape[1])
+                u_off.append(u_off[-1] + U.size)
+                v_off.append(v_off[-1] + V.size)
+        cat = (lambda xs: np.concatenate(xs) if xs else np.zeros(0))
+        return dict(
+            m=self.m, n=self.n, levels=self.levels,
+            row_off=np.ascontiguousarray(self.row_off, dtype=np.int64),
+            col_off=np.ascontiguousarray(self.col_off, dtype=np.int64),
+            leaves=np.ascontiguousarray(leaves, dtype=np.float64),
+            leaf_data_off=np.asarray(leaf_data_off[:-1], dtype=np.int64),
+            U=np.ascontiguousarray(cat(Us), dtype=np.float64),
+            V=np.ascontiguousarray(cat(Vs), dtype=np.float64),
+            ranks=np.asarray(ranks, dtype=np.int32),
+            u_off=np.asarray(u_off[:-1], dtype=np.int64),
+            v_off=np.asarray(v_off[:-1], dtype=np.int64),
+        )
+
     def to_dense(self) -> np.ndarray:
         A = np.zeros((self.m, self.n))
         for j, D in enumerate(self.leaves):

@@ -120,6 +120,20 @@ hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t *leaf_off,
                          hodlr_stream_t stream, hodlr_t **out);
 
 /*
+ * hodlr_build_rect - copy an m x n rectangular HODLR matrix (Sec. 6) to the
+ * device: leaf j is m_j x n_j with m_j >= n_j, on the row partition row_off
+ * (host, 2^l + 1 offsets from 0 to m) and the column partition col_off (from 0
+ * to n); leaf j column-major with leading dimension m_j; block b's left factor
+ * has rows_b rows of the row partition, its right factor cols_b rows of the
+ * column partition; otherwise as hodlr_build.  Products (hodlr_matmul: X has
+ * n rows and Z m rows, or m and n with trans) and the norm estimate accept it.
+ */
+hodlr_status hodlr_build_rect(int64_t m, int64_t n, int32_t levels, const int64_t *row_off,
+                              const int64_t *col_off, const double *leaves, const int64_t *leaf_data_off,
+                              const double *U, const int64_t *u_off, const double *V, const int64_t *v_off,
+                              const int32_t *ranks, int32_t rank_cap, hodlr_stream_t stream, hodlr_t **out);
+
+/*
  * hodlr_qr - hQR factorisation A ~= (I - Y T Y^T) R  (Algorithm hQR, Sec. 4).
  *
  *  eps    truncation tolerance >= 0.  Recompressions of A-valued blocks (the

@@ -24,7 +24,7 @@ __all__ = [
     "hodlr_qr_factor", "hodlr_check", "hodlr_qr_ranklog", "hodlr_plan_check", "hodlr_norm2_est",
     "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time", "hodlr_qr_profile",
     "hodlr_qr_batched", "hodlr_qr_batched_time", "use_torch_allocator", "HodlrMatrix", "QRFactors",
-    "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "HODLR_QR_BY_SHAPE", "HODLR_QR_KEEP", "hodlr_qr_refactor", "tuning", "set_tuning", "HODLR_CHECK_ESTIMATE", "set_allocator",
+    "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "HODLR_QR_BY_SHAPE", "HODLR_QR_KEEP", "hodlr_qr_refactor", "hodlr_build_rect", "tuning", "set_tuning", "HODLR_CHECK_ESTIMATE", "set_allocator",
     "HODLR_CHECK_PLANT", "load",
 ]
 
@@ -130,8 +130,9 @@ class HodlrMatrix:
     """Owning wrapper of a hodlr_t handle (or a borrowed factor view, which
     keeps its QRFactors alive and is never freed)."""
 
-    def __init__(self, handle, n, levels, rank_cap, owner=None):
+    def __init__(self, handle, n, levels, rank_cap, owner=None, m=None):
         self.handle, self.n, self.levels, self.rank_cap = handle, n, levels, rank_cap
+        self.m = n if m is None else m  # rows (a rectangular matrix has m >= n)
         self.owner = owner
 
     def __del__(self):
@@ -167,6 +168,20 @@ def hodlr_build(H, rank_cap: int = 64, stream=None) -> HodlrMatrix:
         _ptr(p["V"], C.c_double), _ptr(p["v_off"], C.c_int64), _ptr(p["ranks"], C.c_int32),
         int(rank_cap), _stream(stream), C.byref(h)))
     return HodlrMatrix(h, int(p["n"]), int(p["levels"]), int(rank_cap))
+
+
+def hodlr_build_rect(H, rank_cap: int = 64, stream=None) -> HodlrMatrix:
+    """Copy a rectangular HODLR matrix (hodlr_gen.RectHodlrInput or its .pack()
+    dict) to the GPU."""
+    lib = _device()
+    p = H.pack() if hasattr(H, "pack") else H
+    h = C.c_void_p()
+    _lib.check(lib.hodlr_build_rect(
+        int(p["m"]), int(p["n"]), int(p["levels"]), _ptr(p["row_off"], C.c_int64), _ptr(p["col_off"], C.c_int64),
+        _ptr(p["leaves"], C.c_double), _ptr(p["leaf_data_off"], C.c_int64), _ptr(p["U"], C.c_double),
+        _ptr(p["u_off"], C.c_int64), _ptr(p["V"], C.c_double), _ptr(p["v_off"], C.c_int64),
+        _ptr(p["ranks"], C.c_int32), int(rank_cap), _stream(stream), C.byref(h)))
+    return HodlrMatrix(h, int(p["n"]), int(p["levels"]), int(rank_cap), m=int(p["m"]))
 
 
 def hodlr_qr(A: HodlrMatrix, eps: float, anorm: float = 0.0, flags: int = 0, stream=None) -> QRFactors:
@@ -255,16 +270,19 @@ def hodlr_solve(F: QRFactors, B, stream=None):
     return B
 
 
-def _new_like(X):
+def _new_like(X, rows=None):
     import torch
-    return torch.empty((X.shape[1], X.shape[0]), dtype=torch.float64, device=X.device).t()
+    rows = X.shape[0] if rows is None else rows
+    return torch.empty((X.shape[1], rows), dtype=torch.float64, device=X.device).t()
 
 
 def hodlr_matmul(A: HodlrMatrix, X, trans: bool = False, stream=None):
-    X, ldx = _operand(X, A.n)
-    Z = _new_like(X)
+    """Z = A X (X: n rows, Z: m rows) or A^T X (X: m rows, Z: n rows)."""
+    xr, zr = (A.m, A.n) if trans else (A.n, A.m)
+    X, ldx = _operand(X, xr)
+    Z = _new_like(X, zr)
     _lib.check(load().hodlr_matmul(A.handle, 1 if trans else 0, X.shape[1], C.c_void_p(X.data_ptr()), ldx,
-                                   C.c_void_p(Z.data_ptr()), A.n, _stream(stream)))
+                                   C.c_void_p(Z.data_ptr()), zr, _stream(stream)))
     return Z
 
 

@@ -113,11 +113,13 @@ struct HBlk {       // A(r0:r0+rows, c0:c0+cols) = U V^T, rank *rank
   int rows, cols;
 };
 
-struct HLeaf {
+struct HLeaf {       // D(0:m, 0:n) of the rows from r0 and the columns from c0
   double* D;
   int ld;
   int64_t r0;
-  int m;
+  int m;             // rows
+  int64_t c0;
+  int n;             // columns (a leaf of a rectangular HODLR matrix has m >= n)
 };
 
 enum : int { LEAF_FULL = 0, LEAF_UNIT_LOWER = 1, LEAF_UPPER = 2 };
@@ -146,7 +148,8 @@ struct MmJob {
   double* Z;
   int ldZ;
   double alpha, beta;
-  int64_t row0;        // global index of row 0 of X and Z
+  int64_t row0;        // global row index of row 0 of the row-space operand (Z; X when trans)
+  int64_t col0;        // global column index of row 0 of the column-space operand (X; Z when trans)
   int64_t red0;        // reduced projection of node u, kind t at
                        // red0 + (2*(rel(u)) + t) * rld*SMAX
   int rld;             // leading dimension of a projection (>= every block rank)

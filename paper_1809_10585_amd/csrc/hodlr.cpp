@@ -176,7 +176,7 @@ hodlr_status make_blocks(DMem& mem, const Tree& t, int cap, BKind kind, int* ran
   B.voff.assign(nn, 0);
   B.usz = B.vsz = 0;
   for (int v = 1; v < nn; ++v) {
-    const int64_t rows = kind == BK_UP ? t.m(2 * v) : t.m(2 * v + 1);
+    const int64_t rows = kind == BK_UP ? t.mr(2 * v) : t.mr(2 * v + 1);
     const int64_t cols = kind == BK_UP ? t.m(2 * v + 1) : t.m(2 * v);
     B.uoff[v] = B.usz;
     B.voff[v] = B.vsz;
@@ -190,9 +190,9 @@ hodlr_status make_blocks(DMem& mem, const Tree& t, int cap, BKind kind, int* ran
   for (int v = 1; v < nn; ++v) {
     HBlk& b = B.hview[v];
     const bool up = kind == BK_UP;
-    b.rows = (int)(up ? t.m(2 * v) : t.m(2 * v + 1));
+    b.rows = (int)(up ? t.mr(2 * v) : t.mr(2 * v + 1));
     b.cols = (int)(up ? t.m(2 * v + 1) : t.m(2 * v));
-    b.r0 = up ? t.lo[2 * v] : t.lo[2 * v + 1];
+    b.r0 = up ? t.rlo[2 * v] : t.rlo[2 * v + 1];
     b.c0 = up ? t.lo[2 * v + 1] : t.lo[2 * v];
     b.U = B.U + B.uoff[v];
     b.V = B.V + B.voff[v];
@@ -209,14 +209,13 @@ hodlr_status make_leaves(DMem& mem, const Tree& t, LeafSet& S) {
   S.size = 0;
   for (int j = 0; j < nl; ++j) {
     S.off[j] = S.size;
-    const int64_t m = t.m(nl + j);
-    S.size += m * m;
+    S.size += t.mr(nl + j) * t.m(nl + j);
   }
   TRY(mem.alloc(&S.D, (size_t)S.size));
   S.hview.assign(nl, HLeaf{});
   for (int j = 0; j < nl; ++j) {
-    const int64_t m = t.m(nl + j);
-    S.hview[j] = HLeaf{S.D + S.off[j], (int)m, t.lo[nl + j], (int)m};
+    const int64_t mr = t.mr(nl + j), n = t.m(nl + j);
+    S.hview[j] = HLeaf{S.D + S.off[j], (int)mr, t.rlo[nl + j], (int)mr, t.lo[nl + j], (int)n};
   }
   return HODLR_OK;
 }
@@ -320,7 +319,7 @@ void Plan::mm(const Tree& t, const std::vector<MmSpec>& specs) {
   const int p_first = (int)mmp.size();
   std::vector<MmProj> reds;
   int64_t rows_total = 0;
-  for (const MmSpec& sp : specs) rows_total += t.m(sp.v);
+  for (const MmSpec& sp : specs) rows_total += sp.trans ? t.m(sp.v) : t.mr(sp.v);
   const int RT = rows_total >= tune.mm_rt64_rows ? 64 : 16;
   std::vector<MmApply> apply;
   for (const MmSpec& sp : specs) {
@@ -336,7 +335,8 @@ void Plan::mm(const Tree& t, const std::vector<MmSpec>& specs) {
     J.ldZ = sp.ldZ;
     J.alpha = sp.alpha;
     J.beta = sp.beta;
-    J.row0 = t.lo[sp.v];
+    J.row0 = t.rlo[sp.v];
+    J.col0 = t.lo[sp.v];
     J.tri = sp.tri;
     J.fc = sp.fc;
     J.xs = sp.xs;
@@ -354,7 +354,7 @@ void Plan::mm(const Tree& t, const std::vector<MmSpec>& specs) {
     for (int u : nodes) {
       for (int kind = 0; kind < 2; ++kind) {
         if ((kind == 0 && !sp.has_up) || (kind == 1 && !sp.has_lo)) continue;
-        const int64_t rows = kind == 0 ? t.m(2 * u) : t.m(2 * u + 1);
+        const int64_t rows = kind == 0 ? t.mr(2 * u) : t.mr(2 * u + 1);
         const int64_t cols = kind == 0 ? t.m(2 * u + 1) : t.m(2 * u);
         const int64_t len = sp.trans ? rows : cols;
         const int nch = (int)((len + MM_CH - 1) / MM_CH);
@@ -372,8 +372,9 @@ void Plan::mm(const Tree& t, const std::vector<MmSpec>& specs) {
     std::vector<int> leaves;
     t.subtree_leaves(sp.v, leaves);
     for (int j : leaves) {
-      const int m = (int)t.m(t.nleaf() + j);
-      mleaf = std::max(mleaf, m);
+      const int lv = t.nleaf() + j;
+      const int m = (int)(sp.trans ? t.m(lv) : t.mr(lv));  // output rows of the leaf
+      mleaf = std::max(mleaf, (int)std::max(t.m(lv), t.mr(lv)));
       for (int r0 = 0; r0 < m; r0 += RT) apply.push_back(MmApply{jid, j, r0, std::min(RT, m - r0)});
     }
   }
@@ -1131,7 +1132,8 @@ struct QRBuilder {
 
 // One power-iteration estimate of |M|_2 per item (iters steps on M^T M from
 // x0 = 1/sqrt(n)), all items in the same launches; writes each result to
-// its out (device).  x, y, z: device vectors of length n per item.
+// its out (device).  x, z: device vectors of the columns' length per item,
+// y of the rows' length.
 struct NormItem {
   HView V;
   int rld;
@@ -1140,18 +1142,18 @@ struct NormItem {
 };
 
 void plan_norm2(Plan& P, const Tree& t, const std::vector<NormItem>& items, int iters) {
-  const int64_t n = t.n;
+  const int64_t n = t.n, nr = t.nr;  // x, z: n entries; y = M x: nr entries
   std::vector<VecJob> fill, norm, last;
   for (const NormItem& it : items) {
     fill.push_back(VecJob{nullptr, it.x, n, nullptr, 1.0 / std::sqrt((double)n), 0.0});
     norm.push_back(VecJob{it.z, it.x, n, nullptr, 0.0, 0.0});
-    last.push_back(VecJob{it.y, nullptr, n, it.out, 0.0, 0.0});
+    last.push_back(VecJob{it.y, nullptr, nr, it.out, 0.0, 0.0});
   }
   P.vec(OP_FILL, fill);
   std::vector<MmSpec> a, b;
   for (const NormItem& it : items) {
-    MmSpec sa = mmspec(it.V, true, true, 1, 0, it.x, (int)n, nullptr, it.y, (int)n, 1.0, 0.0, 0, 1, it.flops);
-    MmSpec sb = mmspec(it.V, true, true, 1, 1, it.y, (int)n, nullptr, it.z, (int)n, 1.0, 0.0, 0, 1, it.flops);
+    MmSpec sa = mmspec(it.V, true, true, 1, 0, it.x, (int)n, nullptr, it.y, (int)nr, 1.0, 0.0, 0, 1, it.flops);
+    MmSpec sb = mmspec(it.V, true, true, 1, 1, it.y, (int)nr, nullptr, it.z, (int)n, 1.0, 0.0, 0, 1, it.flops);
     sa.fc = sb.fc = FC_NORM;
     sa.rld = sb.rld = it.rld;
     a.push_back(sa);
@@ -1211,6 +1213,7 @@ void make_views(hodlr_qr_s& F) {
 // device storage of the factors of A (no schedule yet)
 hodlr_status make_storage(const hodlr_s& A, double eps, double anorm, hipStream_t st,
                           std::unique_ptr<hodlr_qr_s>& out) {
+  if (A.t.rect()) return fail(HODLR_EINVAL, "the QR of a rectangular HODLR matrix is not available yet");
   auto F = std::make_unique<hodlr_qr_s>();
   F->mem.zero = true;
   F->mem.stream = st;
@@ -1745,7 +1748,7 @@ hodlr_status norm2_est_impl(const hodlr_s& A, int iters, hipStream_t st, double*
   CallMem tmp(st);
   double *x, *y, *z, *res;
   TRY(tmp.alloc(&x, n));
-  TRY(tmp.alloc(&y, n));
+  TRY(tmp.alloc(&y, t.nr));
   TRY(tmp.alloc(&z, n));
   TRY(tmp.alloc(&res, 1));
   Plan P;
@@ -1785,31 +1788,39 @@ hodlr_status hodlr_set_allocator(void* (*alloc)(size_t, hodlr_stream_t, void*),
   return HODLR_OK;
 }
 
-hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t* leaf_off, const double* leaves,
-                         const int64_t* leaf_data_off, const double* U, const int64_t* u_off,
-                         const double* V, const int64_t* v_off, const int32_t* ranks, int32_t rank_cap,
-                         hodlr_stream_t stream, hodlr_t** out) {
+}  // extern "C"
+
+namespace hqh {
+namespace {
+// hodlr_build and hodlr_build_rect: row partition row_off, column partition col_off
+hodlr_status build_impl(int64_t nr, int64_t n, int32_t levels, const int64_t* row_off, const int64_t* col_off,
+                        const double* leaves, const int64_t* leaf_data_off, const double* U, const int64_t* u_off,
+                        const double* V, const int64_t* v_off, const int32_t* ranks, int32_t rank_cap,
+                        hodlr_stream_t stream, hodlr_t** out) {
   g_err.clear();
   if (out == nullptr) return fail(HODLR_EINVAL, "out is NULL");
   *out = nullptr;
   if (levels < 0 || levels > MAXGROUPS) return fail(HODLR_EINVAL, "levels out of range");
-  if (n <= 0 || leaf_off == nullptr || leaves == nullptr || leaf_data_off == nullptr)
+  if (n <= 0 || nr < n || col_off == nullptr || row_off == nullptr || leaves == nullptr ||
+      leaf_data_off == nullptr)
     return fail(HODLR_EINVAL, "bad size or NULL array");
   if (rank_cap < 1 || rank_cap > KCAP) return fail(HODLR_EINVAL, "rank_cap must be in 1..64");
   const int nl = 1 << levels;
   const int nb = 2 * (nl - 1);
   if (nb > 0 && (U == nullptr || V == nullptr || u_off == nullptr || v_off == nullptr || ranks == nullptr))
     return fail(HODLR_EINVAL, "NULL block array");
-  if (leaf_off[0] != 0 || leaf_off[nl] != n) return fail(HODLR_EINVAL, "leaf_off must run from 0 to n");
+  if (col_off[0] != 0 || col_off[nl] != n) return fail(HODLR_EINVAL, "leaf_off must run from 0 to n");
+  if (row_off[0] != 0 || row_off[nl] != nr) return fail(HODLR_EINVAL, "row_off must run from 0 to m");
   for (int j = 0; j < nl; ++j) {
-    const int64_t m = leaf_off[j + 1] - leaf_off[j];
-    if (m < 1) return fail(HODLR_EINVAL, "empty leaf");
-    if (m > MAXLEAF) return fail(HODLR_EINVAL, "leaf larger than 512");
+    const int64_t nj = col_off[j + 1] - col_off[j], mj = row_off[j + 1] - row_off[j];
+    if (nj < 1) return fail(HODLR_EINVAL, "empty leaf");
+    if (mj < nj) return fail(HODLR_EINVAL, "a leaf with fewer rows than columns");
+    if (mj > MAXLEAF) return fail(HODLR_EINVAL, "leaf larger than 512");
   }
   hipStream_t st = (hipStream_t)stream;
   auto A = std::make_unique<hodlr_s>();
   A->mem.stream = st;
-  A->t.init(levels, leaf_off);
+  A->t.init(levels, col_off, row_off);
   A->cap = rank_cap;
   const Tree& t = A->t;
   // validate ranks and finiteness
@@ -1817,7 +1828,7 @@ hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t* leaf_off, con
   for (int d = 0; d < levels; ++d)
     for (int v = 1 << d; v < (2 << d); ++v)
       for (int kind = 0; kind < 2; ++kind, ++bi) {
-        const int64_t rows = kind == 0 ? t.m(2 * v) : t.m(2 * v + 1);
+        const int64_t rows = kind == 0 ? t.mr(2 * v) : t.mr(2 * v + 1);
         const int64_t cols = kind == 0 ? t.m(2 * v + 1) : t.m(2 * v);
         const int k = ranks[bi];
         if (k < 0 || k > rows || k > cols || k > rank_cap)
@@ -1825,10 +1836,8 @@ hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t* leaf_off, con
         TRY(check_finite(U + u_off[bi], (size_t)(rows * k), "U"));
         TRY(check_finite(V + v_off[bi], (size_t)(cols * k), "V"));
       }
-  for (int j = 0; j < nl; ++j) {
-    const int64_t m = t.m(nl + j);
-    TRY(check_finite(leaves + leaf_data_off[j], (size_t)(m * m), "leaves"));
-  }
+  for (int j = 0; j < nl; ++j)
+    TRY(check_finite(leaves + leaf_data_off[j], (size_t)(t.mr(nl + j) * t.m(nl + j)), "leaves"));
   TRY(A->mem.alloc(&A->ranks, 2 * (size_t)nl + 8));
   A->rank_up_dev = A->ranks;
   A->rank_lo_dev = A->ranks + nl;
@@ -1840,10 +1849,9 @@ hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t* leaf_off, con
   TRY(upload(A->mem, &A->leaves.dview, A->leaves.hview, st));
   // pack into the capacity layout on the host, then one copy per array
   std::vector<double> hl((size_t)A->leaves.size);
-  for (int j = 0; j < nl; ++j) {
-    const int64_t m = t.m(nl + j);
-    std::memcpy(hl.data() + A->leaves.off[j], leaves + leaf_data_off[j], (size_t)(m * m) * sizeof(double));
-  }
+  for (int j = 0; j < nl; ++j)
+    std::memcpy(hl.data() + A->leaves.off[j], leaves + leaf_data_off[j],
+                (size_t)(t.mr(nl + j) * t.m(nl + j)) * sizeof(double));
   std::vector<double> uu((size_t)A->up.usz, 0.0), uv((size_t)A->up.vsz, 0.0), lu((size_t)A->lo.usz, 0.0),
       lv((size_t)A->lo.vsz, 0.0);
   std::vector<int> hr(2 * (size_t)nl + 8, 0);
@@ -1854,7 +1862,7 @@ hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t* leaf_off, con
         BlockSet& B = kind == 0 ? A->up : A->lo;
         std::vector<double>& bu = kind == 0 ? uu : lu;
         std::vector<double>& bv = kind == 0 ? uv : lv;
-        const int64_t rows = kind == 0 ? t.m(2 * v) : t.m(2 * v + 1);
+        const int64_t rows = kind == 0 ? t.mr(2 * v) : t.mr(2 * v + 1);
         const int64_t cols = kind == 0 ? t.m(2 * v + 1) : t.m(2 * v);
         const int k = ranks[bi];
         std::memcpy(bu.data() + B.uoff[v], U + u_off[bi], (size_t)(rows * k) * sizeof(double));
@@ -1870,6 +1878,26 @@ hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t* leaf_off, con
   HIPCHK(hipStreamSynchronize(st));
   *out = A.release();
   return HODLR_OK;
+}
+}  // namespace
+}  // namespace hqh
+
+extern "C" {
+
+hodlr_status hodlr_build(int64_t n, int32_t levels, const int64_t* leaf_off, const double* leaves,
+                         const int64_t* leaf_data_off, const double* U, const int64_t* u_off,
+                         const double* V, const int64_t* v_off, const int32_t* ranks, int32_t rank_cap,
+                         hodlr_stream_t stream, hodlr_t** out) {
+  return build_impl(n, n, levels, leaf_off, leaf_off, leaves, leaf_data_off, U, u_off, V, v_off, ranks, rank_cap,
+                    stream, out);
+}
+
+hodlr_status hodlr_build_rect(int64_t m, int64_t n, int32_t levels, const int64_t* row_off, const int64_t* col_off,
+                              const double* leaves, const int64_t* leaf_data_off, const double* U,
+                              const int64_t* u_off, const double* V, const int64_t* v_off, const int32_t* ranks,
+                              int32_t rank_cap, hodlr_stream_t stream, hodlr_t** out) {
+  return build_impl(m, n, levels, row_off, col_off, leaves, leaf_data_off, U, u_off, V, v_off, ranks, rank_cap,
+                    stream, out);
 }
 
 void hodlr_free(hodlr_t* A) {
@@ -2002,7 +2030,8 @@ const hodlr_s* factor_view(const hodlr_qr_s* F, char which) {
 
 hodlr_status matmul_impl(const hodlr_s& A, int32_t trans, int64_t nrhs, const double* X, int64_t ldx,
                          double* Z, int64_t ldz, hipStream_t st) {
-  if (X == nullptr || Z == nullptr || nrhs < 0 || ldx < A.t.n || ldz < A.t.n)
+  const int64_t xrows = trans ? A.t.nr : A.t.n, zrows = trans ? A.t.n : A.t.nr;
+  if (X == nullptr || Z == nullptr || nrhs < 0 || ldx < xrows || ldz < zrows)
     return fail(HODLR_EINVAL, "bad operand");
   if (nrhs == 0) return HODLR_OK;
   if (ldx > INT32_MAX || ldz > INT32_MAX) return fail(HODLR_EINVAL, "leading dimension too large");
@@ -2403,15 +2432,15 @@ hodlr_status export_impl(const Tree& t, const LeafSet& L, const BlockSet* up, co
   HIPCHK(hipMemcpy(hl.data(), L.D, hl.size() * sizeof(double), hipMemcpyDeviceToHost));
   int64_t pos = 0;
   for (int j = 0; j < nl; ++j) {
-    const int64_t m = t.m(nl + j);
-    for (int64_t c = 0; c < m; ++c)
+    const int64_t m = t.mr(nl + j), n = t.m(nl + j), ld = L.hview[j].ld;
+    for (int64_t c = 0; c < n; ++c)
       for (int64_t r = 0; r < m; ++r) {
-        double x = hl[L.off[j] + r + c * m];
+        double x = hl[L.off[j] + r + c * ld];
         if (leafmode == LEAF_UNIT_LOWER) x = r > c ? x : (r == c ? 1.0 : 0.0);
         if (leafmode == LEAF_UPPER) x = r <= c ? x : 0.0;
         leaves[pos + r + c * m] = x;
       }
-    pos += m * m;
+    pos += m * n;
   }
   std::vector<int> rk(2 * (size_t)nl, 0);
   if (d_ranks_up) HIPCHK(hipMemcpy(rk.data(), d_ranks_up, nl * sizeof(int), hipMemcpyDeviceToHost));
@@ -2422,7 +2451,7 @@ hodlr_status export_impl(const Tree& t, const LeafSet& L, const BlockSet* up, co
     for (int v = 1 << d; v < (2 << d); ++v)
       for (int kind = 0; kind < 2; ++kind, ++bi) {
         const BlockSet* B = kind == 0 ? up : lo;
-        const int64_t rows = kind == 0 ? t.m(2 * v) : t.m(2 * v + 1);
+        const int64_t rows = kind == 0 ? t.mr(2 * v) : t.mr(2 * v + 1);
         const int64_t cols = kind == 0 ? t.m(2 * v + 1) : t.m(2 * v);
         const int k = B ? rk[(kind == 0 ? 0 : nl) + v] : 0;
         ranks[bi] = k;
@@ -2430,8 +2459,11 @@ hodlr_status export_impl(const Tree& t, const LeafSet& L, const BlockSet* up, co
         v_off[bi] = vp_;
         if (k > 0) {
           if (U == nullptr || V == nullptr) return fail(HODLR_EINVAL, "NULL U or V");
-          HIPCHK(hipMemcpy(U + up_, B->U + B->uoff[v], (size_t)(rows * k) * sizeof(double), hipMemcpyDeviceToHost));
-          HIPCHK(hipMemcpy(V + vp_, B->V + B->voff[v], (size_t)(cols * k) * sizeof(double), hipMemcpyDeviceToHost));
+          const HBlk& hb = B->hview[v];
+          HIPCHK(hipMemcpy2D(U + up_, rows * sizeof(double), hb.U, hb.ldU * sizeof(double), rows * sizeof(double), k,
+                             hipMemcpyDeviceToHost));
+          HIPCHK(hipMemcpy2D(V + vp_, cols * sizeof(double), hb.V, hb.ldV * sizeof(double), cols * sizeof(double), k,
+                             hipMemcpyDeviceToHost));
         }
         up_ += rows * k;
         vp_ += cols * k;

@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(NT_MM) k_mm_proj(const MmJob* __restrict__ job
   const double* F = trans ? b.U : b.V;
   const int ldF = trans ? b.ldU : b.ldV;
   int ldX;
-  const double* X = mm_x(J, op, ldX) + ((trans ? b.r0 : b.c0) - J.row0);
+  const double* X = mm_x(J, op, ldX) + (trans ? b.r0 - J.row0 : b.c0 - J.col0);
   const int c0 = it.chunk * MM_CH;
   const int cn = min(MM_CH, len - c0);
   const int nout = k * s;
@@ -167,8 +167,12 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
   const HLeaf lf = J.M.leaf[it.leaf];
   const int kind = J.M.leaf_kind;
   const int trans = J.trans;
-  const int m = lf.m;
-  const int R = it.row0 + r;  // row of this thread within the leaf
+  // output rows of the leaf are its rows (op N) or columns (op T); the sum runs
+  // over the other dimension (m: its length)
+  const int m = trans ? lf.m : lf.n;
+  const int64_t out0 = trans ? lf.c0 : lf.r0;
+  const int64_t in0 = trans ? lf.r0 : lf.c0;
+  const int R = it.row0 + r;  // output row of this thread within the leaf
   const bool live = r < it.rows;
   double dv[DMAX];
   if constexpr (RT == 16) {
@@ -207,13 +211,13 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
           const HBlk& b = arr[u];
           akb[a] = *b.rank;
           ald[a] = trans ? b.ldV : b.ldU;
-          aF[a] = (trans ? b.V : b.U) + (lf.r0 + R - (trans ? b.c0 : b.r0));
+          aF[a] = (trans ? b.V : b.U) + (out0 + R - (trans ? b.c0 : b.r0));
           aR[a] = ws + J.red0 + (int64_t)(2 * rel_node(u, J.v) + bk) * (rld * SMAX);
         }
       }
     }
   }
-  const double* xl = JX + (lf.r0 - J.row0);
+  const double* xl = JX + (in0 - (trans ? J.row0 : J.col0));
   double* Xs = shm;
   for (int c0 = 0; c0 < s; c0 += CW) {
     const int cn = min(CW, s - c0);
@@ -290,7 +294,7 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
                               (int64_t)c0 * rld;
           const double* F = trans ? b.V : b.U;
           const int ldF = trans ? b.ldV : b.ldU;
-          const int64_t frow = lf.r0 + R - (trans ? b.c0 : b.r0);
+          const int64_t frow = out0 + R - (trans ? b.c0 : b.r0);
           for (int j = 0; j < kb; ++j) {
             const double fv = live ? F[frow + (int64_t)j * ldF] : 0.0;
 #pragma unroll
@@ -313,7 +317,7 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
         double sacc = 0.0;
 #pragma unroll
         for (int g2 = 0; g2 < G; ++g2) sacc += shm[(g2 * RT + rr) * MA_LD + c];
-        double* zp = JZ + (lf.r0 - J.row0 + it.row0 + rr) + (int64_t)(c0 + c) * ldZ;
+        double* zp = JZ + (out0 - (trans ? J.col0 : J.row0) + it.row0 + rr) + (int64_t)(c0 + c) * ldZ;
         const double v = J.alpha * sacc;
         *zp = (J.beta == 0.0) ? v : v + J.beta * (*zp);
       }
@@ -347,7 +351,7 @@ __global__ void __launch_bounds__(NT_MM) k_mm_apply(const MmJob* __restrict__ jo
     const HLeaf lf = J.M.leaf[it.leaf];
     const int trans = J.trans;
     const int hleaf = (1 << J.M.levels) + it.leaf;
-    double flops = 2.0 * it.rows * lf.m * s * (J.tri ? 0.5 : 1.0);
+    double flops = 2.0 * it.rows * (trans ? lf.m : lf.n) * s * (J.tri ? 0.5 : 1.0);
     int child2 = hleaf, u2 = hleaf >> 1;
     while (child2 != J.v && u2 >= 1) {
       const bool left = (child2 == 2 * u2);

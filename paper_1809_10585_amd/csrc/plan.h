@@ -119,16 +119,21 @@ hodlr_status upload(DMem& mem, T** d, const std::vector<T>& h, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ tree
+// The partition of a HODLR matrix: columns [lo[v], hi[v]) and rows
+// [rlo[v], rhi[v]) of heap node v (the same for a square matrix; a rectangular
+// one, Sec. 6, has m_j >= n_j rows per leaf).
 struct Tree {
   int L = 0;
-  int64_t n = 0;
-  std::vector<int64_t> lo, hi;  // heap numbering 1 .. 2^(L+1)-1
+  int64_t n = 0;                  // columns
+  int64_t nr = 0;                 // rows
+  std::vector<int64_t> lo, hi;    // column ranges, heap numbering 1 .. 2^(L+1)-1
+  std::vector<int64_t> rlo, rhi;  // row ranges
   int nleaf() const { return 1 << L; }
   bool is_leaf(int v) const { return v >= (1 << L); }
-  int64_t m(int v) const { return hi[v] - lo[v]; }
-  void init(int levels, const int64_t* off) {
-    L = levels;
-    n = off[1 << L];
+  int64_t m(int v) const { return hi[v] - lo[v]; }     // columns of node v
+  int64_t mr(int v) const { return rhi[v] - rlo[v]; }  // rows of node v
+  bool rect() const { return nr != n || rlo != lo; }
+  static void fill(int L, const int64_t* off, std::vector<int64_t>& lo, std::vector<int64_t>& hi) {
     lo.assign(2 << L, 0);
     hi.assign(2 << L, 0);
     for (int j = 0; j < (1 << L); ++j) {
@@ -139,6 +144,22 @@ struct Tree {
       lo[v] = lo[2 * v];
       hi[v] = hi[2 * v + 1];
     }
+  }
+  void init(int levels, const int64_t* off, const int64_t* row_off = nullptr) {
+    L = levels;
+    n = off[1 << L];
+    fill(L, off, lo, hi);
+    if (row_off == nullptr) row_off = off;
+    nr = row_off[1 << L];
+    fill(L, row_off, rlo, rhi);
+  }
+  // the square tree on the column partition (T, and R on its pivot rows)
+  Tree square() const {
+    Tree q = *this;
+    q.nr = n;
+    q.rlo = lo;
+    q.rhi = hi;
+    return q;
   }
   void subtree_internal(int v, std::vector<int>& out) const {
     if (is_leaf(v)) return;

@@ -105,6 +105,22 @@ def test_invalid_arguments_are_rejected_on_host(lib):
     assert lib.hodlr_qr_batched(C.cast(arr, C.POINTER(C.c_void_p)), 2, 1e-10, None, 0, None, None) == -1
     ms = (C.c_double * 1)()
     assert lib.hodlr_qr_batched_time(None, 1, 1e-10, None, 0, 0, 1, None, ms) == -1
+    # rectangular build: a leaf with fewer rows than columns, rows not summing to m
+    lv = np.zeros(64)
+    for roff, m in (([0, 3, 8], 8), ([0, 4, 9], 8)):
+        ro = np.asarray(roff, dtype=np.int64)
+        co = np.asarray([0, 4, 8], dtype=np.int64)
+        h = C.c_void_p()
+        st = lib.hodlr_build_rect(m, 8, 1, ro.ctypes.data_as(C.POINTER(C.c_int64)),
+                                  co.ctypes.data_as(C.POINTER(C.c_int64)), lv.ctypes.data_as(C.POINTER(C.c_double)),
+                                  np.zeros(2, dtype=np.int64).ctypes.data_as(C.POINTER(C.c_int64)),
+                                  lv.ctypes.data_as(C.POINTER(C.c_double)),
+                                  np.zeros(2, dtype=np.int64).ctypes.data_as(C.POINTER(C.c_int64)),
+                                  lv.ctypes.data_as(C.POINTER(C.c_double)),
+                                  np.zeros(2, dtype=np.int64).ctypes.data_as(C.POINTER(C.c_int64)),
+                                  np.zeros(2, dtype=np.int32).ctypes.data_as(C.POINTER(C.c_int32)), 4, None,
+                                  C.byref(h))
+        assert st == -1 and not h.value
     # refactor: no handles, NULL handle entries
     assert lib.hodlr_qr_refactor(None, None, 1, 0, None) == -1
     assert lib.hodlr_qr_refactor(C.cast(arr, C.POINTER(C.c_void_p)), C.cast(arr, C.POINTER(C.c_void_p)), 2, 0,
