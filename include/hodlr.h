@@ -148,6 +148,16 @@ hodlr_status hodlr_build_rect(int64_t m, int64_t n, int32_t levels, const int64_
  *  out    receives the factors (release with hodlr_qr_free).  A is not modified.
  * Returns HODLR_ECAPACITY if a rank outgrew rank_cap (or a recompression width
  * exceeded 128); the partial factors are then released.
+ *
+ * A rectangular A (hodlr_build_rect, Sec. 6) gets the permuted QR of that
+ * section: block column j is reduced onto the first n_j rows of leaf j (its
+ * pivot rows) and every other row of it becomes zero.  Y (m x n) then has
+ * upper blocks as well, over the rows of a node's first child left unreduced
+ * by it ("free rows", compressed at eps*anorm); T is n x n on the column
+ * partition; R is zero outside the pivot rows, and hodlr_qr_factor(F, 'R') /
+ * hodlr_qr_matmul(F, 'R', ...) act with R on its pivot rows in column order (an
+ * n x n upper triangular HODLR matrix).  Q is m x m: hodlr_apply_q takes m-row
+ * operands.
  */
 hodlr_status hodlr_qr(const hodlr_t *A, double eps, double anorm, uint32_t flags,
                       hodlr_stream_t stream, hodlr_qr_t **out);
@@ -226,9 +236,21 @@ hodlr_status hodlr_apply_q_noalloc(const hodlr_qr_t *F, int32_t trans, int64_t n
  * column of B (device, n x nrhs, ldb >= n).  Back substitution with the upper
  * triangular HODLR R runs leaf by leaf from the last one
  * (x2 = R22^{-1} c2, c1 <- c1 - R12 x2, x1 = R11^{-1} c1).  Stream-ordered and
- * asynchronous.
+ * asynchronous.  A rectangular factorisation is refused (HODLR_EINVAL): use
+ * hodlr_lstsq.
  */
 hodlr_status hodlr_solve(const hodlr_qr_t *F, int64_t nrhs, double *B, int64_t ldb,
+                         hodlr_stream_t stream);
+
+/*
+ * hodlr_lstsq - least-squares solutions x = argmin |A x - b|_2 of every column
+ * of B from the (permuted) QR: B <- Q^T B (device, m x nrhs, ldb >= m), then X
+ * (device, n x nrhs, ldx >= n) <- R_p^{-1} (the pivot rows of Q^T B in column
+ * order), with R_p the n x n triangular factor on the pivot rows.  For a square
+ * factorisation it is hodlr_solve with the result in X.  Stream-ordered and
+ * asynchronous.
+ */
+hodlr_status hodlr_lstsq(const hodlr_qr_t *F, int64_t nrhs, double *B, int64_t ldb, double *X, int64_t ldx,
                          hodlr_stream_t stream);
 
 /*

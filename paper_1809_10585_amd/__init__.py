@@ -24,7 +24,7 @@ __all__ = [
     "hodlr_qr_factor", "hodlr_check", "hodlr_qr_ranklog", "hodlr_plan_check", "hodlr_norm2_est",
     "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time", "hodlr_qr_profile",
     "hodlr_qr_batched", "hodlr_qr_batched_time", "use_torch_allocator", "HodlrMatrix", "QRFactors",
-    "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "HODLR_QR_BY_SHAPE", "HODLR_QR_KEEP", "hodlr_qr_refactor", "hodlr_build_rect", "tuning", "set_tuning", "HODLR_CHECK_ESTIMATE", "set_allocator",
+    "HodlrError", "colmajor", "HODLR_QR_GRAPH", "HODLR_QR_ONE_STREAM", "HODLR_QR_BY_SHAPE", "HODLR_QR_KEEP", "hodlr_qr_refactor", "hodlr_build_rect", "hodlr_lstsq", "tuning", "set_tuning", "HODLR_CHECK_ESTIMATE", "set_allocator",
     "HODLR_CHECK_PLANT", "load",
 ]
 
@@ -148,6 +148,7 @@ class QRFactors:
 
     def __init__(self, handle, A):
         self.handle, self.n, self.levels, self.rank_cap = handle, A.n, A.levels, A.rank_cap
+        self.m = getattr(A, "m", A.n)  # rows of A (and of Q, Y)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -256,8 +257,8 @@ def hodlr_qr_batched_time(As, eps: float, anorm=None, flags: int = 0, warmup: in
 
 
 def hodlr_apply_q(F: QRFactors, X, trans: bool = False, stream=None):
-    """X <- Q X (or Q^T X) in place."""
-    X, ld = _operand(X, F.n)
+    """X <- Q X (or Q^T X) in place (X: m rows)."""
+    X, ld = _operand(X, F.m)
     _lib.check(load().hodlr_apply_q(F.handle, 1 if trans else 0, X.shape[1], C.c_void_p(X.data_ptr()), ld,
                                     _stream(stream)))
     return X
@@ -268,6 +269,16 @@ def hodlr_solve(F: QRFactors, B, stream=None):
     B, ld = _operand(B, F.n)
     _lib.check(load().hodlr_solve(F.handle, B.shape[1], C.c_void_p(B.data_ptr()), ld, _stream(stream)))
     return B
+
+
+def hodlr_lstsq(F: QRFactors, B, stream=None):
+    """Least-squares solutions argmin |A x - b| per column of B (m rows; B is
+    overwritten with Q^T B); returns X (n rows)."""
+    B, ldb = _operand(B, F.m)
+    X = _new_like(B, F.n)
+    _lib.check(load().hodlr_lstsq(F.handle, B.shape[1], C.c_void_p(B.data_ptr()), ldb, C.c_void_p(X.data_ptr()),
+                                  F.n, _stream(stream)))
+    return X
 
 
 def _new_like(X, rows=None):
@@ -287,10 +298,13 @@ def hodlr_matmul(A: HodlrMatrix, X, trans: bool = False, stream=None):
 
 
 def hodlr_qr_matmul(F: QRFactors, which: str, X, trans: bool = False, stream=None):
-    X, ldx = _operand(X, F.n)
-    Z = _new_like(X)
+    """Z = op(M) X for M = Y (m x n), T (n x n) or R on its pivot rows (n x n)."""
+    rows = F.m if which[:1] == "Y" else F.n
+    xr, zr = (rows, F.n) if trans else (F.n, rows)
+    X, ldx = _operand(X, xr)
+    Z = _new_like(X, zr)
     _lib.check(load().hodlr_qr_matmul(F.handle, which.encode()[:1], 1 if trans else 0, X.shape[1],
-                                      C.c_void_p(X.data_ptr()), ldx, C.c_void_p(Z.data_ptr()), F.n,
+                                      C.c_void_p(X.data_ptr()), ldx, C.c_void_p(Z.data_ptr()), zr,
                                       _stream(stream)))
     return Z
 
@@ -300,7 +314,7 @@ def hodlr_qr_factor(F: QRFactors, which: str) -> HodlrMatrix:
     (usable with hodlr_matmul and hodlr_export; keeps F alive)."""
     v = C.c_void_p()
     _lib.check(load().hodlr_qr_factor(F.handle, which.encode()[:1], C.byref(v)))
-    return HodlrMatrix(v, F.n, F.levels, F.rank_cap, owner=F)
+    return HodlrMatrix(v, F.n, F.levels, F.rank_cap, owner=F, m=F.m if which[:1] == "Y" else F.n)
 
 
 def hodlr_check(F: QRFactors, stream=None):

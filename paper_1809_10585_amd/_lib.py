@@ -23,7 +23,7 @@ HODLR_QR_KEEP = 8
 EXPORTS = [
     "hodlr_set_allocator", "hodlr_build", "hodlr_qr", "hodlr_apply_q", "hodlr_apply_q_noalloc",
     "hodlr_solve", "hodlr_matmul",
-    "hodlr_qr_matmul", "hodlr_qr_factor", "hodlr_check", "hodlr_qr_ranklog", "hodlr_plan_check", "hodlr_plan_check_set", "hodlr_qr_refactor", "hodlr_tuning", "hodlr_set_tuning", "hodlr_build_rect",
+    "hodlr_qr_matmul", "hodlr_qr_factor", "hodlr_check", "hodlr_qr_ranklog", "hodlr_plan_check", "hodlr_plan_check_set", "hodlr_qr_refactor", "hodlr_tuning", "hodlr_set_tuning", "hodlr_build_rect", "hodlr_lstsq",
     "hodlr_norm2_est", "hodlr_qr_info", "hodlr_export", "hodlr_qr_export", "hodlr_qr_time",
     "hodlr_qr_profile", "hodlr_op_name", "hodlr_op_count", "hodlr_qr_batched", "hodlr_qr_batched_time",
     "hodlr_free", "hodlr_qr_free", "hodlr_last_error", "hodlr_version",
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
         "hodlr_set_tuning": (I32, [C.POINTER(Tuning)]),
         "hodlr_build": (I32, [I64, I32, PI64, PD, PI64, PD, PI64, PD, PI64, PI32, I32, P, PP]),
         "hodlr_build_rect": (I32, [I64, I64, I32, PI64, PI64, PD, PI64, PD, PI64, PD, PI64, PI32, I32, P, PP]),
+        "hodlr_lstsq": (I32, [P, I64, P, I64, P, I64, P]),
         "hodlr_qr": (I32, [P, D, D, C.c_uint32, P, PP]),
         "hodlr_apply_q": (I32, [P, I32, I64, P, I64, P]),
         "hodlr_apply_q_noalloc": (I32, [P, I32, I64, P, I64, P]),

@@ -225,14 +225,24 @@ struct LeafWs {     // workspace of one leaf QR (one per factorisation: its leav
   double* G;        // Y^T Y blocks above the panel diagonal (ld MAXLEAF)
 };
 struct LeafJob {
-  double* D;        // leaf (m x m, ld m): A on input, R + Y on output
-  int m;
+  double* D;        // leaf (mr x m, ld mr): A on input, R + Y on output
+  int m;            // columns
+  int mr;           // rows of D (m for a square matrix, m_j >= n_j in Sec. 6)
   double* Tleaf;    // T leaf output (m x m, ld m)
   LeafWs ws;
   int* err;
   double* flops;
   int ngroups;
   LeafGroup g[MAXGROUPS];
+};
+struct RowJob {     // copy rows [src_r0, src_r0 + rows) of a column-major array to dst_r0..
+  const double* src;
+  int lds;
+  double* dst;
+  int ldd;
+  int src_r0, dst_r0, rows;
+  const int* ncols_dev;  // columns: *ncols_dev when set, else ncols
+  int ncols;
 };
 struct VecJob {     // one vector of a batched fill / normalise / threshold op
   const double* z;

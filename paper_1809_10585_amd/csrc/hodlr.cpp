@@ -43,7 +43,7 @@ hodlr_status fail(hodlr_status s, const std::string& m) {
 const char* const OP_NAMES[OP_NTYPES] = {
   "tr_qr", "tr_form", "mm_proj", "mm_apply", "gemm_tall", "gemm_red", "leaf_gather", "leaf_panel",
   "leaf_update", "leaf_scatter", "fill", "normalize", "leaf_trsm", "set_scal", "mm_red", "tr_small",
-  "signal", "wait"};
+  "rows", "signal", "wait"};
 
 // ------------------------------------------------------------------ memory
 namespace {
@@ -452,6 +452,7 @@ hodlr_status Plan::upload_all(DMem& mem, hipStream_t st) {
   pk.add(gr, &d_gr);
   pk.add(lj, &d_lj);
   pk.add(vj, &d_vj);
+  pk.add(rj, &d_rj);
   char* base = nullptr;
   TRY(mem.alloc(&base, staged.size()));
   for (auto& f : pk.fix) *f.second = base + f.first;
@@ -597,10 +598,14 @@ void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st, const Lau
     case OP_SETSCAL:
       launch(L, k_set_scal, (o.count + 63) / 64, 64, 0, st, P.d_vj, o.first, o.count);
       break;
+    case OP_ROWS:
+      launch(L, k_rows, o.count, NT_MM, 0, st, P.d_rj, o.first);
+      break;
     case OP_TRSM:
       if (o.xs >= 0) {
         if (op.s > 0)
-          launch(L, k_leaf_trsm, op.s, NT_MM, 0, st, o.p0, o.a0, o.a0, op.p[o.xs] + o.xoff, op.ld[o.xs], op.s);
+          launch(L, k_leaf_trsm, op.s, NT_MM, 0, st, o.p0, o.a0, o.a1 > 0 ? o.a1 : o.a0, op.p[o.xs] + o.xoff,
+                 op.ld[o.xs], op.s);
       } else {
         launch(L, k_leaf_trsm, o.count, NT_MM, 0, st, o.p0, o.a0, o.a0, o.p1, (int)o.n, o.count);
       }
@@ -704,19 +709,27 @@ struct Batch {
 };
 
 // rank-log sites (the first field of a key)
-enum : int { RL_ORTH = 0, RL_S = 1, RL_A12 = 2, RL_UPDATE = 3, RL_T = 4 };
+enum : int { RL_ORTH = 0, RL_S = 1, RL_A12 = 2, RL_UPDATE = 3, RL_T = 4, RL_E = 5 };
 using LogKey = std::array<int, 5>;
 
 }  // namespace
 }  // namespace hqh
 
 struct hodlr_qr_s {
-  Tree t;
+  Tree t;   // A's partition (rows and columns)
+  Tree tc;  // the square partition of the columns (T; R on its pivot rows)
   int cap = 0;
   DMem mem;
   LeafSet leaves, tleaves;
   BlockSet up, lo, tup;
-  int* ranks = nullptr;  // up | lo | t | scalars
+  // rectangular A (Sec. 6): Y's upper blocks (left factor E_L over the rows of
+  // the first child, zero on its pivot rows; right factor E_R, then Y~_E)
+  BlockSet yup;
+  // R on the pivot rows (the first n_j rows of each leaf) as a square HODLR view
+  // of the storage of A's leaves and upper blocks
+  BlockSet rset;
+  LeafSet rleaves;
+  int* ranks = nullptr;  // up | lo | t | yup | scalars
   double anorm = 0, eps = 0, tauA = 0, tauT = 0;
   double anorm_in = 0;     // |A|_2 given by the caller (<= 0: estimated)
   double* scal = nullptr;  // device: |A|_2, eps*|A|_2, eps
@@ -724,7 +737,10 @@ struct hodlr_qr_s {
   // temporaries of the node steps (n x cap each)
   double *SL = nullptr, *SR = nullptr, *SLt = nullptr, *Z1 = nullptr, *Z2 = nullptr, *Z4 = nullptr,
          *SRW = nullptr, *TL = nullptr, *TR = nullptr, *Z5 = nullptr, *Wm = nullptr, *Mg = nullptr;
-  double *X1 = nullptr, *X2 = nullptr;   // n x 2 vectors of the norm estimate
+  double *X1 = nullptr, *X2 = nullptr;   // vectors of the norm estimate (n + rows, n)
+  // rectangular: pivot and free rows of [U12 | Y_A11 S_L] gathered, E_L compact, Y_A11^T E_L
+  double *PU = nullptr, *PZ = nullptr, *FU = nullptr, *FZ = nullptr, *FE = nullptr, *Z6 = nullptr;
+  int* pivrun = nullptr;  // device: per leaf (first row, first column, n_j) of its pivot rows
   std::shared_ptr<Batch> batch;          // the schedule (dropped once the factors are final)
   int64_t n_launch = 0, n_trunc = 0;     // counts of that schedule per factorisation
   // rank log: (input width, kept rank) per recompression, keys on the host
@@ -735,14 +751,18 @@ struct hodlr_qr_s {
   std::unique_ptr<CachedPlan> applyp[2], solvep;
   // borrowed views of the factors (hodlr_qr_factor)
   std::unique_ptr<hodlr_s> vY, vT, vR;
+  bool rect() const { return t.rect(); }
   HView view_gen() const { return HView{t.L, up.dview, lo.dview, leaves.dview, LEAF_FULL}; }
-  HView view_y() const { return HView{t.L, nullptr, lo.dview, leaves.dview, LEAF_UNIT_LOWER}; }
+  HView view_y() const {
+    return HView{t.L, rect() ? yup.dview : nullptr, lo.dview, leaves.dview, LEAF_UNIT_LOWER};
+  }
   HView view_t() const { return HView{t.L, tup.dview, nullptr, tleaves.dview, LEAF_UPPER}; }
-  HView view_r() const { return HView{t.L, up.dview, nullptr, leaves.dview, LEAF_UPPER}; }
+  HView view_r() const { return HView{t.L, rset.dview, nullptr, rleaves.dview, LEAF_UPPER}; }
   int* rank_up(int v) { return ranks + v; }
   int* rank_lo(int v) { return ranks + (1 << t.L) + v; }
   int* rank_t(int v) { return ranks + 2 * (1 << t.L) + v; }
-  int* rank_s() { return ranks + 3 * (1 << t.L); }
+  int* rank_e(int v) { return ranks + 3 * (1 << t.L) + v; }
+  int* rank_s() { return ranks + 4 * (1 << t.L); }
 };
 
 namespace hqh {
@@ -807,9 +827,10 @@ int64_t count_truncs(const Tree& t) {
     void go(int v, int q) {
       if (t.is_leaf(v)) return;
       const int Rc = 2 * v + 1;
-      c += (1 + q) + 1 + 2 * (int64_t)((t.subtree_size(Rc) - 1) / 2) + std::max(1, q);
+      const int e = t.mr(2 * v) > t.m(2 * v) ? 1 : 0;  // E group (rectangular)
+      c += (1 + q) + 1 + e + 2 * (int64_t)((t.subtree_size(Rc) - 1) / 2) + std::max(1, q + e);
       go(2 * v, q + 1);
-      go(Rc, q);
+      go(Rc, q + e);
     }
   } r{t, c};
   r.go(1, 0);
@@ -822,15 +843,23 @@ int64_t count_truncs(const Tree& t) {
 struct QRBuilder {
   std::vector<hodlr_qr_s*> Fs;
   Plan& P;
-  const Tree& t;
+  const Tree& t;   // A's partition
+  const Tree& tc;  // the square partition of the columns
   int cap;
   int plant = 0;  // hazard-checker self test: see hodlr_plan_check
   QRBuilder(const std::vector<hodlr_qr_s*>& fs, Plan& plan)
-      : Fs(fs), P(plan), t(fs[0]->t), cap(fs[0]->cap) {}
+      : Fs(fs), P(plan), t(fs[0]->t), tc(fs[0]->tc), cap(fs[0]->cap) {}
 
-  // right factor slice of ancestor g's lower block over node x's columns
-  double* gslice(hodlr_qr_s& F, int g, int x) { return F.lo.hview[g].V + (t.lo[x] - t.lo[2 * g]); }
-  int gld(int g) { return (int)t.m(2 * g); }
+  // Row groups of the stacked columns.  A group g > 0 is the lower block of
+  // node g (rows below it, right factor over the columns of 2g); g < 0 is the
+  // E group of node -g (free rows of its first child, right factor over the
+  // columns of its second child; rectangular matrices only).
+  const HBlk& gblk(hodlr_qr_s& F, int g) { return g > 0 ? F.lo.hview[g] : F.yup.hview[-g]; }
+  int gchild(int g) { return g > 0 ? 2 * g : 2 * (-g) + 1; }
+  int* grank(hodlr_qr_s& F, int g) { return g > 0 ? F.rank_lo(g) : F.rank_e(-g); }
+  // right factor slice of group g over node x's columns
+  double* gslice(hodlr_qr_s& F, int g, int x) { return gblk(F, g).V + (t.lo[x] - t.lo[gchild(g)]); }
+  int gld(int g) { return (int)t.m(gchild(g)); }
 
   void leaf(int v, const std::vector<int>& groups) {
     const int j = v - t.nleaf();
@@ -841,6 +870,7 @@ struct QRBuilder {
       LeafJob J{};
       J.D = F.leaves.hview[j].D;
       J.m = m;
+      J.mr = (int)t.mr(v);
       J.Tleaf = F.tleaves.hview[j].D;
       J.ws = F.work.leaf;
       J.err = F.work.err;
@@ -848,7 +878,7 @@ struct QRBuilder {
       J.ngroups = (int)groups.size();
       for (size_t i = 0; i < groups.size(); ++i) {
         const int g = groups[i];
-        J.g[i] = LeafGroup{F.lo.hview[g].V, gld(g), (int)(t.lo[v] - t.lo[2 * g]), F.rank_lo(g)};
+        J.g[i] = LeafGroup{gblk(F, g).V, gld(g), (int)(t.lo[v] - t.lo[gchild(g)]), grank(F, g)};
       }
       P.lj.push_back(J);
     }
@@ -866,6 +896,25 @@ struct QRBuilder {
       if (cnt > 0) leafop(OP_LUPDATE, cnt, p);
     }
     leafop(OP_LSCATTER, m, 0);
+  }
+
+  // Row runs of node x's pivot rows (the first n_j rows of each of its leaves,
+  // packed in column order) and free rows (the others, packed in row order):
+  // (row within x, row in the packed array, length).
+  void runs(int x, std::vector<std::array<int, 3>>& piv, std::vector<std::array<int, 3>>& fre) {
+    std::vector<int> lv;
+    t.subtree_leaves(x, lv);
+    int fpos = 0;
+    for (int j : lv) {
+      const int h = t.nleaf() + j;
+      const int r = (int)(t.rlo[h] - t.rlo[x]), c = (int)(t.lo[h] - t.lo[x]);
+      const int nj = (int)t.m(h), mj = (int)t.mr(h);
+      piv.push_back({r, c, nj});
+      if (mj > nj) {
+        fre.push_back({r + nj, fpos, mj - nj});
+        fpos += mj - nj;
+      }
+    }
   }
 
   TrSpec trspec(hodlr_qr_s& F, Seg l0, Seg l1, Seg r0, Seg r1, int mL, int mR, const double* tau,
@@ -899,13 +948,18 @@ struct QRBuilder {
   // are only read again by the parent's S = T1^T S~ (main chain: it waits for
   // the returned event) or by the parent's own T steps (later on lane 1).
   // Returns the event signalled once T of the subtree is complete, -1 for a leaf.
+  // Sizes: n* are columns, m* rows (equal for a square matrix).  A rectangular
+  // matrix (Sec. 6) whose first child has free rows also gets an E group here.
   int node(int v, const std::vector<int>& groups) {
     if (t.is_leaf(v)) {
       leaf(v, groups);
       return -1;
     }
     const int Lc = 2 * v, Rc = 2 * v + 1;
-    const int mL = (int)t.m(Lc), mR = (int)t.m(Rc);
+    const int nL = (int)t.m(Lc), nR = (int)t.m(Rc);
+    const int mL = (int)t.mr(Lc), mR = (int)t.mr(Rc);
+    const bool has_e = t.mr(Lc) > t.m(Lc);  // free rows in the first child
+    const int fL = mL - nL;
     const int klo = (int)t.lo[v], khi = (int)t.hi[v];
     // first block column: hQR(A11, A21, [B_R1; C1])
     std::vector<int> gl;
@@ -919,9 +973,9 @@ struct QRBuilder {
       hodlr_qr_s& F = *Fp;
       const HBlk& A12 = F.up.hview[v];
       const HBlk& A21 = F.lo.hview[v];
-      MmSpec a = mmspec(F.view_y(), false, true, Lc, 1, A12.U, mL, F.rank_up(v), F.Z1, mL, 1.0, 0.0, 1, 0,
+      MmSpec a = mmspec(F.view_y(), F.rect(), true, Lc, 1, A12.U, mL, F.rank_up(v), F.Z1, nL, 1.0, 0.0, 1, 0,
                         F.work.fc);
-      MmSpec b = mmspec(F.view_gen(), true, true, Rc, 1, A21.U, mR, F.rank_lo(v), F.Z2, mR, 1.0, 0.0, 0, 0,
+      MmSpec b = mmspec(F.view_gen(), true, true, Rc, 1, A21.U, mR, F.rank_lo(v), F.Z2, nR, 1.0, 0.0, 0, 0,
                         F.work.fc);
       a.rld = b.rld = cap;
       mms.push_back(a);
@@ -935,8 +989,8 @@ struct QRBuilder {
       const HBlk& A21 = F.lo.hview[v];
       int* k12 = F.rank_up(v);
       int* k21 = F.rank_lo(v);
-      trs.push_back(trspec(F, mkseg(F.Z1, mL, k12), mkseg(A21.V, mL, k21), mkseg(A12.V, mR, k12),
-                           mkseg(F.Z2, mR, k21), mL, mR, F.scal + 1, F.SL, F.SR, mL, mR, F.rank_s(), FC_TRUNC,
+      trs.push_back(trspec(F, mkseg(F.Z1, nL, k12), mkseg(A21.V, nL, k21), mkseg(A12.V, nR, k12),
+                           mkseg(F.Z2, nR, k21), nL, nR, F.scal + 1, F.SL, F.SR, nL, nR, F.rank_s(), FC_TRUNC,
                            LogKey{RL_S, klo, khi, 0, 0}));
     }
     P.trunc(trs);
@@ -946,9 +1000,9 @@ struct QRBuilder {
       for (hodlr_qr_s* Fp : Fs) {
         hodlr_qr_s& F = *Fp;
         int* rS = F.rank_s();
-        trs.push_back(trspec(F, mkseg(F.SL, mL, rS), mkseg(gslice(F, g, Lc), gld(g), F.rank_lo(g)),
-                             mkseg(F.SR, mR, rS), mkseg(gslice(F, g, Rc), gld(g), F.rank_lo(g)), mL, mR,
-                             F.scal + 1, F.SL, F.SR, mL, mR, rS, FC_TRUNC,
+        trs.push_back(trspec(F, mkseg(F.SL, nL, rS), mkseg(gslice(F, g, Lc), gld(g), grank(F, g)),
+                             mkseg(F.SR, nR, rS), mkseg(gslice(F, g, Rc), gld(g), grank(F, g)), nL, nR,
+                             F.scal + 1, F.SL, F.SR, nL, nR, rS, FC_TRUNC,
                              LogKey{RL_S, klo, khi, 1 + (int)gi, 0}));
       }
       P.trunc(trs);
@@ -958,17 +1012,17 @@ struct QRBuilder {
     mms.clear();
     for (hodlr_qr_s* Fp : Fs) {
       hodlr_qr_s& F = *Fp;
-      MmSpec a = mmspec(F.view_t(), true, false, Lc, 1, F.SL, mL, F.rank_s(), F.SLt, mL, 1.0, 0.0, 1, 0,
+      MmSpec a = mmspec(F.view_t(), true, false, Lc, 1, F.SL, nL, F.rank_s(), F.SLt, nL, 1.0, 0.0, 1, 0,
                         F.work.fc);
       a.rld = cap;
       mms.push_back(a);
     }
-    P.mm(t, mms);
+    P.mm(tc, mms);
     // Y_A11 S_L for the new upper block
     mms.clear();
     for (hodlr_qr_s* Fp : Fs) {
       hodlr_qr_s& F = *Fp;
-      MmSpec a = mmspec(F.view_y(), false, true, Lc, 0, F.SLt, mL, F.rank_s(), F.Z4, mL, 1.0, 0.0, 1, 0,
+      MmSpec a = mmspec(F.view_y(), F.rect(), true, Lc, 0, F.SLt, nL, F.rank_s(), F.Z4, mL, 1.0, 0.0, 1, 0,
                         F.work.fc);
       a.rld = cap;
       mms.push_back(a);
@@ -981,39 +1035,81 @@ struct QRBuilder {
         hodlr_qr_s& F = *Fp;
         const HBlk& A21 = F.lo.hview[v];
         int* rS = F.rank_s();
-        red.push_back(GSpec{gjob(1, 0, 0, F.rank_lo(v), 0, rS, mL, nullptr, A21.V, mL, F.SLt, mL, F.Wm, KCAP,
+        red.push_back(GSpec{gjob(1, 0, 0, F.rank_lo(v), 0, rS, nL, nullptr, A21.V, nL, F.SLt, nL, F.Wm, KCAP,
                                  1.0, 0.0, FC_DENSE, F.work.fc),
-                            KCAP, KCAP, mL});
+                            KCAP, KCAP, nL});
         for (size_t i = 0; i < groups.size(); ++i) {
           const int g = groups[i];
-          red.push_back(GSpec{gjob(1, 0, 0, rS, 0, F.rank_lo(g), mL, nullptr, F.SLt, mL, gslice(F, g, Lc),
+          red.push_back(GSpec{gjob(1, 0, 0, rS, 0, grank(F, g), nL, nullptr, F.SLt, nL, gslice(F, g, Lc),
                                    gld(g), F.Mg + i * KCAP * KCAP, KCAP, 1.0, 0.0, FC_DENSE, F.work.fc),
-                              KCAP, KCAP, mL});
+                              KCAP, KCAP, nL});
         }
       }
       P.gemm_red(red);
     }
-    // SRW = S_R W^T (mR x k21);  C_2g -= S_R M_g  (B^_R2 and C^2 of the update)
+    // SRW = S_R W^T (nR x k21);  C_2g -= S_R M_g  (B^_R2 and C^2 of the update)
     {
       std::vector<GSpec> tall;
       for (hodlr_qr_s* Fp : Fs) {
         hodlr_qr_s& F = *Fp;
         int* rS = F.rank_s();
-        tall.push_back(GSpec{gjob(0, 1, mR, nullptr, 0, F.rank_lo(v), 0, rS, F.SR, mR, F.Wm, KCAP, F.SRW, mR,
+        tall.push_back(GSpec{gjob(0, 1, nR, nullptr, 0, F.rank_lo(v), 0, rS, F.SR, nR, F.Wm, KCAP, F.SRW, nR,
                                   1.0, 0.0, FC_DENSE, F.work.fc),
-                             mR, cap, 0});
+                             nR, cap, 0});
         for (size_t i = 0; i < groups.size(); ++i) {
           const int g = groups[i];
-          tall.push_back(GSpec{gjob(0, 0, mR, nullptr, 0, F.rank_lo(g), 0, rS, F.SR, mR,
+          tall.push_back(GSpec{gjob(0, 0, nR, nullptr, 0, grank(F, g), 0, rS, F.SR, nR,
                                     F.Mg + i * KCAP * KCAP, KCAP, gslice(F, g, Rc), gld(g), -1.0, 1.0,
                                     FC_DENSE, F.work.fc),
-                               mR, cap, 0});
+                               nR, cap, 0});
         }
       }
       P.gemm_tall(tall);
     }
-    // A^12 = T([U12 | -Y_A11 S_L] [V12 | S_R]^T) and A^22 = A22 -_H U21 W S_R^T:
-    // every off-diagonal block of the trailing sub-HODLR, one batch
+    // Rectangular: A^12 = U12 V12^T - (Y_A11 S_L) S_R^T splits by rows.  Its
+    // free rows are compressed to E = E_L E_R (E_L into Y's upper block of v,
+    // E_R joins the second block column's groups); its pivot rows become R's
+    // upper block (below).
+    std::vector<std::array<int, 3>> prun, frun;
+    if (has_e) {
+      runs(Lc, prun, frun);
+      std::vector<RowJob> g1;
+      for (hodlr_qr_s* Fp : Fs) {
+        hodlr_qr_s& F = *Fp;
+        const HBlk& A12 = F.up.hview[v];
+        for (const auto& r : prun) {
+          g1.push_back(RowJob{A12.U, mL, F.PU, nL, r[0], r[1], r[2], F.rank_up(v), 0});
+          g1.push_back(RowJob{F.Z4, mL, F.PZ, nL, r[0], r[1], r[2], F.rank_s(), 0});
+        }
+        for (const auto& r : frun) {
+          g1.push_back(RowJob{A12.U, mL, F.FU, fL, r[0], r[1], r[2], F.rank_up(v), 0});
+          g1.push_back(RowJob{F.Z4, mL, F.FZ, fL, r[0], r[1], r[2], F.rank_s(), 0});
+        }
+      }
+      rows(g1);
+      trs.clear();
+      for (hodlr_qr_s* Fp : Fs) {
+        hodlr_qr_s& F = *Fp;
+        const HBlk& A12 = F.up.hview[v];
+        const HBlk& E = F.yup.hview[v];
+        int* k12 = F.rank_up(v);
+        int* rS = F.rank_s();
+        trs.push_back(trspec(F, mkseg(F.FU, fL, k12), mkseg(F.FZ, fL, rS, -1.0), mkseg(A12.V, nR, k12),
+                             mkseg(F.SR, nR, rS), fL, nR, F.scal + 1, F.FE, E.V, fL, nR, F.rank_e(v), FC_TRUNC,
+                             LogKey{RL_E, klo, khi, 0, 0}));
+      }
+      P.trunc(trs);
+      std::vector<RowJob> g2;
+      for (hodlr_qr_s* Fp : Fs) {
+        hodlr_qr_s& F = *Fp;
+        const HBlk& E = F.yup.hview[v];
+        for (const auto& r : frun) g2.push_back(RowJob{F.FE, fL, E.U, mL, r[1], r[0], r[2], F.rank_e(v), 0});
+      }
+      rows(g2);
+    }
+    // A^12 = T([U12 | -Y_A11 S_L] [V12 | S_R]^T) (rectangular: its pivot rows)
+    // and A^22 = A22 -_H U21 W S_R^T: every off-diagonal block of the trailing
+    // sub-HODLR, one batch
     {
       std::vector<int> sub;
       t.subtree_internal(Rc, sub);
@@ -1028,70 +1124,93 @@ struct QRBuilder {
         int* k12 = F.rank_up(v);
         int* k21 = F.rank_lo(v);
         int* rS = F.rank_s();
-        sp.push_back(trspec(F, mkseg(A12.U, mL, k12), mkseg(F.Z4, mL, rS, -1.0), mkseg(A12.V, mR, k12),
-                            mkseg(F.SR, mR, rS), mL, mR, F.scal + 1, A12.U, A12.V, mL, mR, k12, FC_TRUNC,
-                            LogKey{RL_A12, klo, khi, 0, 0}));
+        if (has_e)
+          sp.push_back(trspec(F, mkseg(F.PU, nL, k12), mkseg(F.PZ, nL, rS, -1.0), mkseg(A12.V, nR, k12),
+                              mkseg(F.SR, nR, rS), nL, nR, F.scal + 1, A12.U, A12.V, mL, nR, k12, FC_TRUNC,
+                              LogKey{RL_A12, klo, khi, 0, 0}));
+        else
+          sp.push_back(trspec(F, mkseg(A12.U, mL, k12), mkseg(F.Z4, mL, rS, -1.0), mkseg(A12.V, nR, k12),
+                              mkseg(F.SR, nR, rS), mL, nR, F.scal + 1, A12.U, A12.V, mL, nR, k12, FC_TRUNC,
+                              LogKey{RL_A12, klo, khi, 0, 0}));
         for (int u : sub) {
           for (int kind = 0; kind < 2; ++kind) {
             const HBlk& b = kind == 0 ? F.up.hview[u] : F.lo.hview[u];
             int* kb = kind == 0 ? F.rank_up(u) : F.rank_lo(u);
-            const int64_t ri = b.r0 - t.lo[Rc], cj = b.c0 - t.lo[Rc];
+            const int64_t ri = b.r0 - t.rlo[Rc], cj = b.c0 - t.lo[Rc];
             sp.push_back(trspec(F, mkseg(b.U, b.ldU, kb), mkseg(A21.U + ri, mR, k21), mkseg(b.V, b.ldV, kb),
-                                mkseg(F.SRW + cj, mR, k21, -1.0), b.rows, b.cols, F.scal + 1, b.U, b.V,
+                                mkseg(F.SRW + cj, nR, k21, -1.0), b.rows, b.cols, F.scal + 1, b.U, b.V,
                                 b.ldU, b.ldV, kb, FC_TRUNC, LogKey{RL_UPDATE, klo, khi, (int)b.r0, (int)b.c0}));
           }
         }
-        // leaves of the trailing part: D -= U21(I) (S_R W^T)(I)^T
+        // leaves of the trailing part: D -= U21(I) (S_R W^T)(J)^T
         for (int j : leaves) {
           const int lv = t.nleaf() + j;
-          const int m = (int)t.m(lv);
-          const int64_t ri = t.lo[lv] - t.lo[Rc];
-          lu.push_back(GSpec{gjob(0, 1, m, nullptr, m, nullptr, 0, k21, A21.U + ri, mR, F.SRW + ri, mR,
-                                  F.leaves.hview[j].D, m, -1.0, 1.0, FC_UPDATE, F.work.fc),
-                             m, m, 0});
+          const int mj = (int)t.mr(lv), nj = (int)t.m(lv);
+          const int64_t ri = t.rlo[lv] - t.rlo[Rc], ci = t.lo[lv] - t.lo[Rc];
+          lu.push_back(GSpec{gjob(0, 1, mj, nullptr, nj, nullptr, 0, k21, A21.U + ri, mR, F.SRW + ci, nR,
+                                  F.leaves.hview[j].D, mj, -1.0, 1.0, FC_UPDATE, F.work.fc),
+                             mj, nj, 0});
         }
       }
       P.trunc(sp);
       P.gemm_tall(lu);
     }
-    // second block column: hQR(A^22, [], [B^_R2; C^2])
-    node(Rc, groups);
+    // second block column: hQR(A^22, [], [B^_R2; C^2] (; E_R))
+    std::vector<int> gr = groups;
+    if (has_e) gr.push_back(-v);
+    node(Rc, gr);
     const int evM = P.signal();
     P.lane = 1;
     P.wait(evM);
-    // T~12 = T_eps(Y_A21^T Y_A22 + sum over groups of Y_g1^T Y_g2)
+    // T~12 = T_eps(Y_1^T Y_2): terms over the rows top down: (rectangular) the
+    // free rows of the first child, Y_A11^T E_L Y~_E; Y_A21^T Y_A22; the groups
     mms.clear();
     for (hodlr_qr_s* Fp : Fs) {
       hodlr_qr_s& F = *Fp;
-      MmSpec a = mmspec(F.view_y(), false, true, Rc, 1, F.lo.hview[v].U, mR, F.rank_lo(v), F.Z5, mR, 1.0, 0.0,
-                        1, 0, F.work.fc);
+      MmSpec a = mmspec(F.view_y(), F.rect(), true, Rc, 1, F.lo.hview[v].U, mR, F.rank_lo(v), F.Z5, nR, 1.0,
+                        0.0, 1, 0, F.work.fc);
       a.rld = cap;
       mms.push_back(a);
+      if (has_e) {
+        MmSpec e = mmspec(F.view_y(), true, true, Lc, 1, F.yup.hview[v].U, mL, F.rank_e(v), F.Z6, nL, 1.0, 0.0,
+                          1, 0, F.work.fc);
+        e.rld = cap;
+        mms.push_back(e);
+      }
     }
     P.mm(t, mms);
-    const size_t nterm = groups.empty() ? 1 : groups.size();
-    for (size_t i = 0; i < nterm; ++i) {
+    struct Term {
+      Seg l, r;
+    };
+    const size_t nterm = (has_e ? 1 : 0) + 1 + groups.size();
+    const size_t nchain = std::max<size_t>(1, nterm - 1);
+    for (size_t i = 0; i < nchain; ++i) {
       trs.clear();
       for (hodlr_qr_s* Fp : Fs) {
         hodlr_qr_s& F = *Fp;
         const HBlk& A21 = F.lo.hview[v];
         int* k21 = F.rank_lo(v);
         int* rt = F.rank_t(v);
+        std::vector<Term> terms;
+        if (has_e)
+          terms.push_back(Term{mkseg(F.Z6, nL, F.rank_e(v)), mkseg(F.yup.hview[v].V, nR, F.rank_e(v))});
+        terms.push_back(Term{mkseg(A21.V, nL, k21), mkseg(F.Z5, nR, k21)});
+        for (int g : groups)
+          terms.push_back(Term{mkseg(gslice(F, g, Lc), gld(g), grank(F, g)),
+                               mkseg(gslice(F, g, Rc), gld(g), grank(F, g))});
         // self test of the hazard checker: node 2's first T~12 recompression
         // writes into S~'s buffer, which the root's main chain uses meanwhile
         double* outL = (plant && v == 2 && i == 0) ? F.SL : F.TL;
-        const Seg l0 = i == 0 ? mkseg(A21.V, mL, k21) : mkseg(F.TL, mL, rt);
-        const Seg r0 = i == 0 ? mkseg(F.Z5, mR, k21) : mkseg(F.TR, mR, rt);
+        const Seg l0 = i == 0 ? terms[0].l : mkseg(F.TL, nL, rt);
+        const Seg r0 = i == 0 ? terms[0].r : mkseg(F.TR, nR, rt);
+        const size_t nx = i == 0 ? 1 : i + 1;  // the term added by this recompression
         const LogKey key{RL_T, klo, khi, (int)i, 0};
-        if (groups.empty()) {
-          trs.push_back(trspec(F, l0, noseg(), r0, noseg(), mL, mR, F.scal + 2, outL, F.TR, mL, mR, rt,
+        if (nx >= terms.size())
+          trs.push_back(trspec(F, l0, noseg(), r0, noseg(), nL, nR, F.scal + 2, outL, F.TR, nL, nR, rt, FC_TRUNC,
+                               key));
+        else
+          trs.push_back(trspec(F, l0, terms[nx].l, r0, terms[nx].r, nL, nR, F.scal + 2, outL, F.TR, nL, nR, rt,
                                FC_TRUNC, key));
-        } else {
-          const int g = groups[i];
-          trs.push_back(trspec(F, l0, mkseg(gslice(F, g, Lc), gld(g), F.rank_lo(g)), r0,
-                               mkseg(gslice(F, g, Rc), gld(g), F.rank_lo(g)), mL, mR, F.scal + 2, outL, F.TR,
-                               mL, mR, rt, FC_TRUNC, key));
-        }
       }
       P.trunc(trs);
     }
@@ -1101,16 +1220,22 @@ struct QRBuilder {
       hodlr_qr_s& F = *Fp;
       const HBlk& T12 = F.tup.hview[v];
       int* rt = F.rank_t(v);
-      MmSpec a = mmspec(F.view_t(), true, false, Lc, 0, F.TL, mL, rt, T12.U, mL, -1.0, 0.0, 1, 0, F.work.fc);
-      MmSpec b = mmspec(F.view_t(), true, false, Rc, 1, F.TR, mR, rt, T12.V, mR, 1.0, 0.0, 1, 0, F.work.fc);
+      MmSpec a = mmspec(F.view_t(), true, false, Lc, 0, F.TL, nL, rt, T12.U, nL, -1.0, 0.0, 1, 0, F.work.fc);
+      MmSpec b = mmspec(F.view_t(), true, false, Rc, 1, F.TR, nR, rt, T12.V, nR, 1.0, 0.0, 1, 0, F.work.fc);
       a.rld = b.rld = cap;
       mms.push_back(a);
       mms.push_back(b);
     }
-    P.mm(t, mms);
+    P.mm(tc, mms);
     const int evT = P.signal();
     P.lane = 0;
     return evT;
+  }
+
+  void rows(const std::vector<RowJob>& items) {
+    const int first = (int)P.rj.size();
+    P.rj.insert(P.rj.end(), items.begin(), items.end());
+    P.push(Op{OP_ROWS, first, (int)items.size()});
   }
 
   void build() {
@@ -1190,9 +1315,10 @@ hodlr_status reset_factor(hodlr_qr_s& F, const hodlr_s& A, hipStream_t st) {
 // the borrowed views of F's factors (hodlr_qr_factor)
 void make_views(hodlr_qr_s& F) {
   const int nn = 1 << F.t.L;
-  auto mk = [&](const LeafSet& L, const BlockSet* up, const BlockSet* lo, int* rup, int* rlo, int kind) {
+  auto mk = [&](const LeafSet& L, const BlockSet* up, const BlockSet* lo, int* rup, int* rlo, int kind,
+                const Tree& tree) {
     auto V = std::make_unique<hodlr_s>();
-    V->t = F.t;
+    V->t = tree;
     V->cap = F.cap;
     V->leaves = L;
     if (up) V->up = *up;
@@ -1205,19 +1331,20 @@ void make_views(hodlr_qr_s& F) {
     V->borrowed = true;
     return V;
   };
-  F.vY = mk(F.leaves, nullptr, &F.lo, nullptr, F.ranks + nn, LEAF_UNIT_LOWER);
-  F.vT = mk(F.tleaves, &F.tup, nullptr, F.ranks + 2 * nn, nullptr, LEAF_UPPER);
-  F.vR = mk(F.leaves, &F.up, nullptr, F.ranks, nullptr, LEAF_UPPER);
+  F.vY = mk(F.leaves, F.rect() ? &F.yup : nullptr, &F.lo, F.rect() ? F.ranks + 3 * nn : nullptr, F.ranks + nn,
+            LEAF_UNIT_LOWER, F.t);
+  F.vT = mk(F.tleaves, &F.tup, nullptr, F.ranks + 2 * nn, nullptr, LEAF_UPPER, F.tc);
+  F.vR = mk(F.rleaves, &F.rset, nullptr, F.ranks, nullptr, LEAF_UPPER, F.tc);
 }
 
 // device storage of the factors of A (no schedule yet)
 hodlr_status make_storage(const hodlr_s& A, double eps, double anorm, hipStream_t st,
                           std::unique_ptr<hodlr_qr_s>& out) {
-  if (A.t.rect()) return fail(HODLR_EINVAL, "the QR of a rectangular HODLR matrix is not available yet");
   auto F = std::make_unique<hodlr_qr_s>();
   F->mem.zero = true;
   F->mem.stream = st;
   F->t = A.t;
+  F->tc = A.t.square();
   F->cap = A.cap;
   F->anorm = anorm;
   F->anorm_in = anorm;
@@ -1226,25 +1353,61 @@ hodlr_status make_storage(const hodlr_s& A, double eps, double anorm, hipStream_
   F->tauT = eps;
   const Tree& t = F->t;
   if (t.L > MAXGROUPS) return fail(HODLR_EINVAL, "too many levels");
+  const Tree& tc = F->tc;
   const int nn = 1 << t.L;
   TRY(F->mem.alloc(&F->scal, 8));
-  TRY(F->mem.alloc(&F->ranks, 3 * (size_t)nn + 8));
+  TRY(F->mem.alloc(&F->ranks, 4 * (size_t)nn + 8));
   TRY(make_leaves(F->mem, t, F->leaves));
-  TRY(make_leaves(F->mem, t, F->tleaves));
+  TRY(make_leaves(F->mem, tc, F->tleaves));
   TRY(make_blocks(F->mem, t, F->cap, BK_UP, F->ranks, F->up));
   TRY(make_blocks(F->mem, t, F->cap, BK_LO, F->ranks + nn, F->lo));
-  TRY(make_blocks(F->mem, t, F->cap, BK_UP, F->ranks + 2 * nn, F->tup));
+  TRY(make_blocks(F->mem, tc, F->cap, BK_UP, F->ranks + 2 * nn, F->tup));
+  if (F->rect()) {
+    TRY(make_blocks(F->mem, t, F->cap, BK_UP, F->ranks + 3 * nn, F->yup));
+    TRY(upload(F->mem, &F->yup.dview, F->yup.hview, st));
+  }
+  // R's view: upper blocks over the pivot rows of the first child (the first
+  // n_L rows of the block's left factor), leaves' top n_j x n_j
+  F->rset = F->up;
+  for (int v = 1; v < nn; ++v) {
+    HBlk& b = F->rset.hview[v];
+    b.rows = (int)tc.m(2 * v);
+    b.r0 = tc.lo[2 * v];
+  }
+  F->rleaves = F->leaves;
+  for (int j = 0; j < nn; ++j) {
+    HLeaf& l = F->rleaves.hview[j];
+    l.m = (int)tc.m(nn + j);
+    l.r0 = tc.lo[nn + j];
+  }
   TRY(upload(F->mem, &F->up.dview, F->up.hview, st));
   TRY(upload(F->mem, &F->lo.dview, F->lo.hview, st));
   TRY(upload(F->mem, &F->tup.dview, F->tup.hview, st));
   TRY(upload(F->mem, &F->leaves.dview, F->leaves.hview, st));
   TRY(upload(F->mem, &F->tleaves.dview, F->tleaves.hview, st));
+  TRY(upload(F->mem, &F->rset.dview, F->rset.hview, st));
+  TRY(upload(F->mem, &F->rleaves.dview, F->rleaves.hview, st));
   const size_t nc = (size_t)t.n * F->cap;
-  for (double** p : {&F->SL, &F->SR, &F->SLt, &F->Z1, &F->Z2, &F->Z4, &F->SRW, &F->TL, &F->TR, &F->Z5})
+  for (double** p : {&F->SL, &F->SR, &F->SLt, &F->Z1, &F->Z2, &F->SRW, &F->TL, &F->TR, &F->Z5})
     TRY(F->mem.alloc(p, nc));
+  TRY(F->mem.alloc(&F->Z4, (size_t)t.nr * F->cap));
+  if (F->rect()) {
+    const size_t fc = (size_t)std::max<int64_t>(1, t.nr - t.n) * F->cap;
+    for (double** p : {&F->PU, &F->PZ, &F->Z6}) TRY(F->mem.alloc(p, nc));
+    for (double** p : {&F->FU, &F->FZ, &F->FE}) TRY(F->mem.alloc(p, fc));
+  }
   TRY(F->mem.alloc(&F->Wm, (size_t)KCAP * KCAP));
   TRY(F->mem.alloc(&F->Mg, (size_t)KCAP * KCAP * (t.L + 1)));
-  TRY(F->mem.alloc(&F->X1, (size_t)t.n * 2));
+  TRY(F->mem.alloc(&F->X1, (size_t)(t.n + t.nr)));
+  {
+    std::vector<int> pr;
+    for (int j = 0; j < nn; ++j) {
+      pr.push_back((int)t.rlo[nn + j]);
+      pr.push_back((int)t.lo[nn + j]);
+      pr.push_back((int)t.m(nn + j));
+    }
+    TRY(upload(F->mem, &F->pivrun, pr, st));
+  }
   TRY(F->mem.alloc(&F->X2, (size_t)t.n));
   F->nlog_cap = count_truncs(t);
   TRY(F->mem.alloc(&F->rlog, 2 * (size_t)F->nlog_cap));
@@ -1513,6 +1676,15 @@ void merge_plans(const std::vector<const Plan*>& in, Plan& out, bool plant = fal
         m.count = njobs * nper;
         break;
       }
+      case OP_ROWS: {
+        m.first = (int)out.rj.size();
+        for (int g : grp) {
+          const Op& o = in[g]->ops[seq[g][h[g]]];
+          for (int i = 0; i < o.count; ++i) out.rj.push_back(in[g]->rj[o.first + i]);
+        }
+        m.count = (int)out.rj.size() - m.first;
+        break;
+      }
       case OP_FILL:
       case OP_NORMALIZE:
       case OP_SETSCAL: {
@@ -1607,15 +1779,15 @@ hodlr_status build_apply_plan(hodlr_qr_s& F, int trans, hipStream_t st, std::uni
   C->mem.stream = st;
   Plan& P = C->P;
   P.tune = tuning_for(F.t.n, F.cap);
-  MmSpec a = mmspec(F.view_y(), false, true, 1, 1, nullptr, 0, nullptr, nullptr, 0, 1.0, 0.0, 1);
+  MmSpec a = mmspec(F.view_y(), F.rect(), true, 1, 1, nullptr, 0, nullptr, nullptr, 0, 1.0, 0.0, 1);
   MmSpec b = mmspec(F.view_t(), true, false, 1, trans, nullptr, 0, nullptr, nullptr, 0, 1.0, 0.0, 1);
-  MmSpec c = mmspec(F.view_y(), false, true, 1, 0, nullptr, 0, nullptr, nullptr, 0, -1.0, 1.0, 1);
+  MmSpec c = mmspec(F.view_y(), F.rect(), true, 1, 0, nullptr, 0, nullptr, nullptr, 0, -1.0, 1.0, 1);
   a.xs = 0, a.zs = 1;
   b.xs = 1, b.zs = 2;
   c.xs = 2, c.zs = 0;
   a.rld = b.rld = c.rld = F.cap;
   P.mm(F.t, {a});
-  P.mm(F.t, {b});
+  P.mm(F.tc, {b});
   P.mm(F.t, {c});
   TRY(P.upload_all(C->mem, st));
   out = std::move(C);
@@ -1629,7 +1801,7 @@ hodlr_status build_solve_plan(hodlr_qr_s& F, hipStream_t st, std::unique_ptr<Cac
   auto C = std::make_unique<CachedPlan>();
   C->mem.stream = st;
   Plan& P = C->P;
-  const Tree& t = F.t;
+  const Tree& t = F.tc;  // R on its pivot rows: square on the column partition
   P.tune = tuning_for(t.n, F.cap);
   struct Rec {
     hodlr_qr_s& f;
@@ -1640,24 +1812,25 @@ hodlr_status build_solve_plan(hodlr_qr_s& F, hipStream_t st, std::unique_ptr<Cac
         const int j = v - t.nleaf();
         Op o{OP_TRSM};
         o.a0 = (int)t.m(v);
-        o.p0 = f.leaves.hview[j].D;
+        o.a1 = f.rleaves.hview[j].ld;
+        o.p0 = f.rleaves.hview[j].D;
         o.xs = 0;
         o.xoff = t.lo[v];
         P.push(o);
         return;
       }
       go(2 * v + 1);
-      const HBlk& b = f.up.hview[v];
+      const HBlk& b = f.rset.hview[v];
       const int mL = (int)t.m(2 * v), mR = (int)t.m(2 * v + 1);
       // Wt = V12^T x2 (k x s), c1 -= U12 Wt
-      GemmJob r = gjob(1, 0, 0, f.rank_up(v), 0, nullptr, mR, nullptr, b.V, mR, nullptr, 0, nullptr, KCAP, 1.0,
-                       0.0, FC_DENSE);
+      GemmJob r = gjob(1, 0, 0, f.rank_up(v), 0, nullptr, mR, nullptr, b.V, b.ldV, nullptr, 0, nullptr, KCAP,
+                       1.0, 0.0, FC_DENSE);
       r.bs_ = 0;
       r.boff = t.lo[2 * v + 1];
       r.cs_ = 1;
       P.gemm_red({GSpec{r, KCAP, KCAP, mR}});
-      GemmJob u = gjob(0, 0, mL, nullptr, 0, nullptr, 0, f.rank_up(v), b.U, mL, nullptr, KCAP, nullptr, 0, -1.0,
-                       1.0, FC_DENSE);
+      GemmJob u = gjob(0, 0, mL, nullptr, 0, nullptr, 0, f.rank_up(v), b.U, b.ldU, nullptr, KCAP, nullptr, 0,
+                       -1.0, 1.0, FC_DENSE);
       u.bs_ = 1;
       u.cs_ = 0;
       u.coff = t.lo[2 * v];
@@ -1950,7 +2123,7 @@ hodlr_status make_batch_set(const hodlr_t* const* A, int count, double eps, cons
     for (auto& g : S.groups) {
       const hodlr_s& B = *A[g[0]];
       if (B.t.L == A[i]->t.L && B.t.n == A[i]->t.n && B.cap == A[i]->cap && B.t.lo == A[i]->t.lo &&
-          B.t.hi == A[i]->t.hi) {
+          B.t.hi == A[i]->t.hi && B.t.rlo == A[i]->t.rlo && B.t.rhi == A[i]->t.rhi) {
         g.push_back(i);
         placed = true;
         break;
@@ -2087,7 +2260,7 @@ hodlr_status scratch_ptr(double** out) {
 // from the caller's allocator
 hodlr_status apply_q_impl(const hodlr_qr_s& F, int32_t trans, int64_t nrhs, double* X, int64_t ldx,
                           hipStream_t st, double* scratch, int64_t scratch_doubles) {
-  if (X == nullptr || nrhs < 0 || ldx < F.t.n) return fail(HODLR_EINVAL, "bad argument");
+  if (X == nullptr || nrhs < 0 || ldx < F.t.nr) return fail(HODLR_EINVAL, "bad argument");
   if (ldx > INT32_MAX) return fail(HODLR_EINVAL, "leading dimension too large");
   if (nrhs == 0) return HODLR_OK;
   const CachedPlan& C = *F.applyp[trans ? 1 : 0];
@@ -2153,7 +2326,7 @@ hodlr_status hodlr_qr_refactor(hodlr_qr_t* const* F, const hodlr_t* const* A, in
     const hodlr_s& a = *A[i];
     if (a.borrowed || a.leaf_kind != LEAF_FULL) return fail(HODLR_EINVAL, "a factor view in place of a matrix");
     if (a.t.L != F[i]->t.L || a.t.n != F[i]->t.n || a.cap != F[i]->cap || a.t.lo != F[i]->t.lo ||
-        a.t.hi != F[i]->t.hi)
+        a.t.hi != F[i]->t.hi || a.t.rlo != F[i]->t.rlo || a.t.rhi != F[i]->t.rhi)
       return fail(HODLR_EINVAL, "matrix " + std::to_string(i) + " differs in partition or rank_cap");
   }
   // every schedule is run once, over exactly the factorisations it was built for
@@ -2288,7 +2461,7 @@ hodlr_status hodlr_apply_q_noalloc(const hodlr_qr_t* F, int32_t trans, int64_t n
                                    hodlr_stream_t stream) {
   g_err.clear();
   if (F == nullptr) return fail(HODLR_EINVAL, "NULL factors");
-  if (X == nullptr || nrhs < 0 || ldx < F->t.n) return fail(HODLR_EINVAL, "bad argument");
+  if (X == nullptr || nrhs < 0 || ldx < F->t.nr) return fail(HODLR_EINVAL, "bad argument");
   double* buf = nullptr;
   TRY(scratch_ptr(&buf));
   return apply_q_impl(*F, trans, nrhs, X, ldx, (hipStream_t)stream, buf, NOALLOC_DOUBLES);
@@ -2297,6 +2470,7 @@ hodlr_status hodlr_apply_q_noalloc(const hodlr_qr_t* F, int32_t trans, int64_t n
 hodlr_status hodlr_solve(const hodlr_qr_t* F, int64_t nrhs, double* B, int64_t ldb, hodlr_stream_t stream) {
   g_err.clear();
   if (F == nullptr || B == nullptr || nrhs < 0 || ldb < F->t.n) return fail(HODLR_EINVAL, "bad argument");
+  if (F->rect()) return fail(HODLR_EINVAL, "a rectangular factorisation: use hodlr_lstsq");
   if (ldb > INT32_MAX) return fail(HODLR_EINVAL, "leading dimension too large");
   if (nrhs == 0) return HODLR_OK;
   hipStream_t st = (hipStream_t)stream;
@@ -2310,6 +2484,33 @@ hodlr_status hodlr_solve(const hodlr_qr_t* F, int64_t nrhs, double* B, int64_t l
   TRY(tmp.alloc(&cnt, (size_t)C.P.cnt_need()));
   double* base[2] = {B, wm};
   const int ld[2] = {(int)ldb, KCAP};
+  const bool percol[2] = {true, false};
+  return run_cached(C, st, 2, base, ld, percol, nrhs, SMAX, ws, cnt);
+}
+
+hodlr_status hodlr_lstsq(const hodlr_qr_t* F, int64_t nrhs, double* B, int64_t ldb, double* X, int64_t ldx,
+                         hodlr_stream_t stream) {
+  g_err.clear();
+  if (F == nullptr || B == nullptr || X == nullptr || nrhs < 0 || ldb < F->t.nr || ldx < F->t.n)
+    return fail(HODLR_EINVAL, "bad argument");
+  if (ldb > INT32_MAX || ldx > INT32_MAX) return fail(HODLR_EINVAL, "leading dimension too large");
+  if (nrhs == 0) return HODLR_OK;
+  hipStream_t st = (hipStream_t)stream;
+  TRY(apply_q_impl(*F, 1, nrhs, B, ldb, st, nullptr, 0));
+  // the pivot rows of Q^T B, in column order, into X
+  const int nl = F->t.nleaf();
+  k_pivot_rows<<<dim3(nl, (unsigned)std::min<int64_t>(nrhs, 65535)), NT_MM, 0, st>>>(
+      F->pivrun, nl, B, (int)ldb, X, (int)ldx, (int)nrhs);
+  HIPCHK(hipGetLastError());
+  const CachedPlan& C = *F->solvep;
+  CallMem tmp(st);
+  double *wm = nullptr, *ws = nullptr;
+  int* cnt = nullptr;
+  TRY(tmp.alloc(&wm, (size_t)KCAP * SMAX));
+  TRY(tmp.alloc(&ws, (size_t)std::max<int64_t>(1, C.P.ws_need())));
+  TRY(tmp.alloc(&cnt, (size_t)C.P.cnt_need()));
+  double* base[2] = {X, wm};
+  const int ld[2] = {(int)ldx, KCAP};
   const bool percol[2] = {true, false};
   return run_cached(C, st, 2, base, ld, percol, nrhs, SMAX, ws, cnt);
 }
@@ -2378,7 +2579,7 @@ hodlr_status hodlr_qr_info(const hodlr_qr_t* F, hodlr_qr_info_t* info) {
   g_err.clear();
   if (F == nullptr || info == nullptr) return fail(HODLR_EINVAL, "NULL argument");
   const int nn = 1 << F->t.L;
-  std::vector<int> r(3 * (size_t)nn + 8);
+  std::vector<int> r(4 * (size_t)nn + 8);
   HIPCHK(hipMemcpy(r.data(), F->ranks, r.size() * sizeof(int), hipMemcpyDeviceToHost));
   std::memset(info, 0, sizeof(*info));
   info->n = F->t.n;
@@ -2388,6 +2589,7 @@ hodlr_status hodlr_qr_info(const hodlr_qr_t* F, hodlr_qr_info_t* info) {
     info->max_rank_r = std::max(info->max_rank_r, r[v]);
     info->max_rank_y = std::max(info->max_rank_y, r[nn + v]);
     info->max_rank_t = std::max(info->max_rank_t, r[2 * nn + v]);
+    if (F->rect()) info->max_rank_y = std::max(info->max_rank_y, r[3 * nn + v]);  // Y's upper blocks
   }
   info->anorm = F->anorm;
   info->tau_a = F->tauA;

@@ -14,7 +14,7 @@ namespace hq {
 // form the Gram blocks Y_i^T Y_p and the T block of panel p-1:
 //   T[0:c_q, q] = -T[0:c_q, 0:c_q] (Y_{0:c_q}^T Y_q) T_qq     (eq. recqrcombined)
 __device__ __forceinline__ int leaf_rows(const LeafJob& J) {
-  int M = J.m;
+  int M = J.mr;
   for (int g = 0; g < J.ngroups; ++g) M += *J.g[g].rank;
   return M;
 }
@@ -34,10 +34,10 @@ __global__ void __launch_bounds__(NT_MM) k_leaf_gather(const LeafJob* __restrict
     if (c == 0 && threadIdx.x == 0) atomicOr(err, ERR_STACK);
     return;
   }
-  const int m = J.m;
+  const int mr = J.mr;  // rows of the leaf (its leading dimension)
   double* h = W.H + (int64_t)c * MAXSTACK;
-  for (int r = threadIdx.x; r < m; r += NT_MM) h[r] = J.D[r + (int64_t)c * m];
-  int off = m;
+  for (int r = threadIdx.x; r < mr; r += NT_MM) h[r] = J.D[r + (int64_t)c * mr];
+  int off = mr;
   for (int g = 0; g < J.ngroups; ++g) {
     const int k = *J.g[g].rank;
     const double* V = J.g[g].V + J.g[g].row0 + c;
@@ -421,13 +421,11 @@ __global__ void __launch_bounds__(NT_MM) k_leaf_scatter(const LeafJob* __restric
   const LeafWs W = J.ws;
   const int c = blockIdx.x % nper;
   if (c >= J.m) return;
-  const int m = J.m;
+  const int m = J.m, mr = J.mr;
   const double* h = W.H + (int64_t)c * MAXSTACK;
-  for (int r = threadIdx.x; r < m; r += NT_MM) {
-    J.D[r + (int64_t)c * m] = h[r];
-    J.Tleaf[r + (int64_t)c * m] = (r <= c) ? W.T[r + (int64_t)c * MAXLEAF] : 0.0;
-  }
-  int off = m;
+  for (int r = threadIdx.x; r < mr; r += NT_MM) J.D[r + (int64_t)c * mr] = h[r];
+  for (int r = threadIdx.x; r < m; r += NT_MM) J.Tleaf[r + (int64_t)c * m] = (r <= c) ? W.T[r + (int64_t)c * MAXLEAF] : 0.0;
+  int off = mr;
   for (int g = 0; g < J.ngroups; ++g) {
     const int k = *J.g[g].rank;
     double* V = J.g[g].V + J.g[g].row0 + c;

@@ -98,4 +98,28 @@ __global__ void __launch_bounds__(NT_MM) k_leaf_trsm(const double* __restrict__ 
   for (int r = threadIdx.x; r < m; r += NT_MM) x[r] = xs[r];
 }
 
+// X(c0_j + i, col) = B(r0_j + i, col) for i < n_j: the pivot rows of each leaf
+// (runs[3 j] = r0_j, runs[3 j + 1] = c0_j, runs[3 j + 2] = n_j); block (j, col
+// group), columns col, col + gridDim.y, ...
+__global__ void __launch_bounds__(NT_MM) k_pivot_rows(const int* __restrict__ runs, int nrun, const double* B,
+                                                      int ldb, double* X, int ldx, int ncols) {
+  const int j = blockIdx.x;
+  if (j >= nrun) return;
+  const int r0 = runs[3 * j], c0 = runs[3 * j + 1], nj = runs[3 * j + 2];
+  for (int col = blockIdx.y; col < ncols; col += gridDim.y)
+    for (int i = threadIdx.x; i < nj; i += NT_MM)
+      X[c0 + i + (int64_t)col * ldx] = B[r0 + i + (int64_t)col * ldb];
+}
+
+// Row runs between column-major arrays: one block per run, every column.
+__global__ void __launch_bounds__(NT_MM) k_rows(const RowJob* __restrict__ items, int first) {
+  const RowJob J = items[first + blockIdx.x];
+  const int nc = J.ncols_dev ? *J.ncols_dev : J.ncols;
+  const int64_t total = (int64_t)J.rows * nc;
+  for (int64_t e = threadIdx.x; e < total; e += NT_MM) {
+    const int r = (int)(e % J.rows), c = (int)(e / J.rows);
+    J.dst[J.dst_r0 + r + (int64_t)c * J.ldd] = J.src[J.src_r0 + r + (int64_t)c * J.lds];
+  }
+}
+
 }  // namespace hq

@@ -72,6 +72,9 @@ __global__ void k_set_scal(const VecJob* __restrict__ items, int first, int coun
 __global__ void k_fill_items(const VecJob* __restrict__ items, int first);
 __global__ void k_fill(double* x, int64_t n, double v);
 __global__ void k_zero_i32(int* x, int n);
+__global__ void k_rows(const RowJob* __restrict__ items, int first);
+__global__ void k_pivot_rows(const int* __restrict__ runs, int nrun, const double* B, int ldb, double* X, int ldx,
+                             int ncols);
 __global__ void k_leaf_trsm(const double* __restrict__ D, int m, int ld, double* X, int ldx, int nrhs);
 
 }  // namespace hq

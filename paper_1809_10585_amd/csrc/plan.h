@@ -210,6 +210,7 @@ enum OpType {
   OP_TRQR, OP_TRFORM, OP_MMPROJ, OP_MMAPPLY, OP_GTALL, OP_GRED, OP_LGATHER, OP_LPANEL,
   OP_LUPDATE, OP_LSCATTER, OP_FILL, OP_NORMALIZE, OP_TRSM, OP_SETSCAL,
   OP_MMRED, OP_TRSMALL,
+  OP_ROWS,    // row runs between arrays (k_rows)
   OP_SIGNAL,  // record event a0 on the op's lane (no kernel)
   OP_WAIT,    // the op's lane waits for event a0 (no kernel)
   OP_NTYPES
@@ -312,6 +313,7 @@ struct Plan {
   std::vector<GemmRed> gr;
   std::vector<LeafJob> lj;
   std::vector<VecJob> vj;
+  std::vector<RowJob> rj;
   std::vector<Op> ops;
   // Workspace and counters are reused by consecutive ops of one lane; the two
   // lanes get disjoint regions because their ops may run at the same time.
@@ -361,6 +363,7 @@ struct Plan {
   GemmRed* d_gr = nullptr;
   LeafJob* d_lj = nullptr;
   VecJob* d_vj = nullptr;
+  RowJob* d_rj = nullptr;
 
   std::vector<char> staged;  // host image of the descriptors (kept until the copy is done)
 
