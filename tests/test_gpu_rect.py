@@ -150,3 +150,47 @@ def test_rect_qr_table5_example(H):
     QRX = H.hodlr_apply_q(F, H.colmajor(RXm)).cpu().numpy()
     AX = H.hodlr_matmul(A, H.colmajor(X)).cpu().numpy()
     assert np.linalg.norm(AX - QRX) / (an * np.linalg.norm(X)) <= 10 * 1e-10
+
+
+SITE = {1: "S", 2: "A12", 3: "update", 4: "T", 5: "E"}
+
+
+def _device_log(H, F):
+    out = {}
+    for r in H.hodlr_qr_ranklog(F):
+        site = int(r[0])
+        if site == 0:  # the up-front orthogonalisation (the oracle does it lazily)
+            continue
+        key = (SITE[site], int(r[1]), int(r[2]))
+        if site in (1, 4):
+            key += (int(r[3]),)
+        elif site == 3:
+            key += (int(r[3]), int(r[4]))
+        out[key] = (int(r[5]), int(r[6]))
+    return out
+
+
+def _oracle_log(ref):
+    """The oracle's keys (site, rows, columns, ...) on the device's naming: the
+    node by its column range."""
+    out = {}
+    for t in ref.counter.truncs:
+        k = t["key"]
+        out[(k[0], k[3], k[4]) + tuple(k[5:])] = (t["w"], t["k"])
+    return out
+
+
+@pytest.mark.parametrize("m,n,nmin,k,seed", [(2000, 1000, 63, 3, 11), (3000, 1024, 128, 2, 13)])
+def test_rect_rank_log(H, m, n, nmin, k, seed):
+    """Every recompression of the rectangular factorisation, E groups included,
+    takes the oracle's decision (input width and kept rank)."""
+    inp = G.rect_gaussian_hodlr(m, n, nmin, k, seed=seed)
+    root = RR.rfrom_input(inp)
+    an = RR.rnorm2_est(root)
+    ref = RR.rhqr(root, 1e-10, anorm=an)
+    F = H.hodlr_qr(H.hodlr_build_rect(inp, rank_cap=64), 1e-10, anorm=an)
+    dev, ora = _device_log(H, F), _oracle_log(ref)
+    assert set(dev) == set(ora)
+    assert sum(1 for key in ora if key[0] == "E") > 0
+    bad = [(key, dev[key], ora[key]) for key in ora if dev[key] != ora[key]]
+    assert not bad, bad[:5]
