@@ -115,6 +115,17 @@ def cpu_baseline(inp, min_seconds=10.0, max_reps=8):
                       f"each; one more with 1 thread"}, F.counter.total
 
 
+def cpu_baseline_rect(G):
+    """The rectangular oracle factorising the rectangular workload once on the
+    host (its NumPy threads): seconds per factorisation."""
+    import oracle.rect as RR
+    inp = G.rect_gaussian_hodlr(8000, 4000, 250, 1, seed=5, shift=0.0)
+    t0 = time.perf_counter()
+    RR.rhqr(inp, EPS)
+    return {"s_per_qr": time.perf_counter() - t0, "kind": "oracle", "sample": "one factorisation of the "
+            "8000 x 4000 rectangular workload"}
+
+
 def bench_batched(H, G, np, count=256, seed=3, rank_cap=64, reps=3):
     """Batched workload: `count` independent Gaussian HODLR matrices, n = 256 * 2^d
     with d ~ U{2..6}, leaf 256, exact off-diagonal rank k ~ U{4..32} capped at
@@ -258,6 +269,27 @@ def bench_accuracy(H, G):
     return out
 
 
+def bench_rect(H, G, np, reps=5):
+    """Rectangular workload (Sec. 6, Table 5's random rectangular example): an
+    8000 x 4000 HODLR matrix with random Gaussian leaves and rank-one
+    off-diagonal blocks, n_min 250, eps 1e-10, seed 5; permuted QR on the
+    device (HIP events, input resident), the factors' maximal ranks against the
+    printed 8 / 12 / 8 (the oracle's time for it is in cpu_baseline)."""
+    inp = G.rect_gaussian_hodlr(8000, 4000, 250, 1, seed=5, shift=0.0)
+    A = H.hodlr_build_rect(inp, rank_cap=32)
+    F = H.hodlr_qr(A, EPS)
+    info = H.hodlr_qr_info(F)
+    del F
+    ms = H.hodlr_qr_time(A, EPS, 0.0, 0, 1, reps)
+    out = {"workload": "rectangular HODLR 8000 x 4000, rank-one blocks, n_min 250, eps 1e-10, seed 5 "
+                       "(Table 5's random rectangular example)",
+           "ms_per_qr": float(np.median(ms)), "qr_per_s": 1e3 / float(np.median(ms)),
+           "max_rank_y_t_r": [info["max_rank_y"], info["max_rank_t"], info["max_rank_r"]],
+           "paper_max_rank_y_t_r": [8, 12, 8]}
+    log(f"rect: {out}")
+    return out
+
+
 def bench_host_buffers(H, inp, reps: int = 3) -> dict:
     """The path from host buffers: hodlr_build (validation, and the host-to-device
     copy of the packed matrix) followed by hodlr_qr, per factorisation.  A rate
@@ -301,6 +333,8 @@ def main():
                     help="skip the served measurement (1000 requests of a Poisson stream, continuous "
                          "batching and the plain loop)")
     ap.add_argument("--served-requests", type=int, default=300)
+    ap.add_argument("--no-rect", action="store_true",
+                    help="skip the rectangular measurement (8000 x 4000 permuted QR)")
     ap.add_argument("--accuracy", action="store_true",
                     help="only the accuracy study of the paper's Cauchy examples (e_orth, e_acc)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -385,6 +419,9 @@ def main():
     del A
     batched = None if args.no_batched else bench_batched(H, G, np)
     served = None if args.no_served else bench_served(H, G, np, requests=args.served_requests)
+    rect = None if args.no_rect else bench_rect(H, G, np)
+    if rect is not None and cpu is not None:
+        cpu["rect"] = cpu_baseline_rect(G)
 
     out = {
         "metric": "HODLR QR s & FP64 TFLOP/s at n=65536; batched QR/s + p99 served vs plain",
@@ -415,6 +452,7 @@ def main():
         "from_host_buffers": host,
         "batched": batched,
         "served": served,
+        "rect": rect,
     }
     print(json.dumps(out), flush=True)
 
