@@ -400,7 +400,11 @@ __global__ void __launch_bounds__(NT_LEAF) k_leaf_step(const LeafJob* __restrict
   for (int ks = w; ks < nk; ks += 16) {
     const int row = i0 + (l & 15), colT = i0 + 4 * ks + (l >> 4);
     const double a = (colT >= row) ? gmem(W.T)[(int64_t)row + (int64_t)colT * MAXLEAF] : 0.0;
-    const double g = gmem(W.G)[(int64_t)(i0 + 4 * ks + (l >> 4)) + (int64_t)(cq + (l & 15)) * MAXLEAF];
+    // columns of G beyond panel q's width are not part of this leaf: zero them
+    // (X's columns >= qw then stay zero instead of carrying stale values)
+    const double g = (l & 15) < qw
+                         ? gmem(W.G)[(int64_t)(i0 + 4 * ks + (l >> 4)) + (int64_t)(cq + (l & 15)) * MAXLEAF]
+                         : 0.0;
     acc = mfma16(a, g, acc);
   }
   leaf_reduce_tile(acc, sm + LF_PART, X);
