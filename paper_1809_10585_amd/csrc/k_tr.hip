@@ -53,6 +53,31 @@ __device__ __forceinline__ bool jac_rot_fast(double al, double be, double ga, do
   return true;
 }
 
+// The rotation of jac_rot_fast without the power-of-two scaling of (d, g),
+// computed whether or not the pair needs one (no branch), for columns scaled
+// so that the squared Frobenius norm of the whole matrix is below 1 and the
+// squared norm of every rotated pair above 1e-40 (the caller's eta2): then
+// d^2 + g^2 neither overflows nor underflows whenever a rotation is due
+// (|g|^2 > tol2 a b with max(a, b) > 1e-40).  Same formula, three dependent
+// operations shorter.
+__device__ __forceinline__ void jac_rot_unit(double al, double be, double ga, double& cs, double& sn) {
+  const double d = be - al, g = 2.0 * ga;
+  const double h2 = fma(d, d, g * g);
+  const double hh = -0.5 * h2;
+  double y = __builtin_amdgcn_rsq(h2);
+  y = y * fma(hh * y, y, 1.5);
+  y = y * fma(hh * y, y, 1.5);
+  const double r = h2 * y;
+  const double s = r + fabs(d);
+  const double u = (2.0 * r) * s;
+  const double uh = -0.5 * u;
+  double q = __builtin_amdgcn_rsq(u);
+  q = q * fma(uh * q, q, 1.5);
+  q = q * fma(uh * q, q, 1.5);
+  cs = s * q;
+  sn = (d >= 0.0 ? g : -g) * q;
+}
+
 // One-sided Jacobi on the columns of X (w x w, ld lx), accumulating the
 // rotations in V (ld lv) unless V is null.  Round-robin pairing; one pair per
 // group of TPP lanes; a sweep ends when no pair needed a rotation.  Pairs of two
@@ -124,6 +149,111 @@ __device__ __forceinline__ void jacobi(double* X, int lx, double* V, int lv, int
     __syncthreads();
     if (f == 0) break;
   }
+}
+
+// jacobi() without V and without branches in its rounds, for 16 < w <= 128.
+// X holds n = w + (w & 1) columns of TPP * RPL >= w rows (ld lx >= TPP * RPL),
+// zero beyond row w and in column w when w is odd (rotations keep them zero,
+// so every lane loads and stores its rows unconditionally).  Pair p of a round
+// is taken by TPP lanes, each holding RPL rows of both columns in registers
+// between the dot products and the rotation; a pair that needs no rotation is
+// stored back unchanged (cs = 1, sn = 0).  X is scaled as jac_rot_unit
+// requires, and eta2 >= 1e-40.
+template <int TPP, int RPL>
+__device__ __forceinline__ void jacobi_pad(double* X, int lx, int w, int* sflag, double eta2) {
+  const int tid = threadIdx.x;
+  const int n = w + (w & 1), nm1 = n - 1;
+  const int P = n / 2;
+  const int p = tid / TPP, sub = tid % TPP;
+  const double tol = (double)w * DBL_EPSILON;
+  const double tol2 = tol * tol;
+  constexpr int NA = RPL >= 8 ? 4 : (RPL >= 4 ? 2 : 1);
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) *sflag = 0;
+    __syncthreads();
+    for (int r = 0; r < nm1; ++r) {
+      if (p < P) {
+        int i = r + p;
+        i = i >= nm1 ? i - nm1 : i;
+        int j = r - p;
+        j = j < 0 ? j + nm1 : j;
+        j = p == 0 ? nm1 : j;
+        double* ci = X + min(i, j) * lx + sub;
+        double* cj = X + max(i, j) * lx + sub;
+        double xi[RPL], xj[RPL];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          xi[t] = ci[t * TPP];
+          xj[t] = cj[t * TPP];
+        }
+        double pa[NA], pb[NA], pg[NA];
+#pragma unroll
+        for (int q = 0; q < NA; ++q) pa[q] = pb[q] = pg[q] = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          pa[t % NA] += xi[t] * xi[t];
+          pb[t % NA] += xj[t] * xj[t];
+          pg[t % NA] += xi[t] * xj[t];
+        }
+#pragma unroll
+        for (int h = NA / 2; h >= 1; h /= 2)
+#pragma unroll
+          for (int q = 0; q < h; ++q) {
+            pa[q] += pa[q + h];
+            pb[q] += pb[q + h];
+            pg[q] += pg[q + h];
+          }
+        const double al = gsumt<TPP>(pa[0]);
+        const double be = gsumt<TPP>(pb[0]);
+        const double ga = gsumt<TPP>(pg[0]);
+        const bool rot = (al > eta2 || be > eta2) && ga != 0.0 && ga * ga > tol2 * (al * be);
+        double cr, sr;
+        jac_rot_unit(al, be, ga, cr, sr);
+        const double cs = rot ? cr : 1.0, sn = rot ? sr : 0.0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          ci[t * TPP] = cs * xi[t] - sn * xj[t];
+          cj[t * TPP] = sn * xi[t] + cs * xj[t];
+        }
+        if (rot && sub == 0) *sflag = 1;
+      }
+      __syncthreads();
+    }
+    const int f = *sflag;
+    __syncthreads();
+    if (f == 0) break;
+  }
+}
+
+// Lanes per pair and rows per lane of jacobi_pad for a width 16 < w <= 128.
+__device__ __forceinline__ void jacobi_pad_shape(int w, int& tpp, int& rpl) {
+  if (w <= 32) {
+    tpp = 32;
+    rpl = 1;
+  } else if (w <= 64) {
+    tpp = 16;
+    rpl = w <= 48 ? 3 : 4;
+  } else {
+    tpp = 8;
+    rpl = w <= 80 ? 10 : (w <= 96 ? 12 : (w <= 112 ? 14 : 16));
+  }
+}
+
+__device__ __forceinline__ void jacobi_noacc(double* X, int lx, int w, int* sflag, double eta2) {
+  if (w <= 32)
+    jacobi_pad<32, 1>(X, lx, w, sflag, eta2);
+  else if (w <= 48)
+    jacobi_pad<16, 3>(X, lx, w, sflag, eta2);
+  else if (w <= 64)
+    jacobi_pad<16, 4>(X, lx, w, sflag, eta2);
+  else if (w <= 80)
+    jacobi_pad<8, 10>(X, lx, w, sflag, eta2);
+  else if (w <= 96)
+    jacobi_pad<8, 12>(X, lx, w, sflag, eta2);
+  else if (w <= 112)
+    jacobi_pad<8, 14>(X, lx, w, sflag, eta2);
+  else
+    jacobi_pad<8, 16>(X, lx, w, sflag, eta2);
 }
 
 // The same one-sided Jacobi for w <= WS (WS = 8 or 16) inside one wavefront.
@@ -220,6 +350,57 @@ __device__ __forceinline__ double tr_flops_orth(int m0, int m1, int w) {
   return 2.0 * (2.0 * (double)m0 * w * pq - 2.0 / 3.0 * pq * pq * pq) + 2.0 * (double)w * w * m1;
 }
 
+// Householder QR of X (w x w in LDS, ld w) by the whole block, in place: R in
+// the upper triangle on return (the reflectors below it are not kept).  Column
+// j's reflector is formed by wavefront 0; the later columns take it TPC
+// threads each.  tau_slot: one double of LDS.
+__device__ __forceinline__ void block_qr_r(double* X, int w, int lx, double* tau_slot) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j < w - 1; ++j) {
+    if (tid < 64) {
+      double ss = 0.0;
+      for (int r = j + 1 + tid; r < w; r += 64) {
+        const double x = X[r + j * lx];
+        ss += x * x;
+      }
+      ss = gsumt<64>(ss);
+      double beta, tau, sc;
+      house_scalars(X[j + j * lx], ss, beta, tau, sc);
+      if (tau != 0.0)
+        for (int r = j + 1 + tid; r < w; r += 64) X[r + j * lx] *= sc;
+      if (tid == 0) {
+        X[j + j * lx] = beta;
+        *tau_slot = tau;
+      }
+    }
+    __syncthreads();
+    const double tau = *tau_slot;
+    const int nc = w - 1 - j;  // columns j+1 .. w-1
+    if (tau != 0.0) {
+      int Pp = 1;
+      while (Pp < nc) Pp <<= 1;
+      int TPC = NT_TR / Pp;
+      if (TPC > 64) TPC = 64;
+      if (TPC < 1) TPC = 1;
+      const int ci = tid / TPC, sub = tid % TPC;
+      const bool live = ci < nc;
+      const int c = j + 1 + ci;
+      double d = 0.0;
+      if (live) {
+        if (sub == 0) d = X[j + c * lx];
+        for (int r = j + 1 + sub; r < w; r += TPC) d += X[r + j * lx] * X[r + c * lx];
+      }
+      d = gsum(d, TPC);
+      if (live) {
+        const double f = tau * d;
+        if (sub == 0) X[j + c * lx] -= f;
+        for (int r = j + 1 + sub; r < w; r += TPC) X[r + c * lx] -= f * X[r + j * lx];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Last block of a job: SVD of R1 R2^T and the small factors U_k, P = R1^T U_k.
 template <int W>
 __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0a, int n0b, double* smem, int* err,
@@ -245,7 +426,7 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
     if (tid == 0) add_flops(fc, fcat, tr_flops_orth(m0, m1, w));
   } else {
     const double* R2 = ws + J.side[1].node0 + (int64_t)tr_root_slot(J.side[1].p0, G) * TR_NODE;
-    double* sig = smem + TRS_X + WMAX * WMAX;
+    double* sig = smem + TRS_X + TRS_XSZ;
     int* perm = (int*)(sig + WMAX);
     double* X = smem + TRS_X;
     const double* R1s = R1;
@@ -313,18 +494,25 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
         P[r + p * WMAX] = sacc;
       }
     } else {
-      // M = R1 R2^T (w x w) in X.  When every column that can be kept lies far
-      // above the roundoff level of M (tau^2 > 1e6 eta^2), one-sided Jacobi on
-      // the columns of M: M W = U S with orthogonal W, so once every pair of
-      // kept columns is orthogonal to the relative tolerance, their norms are
-      // the singular values and the columns over their norms are U; no
-      // rotations are accumulated, and pairs of columns at the roundoff level
-      // are left alone.  Otherwise (tau at or near roundoff, e.g. tau = 0) the
-      // Jacobi runs on M^T and accumulates the rotations V, whose columns are U
-      // and stay orthonormal however far the roundoff columns converge.
+      // X = R2 R1^T = M^T (w x w), M = R1 R2^T.  When every column that can be
+      // kept lies far above the roundoff level of M (tau^2 > 1e6 eta^2): the
+      // Householder QR M^T = Q' R' first, then one-sided Jacobi on the columns
+      // of R'^T without accumulating rotations: R'^T W = V' S with V' the right
+      // singular vectors of R', which are those of M^T, i.e. U of M, so the
+      // columns over their norms are U (orthonormal to the relative tolerance
+      // once every kept pair has converged).  The triangular preconditioning
+      // cuts the sweeps several-fold against Jacobi on M itself.  Otherwise
+      // (tau at or near roundoff, e.g. tau = 0) the Jacobi runs on M^T and
+      // accumulates the rotations V, whose columns are U and stay orthonormal
+      // however far the roundoff columns converge.
+      // X: nc = w + (w & 1) columns of the Jacobi's padded height, odd leading
+      // dimension (LDS banks of the column pairs)
+      int tpp, rpl;
+      jacobi_pad_shape(w, tpp, rpl);
+      const int lx = tpp * rpl + 1, nc = w + (w & 1);
       const double* R2s = R2;
-      if (3 * w * w <= WMAX * WMAX) {
-        double* r1 = X + w * w;
+      if (lx * nc + 2 * w * w <= TRS_XSZ) {
+        double* r1 = X + lx * nc;
         double* r2 = r1 + w * w;
         for (int e = tid; e < w * w; e += NT_TR) {
           const int i = e % w, j = e / w;
@@ -339,13 +527,13 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
       for (int e = tid; e < w * w; e += NT_TR) {
         const int i = e % w, j = e / w;
         double sacc = 0.0;
-        for (int l = max(i, j); l < w; ++l) sacc += R1s[i + l * lr] * R2s[j + l * lr];
-        X[e] = sacc;
+        for (int l = max(i, j); l < w; ++l) sacc += R2s[i + l * lr] * R1s[j + l * lr];
+        X[i + j * lx] = sacc;
       }
       __syncthreads();
       for (int cc = tid; cc < w; cc += NT_TR) {
         double sacc = 0.0;
-        for (int r = 0; r < w; ++r) sacc += X[r + cc * w] * X[r + cc * w];
+        for (int r = 0; r < w; ++r) sacc += X[r + cc * lx] * X[r + cc * lx];
         sig[cc] = sacc;
       }
       __syncthreads();
@@ -356,21 +544,35 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
       __syncthreads();
       double* V = nullptr;
       int LV = 0;
+      int scl = 0;  // X = 2^scl (matrix whose column norms are the singular values)
       if (fast) {
-        jacobi(X, w, nullptr, 0, w, sflag, eta2);
-      } else {
-        for (int e = tid; e < w * w; e += NT_TR) {  // X <- M^T in place
+        block_qr_r(X, w, lx, smem + TRS_TAU);
+        // X <- 2^-e R'^T (lower triangular) with |X|_F^2 = 2^-2e fro2 in [1/4, 1):
+        // the unit scale of jac_rot_unit (the rotations are those of the
+        // unscaled matrix; only k's threshold is scaled the same way below)
+        const int ex = __builtin_amdgcn_frexp_exp(sqrt(fro2));
+        for (int e = tid; e < w * w; e += NT_TR) {
           const int i = e % w, j = e / w;
           if (i < j) {
-            const double t = X[i + j * w];
-            X[i + j * w] = X[j + i * w];
-            X[j + i * w] = t;
+            X[j + i * lx] = __builtin_ldexp(X[i + j * lx], -ex);
+            X[i + j * lx] = 0.0;
+          } else if (i == j) {
+            X[i + i * lx] = __builtin_ldexp(X[i + i * lx], -ex);
           }
         }
+        const int hp = lx - 1;  // zero padding: rows w.. of every column, column w
+        for (int e = tid; e < hp * nc; e += NT_TR) {
+          const int i = e % hp, j = e / hp;
+          if (i >= w || j >= w) X[i + j * lx] = 0.0;
+        }
+        scl = -ex;
+        __syncthreads();
+        jacobi_noacc(X, lx, w, sflag, fmax(__builtin_ldexp(eta2, -2 * ex), 1e-40));
+      } else {
         R1s = R1;  // V takes the staging space
         lr = WMAX;
-        if (2 * w * w <= WMAX * WMAX) {
-          V = X + w * w;
+        if (lx * nc + w * w <= TRS_XSZ) {
+          V = X + lx * nc;
           LV = w;
         } else {
           V = hdr + 8 + 2 * WMAX * WMAX;
@@ -382,11 +584,11 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
           V[i + j * LV] = (i == j) ? 1.0 : 0.0;
         }
         __syncthreads();
-        jacobi(X, w, V, LV, w, sflag);
+        jacobi(X, lx, V, LV, w, sflag);
       }
       for (int cc = tid; cc < w; cc += NT_TR) {
         double sacc = 0.0;
-        for (int r = 0; r < w; ++r) sacc += X[r + cc * w] * X[r + cc * w];
+        for (int r = 0; r < w; ++r) sacc += X[r + cc * lx] * X[r + cc * lx];
         sig[cc] = sqrt(sacc);
       }
       __syncthreads();
@@ -401,7 +603,8 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
       }
       __syncthreads();
       k = 0;
-      for (int j = 0; j < w; ++j) k += (sig[j] > tau) ? 1 : 0;
+      const double tau_s = __builtin_ldexp(tau, scl);
+      for (int j = 0; j < w; ++j) k += (sig[j] > tau_s) ? 1 : 0;
       if (k > capk) {
         if (tid == 0) atomicOr(err, ERR_CAPACITY);
         k = capk;
@@ -409,7 +612,7 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
       for (int e = tid; e < w * k; e += NT_TR) {
         const int r = e % w, p = e / w;
         const int pc = perm[p];
-        const double* u = fast ? X + (int64_t)pc * w : V + (int64_t)pc * LV;
+        const double* u = fast ? X + (int64_t)pc * lx : V + (int64_t)pc * LV;
         const double inv = fast ? 1.0 / sig[pc] : 1.0;
         Uk[r + p * WMAX] = u[r] * inv;
         double sacc = 0.0;
@@ -587,31 +790,82 @@ __global__ void __launch_bounds__(NT_TR) k_tr_qr(const TrJob* __restrict__ jobs,
 }
 
 
-// out[r, p] = sum_c A(r, c) B[c + p*ldb] for r < rows, p < k; thread = row
-// (NT threads), 16 output columns at a time in registers.  A(r, c) = a[r + c*lda].
-template <int NT = NT_MM>
-__device__ __forceinline__ void rows_times_small(const double* a, int64_t lda, int rows, int w,
-                                                 const double* B, int ldb, int k, double* out,
-                                                 int64_t ldo) {
+// out[r, p] = sum_c A(r, c) B[c + p*ldb] for r < rows, p < k <= 128 by NT
+// threads: thread (tr, g) keeps the 4 x 8 outputs of rows tr + TR i (i < 4) and
+// columns 8g + j (j < 8) in registers, TR = NT / (the number of 8-column groups
+// rounded up to a power of two), so each A element it loads serves 8 products
+// and each B element 4; row blocks of 4 TR rows.  A(r, c) = aload(r, c) for
+// r < rows (rows and columns past the ends are clamped, computed and dropped).
+// With sync, every thread has read its rows of a row block before any output
+// of that block is stored (out may overwrite A in place, row by row).
+template <int NT, class AL>
+__device__ __forceinline__ void tile_times_small(const AL& aload, int rows, int w, const double* B, int ldb,
+                                                 int k, double* out, int64_t ldo, bool sync) {
   const int tid = threadIdx.x;
-  for (int r = tid; r < rows; r += NT) {
-    for (int p0 = 0; p0 < k; p0 += 16) {
-      double acc[16];
+  const int G = (k + 7) >> 3;
+  int Gp = 1;
+  while (Gp < G) Gp <<= 1;
+  const int TR = NT / Gp;
+  const int tr = tid % TR, g = tid / TR;
+  const bool live = g < G;
+  const int q0 = 8 * g;
+  int qq[8];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int j = 0; j < 8; ++j) qq[j] = min(q0 + j, k - 1) * ldb;
+  for (int rb = 0; rb < rows; rb += 4 * TR) {
+    double acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+    if (live) {
+      int rr[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) rr[i] = min(rb + tr + TR * i, rows - 1);
 #pragma unroll 4
       for (int c = 0; c < w; ++c) {
-        const double x = a[r + (int64_t)c * lda];
+        double av[4], bv[8];
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (p0 + q < k) acc[q] += x * B[c + (p0 + q) * ldb];
+        for (int i = 0; i < 4; ++i) av[i] = aload(rr[i], c);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bv[j] = B[c + qq[j]];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
       }
+    }
+    if (sync) __syncthreads();
+    if (live) {
 #pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (p0 + q < k) out[r + (int64_t)(p0 + q) * ldo] = acc[q];
+      for (int i = 0; i < 4; ++i) {
+        const int r = rb + tr + TR * i;
+        if (r < rows)
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (q0 + j < k) out[r + (int64_t)(q0 + j) * ldo] = acc[i][j];
+      }
     }
   }
 }
+
+// A(r, c) = a[r + c*lda]
+struct ALoadPlain {
+  const double* a;
+  int64_t lda;
+  __device__ __forceinline__ double operator()(int r, int c) const { return a[r + (int64_t)c * lda]; }
+};
+
+// A(r, c): the two scaled segments of a recompression side, side by side
+struct ALoadSegs {
+  Seg s0, s1;
+  int n0;
+  int64_t row0;
+  __device__ __forceinline__ double operator()(int r, int c) const {
+    const int64_t gr = row0 + r;
+    return c < n0 ? s0.scale * s0.p[gr + (int64_t)c * s0.ld] : s1.scale * s1.p[gr + (int64_t)(c - n0) * s1.ld];
+  }
+};
 
 __global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ jobs,
                                                     const TrForm* __restrict__ items, int first,
@@ -656,7 +910,7 @@ __global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ job
       const int cslot = idxs[l - 1] - idxs[l] * G;
       const double* Qn = ws + S.node0 + (int64_t)(bases[l] + idxs[l]) * TR_NODE + WMAX * WMAX + cslot * w;
       if (fits) {
-        rows_times_small(Qn, CH, w, w, Z, w, k, Zn, w);
+        tile_times_small<NT_MM>(ALoadPlain{Qn, CH}, w, w, Z, w, k, Zn, w, false);
         __syncthreads();
         for (int e = tid; e < w * k; e += NT_MM) Z[e] = Zn[e];
         __syncthreads();
@@ -675,7 +929,7 @@ __global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ job
     const int row0 = (int)((int64_t)it.chunk * S.m / S.p0);
     const int h = (int)((int64_t)(it.chunk + 1) * S.m / S.p0) - row0;
     const double* Qc = ws + S.node0 + (int64_t)it.chunk * TR_NODE + WMAX * WMAX;
-    rows_times_small(Qc, CH, h, w, Z, w, k, out + row0, ldo);
+    tile_times_small<NT_MM>(ALoadPlain{Qc, CH}, h, w, Z, w, k, out + row0, ldo, false);
   } else {
     const int n0 = (int)hdr[3];
     const Seg s0 = J.seg[1][0], s1 = J.seg[1][1];
@@ -695,9 +949,9 @@ __global__ void __launch_bounds__(NT_MM) k_tr_form(const TrJob* __restrict__ job
       for (int e = tid; e < w * k; e += NT_MM) Ps[e] = P[(e % w) + (e / w) * WMAX];
     __syncthreads();
     if (fits)
-      rows_times_small(In, 64, rows, w, Ps, w, k, out + it.row0, ldo);
+      tile_times_small<NT_MM>(ALoadPlain{In, 64}, rows, w, Ps, w, k, out + it.row0, ldo, false);
     else
-      rows_times_small(In, 64, rows, w, P, WMAX, k, out + it.row0, ldo);
+      tile_times_small<NT_MM>(ALoadPlain{In, 64}, rows, w, P, WMAX, k, out + it.row0, ldo, false);
   }
 }
 
@@ -1105,61 +1359,22 @@ __device__ __forceinline__ void tr_small_form(const TrJob& J, const double* ws, 
     const double* Zuse = Z;
     if (S.p0 > 1) {
       const double* Qn = ws + S.node0 + (int64_t)S.p0 * TR_NODE + WMAX * WMAX + c * w;
-      rows_times_small<NT_TR>(Qn, CH, w, w, Z, w, k, Zc, w);
+      tile_times_small<NT_TR>(ALoadPlain{Qn, CH}, w, w, Z, w, k, Zc, w, false);
       __syncthreads();
       Zuse = Zc;
     }
     const double* Qc = ws + S.node0 + (int64_t)c * TR_NODE + WMAX * WMAX;
-    rows_times_small<NT_TR>(Qc, CH, h, w, Zuse, w, k, J.out[0] + row0, J.ldout[0]);
+    tile_times_small<NT_TR>(ALoadPlain{Qc, CH}, h, w, Zuse, w, k, J.out[0] + row0, J.ldout[0], false);
     __syncthreads();
   }
-  // R' = R P.  R' may overwrite R in place (row r of R' over row r of R), so a
-  // thread computes all k outputs of its row before it writes them: with
-  // k <= 16 it reads its row straight from the segments (coalesced over the
-  // threads), otherwise 64-row pieces of R are staged in LDS first.
+  // R' = R P.  R' may overwrite R in place (row r of R' over row r of R): every
+  // thread reads its rows of a row block before any of them is stored.
   const int n0 = (int)hdr[3];
-  const Seg s0 = J.seg[1][0], s1 = J.seg[1][1];
-  if (k <= 16) {
-    double* Ps = sm;  // w x k, ld w
-    for (int e = tid; e < w * k; e += NT_TR) Ps[e] = P[(e % w) + (e / w) * WMAX];
-    __syncthreads();
-    for (int r = tid; r < J.side[1].m; r += NT_TR) {
-      double acc[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-      for (int c = 0; c < w; ++c) {
-        const double x = (c < n0) ? s0.scale * s0.p[r + (int64_t)c * s0.ld]
-                                  : s1.scale * s1.p[r + (int64_t)(c - n0) * s1.ld];
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (q < k) acc[q] += x * Ps[c + q * w];
-      }
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (q < k) J.out[1][r + (int64_t)q * J.ldout[1]] = acc[q];
-    }
-    return;
-  }
-  double* In = sm;           // rows x w, ld 64
-  double* Ps = sm + 64 * w;  // w x k, ld w
-  const bool fits = 64 * w + w * k <= WMAX * WMAX;
-  if (fits)
-    for (int e = tid; e < w * k; e += NT_TR) Ps[e] = P[(e % w) + (e / w) * WMAX];
-  for (int r0 = 0; r0 < J.side[1].m; r0 += 64) {
-    const int rows = min(64, J.side[1].m - r0);
-    for (int e = tid; e < rows * w; e += NT_TR) {
-      const int r = e % rows, cc = e / rows;
-      const int64_t gr = r0 + r;
-      In[r + cc * 64] = (cc < n0) ? s0.scale * s0.p[gr + (int64_t)cc * s0.ld]
-                                  : s1.scale * s1.p[gr + (int64_t)(cc - n0) * s1.ld];
-    }
-    __syncthreads();
-    if (fits)
-      rows_times_small<NT_TR>(In, 64, rows, w, Ps, w, k, J.out[1] + r0, J.ldout[1]);
-    else
-      rows_times_small<NT_TR>(In, 64, rows, w, P, WMAX, k, J.out[1] + r0, J.ldout[1]);
-    __syncthreads();
-  }
+  double* Ps = sm;  // w x k, ld w
+  for (int e = tid; e < w * k; e += NT_TR) Ps[e] = P[(e % w) + (e / w) * WMAX];
+  __syncthreads();
+  tile_times_small<NT_TR>(ALoadSegs{J.seg[1][0], J.seg[1][1], n0, 0}, J.side[1].m, w, Ps, w, k, J.out[1],
+                          J.ldout[1], true);
 }
 
 // Wider jobs: the chunk code of k_tr_qr, one block per chunk (the chunks

@@ -13,7 +13,8 @@ constexpr int TRS_VBUF = 0;
 constexpr int TRS_TAU = 2 * CH;
 constexpr int TRS_FLAG = TRS_TAU + WMAX;      // 16 doubles of int flags
 constexpr int TRS_X = TRS_FLAG + 16;
-constexpr int TRS_TOTAL = TRS_X + WMAX * WMAX + 2 * WMAX;   // X (+V for W<=64) + sig + perm
+constexpr int TRS_XSZ = WMAX * (WMAX + 1);                  // X (ld up to WMAX + 1), staging, V
+constexpr int TRS_TOTAL = TRS_X + TRS_XSZ + 2 * WMAX;           // + sig + perm
 constexpr size_t TR_QR_LDS = sizeof(double) * (size_t)TRS_TOTAL;
 constexpr size_t TR_FORM_LDS = sizeof(double) * (size_t)WMAX * WMAX;
 // k_tr_small takes factors of at most this many CH-row chunks per side
