@@ -31,7 +31,7 @@ KERNEL = {"leaf_panel": "k_leaf_step", "leaf_update": "k_leaf_step", "tr_qr": "k
           "gemm_tall": "k_gemm_tall", "gemm_red": "k_gemm_red", "leaf_gather": "k_leaf_gather",
           "leaf_scatter": "k_leaf_scatter", "fill": "k_fill", "normalize": "k_normalize",
           "set_scal": "k_set_scal", "leaf_trsm": "k_leaf_trsm", "mm_red": "k_mm_red",
-          "tr_small": "k_tr_small"}
+          "tr_small": "k_tr_small", "tr_chain": "k_tr_chain", "rows": "k_rows"}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_leaf_step_expkernel_n65536_traffic.txt")

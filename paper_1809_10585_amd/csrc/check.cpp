@@ -254,15 +254,16 @@ void ws_jobs(const Ctx& X, const Op& o, Acc& a) {
     add_bytes(a.r, p, bytes, job);
     add_bytes(a.w, p, bytes, job);
   };
-  auto tr = [&](int j) {
+  // (tag: the job a chain's steps are reported as; they run in order)
+  auto tr = [&](int j, int tag) {
     const TrJob& J = P.trj[j];
-    rw(ws + J.hdr, TR_HDR * sizeof(double), j);
+    rw(ws + J.hdr, TR_HDR * sizeof(double), tag);
     for (int s = 0; s < 2; ++s)
       if (J.side[s].p0 > 0) {
-        rw(ws + J.side[s].node0, 2 * (size_t)J.side[s].p0 * TR_NODE * sizeof(double), j);
-        rw(cnt + J.side[s].cnt0, (size_t)J.side[s].p0 * sizeof(int), j);
+        rw(ws + J.side[s].node0, 2 * (size_t)J.side[s].p0 * TR_NODE * sizeof(double), tag);
+        rw(cnt + J.side[s].cnt0, (size_t)J.side[s].p0 * sizeof(int), tag);
       }
-    rw(cnt + J.jcounter, sizeof(int), j);
+    rw(cnt + J.jcounter, sizeof(int), tag);
   };
   auto mm = [&](int j) {
     const MmJob& J = P.mmj[j];
@@ -273,10 +274,16 @@ void ws_jobs(const Ctx& X, const Op& o, Acc& a) {
   switch (o.type) {
     case OP_TRSMALL:
     case OP_TRQR:
-      for (int i = 0; i < o.count; ++i) tr(P.trc[o.first + i].job);
+      for (int i = 0; i < o.count; ++i) tr(P.trc[o.first + i].job, P.trc[o.first + i].job);
+      break;
+    case OP_TRCHAIN:
+      for (int i = 0; i < o.count; ++i) {
+        const TrChunk& c = P.trc[o.first + i];
+        for (int s = 0; s < c.chunk; ++s) tr(c.job + s, c.job);
+      }
       break;
     case OP_TRFORM:
-      for (int i = 0; i < o.count; ++i) tr(P.trf[o.first + i].job);
+      for (int i = 0; i < o.count; ++i) tr(P.trf[o.first + i].job, P.trf[o.first + i].job);
       break;
     case OP_MMPROJ:
     case OP_MMRED:
@@ -318,6 +325,12 @@ Acc op_access(const Ctx& X, const Op& o) {
       for (int i = 0; i < o.count; ++i) jobs.push_back(P.trc[o.first + i].job);
       uniq(jobs);
       for (int j : jobs) tr_job(X, P.trj[j], j, a);
+      break;
+    case OP_TRCHAIN:  // a chain's steps run in order: one job of the launch
+      for (int i = 0; i < o.count; ++i) {
+        const TrChunk& c = P.trc[o.first + i];
+        for (int s = 0; s < c.chunk; ++s) tr_job(X, P.trj[c.job + s], c.job, a);
+      }
       break;
     case OP_TRFORM:
       for (int i = 0; i < o.count; ++i) jobs.push_back(P.trf[o.first + i].job);
@@ -364,14 +377,15 @@ Acc op_access(const Ctx& X, const Op& o) {
   ws_jobs(X, o, a);
   // workspace and counters of the op's lane (shared by all its jobs)
   const Work* W = X.C.work;
-  const bool uses_ws = o.type == OP_TRSMALL || o.type == OP_TRQR || o.type == OP_TRFORM || o.type == OP_MMPROJ ||
+  const bool uses_ws = o.type == OP_TRSMALL || o.type == OP_TRQR || o.type == OP_TRCHAIN || o.type == OP_TRFORM ||
+                       o.type == OP_MMPROJ ||
                        o.type == OP_MMRED || o.type == OP_MMAPPLY || o.type == OP_GRED;
   if (W != nullptr && uses_ws && W->ws != nullptr) {
     const int64_t sz = P.ws_lane[o.lane];
     add_bytes(a.r, W->ws + P.ws_off(o.lane), (size_t)sz * sizeof(double), -2);
     add_bytes(a.w, W->ws + P.ws_off(o.lane), (size_t)sz * sizeof(double), -2);
   }
-  const bool uses_cnt = o.type == OP_TRSMALL || o.type == OP_TRQR || o.type == OP_GRED;
+  const bool uses_cnt = o.type == OP_TRSMALL || o.type == OP_TRQR || o.type == OP_TRCHAIN || o.type == OP_GRED;
   if (W != nullptr && uses_cnt && W->counters != nullptr) {
     const int sz = P.cnt_lane[o.lane];
     add_bytes(a.r, W->counters + P.cnt_off(o.lane), (size_t)sz * sizeof(int), -2);

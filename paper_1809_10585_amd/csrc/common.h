@@ -93,7 +93,7 @@ struct TrJob {
 };
 
 struct TrChunk {    // one block of the first recompression kernel
-  int job, side, chunk;
+  int job, side, chunk;  // (k_tr_chain: jobs job .. job + chunk - 1 in order; side unused)
 };
 
 struct TrForm {     // one block of the second recompression kernel

@@ -43,7 +43,7 @@ hodlr_status fail(hodlr_status s, const std::string& m) {
 const char* const OP_NAMES[OP_NTYPES] = {
   "tr_qr", "tr_form", "mm_proj", "mm_apply", "gemm_tall", "gemm_red", "leaf_gather", "leaf_panel",
   "leaf_update", "leaf_scatter", "fill", "normalize", "leaf_trsm", "set_scal", "mm_red", "tr_small",
-  "rows", "signal", "wait"};
+  "rows", "tr_chain", "signal", "wait"};
 
 // ------------------------------------------------------------------ memory
 namespace {
@@ -223,8 +223,90 @@ hodlr_status make_leaves(DMem& mem, const Tree& t, LeafSet& S) {
 // ------------------------------------------------------------------ plan building
 bool Plan::uses_counters() const {
   for (const Op& o : ops)
-    if (o.type == OP_TRQR || o.type == OP_TRSMALL || o.type == OP_GRED) return true;
+    if (o.type == OP_TRQR || o.type == OP_TRSMALL || o.type == OP_TRCHAIN || o.type == OP_GRED) return true;
   return false;
+}
+
+// The descriptor of one recompression; its header, tree nodes and counters
+// are taken at off / cnt, which advance past them.
+TrJob Plan::make_trjob(const TrSpec& sp, int64_t& off, int& cnt) const {
+  TrJob J{};
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) J.seg[a][b] = sp.seg[a][b];
+  J.tau = sp.tau;
+  J.flags = sp.flags;
+  J.out[0] = sp.out[0];
+  J.out[1] = sp.out[1];
+  J.ldout[0] = sp.ldout[0];
+  J.ldout[1] = sp.ldout[1];
+  J.cap = sp.cap;
+  J.out_rank = sp.out_rank;
+  J.fc = sp.fc;
+  J.err = sp.err;
+  J.flops = sp.flops;
+  J.log = sp.log;
+  J.hdr = off;
+  off += TR_HDR;
+  for (int side = 0; side < 2; ++side) {
+    TrSide& S = J.side[side];
+    S.m = sp.m[side];
+    if (side == 1 && (sp.flags & TR_ORTH)) {
+      S.p0 = 0;
+      S.node0 = 0;
+      S.cnt0 = 0;
+      continue;
+    }
+    S.p0 = std::max(1, (S.m + CH - 1) / CH);
+    S.node0 = off;
+    off += 2 * (int64_t)S.p0 * TR_NODE;
+    S.cnt0 = cnt;
+    cnt += S.p0;
+  }
+  J.jcounter = cnt++;
+  return J;
+}
+
+// A chain runs in one block when every step would run in k_tr_small (factors
+// of at most tr_small_chunks chunks) and the widths stay in the narrow tiers
+// (rank capacity <= 16): a narrow step (w <= 8) runs as in k_tr_small, a wider
+// one runs its chunks one after another.  The steps share one workspace and one
+// set of counters (the largest step's).
+void Plan::trunc_chain(const std::vector<std::vector<TrSpec>>& steps) {
+  if (steps.empty()) return;
+  bool fuse = steps.size() > 1 && wtop <= 32;
+  for (const auto& st : steps) {
+    if (st.size() != steps[0].size()) fuse = false;
+    for (const TrSpec& sp : st) {
+      const int mx = std::max(sp.m[0], sp.m[1]);
+      if ((sp.flags & TR_ORTH) || mx > std::min(tune.tr_small_chunks, TRS_MAXCH) * CH) fuse = false;
+    }
+  }
+  if (!fuse) {
+    for (const auto& st : steps) trunc(st);
+    return;
+  }
+  const int first = (int)trc.size();
+  int64_t off = 0;
+  int cnt = 0;
+  for (size_t b = 0; b < steps[0].size(); ++b) {
+    const int j0 = (int)trj.size();
+    int64_t end = off;
+    int cend = cnt;
+    for (const auto& st : steps) {
+      int64_t o = off;
+      int c = cnt;
+      trj.push_back(make_trjob(st[b], o, c));
+      ++n_trunc;
+      end = std::max(end, o);
+      cend = std::max(cend, c);
+    }
+    trc.push_back(TrChunk{j0, -1, (int)steps.size()});
+    off = end;
+    cnt = cend;
+  }
+  push(Op{OP_TRCHAIN, first, (int)(trc.size() - first)});
+  ws_lane[lane] = std::max(ws_lane[lane], off);
+  cnt_lane[lane] = std::max(cnt_lane[lane], cnt);
 }
 
 void Plan::trunc(const std::vector<TrSpec>& specs) {
@@ -234,39 +316,7 @@ void Plan::trunc(const std::vector<TrSpec>& specs) {
   const int c_first = (int)trc.size(), f_first = (int)trf.size();
   std::vector<TrChunk> small;
   for (const TrSpec& sp : specs) {
-    TrJob J{};
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) J.seg[a][b] = sp.seg[a][b];
-    J.tau = sp.tau;
-    J.flags = sp.flags;
-    J.out[0] = sp.out[0];
-    J.out[1] = sp.out[1];
-    J.ldout[0] = sp.ldout[0];
-    J.ldout[1] = sp.ldout[1];
-    J.cap = sp.cap;
-    J.out_rank = sp.out_rank;
-    J.fc = sp.fc;
-    J.err = sp.err;
-    J.flops = sp.flops;
-    J.log = sp.log;
-    J.hdr = off;
-    off += TR_HDR;
-    for (int side = 0; side < 2; ++side) {
-      TrSide& S = J.side[side];
-      S.m = sp.m[side];
-      if (side == 1 && (sp.flags & TR_ORTH)) {
-        S.p0 = 0;
-        S.node0 = 0;
-        S.cnt0 = 0;
-        continue;
-      }
-      S.p0 = std::max(1, (S.m + CH - 1) / CH);
-      S.node0 = off;
-      off += 2 * (int64_t)S.p0 * TR_NODE;
-      S.cnt0 = cnt;
-      cnt += S.p0;
-    }
-    J.jcounter = cnt++;
+    const TrJob J = make_trjob(sp, off, cnt);
     const int jid = (int)trj.size();
     trj.push_back(J);
     ++n_trunc;
@@ -512,7 +562,8 @@ hodlr_status set_attrs() {
     };
     for (const void* f : {(const void*)k_tr_qr<16>, (const void*)k_tr_qr<32>, (const void*)k_tr_qr<64>,
                           (const void*)k_tr_qr<128>, (const void*)k_tr_small<16>, (const void*)k_tr_small<32>,
-                          (const void*)k_tr_small<64>, (const void*)k_tr_small<128>})
+                          (const void*)k_tr_small<64>, (const void*)k_tr_small<128>, (const void*)k_tr_chain<16>,
+                          (const void*)k_tr_chain<32>})
       set(f, TR_QR_LDS);
     set((const void*)k_tr_form, TR_FORM_LDS);
     for (const void* f : {(const void*)k_mm_apply<16>, (const void*)k_mm_apply<64>}) set(f, mm_apply_lds(MAXLEAF));
@@ -560,6 +611,10 @@ void run_op(const Plan& P, const Work& W, const Op& o, hipStream_t st, const Lau
       launch(L, kern, o.count, NT_TR, TR_QR_LDS, st, P.d_trj, P.d_trc, o.first, ws, cnt);
       break;
     }
+    case OP_TRCHAIN:
+      launch(L, P.wtop <= 16 ? k_tr_chain<16> : k_tr_chain<32>, o.count, NT_TR, TR_QR_LDS, st, P.d_trj, P.d_trc,
+             o.first, ws, cnt);
+      break;
     case OP_TRFORM:
       launch(L, k_tr_form, o.count, NT_MM, TR_FORM_LDS, st, P.d_trj, P.d_trf, o.first, (const double*)ws);
       break;
@@ -982,31 +1037,32 @@ struct QRBuilder {
       mms.push_back(b);
     }
     P.mm(t, mms);
-    // S~ = T(Y_A11^T A12 + Y_A21^T A22 + sum over groups), term by term
+    // S~ = T(Y_A11^T A12 + Y_A21^T A22 + sum over groups), term by term: one
+    // chain of recompressions
+    std::vector<std::vector<TrSpec>> chain(1);
     for (hodlr_qr_s* Fp : Fs) {
       hodlr_qr_s& F = *Fp;
       const HBlk& A12 = F.up.hview[v];
       const HBlk& A21 = F.lo.hview[v];
       int* k12 = F.rank_up(v);
       int* k21 = F.rank_lo(v);
-      trs.push_back(trspec(F, mkseg(F.Z1, nL, k12), mkseg(A21.V, nL, k21), mkseg(A12.V, nR, k12),
-                           mkseg(F.Z2, nR, k21), nL, nR, F.scal + 1, F.SL, F.SR, nL, nR, F.rank_s(), FC_TRUNC,
-                           LogKey{RL_S, klo, khi, 0, 0}));
+      chain[0].push_back(trspec(F, mkseg(F.Z1, nL, k12), mkseg(A21.V, nL, k21), mkseg(A12.V, nR, k12),
+                                mkseg(F.Z2, nR, k21), nL, nR, F.scal + 1, F.SL, F.SR, nL, nR, F.rank_s(),
+                                FC_TRUNC, LogKey{RL_S, klo, khi, 0, 0}));
     }
-    P.trunc(trs);
     for (size_t gi = 0; gi < groups.size(); ++gi) {
       const int g = groups[gi];
-      trs.clear();
+      chain.emplace_back();
       for (hodlr_qr_s* Fp : Fs) {
         hodlr_qr_s& F = *Fp;
         int* rS = F.rank_s();
-        trs.push_back(trspec(F, mkseg(F.SL, nL, rS), mkseg(gslice(F, g, Lc), gld(g), grank(F, g)),
-                             mkseg(F.SR, nR, rS), mkseg(gslice(F, g, Rc), gld(g), grank(F, g)), nL, nR,
-                             F.scal + 1, F.SL, F.SR, nL, nR, rS, FC_TRUNC,
-                             LogKey{RL_S, klo, khi, 1 + (int)gi, 0}));
+        chain.back().push_back(trspec(F, mkseg(F.SL, nL, rS), mkseg(gslice(F, g, Lc), gld(g), grank(F, g)),
+                                      mkseg(F.SR, nR, rS), mkseg(gslice(F, g, Rc), gld(g), grank(F, g)), nL,
+                                      nR, F.scal + 1, F.SL, F.SR, nL, nR, rS, FC_TRUNC,
+                                      LogKey{RL_S, klo, khi, 1 + (int)gi, 0}));
       }
-      P.trunc(trs);
     }
+    P.trunc_chain(chain);
     // S = T1^T S~  (left factor only); T1 must be complete
     if (evL >= 0) P.wait(evL);
     mms.clear();
@@ -1184,8 +1240,9 @@ struct QRBuilder {
     };
     const size_t nterm = (has_e ? 1 : 0) + 1 + groups.size();
     const size_t nchain = std::max<size_t>(1, nterm - 1);
+    std::vector<std::vector<TrSpec>> tchain;
     for (size_t i = 0; i < nchain; ++i) {
-      trs.clear();
+      std::vector<TrSpec>& trs = tchain.emplace_back();
       for (hodlr_qr_s* Fp : Fs) {
         hodlr_qr_s& F = *Fp;
         const HBlk& A21 = F.lo.hview[v];
@@ -1212,8 +1269,8 @@ struct QRBuilder {
           trs.push_back(trspec(F, l0, terms[nx].l, r0, terms[nx].r, nL, nR, F.scal + 2, outL, F.TR, nL, nR, rt,
                                FC_TRUNC, key));
       }
-      P.trunc(trs);
     }
+    P.trunc_chain(tchain);
     // T12 = -T1 T~12 T2 = (-T1 T~_L)(T2^T T~_R)^T
     mms.clear();
     for (hodlr_qr_s* Fp : Fs) {
@@ -1574,6 +1631,20 @@ void merge_plans(const std::vector<const Plan*>& in, Plan& out, bool plant = fal
           const Op& o = in[g]->ops[seq[g][h[g]]];
           for (int i = 0; i < o.count; ++i) {
             TrChunk c = in[g]->trc[o.first + i];
+            c.job = rebase_tr(g, o.lane, c.job);
+            out.trc.push_back(c);
+          }
+        }
+        m.count = (int)out.trc.size() - m.first;
+        break;
+      }
+      case OP_TRCHAIN: {
+        m.first = (int)out.trc.size();
+        for (int g : grp) {
+          const Op& o = in[g]->ops[seq[g][h[g]]];
+          for (int i = 0; i < o.count; ++i) {
+            TrChunk c = in[g]->trc[o.first + i];
+            for (int s = 1; s < c.chunk; ++s) rebase_tr(g, o.lane, c.job + s);
             c.job = rebase_tr(g, o.lane, c.job);
             out.trc.push_back(c);
           }

@@ -630,8 +630,10 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
   }
 }
 
-template <int W>
-// Returns true in the block that ran the SVD (the job's last block).
+// Returns true in the block that ran the SVD (the job's last block).  LOCAL:
+// every chunk of the job runs in this block (one after another), so the
+// hand-offs between chunks need only block-scope fences.
+template <int W, bool LOCAL = false>
 __device__ __forceinline__ bool tr_chunk(const TrJob& J, int side, int chunk, double* ws, int* counters, int* err,
                          double* fc, double* smem, int w, int n0a, int n0b) {
   constexpr int TPC = NT_TR / W;
@@ -698,7 +700,7 @@ __device__ __forceinline__ bool tr_chunk(const TrJob& J, int side, int chunk, do
     const int nchild = min(G, count - pidx * G);
     const int64_t pbase = base + count;
     const int64_t pslot = pbase + pidx;
-    __threadfence();
+    if constexpr (LOCAL) __threadfence_block(); else __threadfence();
     __syncthreads();
     if (tid == 0) {
       int* cnt = counters + S.cnt0 + (int)(pslot - S.p0);
@@ -711,7 +713,7 @@ __device__ __forceinline__ bool tr_chunk(const TrJob& J, int side, int chunk, do
     const int last = sflag[0];
     __syncthreads();
     if (!last) return false;
-    __threadfence();
+    if constexpr (LOCAL) __threadfence_block(); else __threadfence();
     // become the parent: stack the children's R factors
     const int64_t cbase = base;
     const int cfirst = pidx * G;
@@ -733,7 +735,7 @@ __device__ __forceinline__ bool tr_chunk(const TrJob& J, int side, int chunk, do
   }
   // this side is reduced; join the two sides
   if (!(J.flags & TR_ORTH)) {
-    __threadfence();
+    if constexpr (LOCAL) __threadfence_block(); else __threadfence();
     __syncthreads();
     if (tid == 0) {
       int* cnt = counters + J.jcounter;
@@ -746,7 +748,7 @@ __device__ __forceinline__ bool tr_chunk(const TrJob& J, int side, int chunk, do
     const int last = sflag[0];
     __syncthreads();
     if (!last) return false;
-    __threadfence();
+    if constexpr (LOCAL) __threadfence_block(); else __threadfence();
   }
   tr_svd<W>(J, ws, w, n0a, n0b, smem, err, fc);
   return true;
@@ -1380,20 +1382,20 @@ __device__ __forceinline__ void tr_small_form(const TrJob& J, const double* ws, 
 // Wider jobs: the chunk code of k_tr_qr, one block per chunk (the chunks
 // and sides join through the job's counters); the block that ran the SVD
 // then forms both factors.
-template <int WTOP>
+template <int WTOP, bool LOCAL = false>
 __device__ __forceinline__ void tr_small_wide(const TrJob& J, int side, int chunk, int w, int n0a, int n0b,
                                               double* ws, int* counters, double* smem) {
   const int t = tier_of(w);
   bool last = false;
   if (t == 16) {
-    if constexpr (WTOP >= 16) last = tr_chunk<16>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+    if constexpr (WTOP >= 16) last = tr_chunk<16, LOCAL>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
   } else if (t == 32) {
-    if constexpr (WTOP >= 32) last = tr_chunk<32>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+    if constexpr (WTOP >= 32) last = tr_chunk<32, LOCAL>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
   } else if (t == 64) {
-    if constexpr (WTOP >= 64) last = tr_chunk<64>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+    if constexpr (WTOP >= 64) last = tr_chunk<64, LOCAL>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
   } else {
     if constexpr (WTOP >= 128)
-      last = tr_chunk<128>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
+      last = tr_chunk<128, LOCAL>(J, side, chunk, ws, counters, J.err, J.flops, smem, w, n0a, n0b);
   }
   if (!last) return;
   __threadfence_block();
@@ -1437,6 +1439,55 @@ __global__ void __launch_bounds__(NT_TR) k_tr_small(const TrJob* __restrict__ jo
   }
   tr_small_wide<WTOP>(J, it.side, it.chunk, w, n0a, n0b, ws, counters, smem);
 }
+
+// A chain of recompressions in one block: jobs it.job .. it.job + it.chunk - 1
+// in order, each reading the previous one's output (the term-by-term sums of
+// Sec. 4: every added term is recompressed at once).  A step runs as k_tr_small
+// runs a job: narrow (w <= 8) as one block does; wider, its chunks one after
+// another in this block, the last one running the SVD and forming both
+// factors.  The steps share the chain's workspace and counters; each step's
+// outputs and rank are visible to the next after a block-scope fence (one
+// block, one L2: no device-scope write-back and invalidation between steps).
+// A wide step of a chain: its chunks one after another (out of line, so that
+// the narrow steps keep the register allocation of k_tr_small).
+template <int WTOP>
+__device__ __noinline__ void tr_chain_wide(const TrJob& J, int w, int n0a, int n0b, double* ws, int* counters,
+                                           double* smem) {
+  for (int side = 0; side < 2; ++side)
+    for (int c = 0; c < J.side[side].p0; ++c) {
+      tr_small_wide<WTOP, true>(J, side, c, w, n0a, n0b, ws, counters, smem);
+      __syncthreads();
+    }
+}
+
+template <int WTOP>
+__global__ void __launch_bounds__(NT_TR) k_tr_chain(const TrJob* __restrict__ jobs,
+                                                     const TrChunk* __restrict__ items, int first,
+                                                     double* ws, int* counters) {
+  extern __shared__ double smem[];
+  const TrChunk it = items[first + blockIdx.x];
+#pragma unroll 1
+  for (int s = 0; s < it.chunk; ++s) {
+    const TrJob& J = jobs[it.job + s];
+    const int n0a = seg_n(J.seg[0][0]);
+    const int w = n0a + seg_n(J.seg[0][1]);
+    const int n0b = seg_n(J.seg[1][0]);
+    if (w == 0 || w > WTOP || max(J.side[0].m, J.side[1].m) > TRS_MAXCH * CH) {
+      if (threadIdx.x == 0) {
+        tr_set_rank(J, w, 0);
+        if (w > 0) atomicOr(J.err, ERR_WIDTH);
+      }
+    } else if (w <= 4) {
+      tr_small_narrow<4>(J, w, n0a, n0b, smem);
+    } else if (w <= 8) {
+      tr_small_narrow<8>(J, w, n0a, n0b, smem);
+    } else {
+      tr_chain_wide<WTOP>(J, w, n0a, n0b, ws, counters, smem);
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
 }  // namespace hq
 
 namespace hq {
@@ -1444,6 +1495,8 @@ template __global__ void k_tr_qr<16>(const TrJob*, const TrChunk*, int, double*,
 template __global__ void k_tr_qr<32>(const TrJob*, const TrChunk*, int, double*, int*);
 template __global__ void k_tr_qr<64>(const TrJob*, const TrChunk*, int, double*, int*);
 template __global__ void k_tr_qr<128>(const TrJob*, const TrChunk*, int, double*, int*);
+template __global__ void k_tr_chain<16>(const TrJob*, const TrChunk*, int, double*, int*);
+template __global__ void k_tr_chain<32>(const TrJob*, const TrChunk*, int, double*, int*);
 template __global__ void k_tr_small<16>(const TrJob*, const TrChunk*, int, double*, int*);
 template __global__ void k_tr_small<32>(const TrJob*, const TrChunk*, int, double*, int*);
 template __global__ void k_tr_small<64>(const TrJob*, const TrChunk*, int, double*, int*);

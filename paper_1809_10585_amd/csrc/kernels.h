@@ -24,6 +24,9 @@ template <int WTOP>
 __global__ void k_tr_qr(const TrJob* __restrict__ jobs, const TrChunk* __restrict__ items, int first,
                         double* ws, int* counters);
 template <int WTOP>
+__global__ void k_tr_chain(const TrJob* __restrict__ jobs, const TrChunk* __restrict__ items, int first,
+                           double* ws, int* counters);
+template <int WTOP>
 __global__ void k_tr_small(const TrJob* __restrict__ jobs, const TrChunk* __restrict__ items, int first,
                            double* ws, int* counters);
 __global__ void k_tr_form(const TrJob* __restrict__ jobs, const TrForm* __restrict__ items, int first,

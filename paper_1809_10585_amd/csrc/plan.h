@@ -211,6 +211,7 @@ enum OpType {
   OP_LUPDATE, OP_LSCATTER, OP_FILL, OP_NORMALIZE, OP_TRSM, OP_SETSCAL,
   OP_MMRED, OP_TRSMALL,
   OP_ROWS,    // row runs between arrays (k_rows)
+  OP_TRCHAIN, // chains of recompressions, one block per chain (k_tr_chain)
   OP_SIGNAL,  // record event a0 on the op's lane (no kernel)
   OP_WAIT,    // the op's lane waits for event a0 (no kernel)
   OP_NTYPES
@@ -368,6 +369,10 @@ struct Plan {
   std::vector<char> staged;  // host image of the descriptors (kept until the copy is done)
 
   void trunc(const std::vector<TrSpec>& specs);
+  // steps[s][b]: step s of chain b (step s + 1 reads step s's output); one
+  // launch when every step fits one block, else one trunc() per step
+  void trunc_chain(const std::vector<std::vector<TrSpec>>& steps);
+  TrJob make_trjob(const TrSpec& sp, int64_t& off, int& cnt) const;
   void mm(const Tree& t, const std::vector<MmSpec>& specs);
   void gemm_tall(const std::vector<GSpec>& specs);
   void gemm_red(const std::vector<GSpec>& specs);

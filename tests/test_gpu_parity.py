@@ -656,6 +656,32 @@ def test_recompression_and_leaf_paths(H, n, leaf, k, cap, seed):
     assert np.linalg.norm(QtQX - X) / np.linalg.norm(X) <= 10 * EPS
 
 
+# Chains of recompressions (the term-by-term S~ and T~12 sums) run in one block
+# per chain when the rank capacity is at most 16: narrow steps (w <= 8, the
+# exp kernel, whose parity test_expkernel_parity checks) and wider ones whose
+# chunks the block runs one after another (Gaussian rank 2: widths up to 24).
+def test_recompression_chains(H):
+    inp = G.expkernel_hodlr(4096, 256, seed=2)
+    prof = H.hodlr_qr_profile(H.hodlr_build(inp, rank_cap=16), EPS, anorm=oracle_anorm(inp, ("exp", 4096)))
+    assert prof["tr_chain"]["count"] > 0 and "tr_small" in prof, prof.keys()
+    n, seed = 4096, 11
+    inp = G.gaussian_hodlr(n, 256, 2, seed=seed)
+    A = H.hodlr_build(inp, rank_cap=16)
+    an = oracle_anorm(inp)
+    prof = H.hodlr_qr_profile(A, EPS, anorm=an)
+    assert prof["tr_chain"]["count"] > 0, prof.keys()
+    F = H.hodlr_qr(A, EPS, anorm=an)
+    ref = O.hqr(inp, EPS, anorm=an)
+    widths = [t["w"] for t in ref.counter.truncs]
+    print(f"gaussian n={n}: {prof['tr_chain']['count']} chain launches, widest recompression {max(widths)}")
+    assert max(widths) > 8
+    X = np.random.default_rng(seed).standard_normal((n, 6))
+    rR = _rel(H.hodlr_qr_matmul(F, "R", H.colmajor(X)).cpu().numpy(), O.rmat(ref, X))
+    rQ = _rel(H.hodlr_apply_q(F, H.colmajor(X)).cpu().numpy(), O.apply_q(ref, X), np.linalg.norm(X))
+    assert rR <= 1e-8 and rQ <= 1e-8, (rR, rQ)
+    assert ranklog_check(H, F, ref)[1] == 0
+
+
 def test_batched_time_runs(H):
     inps = _batch_inputs()[:2]
     As = [H.hodlr_build(inp, rank_cap=32) for inp in inps]
