@@ -60,20 +60,26 @@ __device__ __forceinline__ d4_t leaf_ytb_acc(const double* Ys, const double* Bs,
   return acc;
 }
 
-// Sum the 16 wavefronts' 16 x 16 tiles into out (ld NB).
+// Sum the 16 wavefronts' 16 x 16 tiles into out: out[i + NB j] (TOUT = false)
+// or its transpose out[j + NB i] (TOUT = true).  The partial tiles are stored
+// row by row (element (i, j) at j + NB i), so that the lanes of a wavefront,
+// whose j runs fastest, write consecutive doubles (column by column, the
+// 16-double stride put 8 lanes on each bank pair).
+template <bool TOUT = false>
 __device__ __forceinline__ void leaf_reduce_tile(d4_t acc, double* part, double* out) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int i = 4 * e + (l >> 4), j = l & 15;
-    part[w * 256 + i + NB * j] = acc[e];
+    part[w * 256 + j + NB * i] = acc[e];
   }
   __syncthreads();
   if (threadIdx.x < 256) {
     double sacc = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) sacc += part[q * 256 + threadIdx.x];
-    out[threadIdx.x] = sacc;
+    const int j = threadIdx.x & 15, i = threadIdx.x >> 4;
+    out[TOUT ? threadIdx.x : i + NB * j] = sacc;
   }
   __syncthreads();
 }
@@ -285,9 +291,9 @@ __device__ __forceinline__ void leaf_strip(const LeafWs& W, int c0, int pw, int 
   double* Bs = Ys + LF_LD * NB;
   double* Wt = sm + LF_W;
   double* Tt = Wt + 2 * NB * NB;
-  double tval = 0.0;  // T_pp tile, loaded together with the first staging
+  double tval = 0.0;  // T_pp tile (transposed: T(i, j) at j + NB i), loaded with the first staging
   if (tid < 256) {
-    const int i = tid & 15, j = tid >> 4;
+    const int j = tid & 15, i = tid >> 4;
     tval = (i <= j && i < pw && j < pw) ? gmem(W.T)[(int64_t)(c0 + i) + (int64_t)(c0 + j) * MAXLEAF] : 0.0;
   }
   d4_t acc = {0.0, 0.0, 0.0, 0.0};
@@ -300,14 +306,15 @@ __device__ __forceinline__ void leaf_strip(const LeafWs& W, int c0, int pw, int 
     if (!one_chunk) __syncthreads();
   }
   if (tid < 256) Tt[tid] = tval;
-  leaf_reduce_tile(acc, sm + LF_PART, Wt);
+  leaf_reduce_tile<true>(acc, sm + LF_PART, Wt);  // W transposed: W(i, j) at j + NB i
   // W2 = T^T W: A[i][k] = T[k][i], B[k][j] = W[k][j]; D[i][j] sits in lane
   // j + 16 (i % 4), element i / 4, i.e. element e of lane l is W2[4e + l/16][l%16]:
-  // the B operand of k-step e of the update below
+  // the B operand of k-step e of the update below.  Both tiles are stored
+  // transposed, so the lanes (l % 16 fastest) read consecutive doubles.
   d4_t w2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k0 = 0; k0 < NB; k0 += 4)
-    w2 = mfma16(Tt[(k0 + (l >> 4)) + NB * (l & 15)], Wt[(k0 + (l >> 4)) + NB * (l & 15)], w2);
+    w2 = mfma16(Tt[(l & 15) + NB * (k0 + (l >> 4))], Wt[(l & 15) + NB * (k0 + (l >> 4))], w2);
   for (int r0 = c0; r0 < M; r0 += LF_CH) {
     const int rn = min(LF_CH, M - r0);
     if (!one_chunk) {
