@@ -432,13 +432,20 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_tall(const GemmJob* __restrict__
       Bt[kk][cc] = (kk < kn && cc < nc) ? gB(J, k0 + kk, it.col0 + cc) : 0.0;
     }
     __syncthreads();
+    // the tiles are zero past kn: sum over kn rounded up to 4 (the K of the
+    // update's products is a rank, often 1..3, not 32)
+    const int k4 = (kn + 3) & ~3;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int cc = cg + 4 * q;
       if (cc < nc) {  // uniform in the wavefront (cg is its index): skips empty columns
         double sacc = acc[q];
-#pragma unroll 8
-        for (int kk = 0; kk < 32; ++kk) sacc += At[r][kk] * Bt[kk][cc];
+        for (int kk = 0; kk < k4; kk += 4) {
+          sacc += At[r][kk] * Bt[kk][cc];
+          sacc += At[r][kk + 1] * Bt[kk + 1][cc];
+          sacc += At[r][kk + 2] * Bt[kk + 2][cc];
+          sacc += At[r][kk + 3] * Bt[kk + 3][cc];
+        }
         acc[q] = sacc;
       }
     }
