@@ -682,6 +682,29 @@ def test_recompression_chains(H):
     assert ranklog_check(H, F, ref)[1] == 0
 
 
+# Wide recompressions over the lane shapes of the one-sided Jacobi (lanes per
+# column pair x rows per lane: 32 x 1 for widths 17..32, 16 x 3..4 up to 64,
+# 8 x 10..16 up to 128): Gaussian HODLR matrices whose ranks put recompressions
+# in each class up to 81..96 (k = 3: widths 18..27; 7: up to 63; 8: 24..72;
+# 10: 70 and 90), against the oracle decision by decision.  (Rank 11 reaches
+# width 99 but an intermediate rank then exceeds the capacity 64.)
+@pytest.mark.parametrize("k,seed", [(3, 61), (7, 67), (8, 66), (10, 64)])
+def test_wide_recompression_width_classes(H, k, seed):
+    n = 2048
+    inp = G.gaussian_hodlr(n, 256, k, seed=seed)
+    an = oracle_anorm(inp)
+    F = H.hodlr_qr(H.hodlr_build(inp, rank_cap=64), EPS, anorm=an)
+    ref = O.hqr(inp, EPS, anorm=an)
+    widths = sorted({t["w"] for t in ref.counter.truncs})
+    print(f"k={k}: recompression widths {widths[0]}..{widths[-1]}, "
+          f"{sum(1 for w in widths if w > 16)} distinct widths above 16")
+    X = np.random.default_rng(seed).standard_normal((n, 6))
+    rR = _rel(H.hodlr_qr_matmul(F, "R", H.colmajor(X)).cpu().numpy(), O.rmat(ref, X))
+    rQ = _rel(H.hodlr_apply_q(F, H.colmajor(X)).cpu().numpy(), O.apply_q(ref, X), np.linalg.norm(X))
+    assert rR <= 1e-8 and rQ <= 1e-8, (rR, rQ)
+    assert ranklog_check(H, F, ref)[1] == 0
+
+
 def test_batched_time_runs(H):
     inps = _batch_inputs()[:2]
     As = [H.hodlr_build(inp, rank_cap=32) for inp in inps]
