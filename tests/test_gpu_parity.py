@@ -529,6 +529,26 @@ def test_batched_equals_one_at_a_time_bitwise(H, mode):
         assert np.array_equal(H.hodlr_qr_ranklog(Fi), H.hodlr_qr_ranklog(F1))
 
 
+@pytest.mark.parametrize("mode", ["merged", "merged_graph"])
+def test_batched_chains_bitwise(H, mode):
+    """At rank capacity 16 the recompression chains run one block per chain
+    (k_tr_chain); merged across shapes, and captured as a HIP graph, each
+    factorisation still gives the bits hodlr_qr gives alone."""
+    flags = {"merged": 0, "merged_graph": H.HODLR_QR_GRAPH}[mode]
+    inps = [G.gaussian_hodlr(n, 256, k, seed=sd) for n, k, sd in [(1024, 1, 70), (2048, 2, 71), (1024, 2, 72)]]
+    As = [H.hodlr_build(inp, rank_cap=16) for inp in inps]
+    assert H.hodlr_qr_profile(As[1], EPS)["tr_chain"]["count"] > 0
+    Fb = H.hodlr_qr_batched(As, EPS, flags=flags)
+    for inp, A, Fi in zip(inps, As, Fb):
+        X = np.random.default_rng(6).standard_normal((inp.n, 4))
+        F1 = H.hodlr_qr(A, EPS)
+        for which in "YTR":
+            a = H.hodlr_qr_matmul(Fi, which, H.colmajor(X)).cpu().numpy()
+            b = H.hodlr_qr_matmul(F1, which, H.colmajor(X)).cpu().numpy()
+            assert np.array_equal(a, b), which
+        assert np.array_equal(H.hodlr_qr_ranklog(Fi), H.hodlr_qr_ranklog(F1))
+
+
 def test_batched_graph_replays(H):
     """The merged batch schedule kept (HODLR_QR_KEEP) and captured as one HIP
     graph, then replayed by hodlr_qr_refactor several times with eager work and
