@@ -633,14 +633,14 @@ __device__ __forceinline__ void tr_svd(const TrJob& J, double* ws, int w, int n0
 // Returns true in the block that ran the SVD (the job's last block).  LOCAL:
 // every chunk of the job runs in this block (one after another), so the
 // hand-offs between chunks need only block-scope fences.
-template <bool LOCAL>
-__device__ __forceinline__ bool tr_chunk128(const TrJob& J, int side, int chunk, double* ws, int* counters, int* err,
-                                            double* fc, double* smem, int w, int n0a, int n0b);
+template <int W, bool LOCAL>
+__device__ __forceinline__ bool tr_chunk2p(const TrJob& J, int side, int chunk, double* ws, int* counters, int* err,
+                                           double* fc, double* smem, int w, int n0a, int n0b);
 
 template <int W, bool LOCAL = false>
 __device__ __forceinline__ bool tr_chunk(const TrJob& J, int side, int chunk, double* ws, int* counters, int* err,
                          double* fc, double* smem, int w, int n0a, int n0b) {
-  if constexpr (W == 128) return tr_chunk128<LOCAL>(J, side, chunk, ws, counters, err, fc, smem, w, n0a, n0b);
+  if constexpr (W >= 64) return tr_chunk2p<W, LOCAL>(J, side, chunk, ws, counters, err, fc, smem, w, n0a, n0b);
   constexpr int TPC = NT_TR / W;
   constexpr int RPT = CH / TPC;
   constexpr int G = CH / W;
@@ -759,27 +759,28 @@ __device__ __forceinline__ bool tr_chunk(const TrJob& J, int side, int chunk, do
   return true;
 }
 
-// ---- the 128-column tier: a tile of h <= 256 rows and 64 < w <= 128 columns
-// as two panels of 64 columns, each in the register layout of the 64-column
-// tier (thread (c, sub) = (tid / 8, tid % 8) holds rows sub + 8 i, i < 32, of
-// panel column c).  One 256 x 128 tile in registers (64 rows per thread) did
-// not fit beside the rest of the kernel and was spilled to scratch, about six
-// times the time per column of the 64-column tier.  Panel A (columns 0..63) is
-// factorised; its reflectors go to LDS and are applied, one after another, to
-// panel B (columns 64..w-1), whose rows 64.. are then factorised: the
-// Householder QR of the whole tile, column by column.  R goes to node (ld
-// WMAX); with wantq, the explicit Q (h x w, ld CH) to Qa, formed as
-// H_A (H_B [I; 0]) with the reflectors read back from Qa.
-constexpr int T2_TPC = 8, T2_RPT = CH / T2_TPC;
-
-template <class LD>
+// ---- the 64- and 128-column tiers: a tile of h <= 256 rows and PW < w <= 2 PW
+// columns (PW = W / 2) as two panels of PW columns, each in the register layout
+// of the PW-column tier (thread (c, sub) = (tid / TPC, tid % TPC), TPC =
+// NT_TR / PW, holds rows sub + TPC i, i < CH / TPC, of panel column c).  One
+// 256 x W tile in registers holds twice the rows per thread, and at W = 128 it
+// did not fit beside the rest of the kernel (spilled to scratch: about six
+// times the time per column of the 64-column tier); and a panel keeps every
+// thread busy on its columns instead of idling the threads of the finished
+// ones.  Panel A (columns 0..PW-1) is factorised; its reflectors go to LDS and
+// are applied, one after another, to panel B (columns PW..w-1), whose rows
+// PW.. are then factorised: the Householder QR of the whole tile, column by
+// column.  R goes to node (ld WMAX); with wantq, the explicit Q (h x w, ld CH)
+// to Qa, formed as H_A (H_B [I; 0]) with the reflectors read back from Qa.
+template <int PW, class LD>
 __device__ __forceinline__ void qr2_tile(const LD& ld, int h, int w, bool wantq, double* node, double* Qa,
                                          double* smem) {
+  constexpr int T2_TPC = NT_TR / PW, T2_RPT = CH / T2_TPC;
   const int tid = threadIdx.x, c = tid / T2_TPC, sub = tid % T2_TPC;
   double* vbuf = smem + TRS_VBUF;
-  double* taus = smem + TRS_TAU;  // panel A: taus[0..63], panel B: taus[64..]
-  double* Vs = smem + TRS_X;      // panel A's columns (ld CH), later Q's first 64 columns
-  const int wB = w - 64, hB = max(h - 64, 0);
+  double* taus = smem + TRS_TAU;  // panel A: taus[0..PW-1], panel B: taus[PW..]
+  double* Vs = smem + TRS_X;      // panel A's columns (ld CH), later Q's first PW columns
+  const int wB = w - PW, hB = max(h - PW, 0);
   const bool liveB = c < wB;
   {
     double a[T2_RPT];
@@ -788,7 +789,7 @@ __device__ __forceinline__ void qr2_tile(const LD& ld, int h, int w, bool wantq,
       const int r = sub + T2_TPC * i;
       a[i] = (r < h) ? ld(r, c) : 0.0;
     }
-    reg_qr<T2_TPC, T2_RPT>(a, c, sub, h, 64, vbuf, taus, nullptr, 0);
+    reg_qr<T2_TPC, T2_RPT>(a, c, sub, h, PW, vbuf, taus, nullptr, 0);
 #pragma unroll
     for (int i = 0; i < T2_RPT; ++i) {
       const int r = sub + T2_TPC * i;
@@ -798,12 +799,12 @@ __device__ __forceinline__ void qr2_tile(const LD& ld, int h, int w, bool wantq,
     }
   }
   __syncthreads();
-  const int jA = min(h, 64);
+  const int jA = min(h, PW);
   double b[T2_RPT];
 #pragma unroll
   for (int i = 0; i < T2_RPT; ++i) {
     const int r = sub + T2_TPC * i;
-    b[i] = (liveB && r < h) ? ld(r, 64 + c) : 0.0;
+    b[i] = (liveB && r < h) ? ld(r, PW + c) : 0.0;
   }
   if (liveB) {  // whole 8-lane groups: the sums stay inside the group
     for (int j = 0; j < jA; ++j) {
@@ -825,43 +826,44 @@ __device__ __forceinline__ void qr2_tile(const LD& ld, int h, int w, bool wantq,
       }
     }
   }
-  // rows 0..63 of panel B are R's; rows 64.. are factorised
+  // rows 0..PW-1 of panel B are R's; rows PW.. are factorised
+  constexpr int RA = PW / T2_TPC;  // register rows of a thread above row PW
 #pragma unroll
-  for (int i = 0; i < 64 / T2_TPC; ++i) {
+  for (int i = 0; i < RA; ++i) {
     const int r = sub + T2_TPC * i;
-    if (liveB) node[r + (64 + c) * WMAX] = (r < h) ? b[i] : 0.0;
+    if (liveB) node[r + (PW + c) * WMAX] = (r < h) ? b[i] : 0.0;
   }
-  constexpr int RB = T2_RPT - 64 / T2_TPC;
+  constexpr int RB = T2_RPT - RA;
   double bb[RB];
 #pragma unroll
-  for (int i = 0; i < RB; ++i) bb[i] = b[64 / T2_TPC + i];
-  reg_qr<T2_TPC, RB>(bb, c, sub, hB, wB, vbuf, taus + 64, nullptr, 0);
+  for (int i = 0; i < RB; ++i) bb[i] = b[RA + i];
+  reg_qr<T2_TPC, RB>(bb, c, sub, hB, wB, vbuf, taus + PW, nullptr, 0);
 #pragma unroll
   for (int i = 0; i < RB; ++i) {
-    const int r = sub + T2_TPC * i;  // row 64 + r of the tile
-    if (liveB && 64 + r < w) node[(64 + r) + (64 + c) * WMAX] = (r <= c && r < hB) ? bb[i] : 0.0;
-    if (wantq && liveB && r < hB) Qa[(64 + r) + (64 + c) * CH] = bb[i];
+    const int r = sub + T2_TPC * i;  // row PW + r of the tile
+    if (liveB && PW + r < w) node[(PW + r) + (PW + c) * WMAX] = (r <= c && r < hB) ? bb[i] : 0.0;
+    if (wantq && liveB && r < hB) Qa[(PW + r) + (PW + c) * CH] = bb[i];
   }
   if (!wantq) return;
   __threadfence_block();
   __syncthreads();
-  // Q's columns 0..63: H_A [e_c] (panel B's reflectors act on rows >= 64 only)
+  // Q's columns 0..PW-1: H_A [e_c] (panel B's reflectors act on rows >= PW only)
   {
     double q[T2_RPT];
-    reg_formq_g<T2_TPC, T2_RPT>(Qa, q, c, sub, h, 64, vbuf, taus);
+    reg_formq_g<T2_TPC, T2_RPT>(Qa, q, c, sub, h, PW, vbuf, taus);
 #pragma unroll
     for (int i = 0; i < T2_RPT; ++i) {
       const int r = sub + T2_TPC * i;
       Vs[r + c * CH] = q[i];
     }
   }
-  // Q's columns 64..w-1: H_B [e_c] on rows 64.., then H_A on all rows
+  // Q's columns PW..w-1: H_B [e_c] on rows PW.., then H_A on all rows
   double q2[T2_RPT];
   {
     double qb[RB];
-    reg_formq_g<T2_TPC, RB>(Qa + 64 + 64 * (int64_t)CH, qb, c, sub, hB, wB, vbuf, taus + 64);
+    reg_formq_g<T2_TPC, RB>(Qa + PW + PW * (int64_t)CH, qb, c, sub, hB, wB, vbuf, taus + PW);
 #pragma unroll
-    for (int i = 0; i < T2_RPT; ++i) q2[i] = (i < 64 / T2_TPC) ? 0.0 : qb[i - 64 / T2_TPC];
+    for (int i = 0; i < T2_RPT; ++i) q2[i] = (i < RA) ? 0.0 : qb[i - RA];
   }
   for (int j = jA - 1; j >= 0; --j) {
     double* vb = vbuf + (j & 1) * CH;
@@ -889,17 +891,17 @@ __device__ __forceinline__ void qr2_tile(const LD& ld, int h, int w, bool wantq,
     const int r = sub + T2_TPC * i;
     if (r < h) {
       Qa[r + c * CH] = Vs[r + c * CH];
-      if (liveB) Qa[r + (64 + c) * CH] = q2[i];
+      if (liveB) Qa[r + (PW + c) * CH] = q2[i];
     }
   }
 }
 
-// tr_chunk for the 128-column tier (the same tree, joins and SVD) with the
-// tile factorised by qr2_tile.
-template <bool LOCAL>
-__device__ __forceinline__ bool tr_chunk128(const TrJob& J, int side, int chunk, double* ws, int* counters, int* err,
-                                            double* fc, double* smem, int w, int n0a, int n0b) {
-  constexpr int G = CH / 128;
+// tr_chunk for the 64- and 128-column tiers (the same tree, joins and SVD)
+// with the tile factorised by qr2_tile.
+template <int W, bool LOCAL>
+__device__ __forceinline__ bool tr_chunk2p(const TrJob& J, int side, int chunk, double* ws, int* counters, int* err,
+                                           double* fc, double* smem, int w, int n0a, int n0b) {
+  constexpr int G = CH / W;
   const int tid = threadIdx.x;
   int* sflag = (int*)(smem + TRS_FLAG);
   const TrSide S = J.side[side];
@@ -922,14 +924,14 @@ __device__ __forceinline__ bool tr_chunk128(const TrJob& J, int side, int chunk,
         return col < n0 ? s0.scale * s0.p[gr + (int64_t)col * s0.ld]
                         : s1.scale * s1.p[gr + (int64_t)(col - n0) * s1.ld];
       };
-      qr2_tile(ld, h, w, side == 0, node, Qa, smem);
+      qr2_tile<W / 2>(ld, h, w, side == 0, node, Qa, smem);
     } else {
       const double* kids = ws + S.node0 + (cbase + cfirst) * TR_NODE;
       auto ld = [&](int r, int col) -> double {
         const int ch = r / w, rr = r % w;
         return kids[(int64_t)ch * TR_NODE + rr + col * WMAX];
       };
-      qr2_tile(ld, h, w, side == 0, node, Qa, smem);
+      qr2_tile<W / 2>(ld, h, w, side == 0, node, Qa, smem);
     }
     if (count == 1) break;
     const int pidx = idx / G;
@@ -978,7 +980,7 @@ __device__ __forceinline__ bool tr_chunk128(const TrJob& J, int side, int chunk,
     if (!last) return false;
     if constexpr (LOCAL) __threadfence_block(); else __threadfence();
   }
-  tr_svd<128>(J, ws, w, n0a, n0b, smem, err, fc);
+  tr_svd<W>(J, ws, w, n0a, n0b, smem, err, fc);
   return true;
 }
 
