@@ -403,10 +403,12 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_tall(const GemmJob* __restrict__
   const int M = J.Md ? *J.Md : J.M, N = J.Nd ? *J.Nd : J.N, K = J.Kd ? *J.Kd : J.K;
   if (it.row0 >= M || it.col0 >= N) return;
   const int mr = min(64, M - it.row0), nc = min(64, N - it.col0);
-  const int r = tid & 63, cg = tid >> 6;
-  double acc[16];
+  // FP64 MFMA on 16 x 16 x 4 tiles: wavefront w takes rows 16w .. 16w + 15 of
+  // the 64 x 64 block, all four 16-column tiles (those past nc skipped)
+  const int w = tid >> 6, l = tid & 63;
+  d4_t acc[4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int t = 0; t < 4; ++t) acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += 32) {
     const int kn = min(32, K - k0);
     for (int e = tid; e < 64 * 32; e += NT_MM) {
@@ -432,32 +434,28 @@ __global__ void __launch_bounds__(NT_MM) k_gemm_tall(const GemmJob* __restrict__
       Bt[kk][cc] = (kk < kn && cc < nc) ? gB(J, k0 + kk, it.col0 + cc) : 0.0;
     }
     __syncthreads();
-    // the tiles are zero past kn: sum over kn rounded up to 4 (the K of the
+    // the tiles are zero past kn: k-steps of 4 up to kn (the K of the
     // update's products is a rank, often 1..3, not 32)
     const int k4 = (kn + 3) & ~3;
+    if (16 * w < mr) {  // uniform in the wavefront
+      for (int kk = 0; kk < k4; kk += 4) {
+        const double a = At[16 * w + (l & 15)][kk + (l >> 4)];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int cc = cg + 4 * q;
-      if (cc < nc) {  // uniform in the wavefront (cg is its index): skips empty columns
-        double sacc = acc[q];
-        for (int kk = 0; kk < k4; kk += 4) {
-          sacc += At[r][kk] * Bt[kk][cc];
-          sacc += At[r][kk + 1] * Bt[kk + 1][cc];
-          sacc += At[r][kk + 2] * Bt[kk + 2][cc];
-          sacc += At[r][kk + 3] * Bt[kk + 3][cc];
-        }
-        acc[q] = sacc;
+        for (int t = 0; t < 4; ++t)
+          if (16 * t < nc) acc[t] = mfma16(a, Bt[kk + (l >> 4)][16 * t + (l & 15)], acc[t]);
       }
     }
     __syncthreads();
   }
-  if (r < mr) {
+  // element e of lane l of tile t: C[16w + 4e + l/16][16t + l%16]
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int cc = cg + 4 * q;
-      if (cc < nc) {
-        double* cp = J.C + (int64_t)(it.row0 + r) + (int64_t)(it.col0 + cc) * J.ldc;
-        const double v = J.alpha * acc[q];
+  for (int t = 0; t < 4; ++t) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int rr = 16 * w + 4 * e + (l >> 4), cc = 16 * t + (l & 15);
+      if (rr < mr && cc < nc) {
+        double* cp = J.C + (int64_t)(it.row0 + rr) + (int64_t)(it.col0 + cc) * J.ldc;
+        const double v = J.alpha * acc[t][e];
         *cp = (J.beta == 0.0) ? v : v + J.beta * (*cp);
       }
     }
