@@ -161,7 +161,10 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
                                               double* JZ, int ldZ) {
   const int rld = J.rld;
   constexpr int G = NT_MM / RT;
-  constexpr int DMAX = RT == 16 ? MAXLEAF / G : 1;
+  // RT = 16 with 16-column slabs: the leaf part on FP64 MFMA (below), no
+  // preloaded leaf column
+  constexpr bool LEAF_MFMA = RT == 16 && CW == 16;
+  constexpr int DMAX = (RT == 16 && !LEAF_MFMA) ? MAXLEAF / G : 1;
   const int tid = threadIdx.x;
   const int r = tid % RT, g = tid / RT;
   const HLeaf lf = J.M.leaf[it.leaf];
@@ -175,7 +178,7 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
   const int R = it.row0 + r;  // output row of this thread within the leaf
   const bool live = r < it.rows;
   double dv[DMAX];
-  if constexpr (RT == 16) {
+  if constexpr (RT == 16 && !LEAF_MFMA) {
 #pragma unroll
     for (int i = 0; i < DMAX; ++i) {
       const int kk = g + G * i;
@@ -229,7 +232,24 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
     double acc[CW];
 #pragma unroll
     for (int c = 0; c < CW; ++c) acc[c] = 0.0;
-    if constexpr (RT == 16) {
+    if constexpr (LEAF_MFMA) {
+      // 16 x 16 tile (the block's rows x this slab's columns) = D(rows, :) Xs:
+      // wavefront wv takes the k-steps 4 wv, 4 wv + 16, ...; its partial tile
+      // goes to mf (row-major) and is summed with the groups' partial rows below
+      const int wv = tid >> 6, ln = tid & 63;
+      const int Ra = it.row0 + (ln & 15);
+      const bool ra = (ln & 15) < it.rows;
+      d4_t lacc = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 4 * wv; k0 < m; k0 += 16) {
+        const int kk = k0 + (ln >> 4);
+        const double a = (ra && kk < m) ? leaf_elem<RT>(lf, kind, trans, Ra, kk) : 0.0;
+        const double b = (kk < m) ? Xs[kk * MA_LD + (ln & 15)] : 0.0;
+        lacc = mfma16(a, b, lacc);
+      }
+      double* mf = shm + (size_t)MA_LD * (m > 256 ? m : 256);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) mf[wv * 256 + (4 * e + (ln >> 4)) * 16 + (ln & 15)] = lacc[e];
+    } else if constexpr (RT == 16) {
 #pragma unroll
       for (int i = 0; i < DMAX; ++i) {
         const int kk = g + G * i;
@@ -317,6 +337,11 @@ __device__ __forceinline__ void mm_apply_rows(const MmJob& J, const MmApply& it,
         double sacc = 0.0;
 #pragma unroll
         for (int g2 = 0; g2 < G; ++g2) sacc += shm[(g2 * RT + rr) * MA_LD + c];
+        if constexpr (LEAF_MFMA) {
+          const double* mf = shm + (size_t)MA_LD * (m > 256 ? m : 256);
+#pragma unroll
+          for (int q = 0; q < NT_MM / 64; ++q) sacc += mf[q * 256 + rr * 16 + c];
+        }
         double* zp = JZ + (out0 - (trans ? J.col0 : J.row0) + it.row0 + rr) + (int64_t)(c0 + c) * ldZ;
         const double v = J.alpha * sacc;
         *zp = (J.beta == 0.0) ? v : v + J.beta * (*zp);

@@ -35,9 +35,10 @@ __global__ void k_tr_form(const TrJob* __restrict__ jobs, const TrForm* __restri
 // ---------------------------------------------------------------- products (k_mm.hip)
 constexpr int MA_LD = 17;
 constexpr int DT_LD = 65;  // transposed leaf tile, padded row
-// dynamic LDS of k_mm_apply: max(m_leaf, 256) * MA_LD doubles
+// dynamic LDS of k_mm_apply: max(m_leaf, 256) * MA_LD doubles (staged X, then
+// the groups' partial rows) and the wavefronts' 16 x 16 MFMA partial tiles
 __host__ __device__ constexpr size_t mm_apply_lds(int mleaf) {
-  return sizeof(double) * (size_t)MA_LD * (size_t)(mleaf > 256 ? mleaf : 256);
+  return sizeof(double) * ((size_t)MA_LD * (size_t)(mleaf > 256 ? mleaf : 256) + (size_t)(NT_MM / 64) * 256);
 }
 
 __global__ void k_mm_proj(const MmJob* __restrict__ jobs, const MmProj* __restrict__ items, int first,
