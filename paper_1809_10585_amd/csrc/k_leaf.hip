@@ -135,19 +135,19 @@ __device__ __forceinline__ void leaf_panel_rows(LeafWs W, int c0, int pw, int M,
     }
     __syncthreads();
     if (w > j && w < pw) {
+      // tau and v in one round of LDS reads; tau = 0 (a column already zero
+      // below its diagonal, v = e_j) gives f = 0 and leaves a unchanged
       const double tau = taus[j];
-      if (tau != 0.0) {
-        double v[RPT];
-        double d0 = 0.0, d1 = 0.0;
+      double v[RPT];
+      double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-        for (int t = 0; t < RPT; ++t) {
-          v[t] = vb[lane + 64 * t];
-          if (t & 1) d1 += v[t] * a[t]; else d0 += v[t] * a[t];
-        }
-        const double f = tau * gsumt<64>(d0 + d1);
-#pragma unroll
-        for (int t = 0; t < RPT; ++t) a[t] -= f * v[t];
+      for (int t = 0; t < RPT; ++t) {
+        v[t] = vb[lane + 64 * t];
+        if (t & 1) d1 += v[t] * a[t]; else d0 += v[t] * a[t];
       }
+      const double f = tau * gsumt<64>(d0 + d1);
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) a[t] -= f * v[t];
     } else if (w < j) {
       // a finished column: G[w, j] = v_w^T v_j (the Gram matrix for T) while
       // the later columns take reflector j

@@ -39,15 +39,9 @@ __device__ __forceinline__ bool jac_rot_fast(double al, double be, double ga, do
   d = __builtin_ldexp(d, -e);
   g = __builtin_ldexp(g, -e);
   const double h2 = fma(d, d, g * g);  // in [1/4, 2]
-  double y = __builtin_amdgcn_rsq(h2);
-  y = y * fma(-0.5 * h2 * y, y, 1.5);
-  y = y * fma(-0.5 * h2 * y, y, 1.5);
-  const double r = h2 * y;
+  const double r = sqrt_nr(h2);
   const double s = r + fabs(d);
-  const double u = 2.0 * r * s;
-  double q = __builtin_amdgcn_rsq(u);
-  q = q * fma(-0.5 * u * q, q, 1.5);
-  q = q * fma(-0.5 * u * q, q, 1.5);
+  const double q = rsq_nr(2.0 * r * s);
   cs = s * q;
   sn = (d >= 0.0 ? g : -g) * q;
   return true;
@@ -63,17 +57,9 @@ __device__ __forceinline__ bool jac_rot_fast(double al, double be, double ga, do
 __device__ __forceinline__ void jac_rot_unit(double al, double be, double ga, double& cs, double& sn) {
   const double d = be - al, g = 2.0 * ga;
   const double h2 = fma(d, d, g * g);
-  const double hh = -0.5 * h2;
-  double y = __builtin_amdgcn_rsq(h2);
-  y = y * fma(hh * y, y, 1.5);
-  y = y * fma(hh * y, y, 1.5);
-  const double r = h2 * y;
+  const double r = sqrt_nr(h2);
   const double s = r + fabs(d);
-  const double u = (2.0 * r) * s;
-  const double uh = -0.5 * u;
-  double q = __builtin_amdgcn_rsq(u);
-  q = q * fma(uh * q, q, 1.5);
-  q = q * fma(uh * q, q, 1.5);
+  const double q = rsq_nr((2.0 * r) * s);
   cs = s * q;
   sn = (d >= 0.0 ? g : -g) * q;
 }

@@ -48,11 +48,22 @@ __device__ __forceinline__ double dpp_mov(double x) {
   return __hiloint2double(hi2, lo2);
 }
 
-__device__ __forceinline__ double swz_xor16(double x) {  // lane ^ 16 within 32 lanes
-  const int lo = __double2loint(x), hi = __double2hiint(x);
-  const int lo2 = __builtin_amdgcn_ds_swizzle(lo, 0x401F);
-  const int hi2 = __builtin_amdgcn_ds_swizzle(hi, 0x401F);
-  return __hiloint2double(hi2, lo2);
+// x[l] + x[l ^ 16] (ROWS = 16) or x[l] + x[l ^ 32] (ROWS = 32) in every lane l,
+// from the gfx950 permlane swaps: with both operands equal to x, the two
+// results hold x of the even and of the odd row group of each pair, so their
+// sum is the same (commutative) addition on every lane of the pair.
+template <int ROWS>
+__device__ __forceinline__ double swap_add(double x) {
+  const unsigned lo = __double2loint(x), hi = __double2hiint(x);
+  if constexpr (ROWS == 16) {
+    const auto l2 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h2 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double(h2[0], l2[0]) + __hiloint2double(h2[1], l2[1]);
+  } else {
+    const auto l2 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h2 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double(h2[0], l2[0]) + __hiloint2double(h2[1], l2[1]);
+  }
 }
 
 __device__ __forceinline__ double lane_read(double x, int lane) {
@@ -69,30 +80,36 @@ __device__ __forceinline__ double gsumt(double x) {
   if constexpr (W >= 4) x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1]
   if constexpr (W >= 8) x += dpp_mov<0x141>(x);  // row_half_mirror
   if constexpr (W >= 16) x += dpp_mov<0x140>(x); // row_mirror
-  if constexpr (W == 32) {
-    const double r0 = lane_read(x, 0), r1 = lane_read(x, 16), r2 = lane_read(x, 32), r3 = lane_read(x, 48);
-    x = ((int)(__lane_id()) < 32) ? r0 + r1 : r2 + r3;
-  }
-  if constexpr (W >= 64) x = (lane_read(x, 0) + lane_read(x, 16)) + (lane_read(x, 32) + lane_read(x, 48));
+  // rows of 16 lanes: (r0 + r1) and (r2 + r3), then their sum, on VALU only
+  if constexpr (W >= 32) x = swap_add<16>(x);
+  if constexpr (W >= 64) x = swap_add<32>(x);
   return x;
 }
 
-// 1/x and sqrt(x) from the hardware estimates refined by Newton steps (a few
-// ulp), much shorter dependency chains than the correctly rounded sequences.
+// 1/x, 1/sqrt(x) and sqrt(x) from the hardware estimates (relative error about
+// 2^-24 on gfx950) with one correction by the series of the residual
+// e = 1 - x r (resp. 1 - x y^2) up to its second-order term:
+//   1/x = r (1 + e + e^2 + ...),  1/sqrt(x) = y (1 + e/2 + 3e^2/8 + ...),
+// so the truncation error is of order e^3 (about 2^-72) and the result is off
+// by rounding only (an ulp or two), with a dependency chain of three or four
+// operations after the estimate instead of two Newton steps.
 __device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, fma(e, e, e), r);
 }
 
-__device__ __forceinline__ double sqrt_nr(double x) {  // x > 0
-  double y = __builtin_amdgcn_rsq(x);
-  y = y * fma(-0.5 * x * y, y, 1.5);
-  y = y * fma(-0.5 * x * y, y, 1.5);
-  const double sq = x * y;
-  return fma(0.5 * y, fma(-sq, sq, x), sq);
+__device__ __forceinline__ double rsq_nr(double x) {  // x > 0
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+__device__ __forceinline__ double sqrt_nr(double x) {  // x > 0: x y (1 + e/2 + 3e^2/8)
+  const double y = __builtin_amdgcn_rsq(x);
+  const double t = x * y;
+  const double e = fma(-t, y, 1.0);
+  return fma(t * e, fma(e, 0.375, 0.5), t);
 }
 
 // Householder reflector of x = [alpha; x2] from alpha and ss = |x2|^2:
