@@ -132,9 +132,14 @@ __device__ __forceinline__ void leaf_panel_rows(LeafWs W, int c0, int pw, int M,
         vb[lane + 64 * t] = a[t];
       }
       if (lane == 0) taus[j] = tau;
+      __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();
     if (w > j && w < pw) {
+      // The owner of the next column runs the critical chain (this update,
+      // then its own reflector before the next barrier): it issues ahead of
+      // the other wavefronts on its SIMD until its reflector is out.
+      if (w == j + 1) __builtin_amdgcn_s_setprio(3);
       // tau and v in one round of LDS reads; tau = 0 (a column already zero
       // below its diagonal, v = e_j) gives f = 0 and leaves a unchanged
       const double tau = taus[j];

@@ -443,7 +443,11 @@ def test_cauchy_backward_and_floor(H):
     A = H.hodlr_build(inp, rank_cap=64)
     an = oracle_anorm(inp)
     X = np.random.default_rng(1001).standard_normal((inp.n, 16))
-    ref, (fr, fq) = _noise_floor(inp, EPS, an, X)
+    # four oracle runs, as for the other ill-conditioned inputs: with one
+    # perturbed run the rank check cannot see that the runs themselves split
+    # at the T-lane recompressions of the top node (rank 20 or 21 at sigma
+    # within a few tau of each other)
+    ref, (fr, fq) = _noise_floor(inp, EPS, an, X, extra=(12, 13))
     F = H.hodlr_qr(A, EPS, anorm=an)
     d = _factor_dense(H, F, inp)
     Q = np.eye(inp.n) - d["Y"] @ d["T"] @ d["Y"].T
